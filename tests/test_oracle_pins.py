@@ -1,0 +1,397 @@
+"""Pins of the FP64 oracle against results that do not come from the oracle itself.
+
+Each test names the mistake in the oracle that it would catch.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from types import SimpleNamespace
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle as O
+import wolf_inputs as WI
+from tests import closed_forms as CF
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LAM = 632.8e-9
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def spec(**kw):
+    base = dict(model=O.MODEL_GSM, amplitude=1.0, sigma_s_m=math.inf, sigma_g_m=math.inf,
+                geometry=O.GEO_NONE, geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None,
+                lens_focal_m=0.0, wavelength_m=0.0)
+    base.update(kw)
+    return SimpleNamespace(**base)
+
+
+# ---------------------------------------------------------------------------------------------
+# The paper's printed numbers (Table 1 and Sec. 5): units, dx, N_a, N_F.
+# Catches: a wrong omega/lambda relation or a wrong dx formula (N vs N_z, missing 2 pi).
+# ---------------------------------------------------------------------------------------------
+def test_paper_printed_numbers():
+    g = json.load(open(os.path.join(HERE, "golden", "paper_examples.json")))
+    e1 = g["ex1_fresnel_square"]
+    lam1 = O.wavelength_from_omega(e1["omega_rad_s"])
+    assert round(lam1 / 1e-10, 1) == e1["printed"]["lambda_angstrom"]
+    assert round(math.sqrt(2 * math.pi * e1["Nz"])) == e1["printed"]["Na_from_sqrt_2piNz"]
+    a = e1["Na"] * e1["dxi_m"]
+    assert round(a / 1e-6, 1) == e1["printed"]["a_um"]
+    assert round(O.fresnel_number(a, lam1, e1["R_m"]), 2) == e1["printed"]["fresnel_number"]
+    # Dark-spot distance R = a^2 / (2 pi lambda) (eq. darkspot): the paper's R to 1%.
+    assert abs(a * a / (2 * math.pi * lam1) / e1["R_m"] - 1) < 0.01
+
+    e3 = g["ex3_imaging"]
+    lam3 = O.wavelength_from_omega(e3["omega_rad_s"])
+    dxb = O.output_pitch(e3["N"], e3["dxi_m"], lam3, e3["R1_m"])
+    assert round(dxb / 1e-3, 2) == e3["printed"]["dx_planeB_mm"]
+    dxc = O.output_pitch(e3["N"], dxb, lam3, e3["R2_m"])           # plane B -> plane C
+    assert round(dxc / 1e-6, 3) == e3["printed"]["dxi_planeC_um"]
+    # Lens law (eq. imaging) and magnification -R2/R1.
+    assert abs(1 / e3["R1_m"] + 1 / e3["R2_m"] - 1 / e3["f_m"]) < 1e-12
+    assert -e3["R2_m"] / e3["R1_m"] == e3["printed"]["lateral_magnification"]
+
+    e4 = g["ex4_gsm_beam"]
+    lam4 = O.wavelength_from_omega(e4["omega_rad_s"])
+    assert round(lam4 / 1e-9 / 10) * 10 == e4["printed"]["lambda_nm"]
+    dx4 = O.output_pitch(e4["N"], e4["dxi_m"], lam4, e4["R_m"])
+    assert abs(dx4 / e4["dxi_m"] - 1) < 1e-3 and e4["printed"]["dx_equals_dxi"]
+
+
+# ---------------------------------------------------------------------------------------------
+# Closed-form Gaussian Schell-model propagation (Sec. 5.4; Mandel-Wolf beam).
+# Catches: a wrong scale C, a wrong chirp sign (the k (x2^2 - x1^2) / 2R phase), a wrong dx,
+# or a wrong source width convention (4 sS^2 vs 2 sS^2).
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_gsm_closed_form_4d(farfield):
+    n, p, ss, sg, z = 64, 20e-6, 0.08e-3, 0.12e-3, 0.3
+    w = O.build_source(spec(sigma_s_m=ss, sigma_g_m=sg), n, p)
+    wb, dx = O.propagate(w, n, p, LAM, z, farfield)
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    cx = CF.gsm_axis_closed_form(X[:, None], X[None, :], ss, sg, LAM, z, farfield)
+    cy = CF.gsm_axis_closed_form(Y[:, None], Y[None, :], ss, sg, LAM, z, farfield)
+    ref = cx[:, None, :, None] * cy[None, :, None, :]
+    assert rel(wb, ref) < 1e-9
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+def test_gsm_closed_form_separable_n128(farfield):
+    n, p, ss, sg, z = 128, 20e-6, 0.1e-3, 0.05e-3, 0.5
+    bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, ss, sg, "x"),
+                                   O.gsm_axis_factor(n, p, ss, sg, "y"), n, p, LAM, z, farfield)
+    dx = O.output_pitch(n, p, LAM, z)
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    cx = CF.gsm_axis_closed_form(X[:, None], X[None, :], ss, sg, LAM, z, farfield)
+    cy = CF.gsm_axis_closed_form(Y[:, None], Y[None, :], ss, sg, LAM, z, farfield)
+    assert rel(np.kron(bx, by), np.kron(cx, cy)) < 1e-11
+
+
+# ---------------------------------------------------------------------------------------------
+# A tilted, off-centre coherent Gaussian beam (rank-1 W = U* (x) U), exact Gaussian integral.
+# Catches: the transform direction (conj kernel on the wrong point), the y flip applied on one
+# side only, or a transposed operand; each moves the beam the wrong way.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_tilted_beam_closed_form(farfield):
+    n, p, w0, z = 64, 20e-6, 80e-6, 0.3
+    x0, y0 = 40e-6, -30e-6
+    kx, ky = 2 * math.pi / LAM * 1e-3, -2 * math.pi / LAM * 0.7e-3
+    xs, ys = O.grid_x(n, p), O.grid_y(n, p)
+    u = np.exp(-(xs[:, None] - x0) ** 2 / w0 ** 2 - (ys[None, :] - y0) ** 2 / w0 ** 2
+               + 1j * (kx * xs[:, None] + ky * ys[None, :]))
+    w = np.conj(u)[:, :, None, None] * u[None, None, :, :]
+    wb, dx = O.propagate(w, n, p, LAM, z, farfield)
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    v = CF.gaussian_beam_field(X[:, None], x0, w0, kx, LAM, z, farfield) * \
+        CF.gaussian_beam_field(Y[None, :], y0, w0, ky, LAM, z, farfield)
+    ref = np.conj(v)[:, :, None, None] * v[None, None, :, :] / (LAM * z) ** 2
+    assert rel(wb, ref) < 1e-9
+    # The spectral density peaks near the geometric landing point x0 + kappa z / k.
+    s = O.spectral_density(wb)
+    i, j = np.unravel_index(np.argmax(s), s.shape)
+    assert abs(X[i] - (x0 + kx * z * LAM / (2 * math.pi))) < 2 * dx
+    assert abs(Y[j] - (y0 + ky * z * LAM / (2 * math.pi))) < 2 * dx
+
+
+# ---------------------------------------------------------------------------------------------
+# Non-separable coherent source: rank-1 reduction to the textbook field Fresnel transform (FFT).
+# Catches: mistakes that only show on non-separable sources (the 2D geometry, axis pairing).
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_rank1_circle_matches_field_fft(farfield):
+    n, p, z = 32, 20e-6, 0.1
+    w = O.build_source(spec(model=O.MODEL_COHERENT, geometry=O.GEO_CIRCLE, geo_r0_m=10 * p), n, p)
+    u = O.geometry_mask(n, p, O.GEO_CIRCLE, 10 * p)
+    wb, _ = O.propagate(w, n, p, LAM, z, farfield)
+    ub = CF.fresnel_field_fft(u.astype(np.complex128), n, p, LAM, z, farfield)
+    ref = np.conj(ub)[:, :, None, None] * ub[None, None, :, :] / (LAM * z) ** 2
+    assert rel(wb, ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------
+# Invariants on random Hermitian non-negative definite sources.
+# Parseval catches any scale error. Hermiticity and PSD catch a conj on the wrong side.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_parseval_hermitian_psd(farfield):
+    n, p, z = 8, 20e-6, 0.05
+    w = WI.random_hermitian_psd(n, seed=1)
+    wb, dx = O.propagate(w, n, p, LAM, z, farfield)
+    sa, sb = O.spectral_density(w), O.spectral_density(wb)
+    assert abs(sb.sum() * dx ** 2 / (sa.sum() * p ** 2) - 1) < 1e-13
+    m = wb.reshape(n * n, n * n)
+    assert np.abs(m - m.conj().T).max() < 1e-14 * np.abs(m).max()
+    assert np.linalg.eigvalsh(0.5 * (m + m.conj().T)).min() > -1e-12 * np.abs(m).max()
+    mu = O.degree_of_coherence_full(wb)
+    assert np.abs(mu).max() <= 1 + 1e-12
+
+
+def test_primary_source_scale():
+    """eq. (C) with Lambda = 1/(4 pi) for a primary source: the ratio to the secondary source is
+    (lambda / 4 pi)^2."""
+    n, p, z = 4, 20e-6, 0.05
+    w = WI.random_hermitian_psd(n, seed=2)
+    a, _ = O.propagate(w, n, p, LAM, z, False, O.KIND_SECONDARY)
+    b, _ = O.propagate(w, n, p, LAM, z, False, O.KIND_PRIMARY)
+    assert rel(b, a * (LAM / (4 * math.pi)) ** 2) < 1e-14
+
+
+# ---------------------------------------------------------------------------------------------
+# Incoherent sources (Sec. 5.2): S_B is uniform, Fresnel == far field, and the discrete
+# van Cittert-Zernike form holds exactly. The annulus mu follows the Bessel form to pixel accuracy.
+# Catches: the chirp applied on the output side only, or a wrong sign in the x1 - x2 dependence.
+# ---------------------------------------------------------------------------------------------
+def test_incoherent_source_identities():
+    n, p, z = 16, 20e-6, 0.2
+    sp = spec(model=O.MODEL_INCOHERENT, amplitude=2.0, geometry=O.GEO_ANNULUS, geo_r0_m=6 * p,
+              geo_r1_m=2 * p)
+    w = O.build_source(sp, n, p)
+    y = O.geometry_mask(n, p, O.GEO_ANNULUS, 6 * p, 2 * p)
+    wf, dx = O.propagate(w, n, p, LAM, z, False)
+    wff, _ = O.propagate(w, n, p, LAM, z, True)
+    assert rel(wf, wff) < 1e-13
+    s = O.spectral_density(wf)
+    expect = O.coupling_constant(LAM, z) * p ** 4 * 2.0 * y.sum()
+    assert np.abs(s / expect - 1).max() < 1e-13
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    xs, ys = O.grid_x(n, p), O.grid_y(n, p)
+    for (m1, n1, m2, n2) in [(3, 4, 9, 1), (8, 8, 0, 15), (15, 2, 5, 11)]:
+        bx, by = X[m1] - X[m2], Y[n1] - Y[n2]
+        ph = np.exp(2j * math.pi * (bx * xs[:, None] + by * ys[None, :]) / (LAM * z))
+        vcz = O.coupling_constant(LAM, z) * p ** 4 * 2.0 * np.sum(y * ph)
+        chirp = np.exp(-1j * math.pi * (X[m1] ** 2 + Y[n1] ** 2 - X[m2] ** 2 - Y[n2] ** 2) / (LAM * z))
+        assert abs(wf[m1, n1, m2, n2] - chirp * vcz) < 1e-13 * abs(expect)
+
+
+def test_annulus_mu_bessel_form():
+    n, p, z, lam = 64, 1e-3, 5.0, O.wavelength_from_omega(3.7699e15)   # example 2 pitch/omega/R
+    sp = spec(model=O.MODEL_INCOHERENT, geometry=O.GEO_ANNULUS, geo_r0_m=11 * p, geo_r1_m=5 * p)
+    w = O.build_source(sp, n, p)
+    wb, dx = O.propagate(w, n, p, lam, z, True)
+    mu = O.degree_of_coherence(wb, n // 2, n // 2)
+    X = O.grid_x(n, dx)
+    theory = CF.annulus_mu_farfield(np.abs(X), 11 * p, 5 * p, lam, z)
+    row = np.abs(mu[:, n // 2])
+    first_lobe = np.abs(X) < 0.6 * lam * z / (11 * p)
+    assert np.abs(row[first_lobe] - np.abs(theory[first_lobe])).max() < 0.03
+    # Phase of mu(0, x2) is the output chirp q(z, x2) (the eq. theory_mu_annular exponential).
+    k = n // 2 + 3
+    assert abs(np.angle(mu[k, n // 2] / np.sign(theory[k]) * np.exp(-1j * math.pi * X[k] ** 2 / (lam * z)))) < 1e-9
+
+
+# ---------------------------------------------------------------------------------------------
+# Thin lens (Sec. 2.2) and the q algebra (eqs. qprop): Fresnel of a lensed source at z = f equals
+# the far field of the unlensed source. Catches: the lens applied with the wrong conjugation.
+# ---------------------------------------------------------------------------------------------
+def test_lens_at_focal_distance_is_far_field():
+    n, p, f = 16, 20e-6, 0.2
+    base = dict(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3, geometry=O.GEO_CIRCLE, geo_r0_m=6 * p)
+    wl = O.build_source(spec(lens_focal_m=f, wavelength_m=LAM, **base), n, p)
+    w0 = O.build_source(spec(**base), n, p)
+    a, _ = O.propagate(wl, n, p, LAM, f, False)
+    b, _ = O.propagate(w0, n, p, LAM, f, True)
+    assert rel(a, b) < 1e-12
+
+
+def test_q_algebra():
+    n, p, z = 64, 20e-6, 0.3
+    beta = 1.7
+    # q(R, xi / beta) = q(beta^2 R, xi)
+    assert np.abs(O.chirp_table(n, p / beta, LAM, z) - O.chirp_table(n, p, LAM, beta ** 2 * z)).max() < 1e-12
+    # q(R1) q*(R2) = q(R1 R2 / (R2 - R1)), and q q* = 1
+    r1, r2 = 0.3, 0.7
+    lhs = O.chirp_table(n, p, LAM, r1) * np.conj(O.chirp_table(n, p, LAM, r2))
+    assert np.abs(lhs - O.chirp_table(n, p, LAM, r1 * r2 / (r2 - r1))).max() < 1e-11
+    t = O.chirp_table(n, p, LAM, z)
+    assert np.abs(np.abs(t) - 1).max() < 1e-15
+
+
+def test_chirp_table_high_precision():
+    """Each FP64 entry agrees with a 40-digit evaluation of exp(i pi xi^2 / (lambda R))."""
+    n, p, z = 256, 10e-6, 0.1
+    t = O.chirp_table(n, p, LAM, z)
+    mpmath.mp.dps = 40
+    for i in [0, 1, 7, 100, 128, 129, 200, 255]:
+        ph = mpmath.pi * (mpmath.mpf(p) * (i - n // 2)) ** 2 / (mpmath.mpf(LAM) * mpmath.mpf(z))
+        ref = complex(mpmath.cos(ph), mpmath.sin(ph))
+        assert abs(t[i] - ref) < 5e-12
+
+
+# ---------------------------------------------------------------------------------------------
+# Other routes to the same operator: a literal loop over the eight indices (N = 4), the full
+# N^2 x N^2 kernel, and Algorithm 2 step by step with numpy FFTs (checks the centring reading).
+# ---------------------------------------------------------------------------------------------
+def test_brute_force_loop_n4():
+    n, p, z = 4, 20e-6, 0.01
+    w = WI.random_complex((n, n, n, n), seed=3)
+    dx = O.output_pitch(n, p, LAM, z)
+    xs, ys, X, Y = O.grid_x(n, p), O.grid_y(n, p), O.grid_x(n, dx), O.grid_y(n, dx)
+    s = p ** 4 / (LAM * z) ** 2
+
+    def h(xo, yo, xi, eta):
+        return complex(np.exp(1j * math.pi * ((xo - xi) ** 2 + (yo - eta) ** 2) / (LAM * z)))
+
+    out = np.zeros_like(w)
+    for m1 in range(n):
+        for n1 in range(n):
+            for m2 in range(n):
+                for n2 in range(n):
+                    acc = 0j
+                    for i1 in range(n):
+                        for j1 in range(n):
+                            a = np.conj(h(X[m1], Y[n1], xs[i1], ys[j1]))
+                            for i2 in range(n):
+                                for j2 in range(n):
+                                    acc += a * w[i1, j1, i2, j2] * h(X[m2], Y[n2], xs[i2], ys[j2])
+                    out[m1, n1, m2, n2] = s * acc
+    ref, _ = O.propagate(w, n, p, LAM, z)
+    assert rel(ref, out) < 1e-13
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+def test_matrix_and_alg2_routes(farfield):
+    n, p, z = 8, 20e-6, 0.05
+    w = WI.random_complex((n, n, n, n), seed=4)
+    a, _ = O.propagate(w, n, p, LAM, z, farfield)
+    assert rel(O.propagate_matrix(w, n, p, LAM, z, farfield), a) < 1e-13
+    b, _ = O.propagate_alg2(w, n, p, LAM, z, farfield)
+    assert rel(b, a) < 1e-13
+
+
+def test_separable_route():
+    n, p, z = 16, 20e-6, 0.2
+    wx, wy = O.gsm_axis_factor(n, p, 0.1e-3, 0.05e-3, "x"), O.gsm_axis_factor(n, p, 0.1e-3, 0.05e-3, "y")
+    w = wx[:, None, :, None] * wy[None, :, None, :]
+    assert rel(w, O.build_source(spec(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3), n, p)) < 1e-15
+    bx, by = O.propagate_separable(wx, wy, n, p, LAM, z)
+    a, _ = O.propagate(w, n, p, LAM, z)
+    assert rel(bx[:, None, :, None] * by[None, :, None, :], a) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------------
+# Adjoint: dot-product test and, for diagonal G_B, the Toeplitz closed form.
+# Catches: a transposed or unconjugated kernel in the adjoint.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_adjoint_dot_product(farfield):
+    n, p, z = 8, 20e-6, 0.05
+    w = WI.random_complex((n, n, n, n), seed=5)
+    g = WI.random_complex((n, n, n, n), seed=6)
+    pw, _ = O.propagate(w, n, p, LAM, z, farfield)
+    pg = O.propagate_adjoint(g, n, p, LAM, z, farfield)
+    lhs = np.vdot(pw, g)
+    rhs = np.vdot(w, pg)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_adjoint_diagonal_toeplitz():
+    """G_B = diag(g): G_A(xi1, xi2) = s q(xi1) q*(xi2) sum_x g(x) exp(-2 pi i x.(xi1 - xi2) / (lambda z))."""
+    n, p, z = 8, 20e-6, 0.05
+    gs = WI.rng(7).standard_normal((n, n))
+    gb = np.zeros((n, n, n, n), dtype=np.complex128)
+    for i in range(n):
+        for j in range(n):
+            gb[i, j, i, j] = gs[i, j]
+    ga = O.propagate_adjoint(gb, n, p, LAM, z)
+    dx = O.output_pitch(n, p, LAM, z)
+    X, Y, xs, ys = O.grid_x(n, dx), O.grid_y(n, dx), O.grid_x(n, p), O.grid_y(n, p)
+    s = p ** 4 / (LAM * z) ** 2
+    for (i1, j1, i2, j2) in [(0, 0, 0, 0), (1, 2, 3, 4), (7, 0, 2, 6), (5, 5, 1, 3)]:
+        dxi, deta = xs[i1] - xs[i2], ys[j1] - ys[j2]
+        acc = np.sum(gs * np.exp(-2j * math.pi * (X[:, None] * dxi + Y[None, :] * deta) / (LAM * z)))
+        qq = np.exp(1j * math.pi * (xs[i1] ** 2 + ys[j1] ** 2 - xs[i2] ** 2 - ys[j2] ** 2) / (LAM * z))
+        assert abs(ga[i1, j1, i2, j2] - s * qq * acc) < 1e-12 * s * np.abs(gs).sum()
+
+
+# ---------------------------------------------------------------------------------------------
+# Fit gradient vs central finite differences of the oracle's own loss.
+# Catches: a missing factor 2 or a missing term in dL/dI, dL/dsg.
+# ---------------------------------------------------------------------------------------------
+def test_fit_gradient_finite_differences():
+    n, p, z = 8, 20e-6, 0.05
+    imap = WI.intensity_map(n, p, seed=4, env_sigma_m=0.05e-3).astype(np.float64)
+    tsrc = O.build_source(spec(sigma_s_m=0.05e-3, sigma_g_m=0.03e-3), n, p)
+    target = O.spectral_density(O.propagate(tsrc, n, p, LAM, z)[0])
+    sg = 0.04e-3
+    loss, d_i, d_sg = O.fit_gradient(imap, sg, target, n, p, LAM, z)
+    assert abs(loss - O.fit_loss(imap, sg, target, n, p, LAM, z)) < 1e-12 * loss
+    for (i, j) in [(3, 4), (0, 7), (4, 4)]:
+        h = 1e-6 * imap[i, j]
+        ip, im = imap.copy(), imap.copy()
+        ip[i, j] += h
+        im[i, j] -= h
+        fd = (O.fit_loss(ip, sg, target, n, p, LAM, z) - O.fit_loss(im, sg, target, n, p, LAM, z)) / (2 * h)
+        assert abs(fd - d_i[i, j]) < 1e-6 * np.abs(d_i).max()
+    h = 1e-6 * sg
+    fd = (O.fit_loss(imap, sg + h, target, n, p, LAM, z) - O.fit_loss(imap, sg - h, target, n, p, LAM, z)) / (2 * h)
+    assert abs(fd - d_sg) < 1e-6 * abs(d_sg)
+
+
+# ---------------------------------------------------------------------------------------------
+# Source builder (Sec. 3.2; Algorithms 6-7; eqs. circle, W_def).
+# ---------------------------------------------------------------------------------------------
+def test_source_builder_definitions():
+    n, p = 16, 20e-6
+    # Circle: pixel-unit boundary included (20 px radius at 20 um pitch gives 0.4 mm exactly).
+    y = O.geometry_mask(64, 20e-6, O.GEO_CIRCLE, 0.4e-3)
+    assert y[32 + 20, 32] == 1 and y[32 + 12, 32 + 16] == 1 and y[32 + 15, 32 + 14] == 0
+    assert y.sum() == sum(1 for a in range(-32, 32) for b in range(-32, 32) if a * a + b * b <= 400)
+    # GSM diagonal gives S = A exp(-xi^2 / (2 sS^2)) and |mu| = exp(-|d|^2 / (2 sg^2)).
+    w = O.build_source(spec(amplitude=3.0, sigma_s_m=0.1e-3, sigma_g_m=0.05e-3), n, p)
+    s = O.spectral_density(w)
+    xs, ys = O.grid_x(n, p), O.grid_y(n, p)
+    r2 = xs[:, None] ** 2 + ys[None, :] ** 2
+    assert np.abs(s - 3.0 * np.exp(-r2 / (2 * (0.1e-3) ** 2))).max() < 1e-14
+    mu = O.degree_of_coherence(w, 8, 8)
+    d2 = (xs[:, None] - xs[8]) ** 2 + (ys[None, :] - ys[8]) ** 2
+    assert np.abs(mu - np.exp(-d2 / (2 * (0.05e-3) ** 2))).max() < 1e-14
+    # MAP model: S = A I exactly (eq. W_def with mu(xi, xi) = 1).
+    imap = WI.intensity_map(n, p, seed=4)
+    wm = O.build_source(spec(model=O.MODEL_MAP, amplitude=2.0, sigma_g_m=0.05e-3, intensity_map=imap), n, p)
+    assert np.abs(O.spectral_density(wm) - 2.0 * imap).max() < 1e-6 * imap.max()
+    # Lens: |W| unchanged, phase q(f, xi1) q*(f, xi2).
+    wl = O.build_source(spec(sigma_s_m=0.1e-3, lens_focal_m=0.2, wavelength_m=LAM), n, p)
+    w0 = O.build_source(spec(sigma_s_m=0.1e-3), n, p)
+    assert np.abs(np.abs(wl) - np.abs(w0)).max() < 1e-15
+    ph = wl[3, 4, 9, 1] / w0[3, 4, 9, 1]
+    expect = np.exp(1j * math.pi * (r2[3, 4] - r2[9, 1]) / (LAM * 0.2))
+    assert abs(ph - expect) < 1e-13
+
+
+def test_degree_of_coherence_floor():
+    n = 8
+    w = O.build_source(spec(model=O.MODEL_COHERENT, geometry=O.GEO_CIRCLE, geo_r0_m=2 * 20e-6), n, 20e-6)
+    mu = O.degree_of_coherence(w, 4, 4)
+    y = O.geometry_mask(n, 20e-6, O.GEO_CIRCLE, 2 * 20e-6)
+    assert np.array_equal(np.abs(mu) > 0, y > 0)
+    assert np.allclose(mu[y > 0], 1.0)
+    assert not O.degree_of_coherence(w, 0, 0).any()       # P1 outside the source: mu = 0
