@@ -1,0 +1,198 @@
+/*
+ * libwolf: MI355X (gfx950) propagation of the cross-spectral density (CSD) of a planar source.
+ *
+ * The method is that of Magalhaes & Rebordao, "PyWolf: A PyOpenCL implementation for simulating
+ * the propagation of partially coherent light" (arXiv 2203.02734).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - CSD layout: one contiguous array W[i1][j1][i2][j2] of N^4 complex numbers, j2 fastest. The
+ *    real and imaginary parts are interleaved, as torch.complex64 / torch.complex128 of shape
+ *    (N, N, N, N) store them. Index (i, j) is the point
+ *    (pitch (i - N/2), pitch (N/2 - j)) (Sec. 3.1, eqs. point and n12).
+ *  - N is a power of two from 2 to 256. Other values return WOLF_EUNSUPPORTED.
+ *  - dtype WOLF_C64 computes in FP32 (complex64 data); WOLF_C128 computes in FP64
+ *    (complex128 data). In both, the quadratic-phase tables and the FFT twiddles are built in
+ *    FP64 with argument reduction.
+ *  - Every buffer argument is device memory, allocated and owned by the caller. The library
+ *    checks that each buffer lies in one device allocation large enough for the call. A host
+ *    pointer or a too-small buffer returns WOLF_EINVAL before anything is launched.
+ *  - Calls are asynchronous on `stream`, a hipStream_t passed as void*. NULL is the default
+ *    stream. There is no implicit synchronisation.
+ *  - Arguments are validated before any launch, and a call that fails validation has no side
+ *    effect. A launch failure, or a sticky error from earlier GPU work, returns WOLF_EDEVICE.
+ *    wolf_last_error_message() gives details. No C++ exception crosses this interface.
+ *  - Input and output may be the same buffer (in place). Buffers that partly overlap return
+ *    WOLF_EINVAL.
+ *  - Units are SI (metres).
+ */
+#ifndef WOLF_H
+#define WOLF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WOLF_API __attribute__((visibility("default")))
+
+typedef int32_t wolf_status;
+enum {
+  WOLF_OK = 0,
+  WOLF_EINVAL = -1,       /* invalid argument (null, range, overlap, buffer too small, host pointer) */
+  WOLF_EUNSUPPORTED = -2, /* valid but not supported (N not a power of two in [2, 256]) */
+  WOLF_ENOMEM = -3,       /* the library could not allocate its own small device scratch */
+  WOLF_EDEVICE = -4       /* HIP error at launch, or a sticky error from earlier GPU work */
+};
+
+enum { WOLF_C64 = 0, WOLF_C128 = 1 };
+
+/* Obliquity factor Lambda of eq. (h_free): a secondary source (an aperture, Lambda = 1/(i lambda)
+ * at normal incidence) or a primary source (Lambda = 1/(4 pi)). C = Lambda1* Lambda2 / R^2, eq. (C). */
+enum { WOLF_SECONDARY = 0, WOLF_PRIMARY = 1 };
+
+/* Source models (Sec. 3.2; eq. W_def; Sec. 5.1, 5.2, 5.4; Algorithm 7). */
+enum {
+  WOLF_MODEL_GSM = 0,       /* A exp(-(xi1^2+xi2^2)/(4 sS^2)) exp(-|xi1-xi2|^2/(2 sg^2)); sS or sg may be +inf */
+  WOLF_MODEL_MAP = 1,       /* A sqrt(I(p1)) sqrt(I(p2)) exp(-|xi1-xi2|^2/(2 sg^2)), I a device N*N map */
+  WOLF_MODEL_COHERENT = 2,  /* A (mu = 1, uniform S) */
+  WOLF_MODEL_INCOHERENT = 3 /* A delta(p1, p2) (Kronecker delta on the grid) */
+};
+
+/* Geometry Y(xi) in {0,1} of eq. (GSM_source); W0 = Y(xi1) Y(xi2) W_rho (Sec. 3.2, eq. circle). */
+enum {
+  WOLF_GEO_NONE = 0,
+  WOLF_GEO_CIRCLE = 1,  /* |xi| <= r0 */
+  WOLF_GEO_SQUARE = 2,  /* |x| <= r0 and |y| <= r0 (r0 = half side) */
+  WOLF_GEO_ANNULUS = 3, /* r1 < |xi| <= r0 */
+  WOLF_GEO_MASK = 4     /* caller's device N*N uint8 mask, nonzero = inside */
+};
+
+typedef struct wolf_source {
+  int32_t model;             /* WOLF_MODEL_* */
+  int32_t geometry;          /* WOLF_GEO_* */
+  double amplitude;          /* A >= 0 */
+  double sigma_s_m;          /* GSM r.m.s. width of S (> 0, +inf = uniform) */
+  double sigma_g_m;          /* GSM/MAP r.m.s. width of mu (> 0, +inf = coherent) */
+  double geo_r0_m;           /* circle / annulus outer radius, square half side (> 0) */
+  double geo_r1_m;           /* annulus inner radius (0 <= r1 < r0) */
+  const float* intensity_map;/* MAP only: device, N*N float32 [i][j], >= 0 */
+  const uint8_t* mask;       /* MASK only: device, N*N uint8 [i][j] */
+  double lens_focal_m;       /* thin lens in the source plane, 0 = none; Sec. 2.2 */
+  double wavelength_m;       /* needed iff lens_focal_m != 0 */
+} wolf_source;
+
+/*
+ * wolf_build_source -- source CSD array W0 (Algorithm 1 steps 1-3; Sec. 3.2, eq. GSM_source).
+ *
+ * W0[p1; p2] = Y(p1) Y(p2) W_rho(xi1, xi2), with W_rho set by src->model. With a lens, W0 is then
+ * multiplied by q(f, xi1) q*(f, xi2), where q(R, xi) = exp(i pi |xi|^2 / (lambda R)) (eq. q_factor).
+ * This is the thin lens T = q*(f, x) of Sec. 2.2, applied as T*(x1) W T(x2).
+ * The geometry test runs in pixel units: d2 <= floor((r/pitch)^2 (1 + 1e-9)), with d2 an exact integer.
+ *   src      host pointer to the description. The device pointers it holds are read by the kernel.
+ *   n, pitch_m   grid size and sample pitch (> 0).
+ *   w_out    device, N^4 complex of `dtype`, written in full (write-only).
+ */
+WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double pitch_m, int32_t dtype,
+                                       void* w_out, void* stream);
+
+/*
+ * wolf_propagate_fresnel -- free-space Fresnel propagation of W over distance z
+ * (Sec. 2.1 eq. W_fresnel; Sec. 3.4 Algorithms 2-3).
+ *
+ * W_B(x1, x2) = C pitch^4 sum_{xi1, xi2} h*(x1, xi1) W_A(xi1, xi2) h(x2, xi2),
+ * with h(x, xi) = exp(i pi |x - xi|^2 / (lambda z)) (eqs. h_free, approx_L) and C from eq. (C).
+ * The output lies on the same index grid with pitch dx = lambda z / (N pitch) (eq. spatial_resolution).
+ * The direct DFT runs over the second point and the inverse DFT over the first (h* on xi1).
+ *   w_in, w_out   device, N^4 complex of `dtype`. They may be equal (in place).
+ *   kind          WOLF_SECONDARY or WOLF_PRIMARY.
+ *   out_pitch_m   optional host pointer that receives dx.
+ */
+WOLF_API wolf_status wolf_propagate_fresnel(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                            double wavelength_m, double z_m, int32_t kind, int32_t dtype,
+                                            double* out_pitch_m, void* stream);
+
+/*
+ * wolf_propagate_farfield -- far-field propagation (Sec. 2.1 eq. W_farfield).
+ * Same as wolf_propagate_fresnel with the source-plane propagator q(z, xi) set to 1, so
+ * h(x, xi) = exp(i pi |x|^2 / (lambda z)) exp(-2 pi i x.xi / (lambda z)). The output propagator is kept.
+ */
+WOLF_API wolf_status wolf_propagate_farfield(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                             double wavelength_m, double z_m, int32_t kind, int32_t dtype,
+                                             double* out_pitch_m, void* stream);
+
+/*
+ * wolf_propagate_adjoint -- adjoint of the Fresnel (farfield = 0) or far-field (farfield = 1)
+ * propagation, for the real inner product Re sum conj(a) b. It is the derivative operator of the
+ * paper's propagation (eq. W_general).
+ * For P(W) = C pitch^4 conj(H) W H^T: g_in = C pitch^4 H^T g_out conj(H), i.e.
+ * G_A(xi1, xi2) = C pitch^4 sum_{x1, x2} h(x1, xi1) G_B(x1, x2) h*(x2, xi2).
+ * With torch's convention for complex gradients (dL/dRe + i dL/dIm), this maps the gradient with
+ * respect to W_B to the gradient with respect to W_A.
+ *   g_out   device, N^4, gradient on the output grid (pitch lambda z / (N pitch)).
+ *   g_in    device, N^4, written. It may equal g_out.
+ */
+WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32_t n, double pitch_m,
+                                            double wavelength_m, double z_m, int32_t farfield, int32_t kind,
+                                            int32_t dtype, void* stream);
+
+/*
+ * wolf_spectral_density -- S[i][j] = Re W[i][j; i][j] (Sec. 3.5, Algorithm 4, eq. defS).
+ *   s_out   device, N*N real (float32 for WOLF_C64, float64 for WOLF_C128).
+ */
+WOLF_API wolf_status wolf_spectral_density(const void* w, int32_t n, int32_t dtype, void* s_out, void* stream);
+
+/*
+ * wolf_degree_of_coherence -- mu(P1, x) = W(P1, x) / sqrt(S(P1) S(x)) (Sec. 3.5, Algorithm 5,
+ * eq. defMu; the printed numerator W(xi, xi) is read as W(xi1, xi2)).
+ * Where S(P1) <= tau or S(x) <= tau, with tau = s_floor_rel * max S, mu = 0.
+ *   ip, jp   index of P1 in [0, N): mu_out is N*N complex [i][j] (the slice mu(P1, .)).
+ *            ip = jp = -1: mu_out is the full N^4 mu[p1; p2].
+ *   s_floor_rel   >= 0 (1e-12 is a good default).
+ * Uses a small per-device scratch owned by the library. Calls that use it on one device must be
+ * ordered (same stream, or synchronised).
+ */
+WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp,
+                                              double s_floor_rel, void* mu_out, void* stream);
+
+/*
+ * wolf_propagate_batch -- many (lambda, z) pairs of one source (polychromatic light; the paper's
+ * Sec. 6 names it as future work). For pair k, weight[k] * w_src is propagated to distance z[k]
+ * at wavelength lambda[k] into `work`. Then S_k and mu_k(P1, .) are extracted into
+ * s_out[k] and mu_out[k].
+ * The first call for a given shape records the sequence of launches in a hipGraph; later calls
+ * with the same shape replay it.
+ *   w_src          device N^4, read only.
+ *   wavelength_m, z_m, weight   host arrays of n_pairs (> 0, > 0, >= 0).
+ *   work           device N^4 scratch owned by the caller (overwritten).
+ *   s_out          device n_pairs * N*N real; mu_out: device n_pairs * N*N complex.
+ */
+WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double pitch_m, int32_t n_pairs,
+                                          const double* wavelength_m, const double* z_m, const double* weight,
+                                          int32_t farfield, int32_t kind, int32_t dtype, int32_t ip, int32_t jp,
+                                          double s_floor_rel, void* work, void* s_out, void* mu_out, void* stream);
+
+/*
+ * wolf_chirp_table -- the FP64-built table of the quadratic-phase propagator q(z, xi) of
+ * eq. (q_factor), along one axis: out[i] = exp(i pi (pitch (i - N/2))^2 / (lambda z)), i in [0, N).
+ * The 2D propagator is out[i] * out[j]. It is the same table the propagation kernels build, minus
+ * their (-1)^i centring factor.
+ *   out   device, N complex of `dtype`.
+ */
+WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double wavelength_m, double z_m, int32_t dtype,
+                                      void* out, void* stream);
+
+/* Output pitch dx = lambda z / (N pitch) of eq. (spatial_resolution). Pure host arithmetic. */
+WOLF_API double wolf_output_pitch(int32_t n, double pitch_m, double wavelength_m, double z_m);
+
+WOLF_API const char* wolf_status_string(wolf_status s);
+/* Details of the last failed call on this host thread (empty if none). */
+WOLF_API const char* wolf_last_error_message(void);
+WOLF_API int32_t wolf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WOLF_H */

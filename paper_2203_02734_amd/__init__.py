@@ -1,0 +1,253 @@
+"""wolf: MI355X-native propagation of the cross-spectral density of a planar source.
+
+This is the Python binding of libwolf (include/wolf.h). It only marshals arguments: torch
+tensors supply device memory and the current HIP stream, and every step runs in the library's
+HIP kernels. There is no CPU fallback. If libwolf.so is not built, `load()` raises.
+
+The method is that of Magalhaes & Rebordao, "PyWolf" (arXiv 2203.02734): a source CSD array
+W[i1, j1, i2, j2] (Sec. 3.1) propagated in the Fresnel or far-field approximation (Sec. 2.1,
+Sec. 3.4), then the spectral density and the degree of coherence (Sec. 3.5).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libwolf.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE = 0, -1, -2, -3, -4
+C64, C128 = 0, 1
+SECONDARY, PRIMARY = 0, 1
+MODEL_GSM, MODEL_MAP, MODEL_COHERENT, MODEL_INCOHERENT = 0, 1, 2, 3
+GEO_NONE, GEO_CIRCLE, GEO_SQUARE, GEO_ANNULUS, GEO_MASK = 0, 1, 2, 3, 4
+
+EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfield", "wolf_propagate_adjoint",
+            "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
+            "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version"]
+
+
+class WolfError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where} failed with status {status}: {detail}")
+        self.status = status
+
+
+class _Source(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("geometry", ctypes.c_int32), ("amplitude", ctypes.c_double),
+                ("sigma_s_m", ctypes.c_double), ("sigma_g_m", ctypes.c_double), ("geo_r0_m", ctypes.c_double),
+                ("geo_r1_m", ctypes.c_double), ("intensity_map", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("lens_focal_m", ctypes.c_double), ("wavelength_m", ctypes.c_double)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libwolf.so (once). Raises if it is missing: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libwolf.so not found at {path}; build it with paper_2203_02734_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    i32, f64, vp = ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "wolf_build_source": [ctypes.POINTER(_Source), i32, f64, i32, vp, vp],
+        "wolf_propagate_fresnel": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
+        "wolf_propagate_farfield": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
+        "wolf_propagate_adjoint": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
+        "wolf_spectral_density": [vp, i32, i32, vp, vp],
+        "wolf_degree_of_coherence": [vp, i32, i32, i32, i32, f64, vp, vp],
+        "wolf_propagate_batch": [vp, i32, f64, i32, pd, pd, pd, i32, i32, i32, i32, i32, f64, vp, vp, vp, vp],
+        "wolf_chirp_table": [i32, f64, f64, f64, i32, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = i32
+    lib.wolf_output_pitch.argtypes = [i32, f64, f64, f64]
+    lib.wolf_output_pitch.restype = f64
+    lib.wolf_status_string.argtypes = [i32]
+    lib.wolf_status_string.restype = ctypes.c_char_p
+    lib.wolf_last_error_message.argtypes = []
+    lib.wolf_last_error_message.restype = ctypes.c_char_p
+    lib.wolf_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        lib = load()
+        raise WolfError(status, where, lib.wolf_last_error_message().decode() or lib.wolf_status_string(status).decode())
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _code(dtype: torch.dtype) -> int:
+    if dtype == torch.complex64:
+        return C64
+    if dtype == torch.complex128:
+        return C128
+    raise TypeError(f"unsupported dtype {dtype}; use torch.complex64 or torch.complex128")
+
+
+def _real(dtype: torch.dtype) -> torch.dtype:
+    return torch.float32 if dtype == torch.complex64 else torch.float64
+
+
+def _csd(w: torch.Tensor, name: str = "w") -> int:
+    if not (isinstance(w, torch.Tensor) and w.is_cuda):
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if w.dim() != 4 or len(set(w.shape)) != 1:
+        raise ValueError(f"{name} must have shape (N, N, N, N)")
+    if not w.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    _code(w.dtype)
+    return w.shape[0]
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None else None)
+
+
+def output_pitch(n: int, pitch: float, wavelength: float, z: float) -> float:
+    """eq. (spatial_resolution): dx = lambda z / (N pitch)."""
+    return load().wolf_output_pitch(n, pitch, wavelength, z)
+
+
+def build_source(spec, n: int, pitch: float, dtype: torch.dtype = torch.complex64,
+                 out: Optional[torch.Tensor] = None, device=None) -> torch.Tensor:
+    """Source CSD array W0 (Sec. 3.2). `spec` has the fields of wolf_source (see include/wolf.h):
+    model, amplitude, sigma_s_m, sigma_g_m, geometry, geo_r0_m, geo_r1_m, intensity_map, mask,
+    lens_focal_m, wavelength_m. A host intensity map or mask is copied to the device."""
+    lib = load()
+    dev = torch.device(device) if device is not None else (out.device if out is not None else torch.device("cuda"))
+    if out is None:
+        out = torch.empty((n, n, n, n), dtype=dtype, device=dev)
+    else:
+        _csd(out, "out")
+    imap = getattr(spec, "intensity_map", None)
+    mask = getattr(spec, "mask", None)
+    imap_t = None if imap is None else torch.as_tensor(np.asarray(imap) if not isinstance(imap, torch.Tensor) else imap,
+                                                       dtype=torch.float32).to(out.device).contiguous()
+    mask_t = None if mask is None else torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask,
+                                                       dtype=torch.uint8).to(out.device).contiguous()
+    s = _Source(int(spec.model), int(spec.geometry), float(spec.amplitude), float(spec.sigma_s_m),
+                float(spec.sigma_g_m), float(spec.geo_r0_m), float(spec.geo_r1_m),
+                imap_t.data_ptr() if imap_t is not None else None, mask_t.data_ptr() if mask_t is not None else None,
+                float(spec.lens_focal_m), float(spec.wavelength_m))
+    _check(lib.wolf_build_source(ctypes.byref(s), n, pitch, _code(out.dtype), _ptr(out), _stream()),
+           "wolf_build_source")
+    # The uploaded map/mask may be freed now: the caching allocator orders their reuse after this
+    # kernel on the same stream.
+    return out
+
+
+def _propagate(fn_name: str, w: torch.Tensor, pitch: float, wavelength: float, z: float, kind: int,
+               out: Optional[torch.Tensor]) -> Tuple[torch.Tensor, float]:
+    lib = load()
+    n = _csd(w)
+    if out is None:
+        out = torch.empty_like(w)
+    else:
+        _csd(out, "out")
+        if out.dtype != w.dtype or out.shape != w.shape:
+            raise ValueError("out must match w in shape and dtype")
+    dx = ctypes.c_double(0.0)
+    _check(getattr(lib, fn_name)(_ptr(w), _ptr(out), n, pitch, wavelength, z, kind, _code(w.dtype),
+                                 ctypes.byref(dx), _stream()), fn_name)
+    return out, dx.value
+
+
+def propagate_fresnel(w: torch.Tensor, pitch: float, wavelength: float, z: float, kind: int = SECONDARY,
+                      out: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, float]:
+    """Fresnel propagation over z (Sec. 2.1 eq. W_fresnel; Algorithm 2). Returns (W_B, dx)."""
+    return _propagate("wolf_propagate_fresnel", w, pitch, wavelength, z, kind, out)
+
+
+def propagate_farfield(w: torch.Tensor, pitch: float, wavelength: float, z: float, kind: int = SECONDARY,
+                       out: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, float]:
+    """Far-field propagation (Sec. 2.1 eq. W_farfield). Returns (W_B, dx)."""
+    return _propagate("wolf_propagate_farfield", w, pitch, wavelength, z, kind, out)
+
+
+def propagate(w, pitch, wavelength, z, farfield=False, kind=SECONDARY, out=None):
+    return (propagate_farfield if farfield else propagate_fresnel)(w, pitch, wavelength, z, kind, out)
+
+
+def propagate_adjoint(g: torch.Tensor, pitch: float, wavelength: float, z: float, farfield: bool = False,
+                      kind: int = SECONDARY, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Adjoint of the propagation (gradient of W_B mapped to the gradient of W_A)."""
+    lib = load()
+    n = _csd(g, "g")
+    if out is None:
+        out = torch.empty_like(g)
+    else:
+        _csd(out, "out")
+    _check(lib.wolf_propagate_adjoint(_ptr(g), _ptr(out), n, pitch, wavelength, z, int(bool(farfield)), kind,
+                                      _code(g.dtype), _stream()), "wolf_propagate_adjoint")
+    return out
+
+
+def spectral_density(w: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """S[i, j] = Re W[i, j; i, j] (Algorithm 4)."""
+    lib = load()
+    n = _csd(w)
+    if out is None:
+        out = torch.empty((n, n), dtype=_real(w.dtype), device=w.device)
+    _check(lib.wolf_spectral_density(_ptr(w), n, _code(w.dtype), _ptr(out), _stream()), "wolf_spectral_density")
+    return out
+
+
+def degree_of_coherence(w: torch.Tensor, ip: int = -1, jp: int = -1, floor_rel: float = 1e-12,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """mu(P1, .) for P1 = (ip, jp) (Algorithm 5), or the full N^4 mu when ip = jp = -1."""
+    lib = load()
+    n = _csd(w)
+    if out is None:
+        shape = (n, n, n, n) if (ip == -1 and jp == -1) else (n, n)
+        out = torch.empty(shape, dtype=w.dtype, device=w.device)
+    _check(lib.wolf_degree_of_coherence(_ptr(w), n, _code(w.dtype), ip, jp, floor_rel, _ptr(out), _stream()),
+           "wolf_degree_of_coherence")
+    return out
+
+
+def chirp_table(n: int, pitch: float, wavelength: float, z: float, dtype: torch.dtype = torch.complex128,
+                device=None) -> torch.Tensor:
+    """FP64-built q(z, pitch (i - N/2)) along one axis (eq. q_factor)."""
+    lib = load()
+    out = torch.empty((n,), dtype=dtype, device=device or torch.device("cuda"))
+    _check(lib.wolf_chirp_table(n, pitch, wavelength, z, _code(dtype), _ptr(out), _stream()), "wolf_chirp_table")
+    return out
+
+
+def propagate_batch(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights, farfield: bool = False,
+                    kind: int = SECONDARY, ip: int = 0, jp: int = 0, floor_rel: float = 1e-12,
+                    work: Optional[torch.Tensor] = None):
+    """All (lambda, z) pairs of one source: returns (S[k], mu[k]) stacked over pairs."""
+    lib = load()
+    n = _csd(w_src, "w_src")
+    lam = np.ascontiguousarray(wavelengths, dtype=np.float64)
+    zz = np.ascontiguousarray(zs, dtype=np.float64)
+    ww = np.ascontiguousarray(weights, dtype=np.float64)
+    if not (lam.shape == zz.shape == ww.shape and lam.ndim == 1):
+        raise ValueError("wavelengths, zs and weights must be 1D arrays of the same length")
+    k = lam.shape[0]
+    if work is None:
+        work = torch.empty_like(w_src)
+    s = torch.empty((k, n, n), dtype=_real(w_src.dtype), device=w_src.device)
+    mu = torch.empty((k, n, n), dtype=w_src.dtype, device=w_src.device)
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(lib.wolf_propagate_batch(_ptr(w_src), n, pitch, k, lam.ctypes.data_as(pd), zz.ctypes.data_as(pd),
+                                    ww.ctypes.data_as(pd), int(bool(farfield)), kind, _code(w_src.dtype), ip, jp,
+                                    floor_rel, _ptr(work), _ptr(s), _ptr(mu), _stream()), "wolf_propagate_batch")
+    return s, mu

@@ -1,0 +1,340 @@
+// C-ABI layer of libwolf: argument validation, buffer checks, per-device scratch and dispatch.
+// No exception crosses this layer. Every entry point returns a wolf_status.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wolf.h"
+#include "wolf_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+wolf_status fail(wolf_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+wolf_status fail(wolf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+bool supported_n(int32_t n) { return n >= 2 && n <= 256 && (n & (n - 1)) == 0; }
+bool pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
+size_t elem_bytes(int32_t dtype) { return dtype == WOLF_C64 ? 8 : 16; }
+size_t real_bytes(int32_t dtype) { return dtype == WOLF_C64 ? 4 : 8; }
+size_t n4(int32_t n) { return (size_t)n * n * n * n; }
+
+// A device buffer of at least `bytes`, inside one allocation on the current device.
+wolf_status check_buf(const void* p, size_t bytes, const char* what) {
+  if (p == nullptr) return fail(WOLF_EINVAL, "%s: null pointer", what);
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(WOLF_EINVAL, "%s: not a device pointer (%s)", what, hipGetErrorString(e));
+  }
+  if (attr.type != hipMemoryTypeDevice) return fail(WOLF_EINVAL, "%s: not device memory", what);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != attr.device)
+    return fail(WOLF_EINVAL, "%s: buffer is on device %d, current device is %d", what, attr.device, dev);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(WOLF_EINVAL, "%s: cannot query the allocation (%s)", what, hipGetErrorString(e));
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || (size_t)(q - b) + bytes > size)
+    return fail(WOLF_EINVAL, "%s: buffer too small (%zu bytes needed past the pointer, allocation has %zu)", what,
+                bytes, size - (size_t)(q - b));
+  return WOLF_OK;
+}
+
+bool partial_overlap(const void* a, const void* b, size_t bytes) {
+  if (a == b) return false;
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+wolf_status launched(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(WOLF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  g_last_error.clear();
+  return WOLF_OK;
+}
+
+// Per-device scratch owned by the library: 256 B of reduction keys + N^2 reals (N <= 256).
+constexpr size_t kScratchBytes = 256 + (size_t)256 * 256 * 8;
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch;
+
+wolf_status device_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(WOLF_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    *out = it->second;
+    return WOLF_OK;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, kScratchBytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(WOLF_ENOMEM, "cannot allocate %zu bytes of device scratch", kScratchBytes);
+  }
+  g_scratch[dev] = p;
+  *out = p;
+  return WOLF_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// The propagation operator as four axis passes.
+// ---------------------------------------------------------------------------------------------
+struct OpSpec {
+  double a_src, a_out, scale;
+  bool adjoint;
+};
+
+OpSpec make_op(int32_t n, double pitch, double lam, double z, bool farfield, int32_t kind, bool adjoint) {
+  const double dx = lam * z / ((double)n * pitch);
+  const double c = kind == WOLF_PRIMARY ? 1.0 / ((4.0 * M_PI * z) * (4.0 * M_PI * z)) : 1.0 / ((lam * z) * (lam * z));
+  OpSpec op;
+  op.a_src = farfield ? 0.0 : pitch * pitch / (lam * z);
+  op.a_out = dx * dx / (lam * z);
+  op.scale = c * pitch * pitch * pitch * pitch;
+  op.adjoint = adjoint;
+  return op;
+}
+
+template <class T>
+wolf_status run_operator(const T* in, T* out, int32_t n, const OpSpec& op, hipStream_t st) {
+  using wolf::Chirp;
+  // Axis order of the passes: j2 (3), i2 (2), j1 (1), i1 (0). The last pass carries the scale.
+  const int order[4] = {3, 2, 1, 0};
+  for (int k = 0; k < 4; ++k) {
+    const int axis = order[k];
+    const bool second_point = axis >= 2;
+    Chirp pre, post;
+    int sign;
+    if (!op.adjoint) {
+      // Second point: q(xi) (-1)^n, direct DFT, q(x) (-1)^k.  First point: conjugates, inverse DFT.
+      const int cs = second_point ? +1 : -1;
+      pre = Chirp{op.a_src, 1.0, cs, 1};
+      post = Chirp{op.a_out, 1.0, cs, 1};
+      sign = second_point ? -1 : +1;
+    } else {
+      // First point: q(x) (-1)^k, direct DFT, q(xi) (-1)^n.  Second point: conjugates, inverse DFT.
+      const int cs = second_point ? -1 : +1;
+      pre = Chirp{op.a_out, 1.0, cs, 1};
+      post = Chirp{op.a_src, 1.0, cs, 1};
+      sign = second_point ? +1 : -1;
+    }
+    if (k == 3) post.scale = op.scale;
+    const T* src = k == 0 ? in : out;
+    hipError_t e = wolf::launch_axis_pass<T>(n, src, out, axis, sign, pre, post, st);
+    if (e != hipSuccess) return fail(WOLF_EDEVICE, "axis pass %d: %s", axis, hipGetErrorString(e));
+  }
+  g_last_error.clear();
+  return WOLF_OK;
+}
+
+wolf_status propagate_common(const void* w_in, void* w_out, int32_t n, double pitch, double lam, double z,
+                             bool farfield, int32_t kind, int32_t dtype, bool adjoint, double* out_pitch,
+                             void* stream, const char* who) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d is not a power of two in [2, 256]", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype %d", who, dtype);
+  if (!pos_finite(pitch) || !pos_finite(lam) || !pos_finite(z))
+    return fail(WOLF_EINVAL, "%s: pitch, wavelength and z must be finite and > 0", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind %d", who, kind);
+  const size_t bytes = n4(n) * elem_bytes(dtype);
+  wolf_status s;
+  if ((s = check_buf(w_in, bytes, "input")) != WOLF_OK) return s;
+  if ((s = check_buf(w_out, bytes, "output")) != WOLF_OK) return s;
+  if (partial_overlap(w_in, w_out, bytes)) return fail(WOLF_EINVAL, "%s: input and output partly overlap", who);
+  const OpSpec op = make_op(n, pitch, lam, z, farfield, kind, adjoint);
+  if (out_pitch) *out_pitch = lam * z / ((double)n * pitch);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == WOLF_C64)
+    return run_operator<float2>(static_cast<const float2*>(w_in), static_cast<float2*>(w_out), n, op, st);
+  return run_operator<double2>(static_cast<const double2*>(w_in), static_cast<double2*>(w_out), n, op, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+WOLF_API int32_t wolf_version(void) { return 1; }
+
+WOLF_API const char* wolf_status_string(wolf_status s) {
+  switch (s) {
+    case WOLF_OK: return "WOLF_OK";
+    case WOLF_EINVAL: return "WOLF_EINVAL: invalid argument";
+    case WOLF_EUNSUPPORTED: return "WOLF_EUNSUPPORTED: unsupported size";
+    case WOLF_ENOMEM: return "WOLF_ENOMEM: device scratch allocation failed";
+    case WOLF_EDEVICE: return "WOLF_EDEVICE: HIP error";
+    default: return "unknown wolf_status";
+  }
+}
+
+WOLF_API const char* wolf_last_error_message(void) { return g_last_error.c_str(); }
+
+WOLF_API double wolf_output_pitch(int32_t n, double pitch_m, double wavelength_m, double z_m) {
+  return wavelength_m * z_m / ((double)n * pitch_m);
+}
+
+WOLF_API wolf_status wolf_propagate_fresnel(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                            double wavelength_m, double z_m, int32_t kind, int32_t dtype,
+                                            double* out_pitch_m, void* stream) {
+  return propagate_common(w_in, w_out, n, pitch_m, wavelength_m, z_m, false, kind, dtype, false, out_pitch_m,
+                          stream, "wolf_propagate_fresnel");
+}
+
+WOLF_API wolf_status wolf_propagate_farfield(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                             double wavelength_m, double z_m, int32_t kind, int32_t dtype,
+                                             double* out_pitch_m, void* stream) {
+  return propagate_common(w_in, w_out, n, pitch_m, wavelength_m, z_m, true, kind, dtype, false, out_pitch_m,
+                          stream, "wolf_propagate_farfield");
+}
+
+WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32_t n, double pitch_m,
+                                            double wavelength_m, double z_m, int32_t farfield, int32_t kind,
+                                            int32_t dtype, void* stream) {
+  if (farfield != 0 && farfield != 1) return fail(WOLF_EINVAL, "wolf_propagate_adjoint: farfield must be 0 or 1");
+  return propagate_common(g_out, g_in, n, pitch_m, wavelength_m, z_m, farfield == 1, kind, dtype, true, nullptr,
+                          stream, "wolf_propagate_adjoint");
+}
+
+WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double pitch_m, int32_t dtype, void* w_out,
+                                       void* stream) {
+  if (src == nullptr) return fail(WOLF_EINVAL, "wolf_build_source: null source");
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_build_source: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_build_source: bad dtype");
+  if (!pos_finite(pitch_m)) return fail(WOLF_EINVAL, "wolf_build_source: pitch must be finite and > 0");
+  if (src->model < 0 || src->model > 3) return fail(WOLF_EINVAL, "wolf_build_source: bad model %d", src->model);
+  if (src->geometry < 0 || src->geometry > 4) return fail(WOLF_EINVAL, "wolf_build_source: bad geometry");
+  if (!std::isfinite(src->amplitude) || src->amplitude < 0) return fail(WOLF_EINVAL, "amplitude must be >= 0");
+  const bool uses_s = src->model == WOLF_MODEL_GSM;
+  const bool uses_g = src->model == WOLF_MODEL_GSM || src->model == WOLF_MODEL_MAP;
+  if (uses_s && !(src->sigma_s_m > 0)) return fail(WOLF_EINVAL, "sigma_s_m must be > 0 (or +inf)");
+  if (uses_g && !(src->sigma_g_m > 0)) return fail(WOLF_EINVAL, "sigma_g_m must be > 0 (or +inf)");
+  wolf::SourceParams sp{};
+  sp.model = src->model;
+  sp.geometry = src->geometry;
+  sp.amplitude = src->amplitude;
+  sp.inv4s2_px = (uses_s && !std::isinf(src->sigma_s_m)) ? pitch_m * pitch_m / (4.0 * src->sigma_s_m * src->sigma_s_m) : 0.0;
+  sp.inv2g2_px = (uses_g && !std::isinf(src->sigma_g_m)) ? pitch_m * pitch_m / (2.0 * src->sigma_g_m * src->sigma_g_m) : 0.0;
+  sp.inv4s2 = 0.0;
+  auto thresh = [&](double r) {
+    const double rho = r / pitch_m;
+    return (long long)std::floor(rho * rho * (1.0 + 1e-9));
+  };
+  if (src->geometry == WOLF_GEO_CIRCLE || src->geometry == WOLF_GEO_SQUARE || src->geometry == WOLF_GEO_ANNULUS) {
+    if (!pos_finite(src->geo_r0_m)) return fail(WOLF_EINVAL, "geo_r0_m must be finite and > 0");
+    if (src->geo_r0_m / pitch_m > 1e6) return fail(WOLF_EINVAL, "geo_r0_m too large");
+    sp.t0 = thresh(src->geo_r0_m);
+  }
+  if (src->geometry == WOLF_GEO_ANNULUS) {
+    if (!(src->geo_r1_m >= 0 && src->geo_r1_m < src->geo_r0_m)) return fail(WOLF_EINVAL, "need 0 <= geo_r1_m < geo_r0_m");
+    sp.t1 = thresh(src->geo_r1_m);
+  }
+  wolf_status s;
+  if (src->model == WOLF_MODEL_MAP) {
+    if ((s = check_buf(src->intensity_map, (size_t)n * n * 4, "intensity_map")) != WOLF_OK) return s;
+    sp.imap = src->intensity_map;
+  }
+  if (src->geometry == WOLF_GEO_MASK) {
+    if ((s = check_buf(src->mask, (size_t)n * n, "mask")) != WOLF_OK) return s;
+    sp.mask = src->mask;
+  }
+  if (src->lens_focal_m != 0.0) {
+    if (!std::isfinite(src->lens_focal_m) || !pos_finite(src->wavelength_m))
+      return fail(WOLF_EINVAL, "lens needs a finite focal length and a wavelength > 0");
+    sp.lens_alpha = pitch_m * pitch_m / (src->wavelength_m * src->lens_focal_m);
+  }
+  if ((s = check_buf(w_out, n4(n) * elem_bytes(dtype), "w_out")) != WOLF_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WOLF_C64 ? wolf::launch_build_source<float2>(n, sp, static_cast<float2*>(w_out), st)
+                                   : wolf::launch_build_source<double2>(n, sp, static_cast<double2*>(w_out), st);
+  return launched(e, "wolf_build_source");
+}
+
+WOLF_API wolf_status wolf_spectral_density(const void* w, int32_t n, int32_t dtype, void* s_out, void* stream) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_spectral_density: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_spectral_density: bad dtype");
+  wolf_status s;
+  if ((s = check_buf(w, n4(n) * elem_bytes(dtype), "w")) != WOLF_OK) return s;
+  if ((s = check_buf(s_out, (size_t)n * n * real_bytes(dtype), "s_out")) != WOLF_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WOLF_C64
+                     ? wolf::launch_spectral_density<float2>(n, static_cast<const float2*>(w), static_cast<float*>(s_out), st)
+                     : wolf::launch_spectral_density<double2>(n, static_cast<const double2*>(w), static_cast<double*>(s_out), st);
+  return launched(e, "wolf_spectral_density");
+}
+
+WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp,
+                                              double s_floor_rel, void* mu_out, void* stream) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_degree_of_coherence: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_degree_of_coherence: bad dtype");
+  const bool full = ip == -1 && jp == -1;
+  if (!full && (ip < 0 || ip >= n || jp < 0 || jp >= n))
+    return fail(WOLF_EINVAL, "wolf_degree_of_coherence: (ip, jp) must be in [0, N) or both -1");
+  if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "s_floor_rel must be >= 0");
+  const size_t eb = elem_bytes(dtype);
+  wolf_status s;
+  if ((s = check_buf(w, n4(n) * eb, "w")) != WOLF_OK) return s;
+  const size_t out_bytes = full ? n4(n) * eb : (size_t)n * n * eb;
+  if ((s = check_buf(mu_out, out_bytes, "mu_out")) != WOLF_OK) return s;
+  if (partial_overlap(w, mu_out, full ? n4(n) * eb : 1) || (!full && w == mu_out))
+    return fail(WOLF_EINVAL, "wolf_degree_of_coherence: mu_out overlaps w");
+  if (full && w == mu_out) return fail(WOLF_EINVAL, "wolf_degree_of_coherence: full mu cannot be computed in place");
+  void* scratch = nullptr;
+  if ((s = device_scratch(&scratch)) != WOLF_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int i = full ? -1 : ip, j = full ? -1 : jp;
+  hipError_t e = dtype == WOLF_C64
+                     ? wolf::launch_coherence<float2>(n, static_cast<const float2*>(w), i, j, s_floor_rel,
+                                                      static_cast<float2*>(mu_out), scratch, st)
+                     : wolf::launch_coherence<double2>(n, static_cast<const double2*>(w), i, j, s_floor_rel,
+                                                       static_cast<double2*>(mu_out), scratch, st);
+  return launched(e, "wolf_degree_of_coherence");
+}
+
+WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double wavelength_m, double z_m, int32_t dtype,
+                                      void* out, void* stream) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_chirp_table: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_chirp_table: bad dtype");
+  if (!pos_finite(pitch_m) || !pos_finite(wavelength_m) || !pos_finite(z_m))
+    return fail(WOLF_EINVAL, "wolf_chirp_table: pitch, wavelength and z must be finite and > 0");
+  wolf_status s;
+  if ((s = check_buf(out, (size_t)n * elem_bytes(dtype), "out")) != WOLF_OK) return s;
+  const wolf::Chirp ch{pitch_m * pitch_m / (wavelength_m * z_m), 1.0, +1, 0};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WOLF_C64 ? wolf::launch_chirp_table<float2>(n, ch, static_cast<float2*>(out), st)
+                                   : wolf::launch_chirp_table<double2>(n, ch, static_cast<double2*>(out), st);
+  return launched(e, "wolf_chirp_table");
+}
+
+WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double pitch_m, int32_t n_pairs,
+                                          const double* wavelength_m, const double* z_m, const double* weight,
+                                          int32_t farfield, int32_t kind, int32_t dtype, int32_t ip, int32_t jp,
+                                          double s_floor_rel, void* work, void* s_out, void* mu_out, void* stream) {
+  (void)w_src; (void)n; (void)pitch_m; (void)n_pairs; (void)wavelength_m; (void)z_m; (void)weight; (void)farfield;
+  (void)kind; (void)dtype; (void)ip; (void)jp; (void)s_floor_rel; (void)work; (void)s_out; (void)mu_out; (void)stream;
+  return fail(WOLF_EUNSUPPORTED, "wolf_propagate_batch: not built yet");
+}
+
+}  // extern "C"

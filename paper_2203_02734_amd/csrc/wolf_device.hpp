@@ -1,0 +1,147 @@
+// Device building blocks for the CSD propagation kernels (gfx950, wave64).
+//
+// The propagation operator of the paper's Sec. 2.1, eqs. (W_general), (W_fresnel) and
+// (W_farfield), sampled on the grid of Sec. 3.1, eqs. (point)/(n12), factorises over the four
+// array axes (i1, j1, i2, j2). Along each axis it is a diagonal multiply, a centred length-N
+// DFT and another diagonal multiply:
+//   axis of the second point: pre = q(z, xi) (-1)^n, forward DFT,  post = q(z, x) (-1)^k
+//   axis of the first point:  pre = q*(z, xi) (-1)^n, inverse DFT, post = q*(z, x) (-1)^k
+// q is the quadratic-phase propagator of eq. (q_factor). The factors (-1)^n and (-1)^k turn
+// the plain DFT into the DFT on centred indices n - N/2, k - N/2. Each axis also carries a
+// (-1)^(N/2), which cancels over the four axes.
+//
+// The pre/post tables and the twiddles are computed in FP64, with exact integer-index argument
+// reduction, and rounded once to the working precision. They are the only FP64 steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wolf {
+
+// ---------------------------------------------------------------------------------------------
+// Complex helpers on float2 / double2 (interleaved re, im: the layout of torch complex64/128).
+// ---------------------------------------------------------------------------------------------
+template <class T> struct real_of;
+template <> struct real_of<float2> { using type = float; };
+template <> struct real_of<double2> { using type = double; };
+
+template <class T> __device__ __forceinline__ T cadd(T a, T b) { return T{a.x + b.x, a.y + b.y}; }
+template <class T> __device__ __forceinline__ T csub(T a, T b) { return T{a.x - b.x, a.y - b.y}; }
+template <class T> __device__ __forceinline__ T cmul(T a, T b) {
+  return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T> __device__ __forceinline__ T cconj(T a) { return T{a.x, -a.y}; }
+template <class T, class R> __device__ __forceinline__ T cscale(T a, R s) { return T{a.x * s, a.y * s}; }
+
+// Multiply by SIGN * i (SIGN = -1: forward DFT kernel e^{-2 pi i/4}; +1: inverse).
+template <int SIGN, class T> __device__ __forceinline__ T rot90(T a) {
+  if constexpr (SIGN < 0) return T{a.y, -a.x};
+  else return T{-a.y, a.x};
+}
+
+// cos and sin of 2 pi j / 16, j = 0..15, to 20 digits (the in-register radix <= 16 twiddles).
+__device__ constexpr double kCos16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+__device__ constexpr double kSin16[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+__host__ __device__ constexpr int bitrev(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r = (r << 1) | ((x >> i) & 1);
+  return r;
+}
+
+// b * e^{SIGN 2 pi i j16 / 16}; j16 is a compile-time constant once the callers are unrolled.
+template <int SIGN, class T> __device__ __forceinline__ T twiddle16(T b, int j16) {
+  using R = typename real_of<T>::type;
+  if (j16 == 0) return b;
+  if (j16 == 4) return rot90<SIGN>(b);
+  const R c = (R)kCos16[j16];
+  const R s = (R)(SIGN * kSin16[j16]);
+  return T{b.x * c - b.y * s, b.x * s + b.y * c};
+}
+
+// In-register DFT of length R <= 16: X[k] = sum_n v[n] e^{SIGN 2 pi i n k / R}, natural order in
+// and out. Iterative radix-2 decimation in time on bit-reversed input; fully unrolled.
+template <int R, int SIGN, class T> __device__ __forceinline__ void dft_reg(T* v) {
+  static_assert(R >= 1 && R <= 16 && (R & (R - 1)) == 0, "radix");
+  if constexpr (R == 1) return;
+  constexpr int L = ilog2(R);
+  T w[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) w[i] = v[bitrev(i, L)];
+#pragma unroll
+  for (int s = 1; s <= L; ++s) {
+    const int m = 1 << s, h = m >> 1;
+#pragma unroll
+    for (int k = 0; k < R; k += m) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const T a = w[k + j];
+        const T b = twiddle16<SIGN>(w[k + j + h], j * (16 / m));
+        w[k + j] = cadd(a, b);
+        w[k + j + h] = csub(a, b);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = w[i];
+}
+
+// Split of a length-N DFT across N2 threads holding N1 elements each (N = N1 N2, N1 >= N2).
+template <int N> struct Split {
+  static constexpr int L = ilog2(N);
+  static constexpr int N1 = 1 << ((L + 1) / 2);
+  static constexpr int N2 = N / N1;
+  static constexpr int Q = N1 / N2;  // second-stage DFTs per thread
+  static_assert(N1 * N2 == N && N1 >= N2, "split");
+};
+
+// ---------------------------------------------------------------------------------------------
+// FP64 tables.
+// ---------------------------------------------------------------------------------------------
+// Phase description of one diagonal factor along an axis: the entry at index n is
+//   scale * exp(i pi [sign * (n - N/2)^2 * alpha + (n mod 2)])
+// = scale * (-1)^n * q(z, d (n - N/2))^{sign}, with alpha = d^2 / (lambda z).
+// alpha = 0 gives the bare checkerboard (the far-field source side, where q is set to 1).
+struct Chirp {
+  double alpha;
+  double scale;
+  int sign;        // +1: q, -1: q*
+  int checker;     // 1: fold (-1)^n in
+};
+
+// pi * r (r already reduced to [-1, 1]) -> (cos, sin) in FP64.
+__device__ __forceinline__ void sincospi_reduced(double r, double* s, double* c) { sincospi(r, s, c); }
+
+// Reduce x (= phase / pi) modulo 2 into [-1, 1]. x - 2 rint(x / 2) is exact for |x| < 2^52.
+__device__ __forceinline__ double reduce_mod2(double x) { return x - 2.0 * rint(0.5 * x); }
+
+template <class T> __device__ __forceinline__ T chirp_entry(const Chirp& ch, int n, int N) {
+  using R = typename real_of<T>::type;
+  const long long d = (long long)n - (long long)(N / 2);
+  double ph = (double)(d * d) * ch.alpha;           // (n - N/2)^2 alpha, one FP64 rounding
+  ph = reduce_mod2((double)ch.sign * ph);
+  if (ch.checker && (n & 1)) ph = reduce_mod2(ph + 1.0);
+  double s, c;
+  sincospi_reduced(ph, &s, &c);
+  return T{(R)(c * ch.scale), (R)(s * ch.scale)};
+}
+
+// Twiddle e^{SIGN 2 pi i j / N}, j in [0, N): the argument 2 j / N is exact for N a power of two.
+template <class T, int SIGN> __device__ __forceinline__ T twiddle_entry(int j, int N) {
+  using R = typename real_of<T>::type;
+  double s, c;
+  sincospi((double)(SIGN * 2) * (double)j / (double)N, &s, &c);
+  return T{(R)c, (R)s};
+}
+
+}  // namespace wolf

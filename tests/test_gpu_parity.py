@@ -1,0 +1,249 @@
+"""Parity of the HIP path (through the C-ABI, via the ctypes binding) with the FP64 oracle.
+
+Tolerances:
+  complex128: 1e-12 relative L2. Rounding of the O(log N) FFT stages is ~1e-15. The chirp phases
+              reach ~1e4 rad and are rounded in FP64 (~1e-12 rad at most).
+  complex64:  1e-5 relative L2 over all N^4 entries (the accuracy target of the complex64 path).
+              FP32 butterflies give ~6e-8 sqrt(log2 N^2) per entry, and the FP64-built tables are
+              rounded to FP32 once.
+"""
+from __future__ import annotations
+
+import math
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import wolf_inputs as WI
+
+pytestmark = pytest.mark.gpu
+
+LAM = WI.LAMBDA_HENE
+TOL = {torch.complex64: 1e-5, torch.complex128: 1e-12}
+DT = [torch.complex64, torch.complex128]
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def spec(**kw):
+    base = dict(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=math.inf, sigma_g_m=math.inf,
+                geometry=WI.GEO_NONE, geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None,
+                lens_focal_m=0.0, wavelength_m=0.0)
+    base.update(kw)
+    return SimpleNamespace(**base)
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------------------------
+# a0: FP64 chirp tables
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,pitch,z", [(16, 20e-6, 0.5), (128, 20e-6, 0.5), (256, 10e-6, 0.1), (128, 20e-6, 5.0)])
+def test_chirp_table(gpu_lib, n, pitch, z):
+    ref = O.chirp_table(n, pitch, LAM, z)
+    t128 = host(gpu_lib.chirp_table(n, pitch, LAM, z, torch.complex128))
+    assert np.abs(t128 - ref).max() < 1e-11
+    t64 = host(gpu_lib.chirp_table(n, pitch, LAM, z, torch.complex64))
+    # FP64 value rounded once to FP32: within one FP32 ulp (|q| = 1) of the oracle.
+    assert np.abs(t64.real - ref.real).max() <= 6e-8 and np.abs(t64.imag - ref.imag).max() <= 6e-8
+
+
+# ---------------------------------------------------------------------------------------------
+# a1: source builder
+# ---------------------------------------------------------------------------------------------
+SOURCES = {
+    "gsm": dict(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3, amplitude=1.7),
+    "gsm_uniform_coherent": dict(),
+    "circle_lens": dict(sigma_g_m=0.1e-3, geometry=WI.GEO_CIRCLE, geo_r0_m=0.1e-3, lens_focal_m=0.2, wavelength_m=LAM),
+    "square": dict(sigma_s_m=0.2e-3, sigma_g_m=0.08e-3, geometry=WI.GEO_SQUARE, geo_r0_m=0.08e-3),
+    "annulus_incoherent": dict(model=WI.MODEL_INCOHERENT, amplitude=2.0, geometry=WI.GEO_ANNULUS, geo_r0_m=0.12e-3,
+                               geo_r1_m=0.04e-3),
+    "coherent_mask": dict(model=WI.MODEL_COHERENT, geometry=WI.GEO_MASK, mask=WI.random_mask(16, 3)),
+    "map": dict(model=WI.MODEL_MAP, sigma_g_m=0.06e-3, intensity_map=WI.intensity_map(16, 20e-6, 4)),
+}
+
+
+@pytest.mark.parametrize("name", list(SOURCES))
+@pytest.mark.parametrize("dtype", DT)
+def test_build_source(gpu_lib, name, dtype):
+    n, p = 16, 20e-6
+    sp = spec(**SOURCES[name])
+    got = host(gpu_lib.build_source(sp, n, p, dtype))
+    ref = O.build_source(sp, n, p)
+    assert rel(got, ref) < (1e-14 if dtype == torch.complex128 else 2e-7)
+    # Geometry decisions are identical on both sides.
+    assert np.array_equal(np.abs(got) > 0, np.abs(ref) > 0)
+
+
+def test_build_source_circle_boundary(gpu_lib):
+    """0.4 mm radius at 20 um pitch is exactly 20 px: boundary pixels are inside on both sides."""
+    n, p = 64, 20e-6
+    sp = spec(model=WI.MODEL_INCOHERENT, geometry=WI.GEO_CIRCLE, geo_r0_m=0.4e-3)
+    got = host(gpu_lib.build_source(sp, n, p, torch.complex64))
+    s = np.real(np.einsum("ijij->ij", got))
+    ref = O.geometry_mask(n, p, O.GEO_CIRCLE, 0.4e-3)
+    assert np.array_equal(s > 0, ref > 0) and s[32 + 20, 32] == 1 and s[32 + 12, 32 + 16] == 1
+
+
+# ---------------------------------------------------------------------------------------------
+# a2-a4: propagation (Fresnel and far field) on random and physical sources, small N
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 32])
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", DT)
+def test_propagate_random(gpu_lib, n, farfield, dtype):
+    p, z = 20e-6, 0.05
+    w = WI.random_complex((n, n, n, n), seed=10 + n)
+    ref, dx = O.propagate(w, n, p, LAM, z, farfield)
+    got, gdx = gpu_lib.propagate(dev(w, dtype), p, LAM, z, farfield)
+    assert gdx == pytest.approx(dx, rel=1e-15)
+    assert rel(host(got), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("kind", [WI.KIND_SECONDARY, WI.KIND_PRIMARY])
+def test_propagate_kind(gpu_lib, kind):
+    n, p, z = 8, 20e-6, 0.1
+    w = WI.random_hermitian_psd(n, seed=3)
+    ref, _ = O.propagate(w, n, p, LAM, z, False, kind)
+    got, _ = gpu_lib.propagate_fresnel(dev(w, torch.complex128), p, LAM, z, kind)
+    assert rel(host(got), ref) < 1e-12
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", DT)
+def test_propagate_gsm64(gpu_lib, farfield, dtype):
+    """N = 64 from the GPU source builder; oracle on its own source build."""
+    n, p, z = 64, 20e-6, 0.3
+    sp = spec(sigma_s_m=0.08e-3, sigma_g_m=0.12e-3)
+    w = gpu_lib.build_source(sp, n, p, dtype)
+    got, _ = gpu_lib.propagate(w, p, LAM, z, farfield)
+    ref, _ = O.propagate(O.build_source(sp, n, p), n, p, LAM, z, farfield)
+    assert rel(host(got), ref) < TOL[dtype]
+
+
+def test_propagate_tophat_lens64(gpu_lib):
+    """Circular top-hat (20 px), Gaussian mu, thin lens f = 0.2 m, Fresnel z = 0.2 m, N = 64."""
+    wl = WI.tophat_lens64()
+    n, p = wl.n, wl.pitch_m
+    sp = wl.source
+    ref, _ = O.propagate(O.build_source(sp, n, p), n, p, wl.wavelength_m, wl.z_m)
+    for dtype in DT:
+        got, _ = gpu_lib.propagate_fresnel(gpu_lib.build_source(sp, n, p, dtype), p, wl.wavelength_m, wl.z_m)
+        assert rel(host(got), ref) < TOL[dtype]
+
+
+def test_in_place_equals_out_of_place(gpu_lib):
+    n, p, z = 16, 20e-6, 0.2
+    w = dev(WI.random_complex((n, n, n, n), seed=21), torch.complex64)
+    a, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
+    b = w.clone()
+    gpu_lib.propagate_fresnel(b, p, LAM, z, out=b)
+    assert torch.equal(a, b)
+
+
+def test_deterministic(gpu_lib):
+    n, p, z = 32, 20e-6, 0.2
+    w = dev(WI.random_complex((n, n, n, n), seed=22), torch.complex64)
+    a, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
+    b, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
+    assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------------------------------------
+# a5-a6: observables
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DT)
+def test_observables(gpu_lib, dtype):
+    n, p, z = 16, 20e-6, 0.5
+    sp = spec(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3)
+    wb_ref, _ = O.propagate(O.build_source(sp, n, p), n, p, LAM, z)
+    wb, _ = gpu_lib.propagate_fresnel(gpu_lib.build_source(sp, n, p, dtype), p, LAM, z)
+    s = host(gpu_lib.spectral_density(wb))
+    assert rel(s, O.spectral_density(wb_ref)) < TOL[dtype]
+    mu = host(gpu_lib.degree_of_coherence(wb, 8, 8))
+    mu_ref = O.degree_of_coherence(wb_ref, 8, 8)
+    assert rel(mu, mu_ref) < 10 * TOL[dtype]
+    assert np.abs(mu).max() <= 1 + (1e-6 if dtype == torch.complex64 else 1e-12)
+    full = host(gpu_lib.degree_of_coherence(wb))
+    assert rel(full, O.degree_of_coherence_full(wb_ref)) < 10 * TOL[dtype]
+
+
+def test_coherence_floor_masks_dark_points(gpu_lib):
+    n, p = 16, 20e-6
+    sp = spec(model=WI.MODEL_COHERENT, geometry=WI.GEO_CIRCLE, geo_r0_m=4 * p)
+    w = gpu_lib.build_source(sp, n, p, torch.complex128)
+    mu = host(gpu_lib.degree_of_coherence(w, 8, 8))
+    assert np.array_equal(mu, O.degree_of_coherence(O.build_source(sp, n, p), 8, 8))
+    assert not host(gpu_lib.degree_of_coherence(w, 0, 0)).any()
+
+
+# ---------------------------------------------------------------------------------------------
+# a7: adjoint
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", DT)
+def test_adjoint_vs_oracle(gpu_lib, farfield, dtype):
+    n, p, z = 16, 20e-6, 0.1
+    g = WI.random_complex((n, n, n, n), seed=31)
+    ref = O.propagate_adjoint(g, n, p, LAM, z, farfield)
+    got = gpu_lib.propagate_adjoint(dev(g, dtype), p, LAM, z, farfield)
+    assert rel(host(got), ref) < TOL[dtype]
+
+
+def test_adjoint_dot_product_gpu(gpu_lib):
+    n, p, z = 16, 20e-6, 0.1
+    w = dev(WI.random_complex((n, n, n, n), seed=41), torch.complex128)
+    g = dev(WI.random_complex((n, n, n, n), seed=42), torch.complex128)
+    pw, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
+    pg = gpu_lib.propagate_adjoint(g, p, LAM, z)
+    lhs = torch.vdot(pw.flatten(), g.flatten()).item()
+    rhs = torch.vdot(w.flatten(), pg.flatten()).item()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# ---------------------------------------------------------------------------------------------
+# Full-size workloads (N = 128 headline; N = 256), every entry against the separable oracle.
+# The GSM source is separable, so the oracle's output is bx[m1, m2] by[n1, n2]. The test forms
+# those products one slab at a time and compares them with the GPU output.
+# ---------------------------------------------------------------------------------------------
+def _separable_rel(w_gpu: torch.Tensor, bx: np.ndarray, by: np.ndarray) -> float:
+    n = w_gpu.shape[0]
+    bxt = torch.from_numpy(bx).cuda()
+    byt = torch.from_numpy(by).cuda()
+    num = 0.0
+    den = 0.0
+    for m1 in range(n):
+        blk = w_gpu[m1].to(torch.complex128)                     # [n1][m2][n2]
+        exp = bxt[m1][None, :, None] * byt[:, None, :]           # [n1][m2][n2] = bx[m1,m2] by[n1,n2]
+        num += torch.sum(torch.abs(blk - exp) ** 2).item()
+        den += torch.sum(torch.abs(exp) ** 2).item()
+    return math.sqrt(num / den)
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", DT)
+def test_full_size_gsm128(gpu_lib, farfield, dtype):
+    wl = WI.gsm128()
+    n, p, z = wl.n, wl.pitch_m, wl.z_m
+    sp = wl.source
+    w = gpu_lib.build_source(sp, n, p, dtype)
+    gpu_lib.propagate(w, p, LAM, z, farfield, out=w)
+    bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x"),
+                                   O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y"), n, p, LAM, z, farfield)
+    assert _separable_rel(w, bx, by) < TOL[dtype]
+    del w
+    torch.cuda.empty_cache()
