@@ -1,0 +1,281 @@
+"""Benchmark of the CSD propagation hot path on one MI355X.
+
+Headline workload: a Gaussian Schell-model source, N = 128 samples per axis (2^28 CSD elements),
+complex64, pitch 20 um, sigma_S = 0.1 mm, sigma_g = 0.05 mm, lambda = 632.8 nm, Fresnel z = 0.5 m.
+One step is the forward path of Algorithm 1 plus the observables: build W0 -> Fresnel propagation ->
+S -> mu(P1, .). Inputs are synthetic and the source is built on the GPU. The timed region starts
+with everything resident in HBM.
+
+It prints ONE JSON line. `value` = N^4 / (time per step) in CSD elements/s. `roofline` covers the
+propagation operator: algorithmic bytes (2 sweeps x read + write = 32 B/element in complex64)
+divided by the summed duration of its kernel launches, measured with HIP events on the stream the
+kernels run on. `cpu_baseline` times the FP64 oracle on the host for one step of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the c128 / far-field / adjoint / copy detail")
+    ap.add_argument("--big", action="store_true", help="also time the N=256 complex64 workload (34 GB)")
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="for rocprofv3 --pmc: one 2 GiB copy (counter calibration) then one propagation; no JSON")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="rocprofv3 FETCH/WRITE summary for the current kernels (optional)")
+    return ap.parse_args()
+
+
+def timed_steps(fn, steps, warmup, marks):
+    """Run `fn(record)` warmup + steps times; `record(name)` drops a HIP event on the current stream.
+    Returns (total ms over the timed steps, {segment: mean ms})."""
+    import torch
+
+    for _ in range(warmup):
+        fn(lambda name: None)
+    torch.cuda.synchronize()
+    ev = []
+
+    def record(name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        ev[-1].append((name, e))
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        ev.append([])
+        record("begin")
+        fn(record)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    total = start.elapsed_time(stop)
+    seg = {}
+    for step in ev:
+        for (a, ea), (b, eb) in zip(step[:-1], step[1:]):
+            seg.setdefault(b, []).append(ea.elapsed_time(eb))
+    return total, wall, {k: sum(v) / len(v) for k, v in seg.items()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; run it with --gpus 1 "
+              "(multi-GPU sharding of the CSD propagation is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2203_02734_amd as wolf
+    import wolf_inputs as WI
+
+    wolf.load()
+    torch.cuda.set_device(0)
+    wl = WI.gsm128()
+    n, p, lam, z = wl.n, wl.pitch_m, wl.wavelength_m, wl.z_m
+    elems = n ** 4
+    ip, jp = wl.probe
+
+    w = torch.empty((n, n, n, n), dtype=torch.complex64, device="cuda")
+    wb = torch.empty_like(w)
+    # Pick the pass schedule with the library's autotuner (untimed, part of the set-up).
+    plan, tuned_ms = wolf.autotune(n, torch.complex64, reps=3, work=wb)
+    if args.pmc_sample:
+        wolf.build_source(wl.source, n, p, out=w)
+        wb.copy_(w)
+        wolf.propagate_fresnel(w, p, lam, z, out=wb)
+        torch.cuda.synchronize()
+        print("pmc sample done", flush=True)
+        return
+
+    def step(record):
+        wolf.build_source(wl.source, n, p, out=w)
+        record("build")
+        wolf.propagate_fresnel(w, p, lam, z, out=wb)
+        record("propagate")
+        wolf.spectral_density(wb)
+        wolf.degree_of_coherence(wb, ip, jp)
+        record("observables")
+
+    total_ms, wall_ms, seg = timed_steps(step, args.steps, args.warmup, None)
+    ms_per_step = total_ms / args.steps
+    prop_ms = seg["propagate"]
+    bytes_prop = 32.0 * elems            # algorithmic: 2 sweeps x (read + write) x 8 B
+    achieved = bytes_prop / (prop_ms * 1e-3) / 1e9
+
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            tr = json.load(open(args.traffic))
+            if tr.get("kernels_sha") == kernels_sha() and tr.get("workload") == "gsm128_fresnel_c64":
+                traffic = tr.get("propagate_bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    detail = {"plan_c64": plan, "build_ms": round(seg["build"], 4), "propagate_ms": round(prop_ms, 4),
+              "observables_ms": round(seg["observables"], 4),
+              "propagate_elems_per_s": elems / (prop_ms * 1e-3),
+              "wall_ms_timed_region": round(wall_ms, 3)}
+
+    if not args.no_extras:
+        detail.update(extras(wolf, wl, args))
+    if args.big:
+        detail.update(big(wolf, args))
+
+    result = {
+        "metric": "CSD elems/s propagated, N=128 c64 vs c128 at rel err<=1e-5; % HBM peak",
+        "value": elems / (ms_per_step * 1e-3),
+        "unit": "elems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "gsm128_fresnel: GSM source N=128 (2^28 CSD elements) complex64, pitch 20 um, "
+                               "sigma_S 0.1 mm, sigma_g 0.05 mm, lambda 632.8 nm, Fresnel z 0.5 m; step = "
+                               "build W0 + propagate + S + mu(P1)",
+                   "n": n, "elements": elems, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "wolf_propagate_fresnel (all its passes), 32 B/element algorithmic"},
+        "detail": detail,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(result), flush=True)
+
+
+def kernels_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2203_02734_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def extras(wolf, wl, args):
+    """complex128 speedup, far field, adjoint ratio and a copy-kernel ceiling (same N=128 source)."""
+    import torch
+
+    n, p, lam, z = wl.n, wl.pitch_m, wl.wavelength_m, wl.z_m
+    elems = n ** 4
+    out = {}
+    reps = max(3, min(args.steps, 10))
+
+    def time_op(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    w = wolf.build_source(wl.source, n, p, torch.complex64)
+    o = torch.empty_like(w)
+    t64 = time_op(lambda: wolf.propagate_fresnel(w, p, lam, z, out=o))
+    tff = time_op(lambda: wolf.propagate_farfield(w, p, lam, z, out=o))
+    tadj = time_op(lambda: wolf.propagate_adjoint(w, p, lam, z, out=o))
+    out["c64_fresnel_ms"] = round(t64, 4)
+    out["c64_farfield_ms"] = round(tff, 4)
+    out["c64_adjoint_ms"] = round(tadj, 4)
+    out["adjoint_over_forward"] = round(tadj / t64, 3)
+    # Copy ceiling: read + write of the same 2 GiB array.
+    tcp = time_op(lambda: o.copy_(w))
+    out["copy_ceiling_GBps"] = round(2 * w.numel() * 8 / (tcp * 1e-3) / 1e9, 1)
+    del w, o
+    torch.cuda.empty_cache()
+    w = wolf.build_source(wl.source, n, p, torch.complex128)
+    o = torch.empty_like(w)
+    out["plan_c128"] = wolf.autotune(n, torch.complex128, reps=2, work=o)[0]
+    t128 = time_op(lambda: wolf.propagate_fresnel(w, p, lam, z, out=o))
+    out["c128_fresnel_ms"] = round(t128, 4)
+    out["c128_propagate_elems_per_s"] = elems / (t128 * 1e-3)
+    out["c128_achieved_GBps"] = round(64.0 * elems / (t128 * 1e-3) / 1e9, 1)
+    out["c64_speedup_over_c128"] = round(t128 / t64, 3)
+    del w, o
+    torch.cuda.empty_cache()
+    return out
+
+
+def big(wolf, args):
+    import torch
+
+    import wolf_inputs as WI
+
+    wl = WI.gsm256()[0]
+    n, p, lam, z = wl.n, wl.pitch_m, wl.wavelength_m, wl.z_m
+    w = wolf.build_source(wl.source, n, p, torch.complex64)
+    plan = wolf.autotune(n, torch.complex64, reps=1, work=w)[0]
+    w = wolf.build_source(wl.source, n, p, torch.complex64, out=w)
+    for _ in range(1):
+        wolf.propagate_fresnel(w, p, lam, z, out=w)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    reps = 3
+    for _ in range(reps):
+        wolf.propagate_fresnel(w, p, lam, z, out=w)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / reps
+    del w
+    torch.cuda.empty_cache()
+    return {"n256_plan": plan, "n256_c64_fresnel_ms": round(t, 3), "n256_elems_per_s": n ** 4 / (t * 1e-3),
+            "n256_achieved_GBps": round(32.0 * n ** 4 / (t * 1e-3) / 1e9, 1)}
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle, as it stands, for one full step of the same workload on the host cores."""
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    n, p, lam, z = wl.n, wl.pitch_m, wl.wavelength_m, wl.z_m
+    t0 = time.perf_counter()
+    w = O.build_source(wl.source, n, p)
+    wb, _ = O.propagate(w, n, p, lam, z)
+    del w
+    O.spectral_density(wb)
+    O.degree_of_coherence(wb, *wl.probe)
+    t = time.perf_counter() - t0
+    return {"value": n ** 4 / t, "unit": "elems/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full step of the same workload (N={n}, build + FP64 propagate + S + mu), {t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -183,6 +183,32 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
 WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double wavelength_m, double z_m, int32_t dtype,
                                       void* out, void* stream);
 
+/*
+ * Schedule of the propagation passes for one (n, dtype). The operator factorises over the four
+ * axes (see wolf_propagate_fresnel), so its passes can be grouped and ordered freely.
+ *   fused_slab  1: one pass does both second-point axes, one N x N slab per workgroup in LDS
+ *                  (needs N^2 elements <= 160 KB of LDS). 0: a row pass and an i2 pass instead.
+ *   slab_chunk  slabs per chunk of the row + i2 pass pair (0 = all). A power-of-two divisor of N^2.
+ *   col_chunk   columns m2 per chunk of the j1 + i1 pass pair (0 = all). A power-of-two divisor
+ *               of N^2 and a multiple of the axis tile. Chunks of tens of MB let the second pass of
+ *               a pair read the first pass's output from the Infinity Cache instead of HBM.
+ * wolf_set_plan with fused_slab = slab_chunk = col_chunk = -1 restores the built-in default.
+ * A plan that is not valid for (n, dtype) returns WOLF_EINVAL. Plans are per process.
+ */
+WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab, int64_t slab_chunk,
+                                   int64_t col_chunk);
+WOLF_API wolf_status wolf_get_plan(int32_t n, int32_t dtype, int32_t* fused_slab, int64_t* slab_chunk,
+                                   int64_t* col_chunk);
+
+/*
+ * Autotuner: times every candidate schedule for (n, dtype) on `work` with HIP events on `stream`.
+ * Each candidate gets one warm-up run and `reps` timed runs. The fastest is kept for later calls.
+ * `work` is device memory of N^4 elements, overwritten (its contents do not matter).
+ * Blocks the calling thread until the timing is done. best_ms (optional) receives the best time.
+ */
+WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t reps, double* best_ms,
+                                   void* stream);
+
 /* Output pitch dx = lambda z / (N pitch) of eq. (spatial_resolution). Pure host arithmetic. */
 WOLF_API double wolf_output_pitch(int32_t n, double pitch_m, double wavelength_m, double z_m);
 

@@ -28,7 +28,8 @@ GEO_NONE, GEO_CIRCLE, GEO_SQUARE, GEO_ANNULUS, GEO_MASK = 0, 1, 2, 3, 4
 
 EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfield", "wolf_propagate_adjoint",
             "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
-            "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version"]
+            "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
+            "wolf_set_plan", "wolf_get_plan", "wolf_autotune"]
 
 
 class WolfError(RuntimeError):
@@ -66,6 +67,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_degree_of_coherence": [vp, i32, i32, i32, i32, f64, vp, vp],
         "wolf_propagate_batch": [vp, i32, f64, i32, pd, pd, pd, i32, i32, i32, i32, i32, f64, vp, vp, vp, vp],
         "wolf_chirp_table": [i32, f64, f64, f64, i32, vp, vp],
+        "wolf_set_plan": [i32, i32, i32, ctypes.c_int64, ctypes.c_int64],
+        "wolf_get_plan": [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64)],
+        "wolf_autotune": [i32, i32, vp, i32, pd, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -251,3 +256,24 @@ def propagate_batch(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights,
                                     ww.ctypes.data_as(pd), int(bool(farfield)), kind, _code(w_src.dtype), ip, jp,
                                     floor_rel, _ptr(work), _ptr(s), _ptr(mu), _stream()), "wolf_propagate_batch")
     return s, mu
+
+
+def set_plan(n: int, dtype: torch.dtype, fused_slab: int = -1, slab_chunk: int = -1, col_chunk: int = -1) -> None:
+    """Fix the pass schedule for (n, dtype); all -1 restores the default (see include/wolf.h)."""
+    _check(load().wolf_set_plan(n, _code(dtype), fused_slab, slab_chunk, col_chunk), "wolf_set_plan")
+
+
+def get_plan(n: int, dtype: torch.dtype):
+    f, s, c = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().wolf_get_plan(n, _code(dtype), ctypes.byref(f), ctypes.byref(s), ctypes.byref(c)), "wolf_get_plan")
+    return {"fused_slab": f.value, "slab_chunk": s.value, "col_chunk": c.value}
+
+
+def autotune(n: int, dtype: torch.dtype = torch.complex64, reps: int = 3, work: Optional[torch.Tensor] = None):
+    """Time the candidate schedules for (n, dtype) on a scratch array and keep the fastest.
+    Returns (plan, best ms)."""
+    if work is None:
+        work = torch.empty((n, n, n, n), dtype=dtype, device="cuda")
+    best = ctypes.c_double(0.0)
+    _check(load().wolf_autotune(n, _code(dtype), _ptr(work), reps, ctypes.byref(best), _stream()), "wolf_autotune")
+    return get_plan(n, dtype), best.value

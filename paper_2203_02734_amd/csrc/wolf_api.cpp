@@ -102,52 +102,81 @@ wolf_status device_scratch(void** out) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// The propagation operator as four axis passes.
+// The propagation operator and its schedule.
 // ---------------------------------------------------------------------------------------------
-struct OpSpec {
-  double a_src, a_out, scale;
-  bool adjoint;
-};
-
-OpSpec make_op(int32_t n, double pitch, double lam, double z, bool farfield, int32_t kind, bool adjoint) {
+wolf::OperatorTables make_op(int32_t n, double pitch, double lam, double z, bool farfield, int32_t kind,
+                             bool adjoint) {
+  using wolf::Chirp;
   const double dx = lam * z / ((double)n * pitch);
   const double c = kind == WOLF_PRIMARY ? 1.0 / ((4.0 * M_PI * z) * (4.0 * M_PI * z)) : 1.0 / ((lam * z) * (lam * z));
-  OpSpec op;
-  op.a_src = farfield ? 0.0 : pitch * pitch / (lam * z);
-  op.a_out = dx * dx / (lam * z);
+  const double a_src = farfield ? 0.0 : pitch * pitch / (lam * z);
+  const double a_out = dx * dx / (lam * z);
+  wolf::OperatorTables op;
+  if (!adjoint) {
+    // Second point: q(xi) (-1)^n, direct DFT, q(x) (-1)^k. First point: conjugates, inverse DFT.
+    op.pre2 = Chirp{a_src, 1.0, +1, 1};
+    op.post2 = Chirp{a_out, 1.0, +1, 1};
+    op.sign2 = -1;
+    op.pre1 = Chirp{a_src, 1.0, -1, 1};
+    op.post1 = Chirp{a_out, 1.0, -1, 1};
+    op.sign1 = +1;
+  } else {
+    // Adjoint: first point q(x) (-1)^k, direct DFT, q(xi) (-1)^n; second point conjugates, inverse.
+    op.pre1 = Chirp{a_out, 1.0, +1, 1};
+    op.post1 = Chirp{a_src, 1.0, +1, 1};
+    op.sign1 = -1;
+    op.pre2 = Chirp{a_out, 1.0, -1, 1};
+    op.post2 = Chirp{a_src, 1.0, -1, 1};
+    op.sign2 = +1;
+  }
   op.scale = c * pitch * pitch * pitch * pitch;
-  op.adjoint = adjoint;
   return op;
 }
 
+std::mutex g_plan_mu;
+std::map<std::pair<int, int>, wolf::Plan> g_plans;  // (n, dtype) -> plan chosen by wolf_set_plan / autotune
+
+bool plan_valid(int32_t n, int32_t dtype, const wolf::Plan& p) {
+  const long long nn = (long long)n * n;
+  const int c = wolf::axis_tile_cols(n);
+  if (p.fused_slab && !(dtype == WOLF_C64 ? wolf::slab_pass_supported<float2>(n) : wolf::slab_pass_supported<double2>(n)))
+    return false;
+  if (p.col_chunk < 0 || p.col_chunk > nn || (p.col_chunk > 0 && (p.col_chunk % c != 0 || nn % p.col_chunk != 0)))
+    return false;
+  if (p.slab_chunk < 0 || p.slab_chunk > nn || (p.slab_chunk > 0 && nn % p.slab_chunk != 0)) return false;
+  // The row pass over a chunk of slabs needs whole workgroups of rows.
+  if (!p.fused_slab && p.slab_chunk > 0 && (p.slab_chunk * n) % wolf::row_pass_rows(n) != 0) return false;
+  return true;
+}
+
+wolf::Plan default_plan(int32_t n, int32_t dtype) {
+  wolf::Plan p{};
+  p.fused_slab = dtype == WOLF_C64 ? wolf::slab_pass_supported<float2>(n) : wolf::slab_pass_supported<double2>(n);
+  const long long nn = (long long)n * n;
+  const long long eb = (long long)elem_bytes(dtype);
+  // Chunks of about 64 MB, so that the pass pair reuses the chunk from the 256 MB Infinity Cache.
+  const long long target = 64ll << 20;
+  const int c = wolf::axis_tile_cols(n);
+  long long cols = nn;
+  while (cols > c && cols * nn * eb > target) cols >>= 1;
+  p.col_chunk = cols;
+  long long slabs = nn;
+  while (slabs > 1 && slabs * nn * eb > target && ((slabs >> 1) * n) % wolf::row_pass_rows(n) == 0) slabs >>= 1;
+  p.slab_chunk = slabs;
+  return p;
+}
+
+wolf::Plan plan_for(int32_t n, int32_t dtype) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plans.find({n, dtype});
+  return it != g_plans.end() ? it->second : default_plan(n, dtype);
+}
+
 template <class T>
-wolf_status run_operator(const T* in, T* out, int32_t n, const OpSpec& op, hipStream_t st) {
-  using wolf::Chirp;
-  // Axis order of the passes: j2 (3), i2 (2), j1 (1), i1 (0). The last pass carries the scale.
-  const int order[4] = {3, 2, 1, 0};
-  for (int k = 0; k < 4; ++k) {
-    const int axis = order[k];
-    const bool second_point = axis >= 2;
-    Chirp pre, post;
-    int sign;
-    if (!op.adjoint) {
-      // Second point: q(xi) (-1)^n, direct DFT, q(x) (-1)^k.  First point: conjugates, inverse DFT.
-      const int cs = second_point ? +1 : -1;
-      pre = Chirp{op.a_src, 1.0, cs, 1};
-      post = Chirp{op.a_out, 1.0, cs, 1};
-      sign = second_point ? -1 : +1;
-    } else {
-      // First point: q(x) (-1)^k, direct DFT, q(xi) (-1)^n.  Second point: conjugates, inverse DFT.
-      const int cs = second_point ? -1 : +1;
-      pre = Chirp{op.a_out, 1.0, cs, 1};
-      post = Chirp{op.a_src, 1.0, cs, 1};
-      sign = second_point ? +1 : -1;
-    }
-    if (k == 3) post.scale = op.scale;
-    const T* src = k == 0 ? in : out;
-    hipError_t e = wolf::launch_axis_pass<T>(n, src, out, axis, sign, pre, post, st);
-    if (e != hipSuccess) return fail(WOLF_EDEVICE, "axis pass %d: %s", axis, hipGetErrorString(e));
-  }
+wolf_status run_operator(const T* in, T* out, int32_t n, int32_t dtype, const wolf::OperatorTables& op,
+                         hipStream_t st) {
+  const hipError_t e = wolf::launch_operator<T>(n, in, out, op, plan_for(n, dtype), st);
+  if (e != hipSuccess) return fail(WOLF_EDEVICE, "propagation launch: %s", hipGetErrorString(e));
   g_last_error.clear();
   return WOLF_OK;
 }
@@ -165,12 +194,12 @@ wolf_status propagate_common(const void* w_in, void* w_out, int32_t n, double pi
   if ((s = check_buf(w_in, bytes, "input")) != WOLF_OK) return s;
   if ((s = check_buf(w_out, bytes, "output")) != WOLF_OK) return s;
   if (partial_overlap(w_in, w_out, bytes)) return fail(WOLF_EINVAL, "%s: input and output partly overlap", who);
-  const OpSpec op = make_op(n, pitch, lam, z, farfield, kind, adjoint);
+  const wolf::OperatorTables op = make_op(n, pitch, lam, z, farfield, kind, adjoint);
   if (out_pitch) *out_pitch = lam * z / ((double)n * pitch);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == WOLF_C64)
-    return run_operator<float2>(static_cast<const float2*>(w_in), static_cast<float2*>(w_out), n, op, st);
-  return run_operator<double2>(static_cast<const double2*>(w_in), static_cast<double2*>(w_out), n, op, st);
+    return run_operator<float2>(static_cast<const float2*>(w_in), static_cast<float2*>(w_out), n, dtype, op, st);
+  return run_operator<double2>(static_cast<const double2*>(w_in), static_cast<double2*>(w_out), n, dtype, op, st);
 }
 
 }  // namespace
@@ -335,6 +364,98 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   (void)w_src; (void)n; (void)pitch_m; (void)n_pairs; (void)wavelength_m; (void)z_m; (void)weight; (void)farfield;
   (void)kind; (void)dtype; (void)ip; (void)jp; (void)s_floor_rel; (void)work; (void)s_out; (void)mu_out; (void)stream;
   return fail(WOLF_EUNSUPPORTED, "wolf_propagate_batch: not built yet");
+}
+
+WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab, int64_t slab_chunk,
+                                   int64_t col_chunk) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_set_plan: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_set_plan: bad dtype");
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (fused_slab == -1 && slab_chunk == -1 && col_chunk == -1) {
+    g_plans.erase({n, dtype});
+    return WOLF_OK;
+  }
+  if (fused_slab != 0 && fused_slab != 1) return fail(WOLF_EINVAL, "wolf_set_plan: fused_slab must be 0 or 1");
+  const wolf::Plan p{fused_slab == 1, (long long)slab_chunk, (long long)col_chunk};
+  if (!plan_valid(n, dtype, p)) return fail(WOLF_EINVAL, "wolf_set_plan: plan not valid for N=%d", n);
+  g_plans[{n, dtype}] = p;
+  return WOLF_OK;
+}
+
+WOLF_API wolf_status wolf_get_plan(int32_t n, int32_t dtype, int32_t* fused_slab, int64_t* slab_chunk,
+                                   int64_t* col_chunk) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_get_plan: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_get_plan: bad dtype");
+  if (!fused_slab || !slab_chunk || !col_chunk) return fail(WOLF_EINVAL, "wolf_get_plan: null output");
+  const wolf::Plan p = plan_for(n, dtype);
+  *fused_slab = p.fused_slab ? 1 : 0;
+  *slab_chunk = p.slab_chunk;
+  *col_chunk = p.col_chunk;
+  return WOLF_OK;
+}
+
+WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t reps, double* best_ms,
+                                   void* stream) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_autotune: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_autotune: bad dtype");
+  if (reps < 1 || reps > 1000) return fail(WOLF_EINVAL, "wolf_autotune: reps must be in [1, 1000]");
+  wolf_status s;
+  if ((s = check_buf(work, n4(n) * elem_bytes(dtype), "work")) != WOLF_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long nn = (long long)n * n;
+  const int c = wolf::axis_tile_cols(n);
+  std::vector<wolf::Plan> cands;
+  const wolf::Plan def = default_plan(n, dtype);
+  for (int fused = 1; fused >= 0; --fused) {
+    for (long long cols = nn; cols >= c; cols >>= 1) {
+      // Chunks below 4 MB only add launches.
+      if (cols < nn && cols * nn * (long long)elem_bytes(dtype) < (4ll << 20)) break;
+      wolf::Plan p{fused == 1, fused ? def.slab_chunk : def.slab_chunk, cols};
+      if (plan_valid(n, dtype, p)) cands.push_back(p);
+      if (!fused && cols == nn) {
+        wolf::Plan q{false, 0, cols};
+        if (plan_valid(n, dtype, q)) cands.push_back(q);
+      }
+    }
+  }
+  if (hipMemsetAsync(work, 0, n4(n) * elem_bytes(dtype), st) != hipSuccess)
+    return fail(WOLF_EDEVICE, "wolf_autotune: memset failed");
+  const wolf::OperatorTables op = make_op(n, 20e-6, 632.8e-9, 0.5, false, WOLF_SECONDARY, false);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(WOLF_EDEVICE, "wolf_autotune: event creation failed");
+  double best = 1e300;
+  wolf::Plan best_plan = def;
+  hipError_t e = hipSuccess;
+  for (const auto& p : cands) {
+    for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
+      if (r == 1) e = hipEventRecord(a, st);
+      if (e == hipSuccess) {
+        e = dtype == WOLF_C64 ? wolf::launch_operator<float2>(n, (float2*)work, (float2*)work, op, p, st)
+                              : wolf::launch_operator<double2>(n, (double2*)work, (double2*)work, op, p, st);
+      }
+    }
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) break;
+    const double per = ms / reps;
+    if (per < best) {
+      best = per;
+      best_plan = p;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (e != hipSuccess) return fail(WOLF_EDEVICE, "wolf_autotune: %s", hipGetErrorString(e));
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans[{n, dtype}] = best_plan;
+  }
+  if (best_ms) *best_ms = best;
+  g_last_error.clear();
+  return WOLF_OK;
 }
 
 }  // extern "C"

@@ -1,74 +1,89 @@
-// Axis-FFT kernels of the CSD propagation operator, and the operator itself as a sequence of
-// axis passes.
+// Axis-FFT kernels of the CSD propagation operator, and the operator as a schedule of passes.
 //
-// The 4D array W[i1][j1][i2][j2] (Sec. 3.1) lives in HBM as one contiguous block with j2
-// fastest. Every pass transforms one axis of length N for the whole array. It reads each element
-// once and writes it once, and fuses the per-axis diagonal factors into its load and store.
+// The 4D array W[i1][j1][i2][j2] (Sec. 3.1) is one contiguous block in HBM, j2 fastest. The
+// operator of eqs. (W_general)/(W_fresnel) factorises over the four axes. Along each axis it is a
+// diagonal pre-factor, a length-N centred DFT and a diagonal post-factor (see wolf_device.hpp).
+// All four axis operations commute, so the passes may be grouped and ordered freely:
+//   slab pass   : both second-point axes (i2, j2) of one contiguous N x N slab, in LDS (one sweep).
+//                 It also applies the first-point pre-factor, which is a scalar per slab.
+//   axis passes : one strided axis (j1 or i1, or i2 when the slab pass does not fit), over a tile of
+//                 C consecutive columns. It runs over column chunks, so that the two first-point
+//                 passes can reuse the chunk from the 256 MB Infinity Cache.
+//   row pass    : the contiguous axis j2 on its own (when the slab pass does not fit).
 //
-// Length-N DFT across threads (N = N1 N2, N1 >= N2). Thread t of an FFT loads x[N2 a + t],
-// a = 0..N1-1, and does an N1-point DFT in registers. It then multiplies by w_N^{t k1} and passes
-// the values through LDS. After the exchange each thread holds, for its k1 values, the N2 inputs
-// of an N2-point DFT in registers, and the outputs land at X[k1 + N1 k2].
+// Length-N DFT across threads (N = N1 N2, N1 >= N2). Thread t of one FFT loads x[N2 a + t],
+// a = 0..N1-1, does an N1-point DFT in registers and multiplies by w_N^{t k1}. One exchange
+// through LDS follows. Thread t then owns k1 = t + N2 r (r < N1/N2), does the N2-point DFTs over
+// n2 and writes X[k1 + N1 k2]. With this ownership the outputs of the N2 threads are contiguous.
 #include "wolf_device.hpp"
 #include "wolf_internal.hpp"
 
 namespace wolf {
 
 // ---------------------------------------------------------------------------------------------
-// Strided axis: element (o, n, c) at o * outer_stride + n * axis_stride + c, c in [0, inner_len).
-// A workgroup takes one outer index and C consecutive c (coalesced runs of C elements).
+// Strided axis: element (o, n, c) at o * outer_stride + n * axis_stride + inner_offset + c.
+// A workgroup takes one outer index and C consecutive columns c (coalesced runs of C elements).
 // ---------------------------------------------------------------------------------------------
 template <class T, int N, int C, int SIGN>
-__global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* dst,
-                                                              long long outer_stride, long long axis_stride,
-                                                              long long tiles_per_outer, Chirp pre, Chirp post) {
+__global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* dst, AxisJob ja, AxisJob jb) {
   using S = Split<N>;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
   constexpr int NT = N2 * C;
   __shared__ T xch[N * C];
   __shared__ T tpre[N], tpost[N], tw[N];
 
+  // Two independent jobs may share one launch (the j1 pass of one column chunk and the i1 pass of
+  // the previous one). With equal sizes they interleave block by block.
+  long long bid = blockIdx.x;
+  bool second;
+  if (jb.blocks == ja.blocks) {
+    second = (bid & 1) != 0;
+    bid >>= 1;
+  } else {
+    second = bid >= ja.blocks;
+    if (second) bid -= ja.blocks;
+  }
+  const AxisJob& j = second ? jb : ja;
+
   for (int i = threadIdx.x; i < N; i += NT) {
-    tpre[i] = chirp_entry<T>(pre, i, N);
-    tpost[i] = chirp_entry<T>(post, i, N);
+    tpre[i] = chirp_entry<T>(j.pre, i, N);
+    tpost[i] = chirp_entry<T>(j.post, i, N);
     tw[i] = twiddle_entry<T, SIGN>(i, N);
   }
   __syncthreads();
 
   const int c = threadIdx.x % C;
   const int t = threadIdx.x / C;
-  const long long bid = blockIdx.x;
-  const long long o = bid / tiles_per_outer;
-  const long long c0 = (bid - o * tiles_per_outer) * C;
-  const long long base = o * outer_stride + c0 + c;
+  const long long o = bid / j.tiles_per_outer;
+  const long long c0 = (bid - o * j.tiles_per_outer) * C;
+  const long long base = o * j.outer_stride + j.inner_offset + c0 + c;
+  const long long as = j.axis_stride;
 
   T v[N1];
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
     const int n = N2 * a + t;
-    v[a] = cmul(src[base + (long long)n * axis_stride], tpre[n]);
+    v[a] = cmul(src[base + (long long)n * as], tpre[n]);
   }
   dft_reg<N1, SIGN>(v);
 #pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) {
-    xch[(k1 * N2 + t) * C + c] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
-  }
+  for (int k1 = 0; k1 < N1; ++k1) xch[(k1 * N2 + t) * C + c] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
   __syncthreads();
   T u[N1];
 #pragma unroll
   for (int r = 0; r < Q; ++r) {
-    const int k1 = t * Q + r;
+    const int k1 = t + N2 * r;
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) u[r * N2 + n2] = xch[(k1 * N2 + n2) * C + c];
     dft_reg<N2, SIGN>(&u[r * N2]);
   }
 #pragma unroll
   for (int r = 0; r < Q; ++r) {
-    const int k1 = t * Q + r;
+    const int k1 = t + N2 * r;
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int k = k1 + N1 * k2;
-      dst[base + (long long)k * axis_stride] = cmul(u[r * N2 + k2], tpost[k]);
+      dst[base + (long long)k * as] = cmul(u[r * N2 + k2], tpost[k]);
     }
   }
 }
@@ -77,8 +92,7 @@ __global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* 
 // Contiguous axis (rows of N elements). A workgroup takes B consecutive rows.
 // ---------------------------------------------------------------------------------------------
 template <class T, int N, int B, int SIGN>
-__global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* dst,
-                                                             Chirp pre, Chirp post) {
+__global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* dst, Chirp pre, Chirp post) {
   using S = Split<N>;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
   constexpr int NT = N2 * B;
@@ -112,14 +126,14 @@ __global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* d
   T u[N1];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int k1 = t * Q + q;
+    const int k1 = t + N2 * q;
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) u[q * N2 + n2] = xch[(r * N1 + k1) * LD + n2];
     dft_reg<N2, SIGN>(&u[q * N2]);
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int k1 = t * Q + q;
+    const int k1 = t + N2 * q;
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int k = k1 + N1 * k2;
@@ -129,8 +143,118 @@ __global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* d
 }
 
 // ---------------------------------------------------------------------------------------------
+// Slab pass: 2D DFT over (i2, j2) of one contiguous N x N slab per workgroup, N2 * N threads.
+// Phase 1 transforms the columns (i2, stride N): the loads are coalesced along j2. Phase 2
+// transforms the rows (j2) after a transpose through LDS. The LDS row stride SP keeps the 16-lane
+// groups of both phases on distinct banks.
+// ---------------------------------------------------------------------------------------------
+template <int N> constexpr int slab_stride() {
+  constexpr int need = Split<N>::N1 * (Split<N>::N2 + 1);
+  constexpr int s = need > N ? need : N;
+  return N >= 64 ? ((s % 16 == 8) ? s : s + ((8 - s % 16) + 16) % 16) : s;
+}
+
+template <class T, int N> constexpr size_t slab_lds_bytes() {
+  return sizeof(T) * ((size_t)N * slab_stride<N>() + 3 * N + 2);
+}
+
+template <class T, int N, int SIGN>
+__global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T* dst, Chirp pre, Chirp post,
+                                                               Chirp slab_pre) {
+  using S = Split<N>;
+  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
+  constexpr int NT = N2 * N;
+  constexpr int SP = slab_stride<N>();
+  __shared__ T buf[N * SP];
+  __shared__ T tpre[N], tpost[N], tw[N], sc[2];
+
+  const long long p1 = blockIdx.x;
+  for (int i = threadIdx.x; i < N; i += NT) {
+    tpre[i] = chirp_entry<T>(pre, i, N);
+    tpost[i] = chirp_entry<T>(post, i, N);
+    tw[i] = twiddle_entry<T, SIGN>(i, N);
+  }
+  if (threadIdx.x < 2) {
+    const int idx = threadIdx.x == 0 ? (int)(p1 / N) : (int)(p1 % N);
+    sc[threadIdx.x] = chirp_entry<T>(slab_pre, idx, N);
+  }
+  __syncthreads();
+
+  const T* in = src + p1 * N * N;
+  T* out = dst + p1 * N * N;
+
+  // Phase 1: columns. Thread (t, c); c is the j2 column.
+  {
+    const int c = threadIdx.x % N;
+    const int t = threadIdx.x / N;
+    const T cst = cmul(tpre[c], cmul(sc[0], sc[1]));  // j2 pre-factor and the slab's first-point factor
+    T v[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int n = N2 * a + t;
+      v[a] = cmul(in[n * N + c], tpre[n]);
+    }
+    dft_reg<N1, SIGN>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * N + c] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
+    __syncthreads();
+    T u[N1];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      const int k1 = t + N2 * r;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[r * N2 + n2] = buf[(k1 * N2 + n2) * N + c];
+      dft_reg<N2, SIGN>(&u[r * N2]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      const int k1 = t + N2 * r;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int k = k1 + N1 * k2;
+        buf[k * SP + c] = cmul(u[r * N2 + k2], cmul(tpost[k], cst));
+      }
+    }
+  }
+  __syncthreads();
+  // Phase 2: rows. Thread (t, r); r is the i2 row.
+  {
+    const int t = threadIdx.x % N2;
+    const int r = threadIdx.x / N2;
+    T v[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[a] = buf[r * SP + N2 * a + t];
+    dft_reg<N1, SIGN>(v);
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) buf[r * SP + k1 * (N2 + 1) + t] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
+    __syncthreads();
+    T u[N1];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t + N2 * q;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[q * N2 + n2] = buf[r * SP + k1 * (N2 + 1) + n2];
+      dft_reg<N2, SIGN>(&u[q * N2]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t + N2 * q;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int k = k1 + N1 * k2;
+        out[r * N + k] = cmul(u[q * N2 + k2], tpost[k]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------------------------
+constexpr size_t kMaxLds = 160 * 1024;
+
 template <int N> constexpr int axis_cols() {
   constexpr int c = 256 / Split<N>::N2;
   return c < N ? c : N;
@@ -140,58 +264,186 @@ template <int N> constexpr int row_batch() {
   return b < N * N * N ? b : N * N * N;
 }
 
-template <class T, int N, int SIGN>
-static hipError_t launch_axis_n(const T* src, T* dst, int axis, const Chirp& pre, const Chirp& post,
-                                hipStream_t st) {
-  // axis 0 = i1, 1 = j1, 2 = i2 (the strided axes of [i1][j1][i2][j2]).
+// One or two strided-axis blocks in one launch (see AxisRange); `b` may be null.
+template <int N>
+static bool make_job(const AxisRange& ar, const Chirp& pre, const Chirp& post, AxisJob* j) {
   constexpr int C = axis_cols<N>();
-  const long long n = N;
-  long long outer_count, outer_stride, axis_stride, inner_len;
-  if (axis == 0) { outer_count = 1; outer_stride = 0; axis_stride = n * n * n; inner_len = n * n * n; }
-  else if (axis == 1) { outer_count = n; outer_stride = n * n * n; axis_stride = n * n; inner_len = n * n; }
-  else { outer_count = n * n; outer_stride = n * n; axis_stride = n; inner_len = n; }
-  const long long tiles = inner_len / C;
-  const long long blocks = outer_count * tiles;
+  if (ar.ncols % C != 0 || ar.ncols <= 0 || ar.outer_count <= 0) return false;
+  j->outer_stride = ar.outer_stride;
+  j->axis_stride = ar.axis_stride;
+  j->inner_offset = ar.inner_offset;
+  j->tiles_per_outer = ar.ncols / C;
+  j->blocks = ar.outer_count * j->tiles_per_outer;
+  j->pre = pre;
+  j->post = post;
+  return true;
+}
+
+template <class T, int N, int SIGN>
+static hipError_t launch_axis_n(const T* src, T* dst, const AxisRange& a, const Chirp& pre_a, const Chirp& post_a,
+                                const AxisRange* b, const Chirp& pre_b, const Chirp& post_b, hipStream_t st) {
+  constexpr int C = axis_cols<N>();
+  AxisJob ja{}, jb{};
+  if (!make_job<N>(a, pre_a, post_a, &ja)) return hipErrorInvalidValue;
+  if (b != nullptr && !make_job<N>(*b, pre_b, post_b, &jb)) return hipErrorInvalidValue;
+  const long long blocks = ja.blocks + jb.blocks;
+  if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_axis_fft<T, N, C, SIGN>), dim3((unsigned)blocks), dim3(Split<N>::N2 * C), 0, st, src, dst,
-                     outer_stride, axis_stride, tiles, pre, post);
+                     ja, jb);
   return hipGetLastError();
 }
 
 template <class T, int N, int SIGN>
-static hipError_t launch_row_n(const T* src, T* dst, const Chirp& pre, const Chirp& post, hipStream_t st) {
+static hipError_t launch_row_n(const T* src, T* dst, long long rows, const Chirp& pre, const Chirp& post,
+                               hipStream_t st) {
   constexpr int B = row_batch<N>();
-  const long long rows = (long long)N * N * N;
-  const long long blocks = rows / B;   // N^3 is a multiple of B for every supported N
-  hipLaunchKernelGGL((k_row_fft<T, N, B, SIGN>), dim3((unsigned)blocks), dim3(Split<N>::N2 * B), 0, st, src, dst,
-                     pre, post);
+  if (rows % B != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_row_fft<T, N, B, SIGN>), dim3((unsigned)(rows / B)), dim3(Split<N>::N2 * B), 0, st, src,
+                     dst, pre, post);
   return hipGetLastError();
 }
 
-template <class T, int SIGN>
-static hipError_t launch_axis_sign(int n, const T* src, T* dst, int axis, const Chirp& pre, const Chirp& post,
-                                   hipStream_t st) {
-  switch (n) {
-#define WOLF_CASE(NN)                                                                  \
-  case NN:                                                                             \
-    return axis == 3 ? launch_row_n<T, NN, SIGN>(src, dst, pre, post, st)             \
-                     : launch_axis_n<T, NN, SIGN>(src, dst, axis, pre, post, st);
-    WOLF_CASE(2) WOLF_CASE(4) WOLF_CASE(8) WOLF_CASE(16) WOLF_CASE(32) WOLF_CASE(64) WOLF_CASE(128) WOLF_CASE(256)
-#undef WOLF_CASE
-    default:
-      return hipErrorInvalidValue;
+template <class T, int N, int SIGN>
+static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chirp& pre, const Chirp& post,
+                                const Chirp& slab_pre, hipStream_t st) {
+  if constexpr (slab_lds_bytes<T, N>() > kMaxLds) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_slab_fft2<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N), 0, st, src, dst,
+                       pre, post, slab_pre);
+    return hipGetLastError();
   }
 }
 
+#define WOLF_DISPATCH_N(n, CALL)                   \
+  switch (n) {                                     \
+    case 2: { constexpr int NN = 2; return CALL; }     \
+    case 4: { constexpr int NN = 4; return CALL; }     \
+    case 8: { constexpr int NN = 8; return CALL; }     \
+    case 16: { constexpr int NN = 16; return CALL; }   \
+    case 32: { constexpr int NN = 32; return CALL; }   \
+    case 64: { constexpr int NN = 64; return CALL; }   \
+    case 128: { constexpr int NN = 128; return CALL; } \
+    case 256: { constexpr int NN = 256; return CALL; } \
+    default: return hipErrorInvalidValue;          \
+  }
+
 template <class T>
-hipError_t launch_axis_pass(int n, const T* src, T* dst, int axis, int sign, const Chirp& pre, const Chirp& post,
-                            hipStream_t st) {
-  return sign < 0 ? launch_axis_sign<T, -1>(n, src, dst, axis, pre, post, st)
-                  : launch_axis_sign<T, +1>(n, src, dst, axis, pre, post, st);
+hipError_t launch_axis_range(int n, const T* src, T* dst, int sign, const AxisRange& a, const Chirp& pre_a,
+                             const Chirp& post_a, const AxisRange* b, const Chirp& pre_b, const Chirp& post_b,
+                             hipStream_t st) {
+  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_axis_n<T, NN, -1>(src, dst, a, pre_a, post_a, b, pre_b, post_b, st))) }
+  WOLF_DISPATCH_N(n, (launch_axis_n<T, NN, +1>(src, dst, a, pre_a, post_a, b, pre_b, post_b, st)))
 }
 
-template hipError_t launch_axis_pass<float2>(int, const float2*, float2*, int, int, const Chirp&, const Chirp&,
+template <class T>
+hipError_t launch_row_pass(int n, const T* src, T* dst, long long rows, int sign, const Chirp& pre,
+                           const Chirp& post, hipStream_t st) {
+  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_row_n<T, NN, -1>(src, dst, rows, pre, post, st))) }
+  WOLF_DISPATCH_N(n, (launch_row_n<T, NN, +1>(src, dst, rows, pre, post, st)))
+}
+
+template <class T>
+hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slabs, int sign, const Chirp& pre,
+                            const Chirp& post, const Chirp& slab_pre, hipStream_t st) {
+  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, st))) }
+  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, st)))
+}
+
+template <class T> bool slab_pass_supported(int n) {
+  switch (n) {
+    case 2: return slab_lds_bytes<T, 2>() <= kMaxLds;
+    case 4: return slab_lds_bytes<T, 4>() <= kMaxLds;
+    case 8: return slab_lds_bytes<T, 8>() <= kMaxLds;
+    case 16: return slab_lds_bytes<T, 16>() <= kMaxLds;
+    case 32: return slab_lds_bytes<T, 32>() <= kMaxLds;
+    case 64: return slab_lds_bytes<T, 64>() <= kMaxLds;
+    case 128: return slab_lds_bytes<T, 128>() <= kMaxLds;
+    case 256: return slab_lds_bytes<T, 256>() <= kMaxLds;
+    default: return false;
+  }
+}
+
+int row_pass_rows(int n) {
+  switch (n) {
+    case 2: return row_batch<2>();
+    case 4: return row_batch<4>();
+    case 8: return row_batch<8>();
+    case 16: return row_batch<16>();
+    case 32: return row_batch<32>();
+    case 64: return row_batch<64>();
+    case 128: return row_batch<128>();
+    case 256: return row_batch<256>();
+    default: return 1;
+  }
+}
+
+int axis_tile_cols(int n) {
+  switch (n) {
+    case 2: return axis_cols<2>();
+    case 4: return axis_cols<4>();
+    case 8: return axis_cols<8>();
+    case 16: return axis_cols<16>();
+    case 32: return axis_cols<32>();
+    case 64: return axis_cols<64>();
+    case 128: return axis_cols<128>();
+    case 256: return axis_cols<256>();
+    default: return 1;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The operator: a schedule of passes (see Plan).
+// ---------------------------------------------------------------------------------------------
+template <class T>
+hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, hipStream_t st) {
+  const long long N = n, NN = N * N, NNN = NN * N;
+  hipError_t e;
+  const Chirp ident{0.0, 1.0, +1, 0};
+  // Second-point axes (i2, j2).
+  if (plan.fused_slab) {
+    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, st);
+    if (e != hipSuccess) return e;
+  } else {
+    const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk
+    for (long long s0 = 0; s0 < NN; s0 += g) {
+      const long long gs = (s0 + g <= NN) ? g : NN - s0;
+      e = launch_row_pass<T>(n, in + s0 * NN, out + s0 * NN, gs * N, op.sign2, op.pre2, op.post2, st);
+      if (e != hipSuccess) return e;
+      const AxisRange ar{gs, NN, N, 0, N};  // axis i2 inside each slab of the chunk
+      e = launch_axis_range<T>(n, out + s0 * NN, out + s0 * NN, op.sign2, ar, op.pre2, op.post2, nullptr, ident,
+                               ident, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  // First-point axes (j1, i1) over column chunks of the N^2 columns m2. The i1 pass of chunk k - 1
+  // shares a launch with the j1 pass of chunk k: they touch disjoint columns.
+  const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
+  const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
+  Chirp post_last = op.post1;
+  post_last.scale = op.scale;
+  const long long chunks = (NN + m - 1) / m;
+  for (long long k = 0; k <= chunks; ++k) {
+    const bool has_j = k < chunks, has_i = k > 0;
+    const long long cj = k * m, ci = (k - 1) * m;
+    const AxisRange aj{N, NNN, NN, cj, has_j ? ((cj + m <= NN) ? m : NN - cj) : 0};  // j1: outer i1, stride N^2
+    const AxisRange ai{N, NN, NNN, ci, has_i ? ((ci + m <= NN) ? m : NN - ci) : 0};  // i1: outer j1, stride N^3
+    if (has_j && has_i)
+      e = launch_axis_range<T>(n, out, out, op.sign1, aj, pre1, op.post1, &ai, pre1, post_last, st);
+    else if (has_j)
+      e = launch_axis_range<T>(n, out, out, op.sign1, aj, pre1, op.post1, nullptr, ident, ident, st);
+    else
+      e = launch_axis_range<T>(n, out, out, op.sign1, ai, pre1, post_last, nullptr, ident, ident, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_operator<float2>(int, const float2*, float2*, const OperatorTables&, const Plan&,
+                                            hipStream_t);
+template hipError_t launch_operator<double2>(int, const double2*, double2*, const OperatorTables&, const Plan&,
                                              hipStream_t);
-template hipError_t launch_axis_pass<double2>(int, const double2*, double2*, int, int, const Chirp&, const Chirp&,
-                                              hipStream_t);
+template bool slab_pass_supported<float2>(int);
+template bool slab_pass_supported<double2>(int);
 
 }  // namespace wolf

@@ -8,19 +8,41 @@
 
 namespace wolf {
 
-// One pass of the propagation operator: the 1D DFT along `axis` of the N^4 array
-// (0 = i1, 1 = j1, 2 = i2, 3 = j2), with the diagonal factors `pre` (input index) and `post`
-// (output index). sign -1 = direct DFT, +1 = inverse (unnormalised).
-template <class T>
-hipError_t launch_axis_pass(int n, const T* src, T* dst, int axis, int sign, const Chirp& pre, const Chirp& post,
-                            hipStream_t st);
+// The propagation operator along its four axes. Axis of the first point (i1, j1) and of the
+// second point (i2, j2): diagonal pre-factor, DFT of sign `sign` (-1 direct, +1 inverse,
+// unnormalised), diagonal post-factor. The real `scale` multiplies the result.
+struct OperatorTables {
+  Chirp pre1, post1, pre2, post2;
+  int sign1, sign2;
+  double scale;
+};
 
-// Fused pass over the two fastest axes (i2, j2) of each contiguous N x N slab.
-// `slab_scale` multiplies slab (i1, j1) by pre1[i1] * pre1[j1], the first-point pre-factor.
+// Schedule of the passes. fused_slab: one slab pass for (i2, j2). Otherwise a row pass and an
+// i2 pass run over chunks of `slab_chunk` slabs. The j1 and i1 passes run over chunks of
+// `col_chunk` columns m2 (0 = all).
+struct Plan {
+  bool fused_slab;
+  long long slab_chunk;
+  long long col_chunk;
+};
+
+// A strided-axis block: outer_count blocks (stride outer_stride); per block, columns
+// [inner_offset, inner_offset + ncols) at unit stride; the transformed axis has stride axis_stride.
+struct AxisRange {
+  long long outer_count, outer_stride, axis_stride, inner_offset, ncols;
+};
+
+// Kernel-side form of an AxisRange: tiles of C columns, `blocks` workgroups.
+struct AxisJob {
+  long long outer_stride, axis_stride, inner_offset, tiles_per_outer, blocks;
+  Chirp pre, post;
+};
+
 template <class T>
-hipError_t launch_slab_pass(int n, const T* src, T* dst, int sign, const Chirp& pre, const Chirp& post,
-                            const Chirp& slab_pre, hipStream_t st);
+hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, hipStream_t st);
 template <class T> bool slab_pass_supported(int n);
+int axis_tile_cols(int n);
+int row_pass_rows(int n);  // rows per workgroup of the row pass
 
 // Source description after host-side validation and unit conversion.
 struct SourceParams {

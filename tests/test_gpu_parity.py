@@ -247,3 +247,35 @@ def test_full_size_gsm128(gpu_lib, farfield, dtype):
     assert _separable_rel(w, bx, by) < TOL[dtype]
     del w
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------------------------
+# Every pass schedule gives the same operator (fused slab or row + i2 passes; any chunking).
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DT)
+def test_all_schedules_agree(gpu_lib, dtype):
+    n, p, z = 32, 20e-6, 0.05
+    w = WI.random_complex((n, n, n, n), seed=51)
+    ref, _ = O.propagate(w, n, p, LAM, z)
+    adj_ref = O.propagate_adjoint(w, n, p, LAM, z)
+    nn = n * n
+    c = 256 // 4 if 256 // 4 < n else n       # axis tile at N = 32 (N2 = 4)
+    plans = [(1, 0, 0), (1, 0, c), (1, 0, nn // 2), (0, 0, 0), (0, nn // 4, c), (0, 2, nn // 8)]
+    try:
+        for fused, sl, cc in plans:
+            gpu_lib.set_plan(n, dtype, fused, sl, cc)
+            got, _ = gpu_lib.propagate_fresnel(dev(w, dtype), p, LAM, z)
+            assert rel(host(got), ref) < TOL[dtype], (fused, sl, cc)
+            adj = gpu_lib.propagate_adjoint(dev(w, dtype), p, LAM, z)
+            assert rel(host(adj), adj_ref) < TOL[dtype], (fused, sl, cc)
+    finally:
+        gpu_lib.set_plan(n, dtype)
+
+
+def test_invalid_plan_rejected(gpu_lib):
+    with pytest.raises(gpu_lib.WolfError):
+        gpu_lib.set_plan(128, torch.complex128, 1, 0, 0)      # slab does not fit LDS in complex128
+    with pytest.raises(gpu_lib.WolfError):
+        gpu_lib.set_plan(64, torch.complex64, 1, 0, 3)        # chunk not a divisor
+    with pytest.raises(gpu_lib.WolfError):
+        gpu_lib.set_plan(32, torch.complex64, 0, 1, 0)        # one slab is less than a row-pass workgroup
