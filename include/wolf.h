@@ -174,6 +174,30 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
                                           double s_floor_rel, void* work, void* s_out, void* mu_out, void* stream);
 
 /*
+ * wolf_diag_embed -- out[p1; p2] = g[p1] if p1 == p2 else 0: the gradient with respect to W of a
+ * loss that depends on W only through S = Re diag(W) (Algorithm 4), given g = dL/dS.
+ *   g     device, N*N real (float32 for WOLF_C64, float64 for WOLF_C128).
+ *   out   device, N^4 complex, written in full.
+ */
+WOLF_API wolf_status wolf_diag_embed(const void* g, int32_t n, int32_t dtype, void* out, void* stream);
+
+/*
+ * wolf_fit_gradient -- gradients of a loss with respect to the parameters of the custom-map source
+ * W_A[p1; p2] = sqrt(I(p1)) sqrt(I(p2)) exp(-|xi1 - xi2|^2 / (2 sg^2)) (eq. W_def with a Gaussian
+ * degree of coherence, amplitude 1, no geometry, no lens), given G_A = dL/dW_A in torch's complex
+ * convention (dL/dRe + i dL/dIm), e.g. from wolf_propagate_adjoint:
+ *   d_imap[p] = sum_q Re(conj(G_A[p;q]) + conj(G_A[q;p])) sqrt(I(q)) mu_g(p,q) / (2 sqrt(I(p)))
+ *   d_sigma   = sum_{p,q} Re(conj(G_A[p;q]) W_A[p;q]) |xi_p - xi_q|^2 / sg^3
+ *   ga       device N^4 complex of `dtype`.   imap: device N*N float32, every entry > 0.
+ *   work     device scratch of at least wolf_fit_work_bytes(n, dtype) bytes (overwritten).
+ *   d_imap   device N*N float32.   d_sigma: device, one float64.
+ * N <= 128 (WOLF_EUNSUPPORTED above).
+ */
+WOLF_API wolf_status wolf_fit_gradient(const void* ga, const float* imap, int32_t n, double pitch_m, double sigma_g_m,
+                                       int32_t dtype, void* work, float* d_imap, double* d_sigma, void* stream);
+WOLF_API int64_t wolf_fit_work_bytes(int32_t n, int32_t dtype);
+
+/*
  * wolf_chirp_table -- the FP64-built table of the quadratic-phase propagator q(z, xi) of
  * eq. (q_factor), along one axis: out[i] = exp(i pi (pitch (i - N/2))^2 / (lambda z)), i in [0, N).
  * The 2D propagator is out[i] * out[j]. It is the same table the propagation kernels build, minus

@@ -29,7 +29,8 @@ GEO_NONE, GEO_CIRCLE, GEO_SQUARE, GEO_ANNULUS, GEO_MASK = 0, 1, 2, 3, 4
 EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfield", "wolf_propagate_adjoint",
             "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
-            "wolf_set_plan", "wolf_get_plan", "wolf_autotune"]
+            "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
+            "wolf_fit_work_bytes"]
 
 
 class WolfError(RuntimeError):
@@ -71,6 +72,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_get_plan": [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_int64)],
         "wolf_autotune": [i32, i32, vp, i32, pd, vp],
+        "wolf_diag_embed": [vp, i32, i32, vp, vp],
+        "wolf_fit_gradient": [vp, vp, i32, f64, f64, i32, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -83,6 +86,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wolf_last_error_message.argtypes = []
     lib.wolf_last_error_message.restype = ctypes.c_char_p
     lib.wolf_version.restype = i32
+    lib.wolf_fit_work_bytes.argtypes = [i32, i32]
+    lib.wolf_fit_work_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -277,3 +282,30 @@ def autotune(n: int, dtype: torch.dtype = torch.complex64, reps: int = 3, work: 
     best = ctypes.c_double(0.0)
     _check(load().wolf_autotune(n, _code(dtype), _ptr(work), reps, ctypes.byref(best), _stream()), "wolf_autotune")
     return get_plan(n, dtype), best.value
+
+
+def diag_embed(g: torch.Tensor, dtype: torch.dtype) -> torch.Tensor:
+    """out[p1; p2] = g[p1] delta(p1, p2): the gradient with respect to W of a loss of S = Re diag(W)."""
+    n = g.shape[0]
+    if g.shape != (n, n) or g.dtype != _real(dtype) or not g.is_cuda or not g.is_contiguous():
+        raise ValueError("g must be a contiguous CUDA (N, N) tensor of the matching real dtype")
+    out = torch.empty((n, n, n, n), dtype=dtype, device=g.device)
+    _check(load().wolf_diag_embed(_ptr(g), n, _code(dtype), _ptr(out), _stream()), "wolf_diag_embed")
+    return out
+
+
+def fit_gradient(ga: torch.Tensor, imap: torch.Tensor, pitch: float, sigma_g: float):
+    """(dL/dI, dL/dsigma_g) of the custom-map source from G_A = dL/dW_A (see include/wolf.h)."""
+    lib = load()
+    n = _csd(ga, "ga")
+    if imap.shape != (n, n) or imap.dtype != torch.float32 or not imap.is_cuda or not imap.is_contiguous():
+        raise ValueError("imap must be a contiguous CUDA float32 (N, N) tensor")
+    nbytes = lib.wolf_fit_work_bytes(n, _code(ga.dtype))
+    if nbytes < 0:
+        raise WolfError(EUNSUPPORTED, "wolf_fit_gradient", f"N={n} unsupported")
+    work = torch.empty((nbytes,), dtype=torch.uint8, device=ga.device)
+    d_imap = torch.empty((n, n), dtype=torch.float32, device=ga.device)
+    d_sigma = torch.empty((1,), dtype=torch.float64, device=ga.device)
+    _check(lib.wolf_fit_gradient(_ptr(ga), _ptr(imap), n, pitch, sigma_g, _code(ga.dtype), _ptr(work), _ptr(d_imap),
+                                 _ptr(d_sigma), _stream()), "wolf_fit_gradient")
+    return d_imap, d_sigma

@@ -133,6 +133,13 @@ wolf::OperatorTables make_op(int32_t n, double pitch, double lam, double z, bool
   return op;
 }
 
+struct BatchGraph {
+  std::vector<double> key;
+  hipGraphExec_t exec;
+};
+std::mutex g_batch_mu;
+std::vector<BatchGraph> g_batch_graphs;  // recorded batch graphs (most recent last, at most 8)
+
 std::mutex g_plan_mu;
 std::map<std::pair<int, int>, wolf::Plan> g_plans;  // (n, dtype) -> plan chosen by wolf_set_plan / autotune
 
@@ -361,9 +368,135 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
                                           const double* wavelength_m, const double* z_m, const double* weight,
                                           int32_t farfield, int32_t kind, int32_t dtype, int32_t ip, int32_t jp,
                                           double s_floor_rel, void* work, void* s_out, void* mu_out, void* stream) {
-  (void)w_src; (void)n; (void)pitch_m; (void)n_pairs; (void)wavelength_m; (void)z_m; (void)weight; (void)farfield;
-  (void)kind; (void)dtype; (void)ip; (void)jp; (void)s_floor_rel; (void)work; (void)s_out; (void)mu_out; (void)stream;
-  return fail(WOLF_EUNSUPPORTED, "wolf_propagate_batch: not built yet");
+  const char* who = "wolf_propagate_batch";
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d unsupported", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  if (!pos_finite(pitch_m)) return fail(WOLF_EINVAL, "%s: pitch must be finite and > 0", who);
+  if (n_pairs < 1 || n_pairs > 4096) return fail(WOLF_EINVAL, "%s: n_pairs must be in [1, 4096]", who);
+  if (!wavelength_m || !z_m || !weight) return fail(WOLF_EINVAL, "%s: null parameter array", who);
+  for (int k = 0; k < n_pairs; ++k) {
+    if (!pos_finite(wavelength_m[k]) || !pos_finite(z_m[k]) || !std::isfinite(weight[k]) || weight[k] < 0)
+      return fail(WOLF_EINVAL, "%s: pair %d needs lambda > 0, z > 0, weight >= 0", who, k);
+  }
+  if (farfield != 0 && farfield != 1) return fail(WOLF_EINVAL, "%s: farfield must be 0 or 1", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind", who);
+  if (ip < 0 || ip >= n || jp < 0 || jp >= n) return fail(WOLF_EINVAL, "%s: (ip, jp) out of range", who);
+  if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "%s: s_floor_rel must be >= 0", who);
+  const size_t eb = elem_bytes(dtype), big = n4(n) * eb, nn = (size_t)n * n;
+  wolf_status s;
+  if ((s = check_buf(w_src, big, "w_src")) != WOLF_OK) return s;
+  if ((s = check_buf(work, big, "work")) != WOLF_OK) return s;
+  if ((s = check_buf(s_out, (size_t)n_pairs * nn * real_bytes(dtype), "s_out")) != WOLF_OK) return s;
+  if ((s = check_buf(mu_out, (size_t)n_pairs * nn * eb, "mu_out")) != WOLF_OK) return s;
+  if (w_src == work || partial_overlap(w_src, work, big)) return fail(WOLF_EINVAL, "%s: work overlaps w_src", who);
+  void* scratch = nullptr;
+  if ((s = device_scratch(&scratch)) != WOLF_OK) return s;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(WOLF_EDEVICE, "%s: hipGetDevice failed", who);
+  const wolf::Plan plan = plan_for(n, dtype);
+
+  // Key of the recorded graph: every argument that a kernel sees.
+  std::vector<double> key = {(double)dev, (double)n, pitch_m, (double)n_pairs, (double)farfield, (double)kind,
+                             (double)dtype, (double)ip, (double)jp, s_floor_rel,
+                             (double)(uintptr_t)w_src, (double)(uintptr_t)work, (double)(uintptr_t)s_out,
+                             (double)(uintptr_t)mu_out, (double)(uintptr_t)scratch, (double)plan.fused_slab,
+                             (double)plan.slab_chunk, (double)plan.col_chunk};
+  for (int k = 0; k < n_pairs; ++k) {
+    key.push_back(wavelength_m[k]);
+    key.push_back(z_m[k]);
+    key.push_back(weight[k]);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchGraph* hit = nullptr;
+  for (auto& g : g_batch_graphs)
+    if (g.key == key) hit = &g;
+  if (hit == nullptr) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(WOLF_EINVAL, "%s: the first call for a shape records its own graph; call it once outside capture",
+                  who);
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(WOLF_EDEVICE, "%s: cannot create the capture stream", who);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < n_pairs && e == hipSuccess; ++k) {
+      wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m[k], z_m[k], farfield == 1, kind, false);
+      op.scale *= weight[k];
+      if (dtype == WOLF_C64) {
+        e = wolf::launch_operator<float2>(n, (const float2*)w_src, (float2*)work, op, plan, cap);
+        if (e == hipSuccess) e = wolf::launch_spectral_density<float2>(n, (const float2*)work, (float*)s_out + k * nn, cap);
+        if (e == hipSuccess)
+          e = wolf::launch_coherence<float2>(n, (const float2*)work, ip, jp, s_floor_rel, (float2*)mu_out + k * nn,
+                                             scratch, cap);
+      } else {
+        e = wolf::launch_operator<double2>(n, (const double2*)w_src, (double2*)work, op, plan, cap);
+        if (e == hipSuccess)
+          e = wolf::launch_spectral_density<double2>(n, (const double2*)work, (double*)s_out + k * nn, cap);
+        if (e == hipSuccess)
+          e = wolf::launch_coherence<double2>(n, (const double2*)work, ip, jp, s_floor_rel, (double2*)mu_out + k * nn,
+                                              scratch, cap);
+      }
+    }
+    const hipError_t e_end = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = e_end;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(WOLF_EDEVICE, "%s: graph capture failed: %s", who, hipGetErrorString(e));
+    }
+    if (g_batch_graphs.size() >= 8) {
+      hipGraphExecDestroy(g_batch_graphs.front().exec);
+      g_batch_graphs.erase(g_batch_graphs.begin());
+    }
+    g_batch_graphs.push_back(BatchGraph{key, exec});
+    hit = &g_batch_graphs.back();
+  }
+  return launched(hipGraphLaunch(hit->exec, st), who);
+}
+
+WOLF_API wolf_status wolf_diag_embed(const void* g, int32_t n, int32_t dtype, void* out, void* stream) {
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_diag_embed: N=%d unsupported", n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_diag_embed: bad dtype");
+  wolf_status s;
+  if ((s = check_buf(g, (size_t)n * n * real_bytes(dtype), "g")) != WOLF_OK) return s;
+  if ((s = check_buf(out, n4(n) * elem_bytes(dtype), "out")) != WOLF_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WOLF_C64 ? wolf::launch_diag_embed<float2>(n, (const float*)g, (float2*)out, st)
+                                   : wolf::launch_diag_embed<double2>(n, (const double*)g, (double2*)out, st);
+  return launched(e, "wolf_diag_embed");
+}
+
+WOLF_API int64_t wolf_fit_work_bytes(int32_t n, int32_t dtype) {
+  if (!supported_n(n) || n > 128 || (dtype != WOLF_C64 && dtype != WOLF_C128)) return -1;
+  return (int64_t)wolf::fit_work_bytes(n, (int)real_bytes(dtype));
+}
+
+WOLF_API wolf_status wolf_fit_gradient(const void* ga, const float* imap, int32_t n, double pitch_m, double sigma_g_m,
+                                       int32_t dtype, void* work, float* d_imap, double* d_sigma, void* stream) {
+  const char* who = "wolf_fit_gradient";
+  if (!supported_n(n) || n > 128) return fail(WOLF_EUNSUPPORTED, "%s: N=%d unsupported (N <= 128)", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  if (!pos_finite(pitch_m) || !pos_finite(sigma_g_m)) return fail(WOLF_EINVAL, "%s: pitch and sigma_g must be > 0", who);
+  wolf_status s;
+  if ((s = check_buf(ga, n4(n) * elem_bytes(dtype), "ga")) != WOLF_OK) return s;
+  if ((s = check_buf(imap, (size_t)n * n * 4, "imap")) != WOLF_OK) return s;
+  if ((s = check_buf(work, wolf::fit_work_bytes(n, (int)real_bytes(dtype)), "work")) != WOLF_OK) return s;
+  if ((s = check_buf(d_imap, (size_t)n * n * 4, "d_imap")) != WOLF_OK) return s;
+  if ((s = check_buf(d_sigma, 8, "d_sigma")) != WOLF_OK) return s;
+  const double inv2g2_px = pitch_m * pitch_m / (2.0 * sigma_g_m * sigma_g_m);
+  const double sg_scale = pitch_m * pitch_m / (sigma_g_m * sigma_g_m * sigma_g_m);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WOLF_C64
+                     ? wolf::launch_fit_gradient<float2>(n, (const float2*)ga, imap, inv2g2_px, sg_scale, work, d_imap,
+                                                         d_sigma, st)
+                     : wolf::launch_fit_gradient<double2>(n, (const double2*)ga, imap, inv2g2_px, sg_scale, work,
+                                                          d_imap, d_sigma, st);
+  return launched(e, who);
 }
 
 WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab, int64_t slab_chunk,

@@ -72,4 +72,13 @@ hipError_t launch_coherence(int n, const T* w, int ip, int jp, double floor_rel,
 template <class T>
 hipError_t launch_chirp_table(int n, const Chirp& ch, T* out, hipStream_t st);
 
+// Fit gradients (wolf_fit.hip).
+template <class T>
+hipError_t launch_diag_embed(int n, const typename real_of<T>::type* g, T* out, hipStream_t st);
+template <class T>
+hipError_t launch_fit_gradient(int n, const T* ga, const float* imap, double inv2g2_px, double sg_scale, void* work,
+                               float* d_imap, double* d_sigma, hipStream_t st);
+int fit_slabs_per_group(int n);
+size_t fit_work_bytes(int n, int real_bytes);
+
 }  // namespace wolf
