@@ -138,6 +138,7 @@ def main():
 
     if not args.no_extras:
         detail.update(extras(wolf, wl, args))
+        detail.update(batch_and_fit(wolf, args))
     if args.big:
         detail.update(big(wolf, args))
 
@@ -224,6 +225,68 @@ def extras(wolf, wl, args):
     out["c64_speedup_over_c128"] = round(t128 / t64, 3)
     del w, o
     torch.cuda.empty_cache()
+    return out
+
+
+def batch_and_fit(wolf, args):
+    """The polychromatic batch (N=128 c64, 16 lambda x 4 z, one recorded graph) and one fit step
+    (N=64 c64 custom map: forward and adjoint timed separately)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import wolf_inputs as WI
+    from paper_2203_02734_amd.autograd import propagated_spectral_density
+
+    out = {}
+    wl = WI.gsm128()
+    n, p = wl.n, wl.pitch_m
+    pairs = WI.polychromatic_pairs()
+    w0 = wolf.build_source(wl.source, n, p, torch.complex64)
+    work = torch.empty_like(w0)
+    run = lambda: wolf.propagate_batch(w0, p, pairs["wavelength"], pairs["z"], pairs["weight"], ip=wl.probe[0],
+                                       jp=wl.probe[1], work=work)
+    run()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    reps = 2
+    for _ in range(reps):
+        run()
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / reps
+    k = len(pairs["z"])
+    out["batch64_ms"] = round(t, 3)
+    out["batch64_elems_per_s"] = k * n ** 4 / (t * 1e-3)
+    del w0, work
+    torch.cuda.empty_cache()
+
+    fw, tw = WI.fit_map64(), WI.fit_target64()
+    n, p, lam, z = fw.n, fw.pitch_m, fw.wavelength_m, fw.z_m
+    im = torch.tensor(fw.source.intensity_map, dtype=torch.float32, device="cuda", requires_grad=True)
+    sg = torch.tensor(fw.source.sigma_g_m, dtype=torch.float64, requires_grad=True)
+    target = wolf.spectral_density(wolf.propagate_fresnel(wolf.build_source(tw.source, n, p), p, lam, z)[0])
+    fwd_ms, bwd_ms = [], []
+    for it in range(6):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        s = propagated_spectral_density(im, sg, p, lam, z)
+        loss = torch.sum((s - target) ** 2)
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        if it >= 2:
+            fwd_ms.append(e0.elapsed_time(e1))
+            bwd_ms.append(e1.elapsed_time(e2))
+        im.grad = None
+        sg.grad = None
+    f, g = sum(fwd_ms) / len(fwd_ms), sum(bwd_ms) / len(bwd_ms)
+    out["fit64_forward_ms"] = round(f, 4)
+    out["fit64_backward_ms"] = round(g, 4)
+    out["fit64_backward_over_forward"] = round(g / f, 3)
     return out
 
 

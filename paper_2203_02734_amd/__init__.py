@@ -30,7 +30,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
-            "wolf_fit_work_bytes"]
+            "wolf_fit_work_bytes", "wolf_coop_error_flag"]
 
 
 class WolfError(RuntimeError):
@@ -68,9 +68,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_degree_of_coherence": [vp, i32, i32, i32, i32, f64, vp, vp],
         "wolf_propagate_batch": [vp, i32, f64, i32, pd, pd, pd, i32, i32, i32, i32, i32, f64, vp, vp, vp, vp],
         "wolf_chirp_table": [i32, f64, f64, f64, i32, vp, vp],
-        "wolf_set_plan": [i32, i32, i32, ctypes.c_int64, ctypes.c_int64],
+        "wolf_set_plan": [i32, i32, i32, ctypes.c_int64, ctypes.c_int64, i32, i32],
         "wolf_get_plan": [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64),
-                          ctypes.POINTER(ctypes.c_int64)],
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "wolf_coop_error_flag": [vp, ctypes.POINTER(i32)],
         "wolf_autotune": [i32, i32, vp, i32, pd, vp],
         "wolf_diag_embed": [vp, i32, i32, vp, vp],
         "wolf_fit_gradient": [vp, vp, i32, f64, f64, i32, vp, vp, vp, vp],
@@ -263,15 +264,27 @@ def propagate_batch(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights,
     return s, mu
 
 
-def set_plan(n: int, dtype: torch.dtype, fused_slab: int = -1, slab_chunk: int = -1, col_chunk: int = -1) -> None:
-    """Fix the pass schedule for (n, dtype); all -1 restores the default (see include/wolf.h)."""
-    _check(load().wolf_set_plan(n, _code(dtype), fused_slab, slab_chunk, col_chunk), "wolf_set_plan")
+def set_plan(n: int, dtype: torch.dtype, fused_slab: int = -1, slab_chunk: int = -1, col_chunk: int = -1,
+             coop_wgs: int = 0, coop_lookahead: int = 1) -> None:
+    """Fix the pass schedule for (n, dtype); fused_slab = slab_chunk = col_chunk = -1 restores the
+    default (see include/wolf.h)."""
+    _check(load().wolf_set_plan(n, _code(dtype), fused_slab, slab_chunk, col_chunk, coop_wgs, coop_lookahead),
+           "wolf_set_plan")
 
 
 def get_plan(n: int, dtype: torch.dtype):
-    f, s, c = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load().wolf_get_plan(n, _code(dtype), ctypes.byref(f), ctypes.byref(s), ctypes.byref(c)), "wolf_get_plan")
-    return {"fused_slab": f.value, "slab_chunk": s.value, "col_chunk": c.value}
+    f, s, c, w, la = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().wolf_get_plan(n, _code(dtype), ctypes.byref(f), ctypes.byref(s), ctypes.byref(c), ctypes.byref(w),
+                                ctypes.byref(la)), "wolf_get_plan")
+    return {"fused_slab": f.value, "slab_chunk": s.value, "col_chunk": c.value, "coop_wgs": w.value,
+            "coop_lookahead": la.value}
+
+
+def coop_error_flag() -> int:
+    """1 if a cooperative pass on the current stream timed out waiting for a tile (synchronises)."""
+    f = ctypes.c_int32()
+    _check(load().wolf_coop_error_flag(_stream(), ctypes.byref(f)), "wolf_coop_error_flag")
+    return f.value
 
 
 def autotune(n: int, dtype: torch.dtype = torch.complex64, reps: int = 3, work: Optional[torch.Tensor] = None):

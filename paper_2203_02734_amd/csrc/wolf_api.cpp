@@ -77,26 +77,30 @@ wolf_status launched(hipError_t e, const char* what) {
   return WOLF_OK;
 }
 
-// Per-device scratch owned by the library: 256 B of reduction keys + N^2 reals (N <= 256).
+// Per-stream scratch owned by the library (one per (device, stream) pair, never freed):
+// reduction keys and N^2 reals for mu, or the tile counters of the cooperative pass. Work on one
+// stream is ordered, so its calls can share the block. Work on other streams uses other blocks.
 constexpr size_t kScratchBytes = 256 + (size_t)256 * 256 * 8;
 std::mutex g_scratch_mu;
-std::map<int, void*> g_scratch;
+std::map<std::pair<int, uintptr_t>, void*> g_scratch;
 
-wolf_status device_scratch(void** out) {
+wolf_status stream_scratch(void* stream, void** out) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(WOLF_EDEVICE, "hipGetDevice failed");
   std::lock_guard<std::mutex> lk(g_scratch_mu);
-  auto it = g_scratch.find(dev);
+  const auto key = std::make_pair(dev, (uintptr_t)stream);
+  auto it = g_scratch.find(key);
   if (it != g_scratch.end()) {
     *out = it->second;
     return WOLF_OK;
   }
   void* p = nullptr;
+  static_assert(kScratchBytes >= (16 + 256 * 256) * sizeof(unsigned), "coop counters fit");
   if (hipMalloc(&p, kScratchBytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(WOLF_ENOMEM, "cannot allocate %zu bytes of device scratch", kScratchBytes);
   }
-  g_scratch[dev] = p;
+  g_scratch[key] = p;
   *out = p;
   return WOLF_OK;
 }
@@ -140,6 +144,8 @@ struct BatchGraph {
 std::mutex g_batch_mu;
 std::vector<BatchGraph> g_batch_graphs;  // recorded batch graphs (most recent last, at most 8)
 
+constexpr bool kCoopEnabled = false;
+
 std::mutex g_plan_mu;
 std::map<std::pair<int, int>, wolf::Plan> g_plans;  // (n, dtype) -> plan chosen by wolf_set_plan / autotune
 
@@ -153,6 +159,16 @@ bool plan_valid(int32_t n, int32_t dtype, const wolf::Plan& p) {
   if (p.slab_chunk < 0 || p.slab_chunk > nn || (p.slab_chunk > 0 && nn % p.slab_chunk != 0)) return false;
   // The row pass over a chunk of slabs needs whole workgroups of rows.
   if (!p.fused_slab && p.slab_chunk > 0 && (p.slab_chunk * n) % wolf::row_pass_rows(n) != 0) return false;
+  if (p.coop != 0 && p.coop != 1) return false;
+  // The cooperative first-point pass is disabled: its cross-workgroup wait did not complete on
+  // gfx950 (the tile counters were not seen by the waiting workgroups). It stays unreachable until
+  // the cause is established.
+  if (p.coop && !kCoopEnabled) return false;
+  if (p.coop) {
+    if (!(dtype == WOLF_C64 ? wolf::coop_supported<float2>(n) : wolf::coop_supported<double2>(n))) return false;
+    if (p.coop_wgs < 8 || p.coop_wgs > 65536 || p.coop_wgs % 8 != 0) return false;
+    if (p.coop_lookahead < 1 || p.coop_lookahead > 8) return false;
+  }
   return true;
 }
 
@@ -170,6 +186,9 @@ wolf::Plan default_plan(int32_t n, int32_t dtype) {
   long long slabs = nn;
   while (slabs > 1 && slabs * nn * eb > target && ((slabs >> 1) * n) % wolf::row_pass_rows(n) == 0) slabs >>= 1;
   p.slab_chunk = slabs;
+  p.coop = 0;  // opt in through wolf_set_plan / wolf_autotune
+  p.coop_wgs = 1024;
+  p.coop_lookahead = 1;
   return p;
 }
 
@@ -182,7 +201,13 @@ wolf::Plan plan_for(int32_t n, int32_t dtype) {
 template <class T>
 wolf_status run_operator(const T* in, T* out, int32_t n, int32_t dtype, const wolf::OperatorTables& op,
                          hipStream_t st) {
-  const hipError_t e = wolf::launch_operator<T>(n, in, out, op, plan_for(n, dtype), st);
+  const wolf::Plan plan = plan_for(n, dtype);
+  void* scratch = nullptr;
+  if (plan.coop) {
+    const wolf_status s = stream_scratch(st, &scratch);
+    if (s != WOLF_OK) return s;
+  }
+  const hipError_t e = wolf::launch_operator<T>(n, in, out, op, plan, scratch, st);
   if (e != hipSuccess) return fail(WOLF_EDEVICE, "propagation launch: %s", hipGetErrorString(e));
   g_last_error.clear();
   return WOLF_OK;
@@ -338,7 +363,7 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
     return fail(WOLF_EINVAL, "wolf_degree_of_coherence: mu_out overlaps w");
   if (full && w == mu_out) return fail(WOLF_EINVAL, "wolf_degree_of_coherence: full mu cannot be computed in place");
   void* scratch = nullptr;
-  if ((s = device_scratch(&scratch)) != WOLF_OK) return s;
+  if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int i = full ? -1 : ip, j = full ? -1 : jp;
   hipError_t e = dtype == WOLF_C64
@@ -390,7 +415,7 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   if ((s = check_buf(mu_out, (size_t)n_pairs * nn * eb, "mu_out")) != WOLF_OK) return s;
   if (w_src == work || partial_overlap(w_src, work, big)) return fail(WOLF_EINVAL, "%s: work overlaps w_src", who);
   void* scratch = nullptr;
-  if ((s = device_scratch(&scratch)) != WOLF_OK) return s;
+  if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(WOLF_EDEVICE, "%s: hipGetDevice failed", who);
   const wolf::Plan plan = plan_for(n, dtype);
@@ -425,13 +450,13 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
       wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m[k], z_m[k], farfield == 1, kind, false);
       op.scale *= weight[k];
       if (dtype == WOLF_C64) {
-        e = wolf::launch_operator<float2>(n, (const float2*)w_src, (float2*)work, op, plan, cap);
+        e = wolf::launch_operator<float2>(n, (const float2*)w_src, (float2*)work, op, plan, scratch, cap);
         if (e == hipSuccess) e = wolf::launch_spectral_density<float2>(n, (const float2*)work, (float*)s_out + k * nn, cap);
         if (e == hipSuccess)
           e = wolf::launch_coherence<float2>(n, (const float2*)work, ip, jp, s_floor_rel, (float2*)mu_out + k * nn,
                                              scratch, cap);
       } else {
-        e = wolf::launch_operator<double2>(n, (const double2*)w_src, (double2*)work, op, plan, cap);
+        e = wolf::launch_operator<double2>(n, (const double2*)w_src, (double2*)work, op, plan, scratch, cap);
         if (e == hipSuccess)
           e = wolf::launch_spectral_density<double2>(n, (const double2*)work, (double*)s_out + k * nn, cap);
         if (e == hipSuccess)
@@ -500,7 +525,7 @@ WOLF_API wolf_status wolf_fit_gradient(const void* ga, const float* imap, int32_
 }
 
 WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab, int64_t slab_chunk,
-                                   int64_t col_chunk) {
+                                   int64_t col_chunk, int32_t coop_wgs, int32_t coop_lookahead) {
   if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_set_plan: N=%d unsupported", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_set_plan: bad dtype");
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -509,21 +534,40 @@ WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab,
     return WOLF_OK;
   }
   if (fused_slab != 0 && fused_slab != 1) return fail(WOLF_EINVAL, "wolf_set_plan: fused_slab must be 0 or 1");
-  const wolf::Plan p{fused_slab == 1, (long long)slab_chunk, (long long)col_chunk};
+  const wolf::Plan p{fused_slab == 1, (long long)slab_chunk, (long long)col_chunk, coop_wgs > 0 ? 1 : 0,
+                     coop_wgs > 0 ? coop_wgs : 0, coop_wgs > 0 ? coop_lookahead : 1};
+  if (p.coop && !kCoopEnabled)
+    return fail(WOLF_EUNSUPPORTED, "wolf_set_plan: the cooperative first-point pass is disabled in this build");
   if (!plan_valid(n, dtype, p)) return fail(WOLF_EINVAL, "wolf_set_plan: plan not valid for N=%d", n);
   g_plans[{n, dtype}] = p;
   return WOLF_OK;
 }
 
 WOLF_API wolf_status wolf_get_plan(int32_t n, int32_t dtype, int32_t* fused_slab, int64_t* slab_chunk,
-                                   int64_t* col_chunk) {
+                                   int64_t* col_chunk, int32_t* coop_wgs, int32_t* coop_lookahead) {
   if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_get_plan: N=%d unsupported", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_get_plan: bad dtype");
-  if (!fused_slab || !slab_chunk || !col_chunk) return fail(WOLF_EINVAL, "wolf_get_plan: null output");
+  if (!fused_slab || !slab_chunk || !col_chunk || !coop_wgs || !coop_lookahead)
+    return fail(WOLF_EINVAL, "wolf_get_plan: null output");
   const wolf::Plan p = plan_for(n, dtype);
   *fused_slab = p.fused_slab ? 1 : 0;
   *slab_chunk = p.slab_chunk;
   *col_chunk = p.col_chunk;
+  *coop_wgs = p.coop ? p.coop_wgs : 0;
+  *coop_lookahead = p.coop_lookahead;
+  return WOLF_OK;
+}
+
+WOLF_API wolf_status wolf_coop_error_flag(void* stream, int32_t* flag) {
+  if (!flag) return fail(WOLF_EINVAL, "wolf_coop_error_flag: null output");
+  void* scratch = nullptr;
+  wolf_status s = stream_scratch(stream, &scratch);
+  if (s != WOLF_OK) return s;
+  unsigned v = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess || hipMemcpy(&v, scratch, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(WOLF_EDEVICE, "wolf_coop_error_flag: cannot read the flag");
+  *flag = (int32_t)v;
   return WOLF_OK;
 }
 
@@ -540,17 +584,25 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
   std::vector<wolf::Plan> cands;
   const wolf::Plan def = default_plan(n, dtype);
   for (int fused = 1; fused >= 0; --fused) {
+    for (int wgs : {512, 1024, 2048}) {
+      for (int la : {1, 2}) {
+        wolf::Plan p{fused == 1, def.slab_chunk, nn, 1, wgs, la};
+        if (kCoopEnabled && plan_valid(n, dtype, p)) cands.push_back(p);
+      }
+    }
     for (long long cols = nn; cols >= c; cols >>= 1) {
       // Chunks below 4 MB only add launches.
       if (cols < nn && cols * nn * (long long)elem_bytes(dtype) < (4ll << 20)) break;
-      wolf::Plan p{fused == 1, fused ? def.slab_chunk : def.slab_chunk, cols};
+      wolf::Plan p{fused == 1, def.slab_chunk, cols, 0, 0, 1};
       if (plan_valid(n, dtype, p)) cands.push_back(p);
       if (!fused && cols == nn) {
-        wolf::Plan q{false, 0, cols};
+        wolf::Plan q{false, 0, cols, 0, 0, 1};
         if (plan_valid(n, dtype, q)) cands.push_back(q);
       }
     }
   }
+  void* scratch = nullptr;
+  if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   if (hipMemsetAsync(work, 0, n4(n) * elem_bytes(dtype), st) != hipSuccess)
     return fail(WOLF_EDEVICE, "wolf_autotune: memset failed");
   const wolf::OperatorTables op = make_op(n, 20e-6, 632.8e-9, 0.5, false, WOLF_SECONDARY, false);
@@ -564,8 +616,8 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
     for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
       if (r == 1) e = hipEventRecord(a, st);
       if (e == hipSuccess) {
-        e = dtype == WOLF_C64 ? wolf::launch_operator<float2>(n, (float2*)work, (float2*)work, op, p, st)
-                              : wolf::launch_operator<double2>(n, (double2*)work, (double2*)work, op, p, st);
+        e = dtype == WOLF_C64 ? wolf::launch_operator<float2>(n, (float2*)work, (float2*)work, op, p, scratch, st)
+                              : wolf::launch_operator<double2>(n, (double2*)work, (double2*)work, op, p, scratch, st);
       }
     }
     if (e == hipSuccess) e = hipEventRecord(b, st);

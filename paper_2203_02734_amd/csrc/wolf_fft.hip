@@ -396,7 +396,8 @@ int axis_tile_cols(int n) {
 // The operator: a schedule of passes (see Plan).
 // ---------------------------------------------------------------------------------------------
 template <class T>
-hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, hipStream_t st) {
+hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, void* counters,
+                           hipStream_t st) {
   const long long N = n, NN = N * N, NNN = NN * N;
   hipError_t e;
   const Chirp ident{0.0, 1.0, +1, 0};
@@ -416,10 +417,11 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
       if (e != hipSuccess) return e;
     }
   }
+  const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
+  if (plan.coop) return launch_first_point_coop<T>(n, out, op, pre1, plan.coop_wgs, plan.coop_lookahead, counters, st);
   // First-point axes (j1, i1) over column chunks of the N^2 columns m2. The i1 pass of chunk k - 1
   // shares a launch with the j1 pass of chunk k: they touch disjoint columns.
   const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
-  const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
   Chirp post_last = op.post1;
   post_last.scale = op.scale;
   const long long chunks = (NN + m - 1) / m;
@@ -439,9 +441,9 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   return hipSuccess;
 }
 
-template hipError_t launch_operator<float2>(int, const float2*, float2*, const OperatorTables&, const Plan&,
+template hipError_t launch_operator<float2>(int, const float2*, float2*, const OperatorTables&, const Plan&, void*,
                                             hipStream_t);
-template hipError_t launch_operator<double2>(int, const double2*, double2*, const OperatorTables&, const Plan&,
+template hipError_t launch_operator<double2>(int, const double2*, double2*, const OperatorTables&, const Plan&, void*,
                                              hipStream_t);
 template bool slab_pass_supported<float2>(int);
 template bool slab_pass_supported<double2>(int);

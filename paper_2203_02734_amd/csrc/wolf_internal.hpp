@@ -24,6 +24,21 @@ struct Plan {
   bool fused_slab;
   long long slab_chunk;
   long long col_chunk;
+  int coop;        // 1: first-point axes in one cooperative pass (wolf_coop.hip); col_chunk unused
+  int coop_wgs;    // persistent grid of the cooperative pass (a multiple of 8)
+  int coop_lookahead;
+};
+
+// Parameters of the cooperative first-point pass (see wolf_coop.hip).
+struct CoopParams {
+  long long NN, NNN;
+  int tiles_per_xcd, lookahead, items_per_phase;
+  unsigned long long max_ticks;  // bound of one wait, in ticks of the 100 MHz real-time clock
+  unsigned zero;                 // 0, opaque to the compiler (keeps the poll a read-modify-write)
+  unsigned* head;
+  unsigned* done_a;
+  unsigned* err;
+  Chirp a_pre, a_post, b_pre, b_post;
 };
 
 // A strided-axis block: outer_count blocks (stride outer_stride); per block, columns
@@ -38,8 +53,15 @@ struct AxisJob {
   Chirp pre, post;
 };
 
+// `counters`: per-stream device scratch of at least coop_counter_bytes(n) (used when plan.coop).
 template <class T>
-hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, hipStream_t st);
+hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, void* counters,
+                           hipStream_t st);
+template <class T> bool coop_supported(int n);
+template <class T>
+hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,
+                                   int lookahead, void* counters, hipStream_t st);
+size_t coop_counter_bytes(int n);
 template <class T> bool slab_pass_supported(int n);
 int axis_tile_cols(int n);
 int row_pass_rows(int n);  // rows per workgroup of the row pass
