@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the c128 / far-field / adjoint / copy detail")
     ap.add_argument("--big", action="store_true", help="also time the N=256 complex64 workload (34 GB)")
+    ap.add_argument("--plan", default="auto",
+                    help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or 'fused,slab_chunk,col_chunk'")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="for rocprofv3 --pmc: one 2 GiB copy (counter calibration) then one propagation; no JSON")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -97,8 +99,13 @@ def main():
 
     w = torch.empty((n, n, n, n), dtype=torch.complex64, device="cuda")
     wb = torch.empty_like(w)
-    # Pick the pass schedule with the library's autotuner (untimed, part of the set-up).
-    plan, tuned_ms = wolf.autotune(n, torch.complex64, reps=3, work=wb)
+    # Pass schedule: the library's autotuner (untimed, part of the set-up), or a given one.
+    if args.plan == "auto":
+        plan, _ = wolf.autotune(n, torch.complex64, reps=3, work=wb)
+    elif args.plan != "default":
+        f, sc, cc = (int(x) for x in args.plan.split(","))
+        wolf.set_plan(n, torch.complex64, f, sc, cc)
+    plan = wolf.get_plan(n, torch.complex64)
     if args.pmc_sample:
         wolf.build_source(wl.source, n, p, out=w)
         wb.copy_(w)
