@@ -138,6 +138,18 @@ WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32
                                             int32_t dtype, void* stream);
 
 /*
+ * wolf_propagate_adjoint_diag -- wolf_propagate_adjoint applied to diag(g), without reading an N^4
+ * input: g_in = P^H(G_B) with G_B[x1; x2] = g(x1) delta(x1, x2). This is the gradient with respect
+ * to W_A of a loss that depends on the propagated CSD only through S_B = Re diag W_B
+ * (Algorithm 4), given g = dL/dS_B.
+ *   g_diag   device, N*N real (float32 for WOLF_C64, float64 for WOLF_C128), on the output grid.
+ *   g_in     device, N^4 complex, written in full.
+ */
+WOLF_API wolf_status wolf_propagate_adjoint_diag(const void* g_diag, void* g_in, int32_t n, double pitch_m,
+                                                 double wavelength_m, double z_m, int32_t farfield, int32_t kind,
+                                                 int32_t dtype, void* stream);
+
+/*
  * wolf_spectral_density -- S[i][j] = Re W[i][j; i][j] (Sec. 3.5, Algorithm 4, eq. defS).
  *   s_out   device, N*N real (float32 for WOLF_C64, float64 for WOLF_C128).
  */

@@ -30,7 +30,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
-            "wolf_fit_work_bytes", "wolf_coop_error_flag"]
+            "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag"]
 
 
 class WolfError(RuntimeError):
@@ -64,6 +64,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_propagate_fresnel": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_farfield": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_adjoint": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
+        "wolf_propagate_adjoint_diag": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_spectral_density": [vp, i32, i32, vp, vp],
         "wolf_degree_of_coherence": [vp, i32, i32, i32, i32, f64, vp, vp],
         "wolf_propagate_batch": [vp, i32, f64, i32, pd, pd, pd, i32, i32, i32, i32, i32, f64, vp, vp, vp, vp],
@@ -206,6 +207,23 @@ def propagate_adjoint(g: torch.Tensor, pitch: float, wavelength: float, z: float
         _csd(out, "out")
     _check(lib.wolf_propagate_adjoint(_ptr(g), _ptr(out), n, pitch, wavelength, z, int(bool(farfield)), kind,
                                       _code(g.dtype), _stream()), "wolf_propagate_adjoint")
+    return out
+
+
+def propagate_adjoint_diag(g: torch.Tensor, pitch: float, wavelength: float, z: float, farfield: bool = False,
+                           kind: int = SECONDARY, dtype: torch.dtype = torch.complex64,
+                           out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Adjoint propagation of diag(g) for a real (N, N) g (the gradient of a loss of S_B)."""
+    lib = load()
+    n = g.shape[0]
+    if g.shape != (n, n) or g.dtype != _real(dtype) or not g.is_cuda or not g.is_contiguous():
+        raise ValueError("g must be a contiguous CUDA (N, N) tensor of the matching real dtype")
+    if out is None:
+        out = torch.empty((n, n, n, n), dtype=dtype, device=g.device)
+    else:
+        _csd(out, "out")
+    _check(lib.wolf_propagate_adjoint_diag(_ptr(g), _ptr(out), n, pitch, wavelength, z, int(bool(farfield)), kind,
+                                           _code(dtype), _stream()), "wolf_propagate_adjoint_diag")
     return out
 
 

@@ -2,7 +2,7 @@
 
 Forward:  I, sigma_g -> W_A (custom map with a Gaussian degree of coherence; eq. W_def)
           -> W_B (Fresnel or far-field propagation; eqs. W_fresnel, W_farfield) -> S_B = Re diag W_B.
-Backward: dL/dS_B -> diag -> adjoint propagation -> dL/dI and dL/dsigma_g.
+Backward: dL/dS_B -> adjoint propagation of diag(dL/dS_B) -> dL/dI and dL/dsigma_g.
 Every step runs in libwolf kernels; this module only orders the calls.
 """
 from __future__ import annotations
@@ -12,7 +12,7 @@ from types import SimpleNamespace
 
 import torch
 
-from . import (GEO_NONE, MODEL_MAP, build_source, diag_embed, fit_gradient, propagate, propagate_adjoint,
+from . import (GEO_NONE, MODEL_MAP, build_source, fit_gradient, propagate, propagate_adjoint_diag,
                spectral_density)
 
 
@@ -46,8 +46,8 @@ class PropagatedSpectralDensity(torch.autograd.Function):
         (imap,) = ctx.saved_tensors
         pitch, wavelength, z, farfield, dtype, sg, sg_dev, sg_dtype = ctx.cfg
         real = torch.float32 if dtype == torch.complex64 else torch.float64
-        g = diag_embed(grad_s.detach().to(real).contiguous(), dtype)
-        propagate_adjoint(g, pitch, wavelength, z, farfield, out=g)
+        g = propagate_adjoint_diag(grad_s.detach().to(real).contiguous(), pitch, wavelength, z, farfield,
+                                   dtype=dtype)
         d_imap, d_sigma = fit_gradient(g, imap, pitch, sg)
         return d_imap, d_sigma.reshape(()).to(device=sg_dev, dtype=sg_dtype), None, None, None, None, None
 

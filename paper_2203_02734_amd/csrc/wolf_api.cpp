@@ -64,6 +64,13 @@ wolf_status check_buf(const void* p, size_t bytes, const char* what) {
   return WOLF_OK;
 }
 
+// [a, a + na) and [b, b + nb) share a byte.
+bool intervals_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
 bool partial_overlap(const void* a, const void* b, size_t bytes) {
   if (a == b) return false;
   const char* x = static_cast<const char*>(a);
@@ -359,9 +366,8 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
   if ((s = check_buf(w, n4(n) * eb, "w")) != WOLF_OK) return s;
   const size_t out_bytes = full ? n4(n) * eb : (size_t)n * n * eb;
   if ((s = check_buf(mu_out, out_bytes, "mu_out")) != WOLF_OK) return s;
-  if (partial_overlap(w, mu_out, full ? n4(n) * eb : 1) || (!full && w == mu_out))
-    return fail(WOLF_EINVAL, "wolf_degree_of_coherence: mu_out overlaps w");
-  if (full && w == mu_out) return fail(WOLF_EINVAL, "wolf_degree_of_coherence: full mu cannot be computed in place");
+  if (intervals_overlap(w, n4(n) * eb, mu_out, out_bytes))
+    return fail(WOLF_EINVAL, "wolf_degree_of_coherence: mu_out overlaps w (mu is never computed in place)");
   void* scratch = nullptr;
   if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -413,7 +419,11 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   if ((s = check_buf(work, big, "work")) != WOLF_OK) return s;
   if ((s = check_buf(s_out, (size_t)n_pairs * nn * real_bytes(dtype), "s_out")) != WOLF_OK) return s;
   if ((s = check_buf(mu_out, (size_t)n_pairs * nn * eb, "mu_out")) != WOLF_OK) return s;
-  if (w_src == work || partial_overlap(w_src, work, big)) return fail(WOLF_EINVAL, "%s: work overlaps w_src", who);
+  const size_t s_bytes = (size_t)n_pairs * nn * real_bytes(dtype), mu_bytes = (size_t)n_pairs * nn * eb;
+  if (intervals_overlap(w_src, big, work, big) || intervals_overlap(s_out, s_bytes, mu_out, mu_bytes) ||
+      intervals_overlap(s_out, s_bytes, w_src, big) || intervals_overlap(s_out, s_bytes, work, big) ||
+      intervals_overlap(mu_out, mu_bytes, w_src, big) || intervals_overlap(mu_out, mu_bytes, work, big))
+    return fail(WOLF_EINVAL, "%s: buffers overlap", who);
   void* scratch = nullptr;
   if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   int dev = -1;
@@ -482,6 +492,33 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
     hit = &g_batch_graphs.back();
   }
   return launched(hipGraphLaunch(hit->exec, st), who);
+}
+
+WOLF_API wolf_status wolf_propagate_adjoint_diag(const void* g_diag, void* g_in, int32_t n, double pitch_m,
+                                                 double wavelength_m, double z_m, int32_t farfield, int32_t kind,
+                                                 int32_t dtype, void* stream) {
+  const char* who = "wolf_propagate_adjoint_diag";
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d unsupported", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  if (!pos_finite(pitch_m) || !pos_finite(wavelength_m) || !pos_finite(z_m))
+    return fail(WOLF_EINVAL, "%s: pitch, wavelength and z must be finite and > 0", who);
+  if (farfield != 0 && farfield != 1) return fail(WOLF_EINVAL, "%s: farfield must be 0 or 1", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind", who);
+  wolf_status s;
+  if ((s = check_buf(g_diag, (size_t)n * n * real_bytes(dtype), "g_diag")) != WOLF_OK) return s;
+  if ((s = check_buf(g_in, n4(n) * elem_bytes(dtype), "g_in")) != WOLF_OK) return s;
+  if (intervals_overlap(g_diag, (size_t)n * n * real_bytes(dtype), g_in, n4(n) * elem_bytes(dtype)))
+    return fail(WOLF_EINVAL, "%s: g_in overlaps g_diag", who);
+  const wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m, z_m, farfield == 1, kind, true);
+  const wolf::Plan plan = plan_for(n, dtype);
+  void* scratch = nullptr;
+  if (plan.coop && (s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WOLF_C64
+                     ? wolf::launch_operator_diag<float2>(n, (const float*)g_diag, (float2*)g_in, op, plan, scratch, st)
+                     : wolf::launch_operator_diag<double2>(n, (const double*)g_diag, (double2*)g_in, op, plan, scratch,
+                                                           st);
+  return launched(e, who);
 }
 
 WOLF_API wolf_status wolf_diag_embed(const void* g, int32_t n, int32_t dtype, void* out, void* stream) {

@@ -441,6 +441,80 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Operator applied to a diagonal input diag(g) (e.g. the gradient of a loss of S = Re diag W).
+// The second-point 2D DFT of row m1 = (a, b) of diag(g) is a plane wave:
+//   Y[m1; (p, q)] = g(m1) pre1[a] pre1[b] pre2[a] pre2[b] w^{a p} w^{b q} post2[p] post2[q],
+// with w = e^{sign2 2 pi i / N}. A write-only kernel makes it without reading an N^4 input.
+// ---------------------------------------------------------------------------------------------
+template <class T, int SIGN>
+__global__ __launch_bounds__(256) void k_slab_from_diag(const typename real_of<T>::type* __restrict__ g, T* dst, int n,
+                                                        Chirp pre1, Chirp pre2, Chirp post2) {
+  __shared__ T tp[256], tw[256];
+  __shared__ T sc[1];
+  const long long m1 = blockIdx.x;
+  const int a = (int)(m1 / n), b = (int)(m1 % n);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    tp[i] = chirp_entry<T>(post2, i, n);
+    tw[i] = twiddle_entry<T, SIGN>(i, n);
+  }
+  if (threadIdx.x == 0) {
+    using R = typename real_of<T>::type;
+    const T f = cmul(cmul(chirp_entry<T>(pre1, a, n), chirp_entry<T>(pre1, b, n)),
+                     cmul(chirp_entry<T>(pre2, a, n), chirp_entry<T>(pre2, b, n)));
+    sc[0] = cscale(f, (R)g[m1]);
+  }
+  __syncthreads();
+  const T s = sc[0];
+  const long long nn = (long long)n * n;
+  T* out = dst + m1 * nn;
+  for (long long e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int p = (int)(e / n), q = (int)(e % n);
+    const T row = cmul(tw[(a * p) & (n - 1)], tp[p]);
+    const T col = cmul(tw[(b * q) & (n - 1)], tp[q]);
+    out[e] = cmul(s, cmul(row, col));
+  }
+}
+
+template <class T>
+hipError_t launch_operator_diag(int n, const typename real_of<T>::type* g, T* out, const OperatorTables& op,
+                                const Plan& plan, void* counters, hipStream_t st) {
+  const long long N = n, NN = N * N, NNN = NN * N;
+  const Chirp ident{0.0, 1.0, +1, 0};
+  if (op.sign2 < 0)
+    hipLaunchKernelGGL((k_slab_from_diag<T, -1>), dim3((unsigned)NN), dim3(256), 0, st, g, out, n, op.pre1, op.pre2,
+                       op.post2);
+  else
+    hipLaunchKernelGGL((k_slab_from_diag<T, +1>), dim3((unsigned)NN), dim3(256), 0, st, g, out, n, op.pre1, op.pre2,
+                       op.post2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (plan.coop) return launch_first_point_coop<T>(n, out, op, ident, plan.coop_wgs, plan.coop_lookahead, counters, st);
+  const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
+  Chirp post_last = op.post1;
+  post_last.scale = op.scale;
+  const long long chunks = (NN + m - 1) / m;
+  for (long long k = 0; k <= chunks; ++k) {
+    const bool has_j = k < chunks, has_i = k > 0;
+    const long long cj = k * m, ci = (k - 1) * m;
+    const AxisRange aj{N, NNN, NN, cj, has_j ? ((cj + m <= NN) ? m : NN - cj) : 0};
+    const AxisRange ai{N, NN, NNN, ci, has_i ? ((ci + m <= NN) ? m : NN - ci) : 0};
+    if (has_j && has_i)
+      e = launch_axis_range<T>(n, out, out, op.sign1, aj, ident, op.post1, &ai, ident, post_last, st);
+    else if (has_j)
+      e = launch_axis_range<T>(n, out, out, op.sign1, aj, ident, op.post1, nullptr, ident, ident, st);
+    else
+      e = launch_axis_range<T>(n, out, out, op.sign1, ai, ident, post_last, nullptr, ident, ident, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_operator_diag<float2>(int, const float*, float2*, const OperatorTables&, const Plan&, void*,
+                                                 hipStream_t);
+template hipError_t launch_operator_diag<double2>(int, const double*, double2*, const OperatorTables&, const Plan&,
+                                                  void*, hipStream_t);
+
 template hipError_t launch_operator<float2>(int, const float2*, float2*, const OperatorTables&, const Plan&, void*,
                                             hipStream_t);
 template hipError_t launch_operator<double2>(int, const double2*, double2*, const OperatorTables&, const Plan&, void*,

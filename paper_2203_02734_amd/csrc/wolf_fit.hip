@@ -144,8 +144,8 @@ hipError_t launch_fit_gradient(int n, const T* ga, const float* imap, double inv
 
 int fit_slabs_per_group(int n) {
   const long long nn = (long long)n * n;
-  // About 64 groups of slabs: enough workgroups, and a small partial buffer (groups x N^2 reals).
-  long long s = nn / 64;
+  // About 512 groups of slabs: two workgroups per CU, and a partial buffer of 512 x N^2 reals.
+  long long s = nn / 512;
   return (int)(s < 1 ? 1 : s);
 }
 

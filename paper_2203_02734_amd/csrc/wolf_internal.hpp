@@ -57,6 +57,10 @@ struct AxisJob {
 template <class T>
 hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, void* counters,
                            hipStream_t st);
+// The operator applied to diag(g), g an N*N real array (no N^4 input is read).
+template <class T>
+hipError_t launch_operator_diag(int n, const typename real_of<T>::type* g, T* out, const OperatorTables& op,
+                                const Plan& plan, void* counters, hipStream_t st);
 template <class T> bool coop_supported(int n);
 template <class T>
 hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,

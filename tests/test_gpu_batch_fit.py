@@ -174,3 +174,23 @@ def test_fit_step_full_size(gpu_lib):
     from paper_2203_02734_amd.autograd import propagated_spectral_density
     s2 = propagated_spectral_density(im2.contiguous(), sgt.detach(), p, lam, z)
     assert torch.sum((s2.double() - tt) ** 2).item() < loss.item()
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("n", [16, 64])
+def test_adjoint_diag_matches_embed_and_oracle(gpu_lib, farfield, dtype, n):
+    """P^H(diag g) from the write-only generated first pass equals diag_embed + adjoint, and the oracle."""
+    p, lam, z = 20e-6, WI.LAMBDA_HENE, 0.3
+    real = torch.float32 if dtype == torch.complex64 else torch.float64
+    g = torch.from_numpy(WI.rng(11).standard_normal((n, n))).to(real).cuda()
+    a = gpu_lib.propagate_adjoint_diag(g, p, lam, z, farfield, dtype=dtype)
+    b = gpu_lib.propagate_adjoint(gpu_lib.diag_embed(g, dtype), p, lam, z, farfield)
+    gh = g.double().cpu().numpy()
+    gb = np.zeros((n, n, n, n), dtype=np.complex128)
+    for i in range(n):
+        for j in range(n):
+            gb[i, j, i, j] = gh[i, j]
+    ref = O.propagate_adjoint(gb, n, p, lam, z, farfield)
+    assert rel(host(a), ref) < TOL[dtype]
+    assert rel(host(a), host(b)) < TOL[dtype]

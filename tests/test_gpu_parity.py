@@ -327,3 +327,26 @@ def test_invalid_plan_rejected(gpu_lib):
         gpu_lib.set_plan(32, torch.complex64, 0, 1, 0)        # one slab is less than a row-pass workgroup
     with pytest.raises(gpu_lib.WolfError):
         gpu_lib.set_plan(64, torch.complex64, 1, 0, 0, 1024, 1)    # cooperative pass disabled in this build
+
+
+def test_overlapping_buffers_rejected(gpu_lib):
+    n = 8
+    big = torch.zeros((2 * n ** 4,), dtype=torch.complex64, device="cuda")
+    w = big[: n ** 4].view(n, n, n, n)
+    shifted = big[17: 17 + n ** 4].view(n, n, n, n)
+    with pytest.raises(gpu_lib.WolfError):
+        gpu_lib.propagate_fresnel(w, 20e-6, LAM, 0.1, out=shifted)           # partial overlap
+    with pytest.raises(gpu_lib.WolfError):
+        gpu_lib.degree_of_coherence(w, 1, 1, out=big[5: 5 + n * n].view(n, n))   # mu inside w
+    # A buffer one element short of N^4, in an allocation of its own (torch's caching allocator would
+    # place it inside a larger segment).
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    ptr = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(ptr), ctypes.c_size_t(8 * (n ** 4 - 1))) == 0
+    try:
+        lib = gpu_lib.load()
+        assert lib.wolf_propagate_fresnel(ptr, ptr, n, 20e-6, LAM, 0.1, 0, 0, None, None) == -1
+        assert b"too small" in lib.wolf_last_error_message()
+    finally:
+        hip.hipFree(ptr)
