@@ -171,19 +171,32 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
 /*
  * wolf_propagate_batch -- many (lambda, z) pairs of one source (polychromatic light; the paper's
  * Sec. 6 names it as future work). For pair k, weight[k] * w_src is propagated to distance z[k]
- * at wavelength lambda[k] into `work`. Then S_k and mu_k(P1, .) are extracted into
- * s_out[k] and mu_out[k].
+ * at wavelength lambda[k] (Sec. 2.1, eqs. W_fresnel / W_farfield), and S_k (Algorithm 4) and
+ * mu_k(P1, .) (Algorithm 5) are written to s_out[k] and mu_out[k]. No propagated N^4 array is
+ * returned.
+ * Where the observables pass fits (complex64 N <= 128, complex128 N <= 64) the propagated CSD
+ * is never stored: S and the row W_B[P1; .] are summed straight from the slab transforms of the
+ * source, one read of w_src per pair. In the far field the source-side factors do not depend on
+ * (lambda, z), so a single read serves every pair. Elsewhere each pair is propagated into `work`.
  * The first call for a given shape records the sequence of launches in a hipGraph; later calls
  * with the same shape replay it.
  *   w_src          device N^4, read only.
  *   wavelength_m, z_m, weight   host arrays of n_pairs (> 0, > 0, >= 0).
- *   work           device N^4 scratch owned by the caller (overwritten).
+ *   work           device scratch owned by the caller, at least wolf_batch_work_bytes(n, dtype)
+ *                  bytes (overwritten).
  *   s_out          device n_pairs * N*N real; mu_out: device n_pairs * N*N complex.
  */
 WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double pitch_m, int32_t n_pairs,
                                           const double* wavelength_m, const double* z_m, const double* weight,
                                           int32_t farfield, int32_t kind, int32_t dtype, int32_t ip, int32_t jp,
                                           double s_floor_rel, void* work, void* s_out, void* mu_out, void* stream);
+
+/*
+ * wolf_batch_work_bytes -- bytes of the `work` buffer that wolf_propagate_batch needs for (n, dtype):
+ * per-workgroup partial sums when the observables pass fits, else one N^4 array. -1 if (n, dtype)
+ * is not supported.
+ */
+WOLF_API int64_t wolf_batch_work_bytes(int32_t n, int32_t dtype);
 
 /*
  * wolf_diag_embed -- out[p1; p2] = g[p1] if p1 == p2 else 0: the gradient with respect to W of a

@@ -30,7 +30,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
-            "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag"]
+            "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes"]
 
 
 class WolfError(RuntimeError):
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wolf_version.restype = i32
     lib.wolf_fit_work_bytes.argtypes = [i32, i32]
     lib.wolf_fit_work_bytes.restype = ctypes.c_int64
+    lib.wolf_batch_work_bytes.argtypes = [i32, i32]
+    lib.wolf_batch_work_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -272,7 +274,7 @@ def propagate_batch(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights,
         raise ValueError("wavelengths, zs and weights must be 1D arrays of the same length")
     k = lam.shape[0]
     if work is None:
-        work = torch.empty_like(w_src)
+        work = torch.empty(batch_work_bytes(n, w_src.dtype), dtype=torch.uint8, device=w_src.device)
     s = torch.empty((k, n, n), dtype=_real(w_src.dtype), device=w_src.device)
     mu = torch.empty((k, n, n), dtype=w_src.dtype, device=w_src.device)
     pd = ctypes.POINTER(ctypes.c_double)
@@ -280,6 +282,14 @@ def propagate_batch(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights,
                                     ww.ctypes.data_as(pd), int(bool(farfield)), kind, _code(w_src.dtype), ip, jp,
                                     floor_rel, _ptr(work), _ptr(s), _ptr(mu), _stream()), "wolf_propagate_batch")
     return s, mu
+
+
+def batch_work_bytes(n: int, dtype: torch.dtype) -> int:
+    """Bytes of the `work` buffer that propagate_batch needs for (n, dtype)."""
+    b = int(load().wolf_batch_work_bytes(n, _code(dtype)))
+    if b < 0:
+        raise WolfError(EUNSUPPORTED, "wolf_batch_work_bytes", f"N={n} unsupported")
+    return b
 
 
 def set_plan(n: int, dtype: torch.dtype, fused_slab: int = -1, slab_chunk: int = -1, col_chunk: int = -1,

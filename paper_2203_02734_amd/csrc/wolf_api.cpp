@@ -144,6 +144,46 @@ wolf::OperatorTables make_op(int32_t n, double pitch, double lam, double z, bool
   return op;
 }
 
+// The batch extracts S and mu(P, .) without an N^4 output where the observables pass fits.
+bool batch_uses_observables(int32_t n, int32_t dtype) {
+  return dtype == WOLF_C64 ? wolf::obs_supported<float2>(n) : wolf::obs_supported<double2>(n);
+}
+
+size_t batch_work_bytes(int32_t n, int32_t dtype) {
+  if (batch_uses_observables(n, dtype))
+    return dtype == WOLF_C64 ? wolf::obs_work_bytes<float2>(n) : wolf::obs_work_bytes<double2>(n);
+  return n4(n) * elem_bytes(dtype);
+}
+
+template <class T>
+hipError_t record_obs_pairs(int32_t n, const T* w_src, double pitch, int32_t n_pairs, const double* lam, const double* z,
+                            const double* weight, bool farfield, int32_t kind, int32_t ip, int32_t jp, double floor_rel,
+                            void* work, typename wolf::real_of<T>::type* s_out, T* mu_out, hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  wolf::ObsSums<T> sums{};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < n_pairs && e == hipSuccess; ++k) {
+    const wolf::OperatorTables op = make_op(n, pitch, lam[k], z[k], farfield, kind, false);
+    // In the far field the source side carries no chirp: the raw sums do not depend on (lambda, z),
+    // and one pass over the source serves every pair.
+    if (k == 0 || !farfield) e = wolf::launch_obs_sums<T>(n, w_src, op, ip, jp, work, &sums, st);
+    if (e == hipSuccess)
+      e = wolf::launch_obs_emit<T>(n, sums, op, weight[k], ip, jp, floor_rel, s_out + k * nn, mu_out + k * nn, st);
+  }
+  return e;
+}
+
+hipError_t record_batch_observables(int32_t n, const void* w_src, double pitch, int32_t n_pairs, const double* lam,
+                                    const double* z, const double* weight, bool farfield, int32_t kind, int32_t dtype,
+                                    int32_t ip, int32_t jp, double floor_rel, void* work, void* s_out, void* mu_out,
+                                    hipStream_t st) {
+  if (dtype == WOLF_C64)
+    return record_obs_pairs<float2>(n, (const float2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
+                                    floor_rel, work, (float*)s_out, (float2*)mu_out, st);
+  return record_obs_pairs<double2>(n, (const double2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
+                                   floor_rel, work, (double*)s_out, (double2*)mu_out, st);
+}
+
 struct BatchGraph {
   std::vector<double> key;
   hipGraphExec_t exec;
@@ -415,14 +455,16 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "%s: s_floor_rel must be >= 0", who);
   const size_t eb = elem_bytes(dtype), big = n4(n) * eb, nn = (size_t)n * n;
   wolf_status s;
+  const bool obs = batch_uses_observables(n, dtype);
+  const size_t wb = batch_work_bytes(n, dtype);
   if ((s = check_buf(w_src, big, "w_src")) != WOLF_OK) return s;
-  if ((s = check_buf(work, big, "work")) != WOLF_OK) return s;
+  if ((s = check_buf(work, wb, "work")) != WOLF_OK) return s;
   if ((s = check_buf(s_out, (size_t)n_pairs * nn * real_bytes(dtype), "s_out")) != WOLF_OK) return s;
   if ((s = check_buf(mu_out, (size_t)n_pairs * nn * eb, "mu_out")) != WOLF_OK) return s;
   const size_t s_bytes = (size_t)n_pairs * nn * real_bytes(dtype), mu_bytes = (size_t)n_pairs * nn * eb;
-  if (intervals_overlap(w_src, big, work, big) || intervals_overlap(s_out, s_bytes, mu_out, mu_bytes) ||
-      intervals_overlap(s_out, s_bytes, w_src, big) || intervals_overlap(s_out, s_bytes, work, big) ||
-      intervals_overlap(mu_out, mu_bytes, w_src, big) || intervals_overlap(mu_out, mu_bytes, work, big))
+  if (intervals_overlap(w_src, big, work, wb) || intervals_overlap(s_out, s_bytes, mu_out, mu_bytes) ||
+      intervals_overlap(s_out, s_bytes, w_src, big) || intervals_overlap(s_out, s_bytes, work, wb) ||
+      intervals_overlap(mu_out, mu_bytes, w_src, big) || intervals_overlap(mu_out, mu_bytes, work, wb))
     return fail(WOLF_EINVAL, "%s: buffers overlap", who);
   void* scratch = nullptr;
   if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
@@ -434,7 +476,7 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   std::vector<double> key = {(double)dev, (double)n, pitch_m, (double)n_pairs, (double)farfield, (double)kind,
                              (double)dtype, (double)ip, (double)jp, s_floor_rel,
                              (double)(uintptr_t)w_src, (double)(uintptr_t)work, (double)(uintptr_t)s_out,
-                             (double)(uintptr_t)mu_out, (double)(uintptr_t)scratch, (double)plan.fused_slab,
+                             (double)(uintptr_t)mu_out, (double)(uintptr_t)scratch, (double)obs, (double)plan.fused_slab,
                              (double)plan.slab_chunk, (double)plan.col_chunk};
   for (int k = 0; k < n_pairs; ++k) {
     key.push_back(wavelength_m[k]);
@@ -456,7 +498,10 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
       return fail(WOLF_EDEVICE, "%s: cannot create the capture stream", who);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; k < n_pairs && e == hipSuccess; ++k) {
+    if (obs && e == hipSuccess) e = record_batch_observables(n, w_src, pitch_m, n_pairs, wavelength_m, z_m, weight,
+                                                             farfield == 1, kind, dtype, ip, jp, s_floor_rel, work,
+                                                             s_out, mu_out, cap);
+    for (int k = 0; k < n_pairs && e == hipSuccess && !obs; ++k) {
       wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m[k], z_m[k], farfield == 1, kind, false);
       op.scale *= weight[k];
       if (dtype == WOLF_C64) {
@@ -492,6 +537,11 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
     hit = &g_batch_graphs.back();
   }
   return launched(hipGraphLaunch(hit->exec, st), who);
+}
+
+WOLF_API int64_t wolf_batch_work_bytes(int32_t n, int32_t dtype) {
+  if (!supported_n(n) || (dtype != WOLF_C64 && dtype != WOLF_C128)) return -1;
+  return (int64_t)batch_work_bytes(n, dtype);
 }
 
 WOLF_API wolf_status wolf_propagate_adjoint_diag(const void* g_diag, void* g_in, int32_t n, double pitch_m,

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace wolf {
 
 // ---------------------------------------------------------------------------------------------
@@ -136,12 +138,34 @@ template <class T> __device__ __forceinline__ T chirp_entry(const Chirp& ch, int
   return T{(R)(c * ch.scale), (R)(s * ch.scale)};
 }
 
+// Host copy of chirp_entry in FP64 (std math, not rounded to the working precision), for
+// scalars set up at launch time.
+inline double2 chirp_entry_host(const Chirp& ch, int n, int N) {
+  const long long d = (long long)n - (long long)(N / 2);
+  auto red = [](double x) { return x - 2.0 * std::rint(0.5 * x); };
+  double ph = (double)(d * d) * ch.alpha;
+  ph = red((double)ch.sign * ph);
+  if (ch.checker && (n & 1)) ph = red(ph + 1.0);
+  const double c = std::cos(M_PI * ph), s = std::sin(M_PI * ph);
+  return double2{c * ch.scale, s * ch.scale};
+}
+
 // Twiddle e^{SIGN 2 pi i j / N}, j in [0, N): the argument 2 j / N is exact for N a power of two.
 template <class T, int SIGN> __device__ __forceinline__ T twiddle_entry(int j, int N) {
   using R = typename real_of<T>::type;
   double s, c;
   sincospi((double)(SIGN * 2) * (double)j / (double)N, &s, &c);
   return T{(R)c, (R)s};
+}
+
+// Monotone map of a double to an unsigned 64-bit key (for atomicMax over reals) and back.
+__device__ __forceinline__ unsigned long long order_key(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+__device__ __forceinline__ double key_value(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+  return __longlong_as_double((long long)b);
 }
 
 }  // namespace wolf

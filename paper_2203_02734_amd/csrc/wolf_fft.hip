@@ -158,6 +158,109 @@ template <class T, int N> constexpr size_t slab_lds_bytes() {
   return sizeof(T) * ((size_t)N * slab_stride<N>() + 3 * N + 2);
 }
 
+// The 2D transform of one slab, shared by the slab pass and the observables pass. The work is
+// laid out for N2 N virtual threads; each real thread runs VT of them (virtual id = tid + vt NT / VT).
+// `tid` is the real thread id. On return, virtual thread (t, r) = (id % N2, id / N2) holds in u[vt N1 + q N2 + k2] the transformed
+// value of row r at column k = t + N2 q + N1 k2, before the column post-factor tpost[k]. The row
+// post-factor tpost[r] is applied only if ROW_POST.
+template <class T, int N, int SIGN, bool ROW_POST = true, int VT = 1>
+__device__ __forceinline__ void slab_transform(const T* in, T* buf, const T* tpre, const T* tpost, const T* tw,
+                                               const T scal, T* u, int tid) {
+  using S = Split<N>;
+  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
+  constexpr int SP = slab_stride<N>();
+  constexpr int NTR = N2 * N / VT;  // real threads
+  // Phase 1: columns. Virtual thread (t, c); c is the j2 column.
+  {
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int c = id % N;
+      const int t = id / N;
+      T v[N1];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const int n = N2 * a + t;
+        v[a] = cmul(in[n * N + c], tpre[n]);
+      }
+      dft_reg<N1, SIGN>(v);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * N + c] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
+    }
+    __syncthreads();
+    T w[VT * N1];
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int c = id % N;
+      const int t = id / N;
+#pragma unroll
+      for (int r = 0; r < Q; ++r) {
+        const int k1 = t + N2 * r;
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) w[vt * N1 + r * N2 + n2] = buf[(k1 * N2 + n2) * N + c];
+        dft_reg<N2, SIGN>(&w[vt * N1 + r * N2]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int c = id % N;
+      const int t = id / N;
+      const T cst = cmul(tpre[c], scal);  // j2 pre-factor and the slab's first-point factor
+#pragma unroll
+      for (int r = 0; r < Q; ++r) {
+        const int k1 = t + N2 * r;
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const int k = k1 + N1 * k2;
+          if constexpr (ROW_POST) buf[k * SP + c] = cmul(w[vt * N1 + r * N2 + k2], cmul(tpost[k], cst));
+          else buf[k * SP + c] = cmul(w[vt * N1 + r * N2 + k2], cst);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // Phase 2: rows. Virtual thread (t, r); r is the i2 row.
+  {
+    T v[VT * N1];
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int t = id % N2;
+      const int r = id / N2;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) v[vt * N1 + a] = buf[r * SP + N2 * a + t];
+      dft_reg<N1, SIGN>(&v[vt * N1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int t = id % N2;
+      const int r = id / N2;
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1)
+        buf[r * SP + k1 * (N2 + 1) + t] = cmul(v[vt * N1 + k1], tw[(t * k1) & (N - 1)]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int t = id % N2;
+      const int r = id / N2;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int k1 = t + N2 * q;
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) u[vt * N1 + q * N2 + n2] = buf[r * SP + k1 * (N2 + 1) + n2];
+        dft_reg<N2, SIGN>(&u[vt * N1 + q * N2]);
+      }
+    }
+  }
+}
+
 template <class T, int N, int SIGN>
 __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T* dst, Chirp pre, Chirp post,
                                                                Chirp slab_pre) {
@@ -179,72 +282,109 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
     sc[threadIdx.x] = chirp_entry<T>(slab_pre, idx, N);
   }
   __syncthreads();
-
-  const T* in = src + p1 * N * N;
+  T u[N1];
+  slab_transform<T, N, SIGN>(src + p1 * N * N, buf, tpre, tpost, tw, cmul(sc[0], sc[1]), u, (int)threadIdx.x);
   T* out = dst + p1 * N * N;
-
-  // Phase 1: columns. Thread (t, c); c is the j2 column.
-  {
-    const int c = threadIdx.x % N;
-    const int t = threadIdx.x / N;
-    const T cst = cmul(tpre[c], cmul(sc[0], sc[1]));  // j2 pre-factor and the slab's first-point factor
-    T v[N1];
+  const int t = threadIdx.x % N2;
+  const int r = threadIdx.x / N2;
 #pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int n = N2 * a + t;
-      v[a] = cmul(in[n * N + c], tpre[n]);
-    }
-    dft_reg<N1, SIGN>(v);
+  for (int q = 0; q < Q; ++q) {
+    const int k1 = t + N2 * q;
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * N + c] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
-    __syncthreads();
-    T u[N1];
-#pragma unroll
-    for (int r = 0; r < Q; ++r) {
-      const int k1 = t + N2 * r;
-#pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) u[r * N2 + n2] = buf[(k1 * N2 + n2) * N + c];
-      dft_reg<N2, SIGN>(&u[r * N2]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < Q; ++r) {
-      const int k1 = t + N2 * r;
-#pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int k = k1 + N1 * k2;
-        buf[k * SP + c] = cmul(u[r * N2 + k2], cmul(tpost[k], cst));
-      }
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int k = k1 + N1 * k2;
+      out[r * N + k] = cmul(u[q * N2 + k2], tpost[k]);
     }
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Observables pass. For the forward operator the post-factors of the two points cancel on the
+// diagonal: post1[k] post2[k] = q*(x_k) q(x_k) (-1)^{2k} = 1. With Z[p1; m] the slab transform of
+// slab p1 = (a, b) before any post-factor and w1 = e^{sign1 2 pi i / N},
+//   S(m)      = s Re sum_p1 w1^(m_i a + m_j b) Z[p1; m]
+//   W_B[P; m] = s post1[P_i] post1[P_j] post2[m_i] post2[m_j] sum_p1 w1^(P_i a + P_j b) Z[p1; m].
+// Each workgroup takes every gridDim-th slab and keeps the two raw sums for all N^2 columns m in
+// registers; no N^4 array is written. k_obs_reduce adds the per-workgroup partials; k_obs_emit
+// applies s, the weight and the post-factors, so one set of raw sums serves every (lambda, z)
+// whose pre-factors are the same (the far field, where the source side carries no chirp).
+// ---------------------------------------------------------------------------------------------
+// Virtual threads per real thread in the observables pass: at N = 128 complex64 the raw sums and
+// the slab transform of 1024 threads do not fit the 128 VGPRs that a 1024-thread workgroup allows;
+// 512 threads with two virtual threads each get 256.
+template <class T, int N> constexpr int obs_vt() { return (sizeof(T) == 8 && N >= 128) ? 2 : 1; }
+
+template <class T, int N, int SIGN>
+__global__ __launch_bounds__((Split<N>::N2 * N / obs_vt<T, N>())) void k_slab_obs(const T* src, Chirp pre,
+                                                                               Chirp slab_pre, int pi, int pj,
+                                                                               typename real_of<T>::type* s_part,
+                                                                               T* b_part) {
+  using R = typename real_of<T>::type;
+  using S = Split<N>;
+  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
+  constexpr int VT = obs_vt<T, N>();
+  constexpr int NTR = N2 * N / VT;
+  constexpr int SP = slab_stride<N>();
+  __shared__ T buf[N * SP];
+  __shared__ T tpre[N], tw[N], tw1[N], tpre1[N];
+  for (int i = threadIdx.x; i < N; i += NTR) {
+    tpre[i] = chirp_entry<T>(pre, i, N);
+    tw[i] = twiddle_entry<T, SIGN>(i, N);
+    tw1[i] = twiddle_entry<T, -SIGN>(i, N);
+    tpre1[i] = chirp_entry<T>(slab_pre, i, N);
+  }
   __syncthreads();
-  // Phase 2: rows. Thread (t, r); r is the i2 row.
-  {
-    const int t = threadIdx.x % N2;
-    const int r = threadIdx.x / N2;
-    T v[N1];
+  R sacc[VT * N1];
+  T bacc[VT * N1];
 #pragma unroll
-    for (int a = 0; a < N1; ++a) v[a] = buf[r * SP + N2 * a + t];
-    dft_reg<N1, SIGN>(v);
-    __syncthreads();
+  for (int i = 0; i < VT * N1; ++i) {
+    sacc[i] = (R)0;
+    bacc[i] = T{(R)0, (R)0};
+  }
+  const long long nn = (long long)N * N;
+  for (long long p1 = blockIdx.x; p1 < nn; p1 += gridDim.x) {
+    const int a = (int)(p1 / N), b = (int)(p1 % N);
+    T u[VT * N1];
+    // An opaque copy of the thread id: the addresses derived from it are recomputed per slab
+    // instead of being held (and spilled) across the loop next to the raw sums.
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    slab_transform<T, N, SIGN, false, VT>(src + p1 * nn, buf, tpre, tpre, tw, cmul(tpre1[a], tpre1[b]), u, tid);
+    const T cb = tw1[(pi * a + pj * b) & (N - 1)];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) buf[r * SP + k1 * (N2 + 1) + t] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
-    __syncthreads();
-    T u[N1];
+    for (int vt = 0; vt < VT; ++vt) {
+      const int id = tid + vt * NTR;
+      const int t = id % N2;
+      const int r = id / N2;
+      const int base = r * a + t * b;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int k1 = t + N2 * q;
+      for (int q = 0; q < Q; ++q) {
 #pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) u[q * N2 + n2] = buf[r * SP + k1 * (N2 + 1) + n2];
-      dft_reg<N2, SIGN>(&u[q * N2]);
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const int i = vt * N1 + q * N2 + k2;
+          const T co = tw1[(base + (N2 * q + N1 * k2) * b) & (N - 1)];
+          const T v = u[i];
+          sacc[i] += co.x * v.x - co.y * v.y;
+          bacc[i] = cadd(bacc[i], cmul(cb, v));
+        }
+      }
     }
+    __syncthreads();  // buf is reused by the next slab
+  }
+  R* sp = s_part + (long long)blockIdx.x * nn;
+  T* bp = b_part + (long long)blockIdx.x * nn;
+#pragma unroll
+  for (int vt = 0; vt < VT; ++vt) {
+    const int id = threadIdx.x + vt * NTR;
+    const int t = id % N2;
+    const int r = id / N2;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int k1 = t + N2 * q;
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
-        const int k = k1 + N1 * k2;
-        out[r * N + k] = cmul(u[q * N2 + k2], tpost[k]);
+        const int k = t + N2 * q + N1 * k2;
+        sp[r * N + k] = sacc[vt * N1 + q * N2 + k2];
+        bp[r * N + k] = bacc[vt * N1 + q * N2 + k2];
       }
     }
   }
@@ -440,6 +580,162 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   }
   return hipSuccess;
 }
+
+// ---------------------------------------------------------------------------------------------
+// Observables pass launch, reduction and emission.
+// ---------------------------------------------------------------------------------------------
+template <class T> int obs_parts(int n) {
+  const long long nn = (long long)n * n;
+  long long g = 256;  // one workgroup per CU (the slab buffer takes most of the LDS at N = 128)
+  if (g > nn) g = nn;
+  return (int)g;
+}
+
+template <class T> size_t obs_work_bytes(int n) {
+  using R = typename real_of<T>::type;
+  const size_t nn = (size_t)n * n;
+  return ((size_t)obs_parts<T>(n) + 1) * nn * (sizeof(R) + sizeof(T)) + 256;
+}
+template size_t obs_work_bytes<float2>(int);
+template size_t obs_work_bytes<double2>(int);
+
+template <class T>
+__global__ __launch_bounds__(256) void k_obs_reduce(const typename real_of<T>::type* __restrict__ s_part,
+                                                    const T* __restrict__ b_part, int parts, long long nn,
+                                                    typename real_of<T>::type* __restrict__ s0, T* __restrict__ b0,
+                                                    unsigned long long* key) {
+  using R = typename real_of<T>::type;
+  __shared__ unsigned long long red[256];
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long kk = 0ull;
+  if (m < nn) {
+    R sv = (R)0;
+    T bv{(R)0, (R)0};
+    for (int g = 0; g < parts; ++g) {
+      sv += s_part[(long long)g * nn + m];
+      bv = cadd(bv, b_part[(long long)g * nn + m]);
+    }
+    s0[m] = sv;
+    b0[m] = bv;
+    kk = order_key((double)sv);
+  }
+  red[threadIdx.x] = kk;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(key, red[0]);
+}
+
+__global__ void k_obs_clear_key(unsigned long long* key) { *key = 0ull; }
+
+// S = c s0; mu(P, m) = post1[P_i] post1[P_j] post2[m_i] post2[m_j] b0[m] / sqrt(s0[P] s0[m]) where
+// both s0 exceed floor * max s0 (and c > 0), 0 elsewhere. The factor s c cancels in mu.
+template <class T>
+__global__ __launch_bounds__(256) void k_obs_emit(const typename real_of<T>::type* __restrict__ s0,
+                                                  const T* __restrict__ b0, const unsigned long long* key, int n, int pi,
+                                                  int pj, double c, Chirp post1, Chirp post2, double floor_rel,
+                                                  typename real_of<T>::type* __restrict__ s_out, T* __restrict__ mu_out) {
+  using R = typename real_of<T>::type;
+  const long long nn = (long long)n * n;
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nn) return;
+  const int mi = (int)(m / n), mj = (int)(m - (long long)mi * n);
+  const R sm = s0[m];
+  s_out[m] = (R)(c * (double)sm);
+  const R tau = (R)(floor_rel * key_value(*key));
+  const R sp = s0[(long long)pi * n + pj];
+  T out{(R)0, (R)0};
+  if (c > 0.0 && sp > tau && sm > tau) {
+    const double2 ph = cmul(cmul(chirp_entry<double2>(post1, pi, n), chirp_entry<double2>(post1, pj, n)),
+                            cmul(chirp_entry<double2>(post2, mi, n), chirp_entry<double2>(post2, mj, n)));
+    const T f{(R)ph.x, (R)ph.y};
+    const R d = sqrt(sp) * sqrt(sm);
+    const T v = cmul(f, b0[m]);
+    out = T{v.x / d, v.y / d};
+  }
+  mu_out[m] = out;
+}
+
+template <class T, int N, int SIGN>
+static hipError_t launch_obs_n(const T* src, const OperatorTables& op, int pi, int pj, int parts,
+                               typename real_of<T>::type* s_part, T* b_part, hipStream_t st) {
+  if constexpr (slab_lds_bytes<T, N>() + N * sizeof(T) > kMaxLds || Split<N>::N2 * N / obs_vt<T, N>() > 1024) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_slab_obs<T, N, SIGN>), dim3((unsigned)parts), dim3(Split<N>::N2 * N / obs_vt<T, N>()), 0, st,
+                       src, op.pre2,
+                       op.pre1, pi, pj, s_part, b_part);
+    return hipGetLastError();
+  }
+}
+
+template <class T> bool obs_supported(int n) {
+  switch (n) {
+#define WOLF_OBS_CASE(NN) \
+  case NN: return slab_lds_bytes<T, NN>() + NN * sizeof(T) <= kMaxLds && Split<NN>::N2 * NN / obs_vt<T, NN>() <= 1024;
+    WOLF_OBS_CASE(2) WOLF_OBS_CASE(4) WOLF_OBS_CASE(8) WOLF_OBS_CASE(16) WOLF_OBS_CASE(32) WOLF_OBS_CASE(64)
+    WOLF_OBS_CASE(128) WOLF_OBS_CASE(256)
+#undef WOLF_OBS_CASE
+    default: return false;
+  }
+}
+template bool obs_supported<float2>(int);
+template bool obs_supported<double2>(int);
+
+// Raw sums of one forward operator's first-point pre-factors and DFTs over `src` (layout in `work`:
+// per-workgroup partials, then s0 (N^2 reals), b0 (N^2 complex), the max key).
+template <class T>
+hipError_t launch_obs_sums(int n, const T* src, const OperatorTables& op, int pi, int pj, void* work, ObsSums<T>* out,
+                           hipStream_t st) {
+  using R = typename real_of<T>::type;
+  if (op.sign2 != -1 || op.sign1 != +1) return hipErrorInvalidValue;  // forward operators only
+  if (!obs_supported<T>(n)) return hipErrorInvalidValue;
+  const long long nn = (long long)n * n;
+  const int parts = obs_parts<T>(n);
+  char* w = reinterpret_cast<char*>(work);
+  R* s_part = reinterpret_cast<R*>(w);
+  T* b_part = reinterpret_cast<T*>(w + (size_t)parts * nn * sizeof(R));
+  char* tail = w + (size_t)parts * nn * (sizeof(R) + sizeof(T));
+  out->s0 = reinterpret_cast<R*>(tail);
+  out->b0 = reinterpret_cast<T*>(tail + (size_t)nn * sizeof(R));
+  out->key = reinterpret_cast<unsigned long long*>(tail + (size_t)nn * (sizeof(R) + sizeof(T)));
+  hipError_t e;
+  switch (n) {
+#define WOLF_OBS_LAUNCH(NN) \
+  case NN: e = launch_obs_n<T, NN, -1>(src, op, pi, pj, parts, s_part, b_part, st); break;
+    WOLF_OBS_LAUNCH(2) WOLF_OBS_LAUNCH(4) WOLF_OBS_LAUNCH(8) WOLF_OBS_LAUNCH(16) WOLF_OBS_LAUNCH(32) WOLF_OBS_LAUNCH(64)
+    WOLF_OBS_LAUNCH(128) WOLF_OBS_LAUNCH(256)
+#undef WOLF_OBS_LAUNCH
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_obs_clear_key, dim3(1), dim3(1), 0, st, out->key);
+  hipLaunchKernelGGL(k_obs_reduce<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const R*)s_part,
+                     (const T*)b_part, parts, nn, out->s0, out->b0, out->key);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_obs_emit(int n, const ObsSums<T>& sums, const OperatorTables& op, double weight, int pi, int pj,
+                           double floor_rel, typename real_of<T>::type* s_out, T* mu_out, hipStream_t st) {
+  using R = typename real_of<T>::type;
+  const long long nn = (long long)n * n;
+  hipLaunchKernelGGL(k_obs_emit<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const R*)sums.s0,
+                     (const T*)sums.b0, (const unsigned long long*)sums.key, n, pi, pj, weight * op.scale, op.post1,
+                     op.post2, floor_rel, s_out, mu_out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_obs_sums<float2>(int, const float2*, const OperatorTables&, int, int, void*, ObsSums<float2>*,
+                                            hipStream_t);
+template hipError_t launch_obs_sums<double2>(int, const double2*, const OperatorTables&, int, int, void*,
+                                             ObsSums<double2>*, hipStream_t);
+template hipError_t launch_obs_emit<float2>(int, const ObsSums<float2>&, const OperatorTables&, double, int, int, double,
+                                            float*, float2*, hipStream_t);
+template hipError_t launch_obs_emit<double2>(int, const ObsSums<double2>&, const OperatorTables&, double, int, int,
+                                             double, double*, double2*, hipStream_t);
 
 // ---------------------------------------------------------------------------------------------
 // Operator applied to a diagonal input diag(g) (e.g. the gradient of a loss of S = Re diag W).

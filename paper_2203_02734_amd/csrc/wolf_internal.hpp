@@ -61,6 +61,20 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
 template <class T>
 hipError_t launch_operator_diag(int n, const typename real_of<T>::type* g, T* out, const OperatorTables& op,
                                 const Plan& plan, void* counters, hipStream_t st);
+// Observables-only forward propagation: S and mu(P, .) without an N^4 output (k_slab_obs).
+template <class T> struct ObsSums {
+  typename real_of<T>::type* s0;  // raw sums for S, N^2
+  T* b0;                          // raw sums for the row W_B[P; .], N^2
+  unsigned long long* key;        // order key of max s0
+};
+template <class T> bool obs_supported(int n);
+template <class T> size_t obs_work_bytes(int n);
+template <class T>
+hipError_t launch_obs_sums(int n, const T* src, const OperatorTables& op, int pi, int pj, void* work, ObsSums<T>* out,
+                           hipStream_t st);
+template <class T>
+hipError_t launch_obs_emit(int n, const ObsSums<T>& sums, const OperatorTables& op, double weight, int pi, int pj,
+                           double floor_rel, typename real_of<T>::type* s_out, T* mu_out, hipStream_t st);
 template <class T> bool coop_supported(int n);
 template <class T>
 hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,

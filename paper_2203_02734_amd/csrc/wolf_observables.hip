@@ -9,15 +9,6 @@
 
 namespace wolf {
 
-__device__ __forceinline__ unsigned long long order_key(double v) {
-  const unsigned long long b = __double_as_longlong(v);
-  return (b >> 63) ? ~b : (b | (1ull << 63));
-}
-__device__ __forceinline__ double key_value(unsigned long long k) {
-  const unsigned long long b = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
-  return __longlong_as_double((long long)b);
-}
-
 template <class T>
 __global__ __launch_bounds__(256) void k_sdiag(const T* __restrict__ w, int n, typename real_of<T>::type* __restrict__ s) {
   const long long nn = (long long)n * n;

@@ -55,6 +55,60 @@ def test_batch_small_vs_oracle(gpu_lib, farfield, dtype):
         assert rel(host(mu[k]), O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor)
 
 
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("n", [2, 4, 8, 32])
+def test_batch_sizes_vs_oracle(gpu_lib, n, dtype, farfield):
+    """Random Hermitian source (not separable), every supported small N, one probe off-centre."""
+    p = 20e-6
+    w = WI.random_hermitian_psd(n, seed=5 + n)
+    lam = np.array([633e-9, 500e-9])
+    zs = np.array([0.2, 2.0])
+    ws = np.array([1.0, 0.5])
+    ip, jp = n - 1, n // 2
+    floor = 1e-4 if dtype == torch.complex64 else 1e-8
+    wt = torch.from_numpy(w).to(dtype).cuda()
+    s, mu = gpu_lib.propagate_batch(wt, p, lam, zs, ws, farfield=farfield, ip=ip, jp=jp, floor_rel=floor)
+    for k in range(2):
+        wb, _ = O.propagate(ws[k] * w, n, p, lam[k], zs[k], farfield)
+        assert rel(host(s[k]), O.spectral_density(wb)) < TOL[dtype]
+        assert rel(host(mu[k]), O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor)
+
+
+def test_batch_work_bytes(gpu_lib):
+    nn = 128 * 128
+    # observables pass: per-workgroup partial sums; otherwise one N^4 array
+    assert gpu_lib.batch_work_bytes(128, torch.complex64) < 128 ** 4 * 8
+    assert gpu_lib.batch_work_bytes(128, torch.complex64) >= nn * 12
+    assert gpu_lib.batch_work_bytes(128, torch.complex128) == 128 ** 4 * 16
+    assert gpu_lib.batch_work_bytes(256, torch.complex64) == 256 ** 4 * 8
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+def test_batch_n128_complex128_full_propagation(gpu_lib, farfield):
+    """complex128 at N = 128 takes the path that propagates each pair into `work`."""
+    wl = WI.gsm128()
+    n, p = wl.n, wl.pitch_m
+    sp = wl.source
+    ip, jp = wl.probe
+    lam, zs, ws = np.array([550e-9, 650e-9]), np.array([0.5, 1.0]), np.array([1.0, 0.25])
+    w0 = gpu_lib.build_source(sp, n, p, torch.complex128)
+    floor = 1e-8
+    s, mu = gpu_lib.propagate_batch(w0, p, lam, zs, ws, farfield=farfield, ip=ip, jp=jp, floor_rel=floor)
+    s, mu = host(s), host(mu)
+    del w0
+    wx = O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x")
+    wy = O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y")
+    for k in range(2):
+        bx, by = O.propagate_separable(ws[k] * wx, wy, n, p, lam[k], zs[k], farfield)
+        sr = np.real(np.diag(bx)[:, None] * np.diag(by)[None, :])
+        row = bx[ip][:, None] * by[jp][None, :]
+        mur = row / np.sqrt(sr[ip, jp] * sr)
+        mur[sr <= floor * sr.max()] = 0
+        assert rel(s[k], sr) < 1e-12
+        assert rel(mu[k], mur) < 1e-12 / math.sqrt(floor)
+
+
 def test_batch_full_size_polychromatic(gpu_lib):
     """N = 128 complex64 GSM, 16 wavelengths x 4 distances, every pair against the separable oracle."""
     wl = WI.gsm128()
