@@ -199,6 +199,7 @@ std::map<std::pair<int, int>, wolf::Plan> g_plans;  // (n, dtype) -> plan chosen
 bool plan_valid(int32_t n, int32_t dtype, const wolf::Plan& p) {
   const long long nn = (long long)n * n;
   const int c = wolf::axis_tile_cols(n);
+  if (p.fused_slab < 0 || p.fused_slab > 2) return false;
   if (p.fused_slab && !(dtype == WOLF_C64 ? wolf::slab_pass_supported<float2>(n) : wolf::slab_pass_supported<double2>(n)))
     return false;
   if (p.col_chunk < 0 || p.col_chunk > nn || (p.col_chunk > 0 && (p.col_chunk % c != 0 || nn % p.col_chunk != 0)))
@@ -620,8 +621,8 @@ WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab,
     g_plans.erase({n, dtype});
     return WOLF_OK;
   }
-  if (fused_slab != 0 && fused_slab != 1) return fail(WOLF_EINVAL, "wolf_set_plan: fused_slab must be 0 or 1");
-  const wolf::Plan p{fused_slab == 1, (long long)slab_chunk, (long long)col_chunk, coop_wgs > 0 ? 1 : 0,
+  if (fused_slab < 0 || fused_slab > 2) return fail(WOLF_EINVAL, "wolf_set_plan: fused_slab must be 0, 1 or 2");
+  const wolf::Plan p{fused_slab, (long long)slab_chunk, (long long)col_chunk, coop_wgs > 0 ? 1 : 0,
                      coop_wgs > 0 ? coop_wgs : 0, coop_wgs > 0 ? coop_lookahead : 1};
   if (p.coop && !kCoopEnabled)
     return fail(WOLF_EUNSUPPORTED, "wolf_set_plan: the cooperative first-point pass is disabled in this build");
@@ -637,7 +638,7 @@ WOLF_API wolf_status wolf_get_plan(int32_t n, int32_t dtype, int32_t* fused_slab
   if (!fused_slab || !slab_chunk || !col_chunk || !coop_wgs || !coop_lookahead)
     return fail(WOLF_EINVAL, "wolf_get_plan: null output");
   const wolf::Plan p = plan_for(n, dtype);
-  *fused_slab = p.fused_slab ? 1 : 0;
+  *fused_slab = p.fused_slab;
   *slab_chunk = p.slab_chunk;
   *col_chunk = p.col_chunk;
   *coop_wgs = p.coop ? p.coop_wgs : 0;
@@ -670,20 +671,20 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
   const int c = wolf::axis_tile_cols(n);
   std::vector<wolf::Plan> cands;
   const wolf::Plan def = default_plan(n, dtype);
-  for (int fused = 1; fused >= 0; --fused) {
+  for (int fused = 2; fused >= 0; --fused) {
     for (int wgs : {512, 1024, 2048}) {
       for (int la : {1, 2}) {
-        wolf::Plan p{fused == 1, def.slab_chunk, nn, 1, wgs, la};
+        wolf::Plan p{fused, def.slab_chunk, nn, 1, wgs, la};
         if (kCoopEnabled && plan_valid(n, dtype, p)) cands.push_back(p);
       }
     }
     for (long long cols = nn; cols >= c; cols >>= 1) {
       // Chunks below 4 MB only add launches.
       if (cols < nn && cols * nn * (long long)elem_bytes(dtype) < (4ll << 20)) break;
-      wolf::Plan p{fused == 1, def.slab_chunk, cols, 0, 0, 1};
+      wolf::Plan p{fused, def.slab_chunk, cols, 0, 0, 1};
       if (plan_valid(n, dtype, p)) cands.push_back(p);
       if (!fused && cols == nn) {
-        wolf::Plan q{false, 0, cols, 0, 0, 1};
+        wolf::Plan q{0, 0, cols, 0, 0, 1};
         if (plan_valid(n, dtype, q)) cands.push_back(q);
       }
     }

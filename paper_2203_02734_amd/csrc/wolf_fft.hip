@@ -163,9 +163,53 @@ template <class T, int N> constexpr size_t slab_lds_bytes() {
 // `tid` is the real thread id. On return, virtual thread (t, r) = (id % N2, id / N2) holds in u[vt N1 + q N2 + k2] the transformed
 // value of row r at column k = t + N2 q + N1 k2, before the column post-factor tpost[k]. The row
 // post-factor tpost[r] is applied only if ROW_POST.
-template <class T, int N, int SIGN, bool ROW_POST = true, int VT = 1>
+template <class T, int N> constexpr int slab_lines() { return (N * N * (int)sizeof(T) + 127) / 128; }
+
+// Raw loads of one slab for the column phase: virtual thread (t, c) takes rows n = N2 a + t of
+// column c into v[vt N1 + a].
+template <class T, int N, int VT = 1>
+__device__ __forceinline__ void slab_load(const T* in, T* v, int tid) {
+  using S = Split<N>;
+  constexpr int N1 = S::N1, N2 = S::N2;
+  constexpr int NTR = N2 * N / VT;
+#pragma unroll
+  for (int vt = 0; vt < VT; ++vt) {
+    const int id = tid + vt * NTR;
+    const int c = id % N;
+    const int t = id / N;
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[vt * N1 + a] = in[(N2 * a + t) * N + c];
+  }
+}
+
+template <class T, int N, int SIGN, bool ROW_POST, int VT>
+__device__ __forceinline__ void slab_transform_loaded(T* v, T* buf, const T* tpre, const T* tpost, const T* tw,
+                                                      const T scal, T* u, int tid);
+
+template <class T, int N, int SIGN, bool ROW_POST = true, int VT = 1, int PFT = 0>
 __device__ __forceinline__ void slab_transform(const T* in, T* buf, const T* tpre, const T* tpost, const T* tw,
-                                               const T scal, T* u, int tid) {
+                                               const T scal, T* u, int tid, const T* next = nullptr,
+                                               uint32_t* pf = nullptr) {
+  constexpr int NTR = Split<N>::N2 * N / VT;  // real threads
+  T v[VT * Split<N>::N1];
+  slab_load<T, N, VT>(in, v, tid);
+  // Touch one dword of each 128-byte line of the next slab: the lines travel to the L2 while this
+  // slab is transformed. The caller keeps pf[] live until the end of its iteration.
+  if constexpr (PFT > 0) {
+    const uint32_t* nx = reinterpret_cast<const uint32_t*>(next);
+#pragma unroll
+    for (int l = 0; l < PFT; ++l) {
+      const int line = tid + l * NTR;
+      pf[l] = (nx != nullptr && line < slab_lines<T, N>()) ? nx[line * 32] : 0u;
+    }
+  }
+  slab_transform_loaded<T, N, SIGN, ROW_POST, VT>(v, buf, tpre, tpost, tw, scal, u, tid);
+}
+
+// The transform of a slab whose raw values slab_load put in v (v is overwritten).
+template <class T, int N, int SIGN, bool ROW_POST, int VT>
+__device__ __forceinline__ void slab_transform_loaded(T* v, T* buf, const T* tpre, const T* tpost, const T* tw,
+                                                      const T scal, T* u, int tid) {
   using S = Split<N>;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
   constexpr int SP = slab_stride<N>();
@@ -177,15 +221,11 @@ __device__ __forceinline__ void slab_transform(const T* in, T* buf, const T* tpr
       const int id = tid + vt * NTR;
       const int c = id % N;
       const int t = id / N;
-      T v[N1];
 #pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        const int n = N2 * a + t;
-        v[a] = cmul(in[n * N + c], tpre[n]);
-      }
-      dft_reg<N1, SIGN>(v);
+      for (int a = 0; a < N1; ++a) v[vt * N1 + a] = cmul(v[vt * N1 + a], tpre[N2 * a + t]);
+      dft_reg<N1, SIGN>(&v[vt * N1]);
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * N + c] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
+      for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * N + c] = cmul(v[vt * N1 + k1], tw[(t * k1) & (N - 1)]);
     }
     __syncthreads();
     T w[VT * N1];
@@ -298,6 +338,57 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
   }
 }
 
+// Persistent form of the slab pass: each workgroup takes every gridDim-th slab and keeps its
+// tables. The raw values of its next slab are loaded into registers while it transforms the
+// current one, so the loads of one slab overlap the arithmetic of the previous one.
+template <class T, int N, int SIGN>
+__global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T* dst, long long slabs, Chirp pre,
+                                                                Chirp post, Chirp slab_pre) {
+  using S = Split<N>;
+  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
+  constexpr int NT = N2 * N;
+  constexpr int SP = slab_stride<N>();
+  __shared__ T buf[N * SP];
+  __shared__ T tpre[N], tpost[N], tw[N], tpre1[N];
+  for (int i = threadIdx.x; i < N; i += NT) {
+    tpre[i] = chirp_entry<T>(pre, i, N);
+    tpost[i] = chirp_entry<T>(post, i, N);
+    tw[i] = twiddle_entry<T, SIGN>(i, N);
+    tpre1[i] = chirp_entry<T>(slab_pre, i, N);
+  }
+  __syncthreads();
+  const long long nn = (long long)N * N;
+  long long p1 = blockIdx.x;
+  if (p1 >= slabs) return;
+  T cur[N1];
+  slab_load<T, N>(src + p1 * nn, cur, (int)threadIdx.x);
+  for (; p1 < slabs; p1 += gridDim.x) {
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));  // recompute thread-derived addresses per slab
+    const long long pn = p1 + gridDim.x;
+    T nxt[N1];
+    if (pn < slabs) slab_load<T, N>(src + pn * nn, nxt, tid);
+    T u[N1];
+    slab_transform_loaded<T, N, SIGN, true, 1>(cur, buf, tpre, tpost, tw,
+                                               cmul(tpre1[(int)(p1 / N)], tpre1[(int)(p1 % N)]), u, tid);
+    __syncthreads();  // buf is reused by the next slab
+    T* out = dst + p1 * nn;
+    const int t = tid % N2;
+    const int r = tid / N2;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t + N2 * q;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int k = k1 + N1 * k2;
+        out[r * N + k] = cmul(u[q * N2 + k2], tpost[k]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N1; ++i) cur[i] = nxt[i];
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Observables pass. For the forward operator the post-factors of the two points cancel on the
 // diagonal: post1[k] post2[k] = q*(x_k) q(x_k) (-1)^{2k} = 1. With Z[p1; m] the slab transform of
@@ -309,22 +400,18 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
 // applies s, the weight and the post-factors, so one set of raw sums serves every (lambda, z)
 // whose pre-factors are the same (the far field, where the source side carries no chirp).
 // ---------------------------------------------------------------------------------------------
-// Virtual threads per real thread in the observables pass: at N = 128 complex64 the raw sums and
-// the slab transform of 1024 threads do not fit the 128 VGPRs that a 1024-thread workgroup allows;
-// 512 threads with two virtual threads each get 256.
-template <class T, int N> constexpr int obs_vt() { return (sizeof(T) == 8 && N >= 128) ? 2 : 1; }
-
 template <class T, int N, int SIGN>
-__global__ __launch_bounds__((Split<N>::N2 * N / obs_vt<T, N>())) void k_slab_obs(const T* src, Chirp pre,
+__global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_obs(const T* src, Chirp pre,
                                                                                Chirp slab_pre, int pi, int pj,
                                                                                typename real_of<T>::type* s_part,
                                                                                T* b_part) {
   using R = typename real_of<T>::type;
   using S = Split<N>;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
-  constexpr int VT = obs_vt<T, N>();
+  constexpr int VT = 1;
   constexpr int NTR = N2 * N / VT;
   constexpr int SP = slab_stride<N>();
+  constexpr int PFT = (slab_lines<T, N>() + NTR - 1) / NTR;
   __shared__ T buf[N * SP];
   __shared__ T tpre[N], tw[N], tw1[N], tpre1[N];
   for (int i = threadIdx.x; i < N; i += NTR) {
@@ -349,7 +436,10 @@ __global__ __launch_bounds__((Split<N>::N2 * N / obs_vt<T, N>())) void k_slab_ob
     // instead of being held (and spilled) across the loop next to the raw sums.
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
-    slab_transform<T, N, SIGN, false, VT>(src + p1 * nn, buf, tpre, tpre, tw, cmul(tpre1[a], tpre1[b]), u, tid);
+    const long long pn = p1 + gridDim.x;
+    uint32_t pf[PFT];
+    slab_transform<T, N, SIGN, false, VT, PFT>(src + p1 * nn, buf, tpre, tpre, tw, cmul(tpre1[a], tpre1[b]), u, tid,
+                                               pn < nn ? src + pn * nn : nullptr, pf);
     const T cb = tw1[(pi * a + pj * b) & (N - 1)];
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt) {
@@ -369,6 +459,8 @@ __global__ __launch_bounds__((Split<N>::N2 * N / obs_vt<T, N>())) void k_slab_ob
         }
       }
     }
+#pragma unroll
+    for (int l = 0; l < PFT; ++l) asm volatile("" ::"v"(pf[l]));
     __syncthreads();  // buf is reused by the next slab
   }
   R* sp = s_part + (long long)blockIdx.x * nn;
@@ -443,14 +535,29 @@ static hipError_t launch_row_n(const T* src, T* dst, long long rows, const Chirp
   return hipGetLastError();
 }
 
+// Workgroups of the persistent slab pass: as many as fit on the 256 CUs at once (LDS and waves).
+template <class T, int N> constexpr long long slab_resident_wgs() {
+  constexpr long long by_lds = (long long)(kMaxLds / slab_lds_bytes<T, N>());
+  constexpr long long by_waves = 32 / ((Split<N>::N2 * N + 63) / 64);
+  constexpr long long k = by_lds < by_waves ? by_lds : by_waves;
+  return 256 * (k < 1 ? 1 : k);
+}
+
 template <class T, int N, int SIGN>
 static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chirp& pre, const Chirp& post,
-                                const Chirp& slab_pre, hipStream_t st) {
+                                const Chirp& slab_pre, int mode, hipStream_t st) {
   if constexpr (slab_lds_bytes<T, N>() > kMaxLds) {
     return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL((k_slab_fft2<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N), 0, st, src, dst,
-                       pre, post, slab_pre);
+    if (slabs > 0x7fffffffll) return hipErrorInvalidValue;
+    if (mode == 2) {
+      const long long g = slabs < slab_resident_wgs<T, N>() ? slabs : slab_resident_wgs<T, N>();
+      hipLaunchKernelGGL((k_slab_fft2p<T, N, SIGN>), dim3((unsigned)g), dim3(Split<N>::N2 * N), 0, st, src, dst,
+                         slabs, pre, post, slab_pre);
+    } else {
+      hipLaunchKernelGGL((k_slab_fft2<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N), 0, st, src, dst,
+                         pre, post, slab_pre);
+    }
     return hipGetLastError();
   }
 }
@@ -485,9 +592,9 @@ hipError_t launch_row_pass(int n, const T* src, T* dst, long long rows, int sign
 
 template <class T>
 hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slabs, int sign, const Chirp& pre,
-                            const Chirp& post, const Chirp& slab_pre, hipStream_t st) {
-  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, st))) }
-  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, st)))
+                            const Chirp& post, const Chirp& slab_pre, int mode, hipStream_t st) {
+  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, mode, st))) }
+  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, mode, st)))
 }
 
 template <class T> bool slab_pass_supported(int n) {
@@ -543,7 +650,7 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   const Chirp ident{0.0, 1.0, +1, 0};
   // Second-point axes (i2, j2).
   if (plan.fused_slab) {
-    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, st);
+    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, plan.fused_slab, st);
     if (e != hipSuccess) return e;
   } else {
     const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk
@@ -599,29 +706,51 @@ template <class T> size_t obs_work_bytes(int n) {
 template size_t obs_work_bytes<float2>(int);
 template size_t obs_work_bytes<double2>(int);
 
+// Sum of the per-workgroup partials. A block covers 64 columns m with 4 threads each; thread q adds
+// the partials g = q, q + 4, ... (four independent chains), and the four sums are combined in a
+// fixed order, so the result does not depend on scheduling.
 template <class T>
 __global__ __launch_bounds__(256) void k_obs_reduce(const typename real_of<T>::type* __restrict__ s_part,
                                                     const T* __restrict__ b_part, int parts, long long nn,
                                                     typename real_of<T>::type* __restrict__ s0, T* __restrict__ b0,
                                                     unsigned long long* key) {
   using R = typename real_of<T>::type;
-  __shared__ unsigned long long red[256];
-  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long kk = 0ull;
+  __shared__ R ss[4][64];
+  __shared__ T sb[4][64];
+  __shared__ unsigned long long red[64];
+  const int lane = threadIdx.x % 64, q = threadIdx.x / 64;
+  const long long m = (long long)blockIdx.x * 64 + lane;
+  R sv[4] = {(R)0, (R)0, (R)0, (R)0};
+  T bv[4] = {T{(R)0, (R)0}, T{(R)0, (R)0}, T{(R)0, (R)0}, T{(R)0, (R)0}};
   if (m < nn) {
-    R sv = (R)0;
-    T bv{(R)0, (R)0};
-    for (int g = 0; g < parts; ++g) {
-      sv += s_part[(long long)g * nn + m];
-      bv = cadd(bv, b_part[(long long)g * nn + m]);
+    int g = q;
+    for (; g + 12 < parts; g += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sv[u] += s_part[(long long)(g + 4 * u) * nn + m];
+        bv[u] = cadd(bv[u], b_part[(long long)(g + 4 * u) * nn + m]);
+      }
     }
-    s0[m] = sv;
-    b0[m] = bv;
-    kk = order_key((double)sv);
+    for (; g < parts; g += 4) {
+      sv[0] += s_part[(long long)g * nn + m];
+      bv[0] = cadd(bv[0], b_part[(long long)g * nn + m]);
+    }
   }
-  red[threadIdx.x] = kk;
+  ss[q][lane] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
+  sb[q][lane] = cadd(cadd(bv[0], bv[1]), cadd(bv[2], bv[3]));
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+  if (q == 0) {
+    unsigned long long kk = 0ull;
+    if (m < nn) {
+      const R s = (ss[0][lane] + ss[1][lane]) + (ss[2][lane] + ss[3][lane]);
+      s0[m] = s;
+      b0[m] = cadd(cadd(sb[0][lane], sb[1][lane]), cadd(sb[2][lane], sb[3][lane]));
+      kk = order_key((double)s);
+    }
+    red[lane] = kk;
+  }
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + h];
     __syncthreads();
   }
@@ -661,10 +790,10 @@ __global__ __launch_bounds__(256) void k_obs_emit(const typename real_of<T>::typ
 template <class T, int N, int SIGN>
 static hipError_t launch_obs_n(const T* src, const OperatorTables& op, int pi, int pj, int parts,
                                typename real_of<T>::type* s_part, T* b_part, hipStream_t st) {
-  if constexpr (slab_lds_bytes<T, N>() + N * sizeof(T) > kMaxLds || Split<N>::N2 * N / obs_vt<T, N>() > 1024) {
+  if constexpr (slab_lds_bytes<T, N>() + N * sizeof(T) > kMaxLds || Split<N>::N2 * N > 1024) {
     return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL((k_slab_obs<T, N, SIGN>), dim3((unsigned)parts), dim3(Split<N>::N2 * N / obs_vt<T, N>()), 0, st,
+    hipLaunchKernelGGL((k_slab_obs<T, N, SIGN>), dim3((unsigned)parts), dim3(Split<N>::N2 * N), 0, st,
                        src, op.pre2,
                        op.pre1, pi, pj, s_part, b_part);
     return hipGetLastError();
@@ -674,7 +803,7 @@ static hipError_t launch_obs_n(const T* src, const OperatorTables& op, int pi, i
 template <class T> bool obs_supported(int n) {
   switch (n) {
 #define WOLF_OBS_CASE(NN) \
-  case NN: return slab_lds_bytes<T, NN>() + NN * sizeof(T) <= kMaxLds && Split<NN>::N2 * NN / obs_vt<T, NN>() <= 1024;
+  case NN: return slab_lds_bytes<T, NN>() + NN * sizeof(T) <= kMaxLds && Split<NN>::N2 * NN <= 1024;
     WOLF_OBS_CASE(2) WOLF_OBS_CASE(4) WOLF_OBS_CASE(8) WOLF_OBS_CASE(16) WOLF_OBS_CASE(32) WOLF_OBS_CASE(64)
     WOLF_OBS_CASE(128) WOLF_OBS_CASE(256)
 #undef WOLF_OBS_CASE
@@ -712,7 +841,7 @@ hipError_t launch_obs_sums(int n, const T* src, const OperatorTables& op, int pi
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_obs_clear_key, dim3(1), dim3(1), 0, st, out->key);
-  hipLaunchKernelGGL(k_obs_reduce<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const R*)s_part,
+  hipLaunchKernelGGL(k_obs_reduce<T>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, st, (const R*)s_part,
                      (const T*)b_part, parts, nn, out->s0, out->b0, out->key);
   return hipGetLastError();
 }

@@ -21,7 +21,7 @@ struct OperatorTables {
 // i2 pass run over chunks of `slab_chunk` slabs. The j1 and i1 passes run over chunks of
 // `col_chunk` columns m2 (0 = all).
 struct Plan {
-  bool fused_slab;
+  int fused_slab;  // 0: row pass + i2 axis pass; 1: one slab per workgroup; 2: persistent slab pass
   long long slab_chunk;
   long long col_chunk;
   int coop;        // 1: first-point axes in one cooperative pass (wolf_coop.hip); col_chunk unused

@@ -261,7 +261,7 @@ def test_all_schedules_agree(gpu_lib, dtype):
     nn = n * n
     c = 256 // 4 if 256 // 4 < n else n       # axis tile at N = 32 (N2 = 4)
     plans = [(1, 0, 0, 0, 1), (1, 0, c, 0, 1), (1, 0, nn // 2, 0, 1), (0, 0, 0, 0, 1), (0, nn // 4, c, 0, 1),
-             (0, 2, nn // 8, 0, 1)]
+             (0, 2, nn // 8, 0, 1), (2, 0, 0, 0, 1), (2, 0, c, 0, 1)]
     try:
         for plan in plans:
             gpu_lib.set_plan(n, dtype, *plan)
@@ -272,6 +272,31 @@ def test_all_schedules_agree(gpu_lib, dtype):
             assert gpu_lib.coop_error_flag() == 0, plan
     finally:
         gpu_lib.set_plan(n, dtype)
+
+
+@pytest.mark.parametrize("n,dtype", [(16, torch.complex64), (64, torch.complex64), (128, torch.complex64),
+                                     (16, torch.complex128), (64, torch.complex128)])
+def test_persistent_slab_pass_matches_per_slab(gpu_lib, n, dtype):
+    """The persistent slab pass (fused_slab = 2, grid-stride over slabs with the next slab in flight)
+    runs the same arithmetic as one workgroup per slab, so the outputs agree to rounding (in practice
+    bit for bit). At N = 128 each workgroup takes 64 slabs."""
+    p, z = 20e-6, 0.5
+    if n == 128:
+        w = gpu_lib.build_source(WI.gsm128().source, n, p, dtype)
+    else:
+        w = dev(WI.random_complex((n, n, n, n), seed=60 + n), dtype)
+    nn = n * n
+    outs = []
+    try:
+        for mode in (1, 2):
+            gpu_lib.set_plan(n, dtype, mode, 0, nn, 0, 1)
+            got, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
+            outs.append(got)
+    finally:
+        gpu_lib.set_plan(n, dtype)
+    torch.cuda.synchronize()
+    d = float(torch.linalg.vector_norm(outs[1] - outs[0]) / torch.linalg.vector_norm(outs[0]))
+    assert d <= (1e-6 if dtype == torch.complex64 else 1e-14), d
 
 
 COOP_SKIP = ("the cooperative first-point pass is disabled: its cross-workgroup wait did not complete "
