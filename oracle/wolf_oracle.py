@@ -319,6 +319,55 @@ def propagate_adjoint(g: np.ndarray, n: int, pitch: float, lam: float, z: float,
 
 
 # ----------------------------------------------------------------------------------------------
+# Thin lens and imaging (Sec. 2.2: lens transmission, eqs. WA_imaging, imaging, WC_imaging; R5)
+# ----------------------------------------------------------------------------------------------
+def lens_transmission(n: int, pitch: float, lam: float, focal: float, pupil_geometry: int = GEO_NONE,
+                      pupil_radius: float = 0.0) -> np.ndarray:
+    """T(x) = P(x) q*(f, x) on the N x N grid of `pitch` (Sec. 2.2).
+
+    P is the pupil: 1 inside a circle (or a square of half side `pupil_radius`), decided in pixel
+    units as R4, and 0 outside; GEO_NONE means no aperture (P = 1). The pupil carries no aberration
+    phase. focal = inf (or 0) means no lens phase, only the aperture.
+    """
+    x, y = grid_x(n, pitch), grid_y(n, pitch)
+    r2 = x[:, None] ** 2 + y[None, :] ** 2
+    if math.isinf(focal) or focal == 0.0:
+        t = np.ones((n, n), dtype=np.complex128)
+    else:
+        t = np.conj(q(focal, r2, lam))
+    if pupil_geometry != GEO_NONE:
+        if pupil_geometry not in (GEO_CIRCLE, GEO_SQUARE):
+            raise ValueError("pupil geometry")
+        t = t * geometry_mask(n, pitch, pupil_geometry, pupil_radius)
+    return t
+
+
+def apply_lens(w: np.ndarray, n: int, pitch: float, lam: float, focal: float, pupil_geometry: int = GEO_NONE,
+               pupil_radius: float = 0.0) -> np.ndarray:
+    """W+(x1, x2) = T*(x1) W-(x1, x2) T(x2): the CSD just after a thin lens (Sec. 2.2, R5)."""
+    t = lens_transmission(n, pitch, lam, focal, pupil_geometry, pupil_radius)
+    return np.conj(t)[:, :, None, None] * w * t[None, None, :, :]
+
+
+def propagate_lens(w: np.ndarray, n: int, pitch: float, lam: float, focal: float, z: float,
+                   pupil_geometry: int = GEO_NONE, pupil_radius: float = 0.0,
+                   kind: int = KIND_SECONDARY) -> Tuple[np.ndarray, float]:
+    """A thin lens at the plane of `w` (grid `pitch`), then Fresnel propagation by z: the second
+    stage of eq. (WC_imaging) before the lens law is used. Returns (W, output pitch)."""
+    return propagate(apply_lens(w, n, pitch, lam, focal, pupil_geometry, pupil_radius), n, pitch, lam, z,
+                     False, kind)
+
+
+def image_through_lens(w: np.ndarray, n: int, pitch: float, lam: float, r1: float, focal: float, r2: float,
+                       pupil_geometry: int = GEO_NONE, pupil_radius: float = 0.0,
+                       kind: int = KIND_SECONDARY) -> Tuple[np.ndarray, float]:
+    """Source plane A -> lens plane B (Fresnel, R1) -> lens T = P q*(f) -> image plane C (Fresnel, R2),
+    eq. (WC_imaging) without the approximations that follow it. Returns (W_C, pitch at C)."""
+    wb, pb = propagate(w, n, pitch, lam, r1, False, kind)
+    return propagate_lens(wb, n, pb, lam, focal, r2, pupil_geometry, pupil_radius, kind)
+
+
+# ----------------------------------------------------------------------------------------------
 # Observables (Sec. 3.5, Algorithms 4-5, eqs. defS, defMu)
 # ----------------------------------------------------------------------------------------------
 def spectral_density(w: np.ndarray) -> np.ndarray:

@@ -222,6 +222,60 @@ def test_lens_at_focal_distance_is_far_field():
     assert rel(a, b) < 1e-12
 
 
+# ---------------------------------------------------------------------------------------------
+# Imaging through a thin lens (Sec. 2.2, eqs. WA_imaging, imaging, WC_imaging). On the sampled
+# grids the chain is exact: with the lens law 1/R1 + 1/R2 = 1/f the three middle chirps cancel
+# (q(R1) q*(f) q(R2) = 1), and two forward DFTs reverse the index. So, per axis, the plane-C
+# sample k sees the source sample N - k (mod N), and
+#   W_C[k1; k2] = (R1/R2)^2 phi*(k1) phi(k2) W_A[N - k1; N - k2],
+#   phi(k) = exp(i pi (|x'_k|^2 / R2 + |xi_(N-k)|^2 / R1) / lambda),   x' on the pitch (R2/R1) d.
+# Catches: the lens with the wrong conjugation or focal length, a dropped lens, the stages in the
+# wrong order, the wrong plane-B pitch.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,r1,r2", [(8, 0.2, 0.2), (16, 0.2, 0.2), (16, 0.15, 0.45), (8, 0.5, 0.25)])
+def test_imaging_conjugate_planes_reverse_the_source(n, r1, r2):
+    p = 20e-6
+    f = r1 * r2 / (r1 + r2)
+    wa = WI.random_hermitian_psd(n, seed=21 + n)
+    wc, pc = O.image_through_lens(wa, n, p, LAM, r1, f, r2)
+    assert abs(pc / (p * r2 / r1) - 1) < 1e-14
+    rev = (n - np.arange(n)) % n
+    c = np.arange(n) - n / 2
+    xi2 = (p * c[rev]) ** 2                       # xi of the reversed source index, per axis
+    xc2 = (pc * c) ** 2                           # x' of the image index, per axis
+    ph = np.exp(1j * math.pi * ((xc2[:, None] + xc2[None, :]) / r2 + (xi2[:, None] + xi2[None, :]) / r1) / LAM)
+    ref = (r1 / r2) ** 2 * np.conj(ph)[:, :, None, None] * wa[np.ix_(rev, rev, rev, rev)] * ph[None, None, :, :]
+    assert rel(wc, ref) < 1e-11
+    # the image S is the mirrored source S scaled by 1 / magnification^2
+    assert rel(O.spectral_density(wc), (r1 / r2) ** 2 * O.spectral_density(wa)[np.ix_(rev, rev)]) < 1e-11
+
+
+@pytest.mark.parametrize("geo", [O.GEO_CIRCLE, O.GEO_SQUARE])
+def test_imaging_coherent_source_with_pupil_matches_field_optics(geo):
+    """A coherent source W = U* U stays rank one; through the lens with a finite pupil its image is
+    U_C* U_C, with U_C from two single-field Fresnel transforms (numpy FFT) and the pupil-limited
+    lens T = P q*(f) in between. Catches: the pupil on the wrong point, P applied twice or not at all."""
+    n, p, lam, r1, r2 = 16, 20e-6, LAM, 0.2, 0.3
+    f = r1 * r2 / (r1 + r2) * 1.1                      # slightly defocused: no exact cancellation
+    rng = WI.rng(17)
+    u = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    wa = np.conj(u)[:, :, None, None] * u[None, None, :, :]
+    pb = lam * r1 / (n * p)
+    a = 0.3 * n * pb                                   # pupil radius (half side for the square)
+    ub = CF.fresnel_field_fft(u, n, p, lam, r1)
+    c = np.arange(n) - n / 2
+    d2i, d2j = c[:, None] ** 2 + 0 * c[None, :], 0 * c[:, None] + c[None, :] ** 2
+    thr = (a / pb) ** 2 * (1 + 1e-9)
+    pupil = (d2i + d2j <= thr) if geo == O.GEO_CIRCLE else ((d2i <= thr) & (d2j <= thr))
+    assert 0 < pupil.sum() < n * n
+    xb2 = (pb * c[:, None]) ** 2 + (pb * c[None, :]) ** 2
+    uc = CF.fresnel_field_fft(pupil * np.exp(-1j * math.pi * xb2 / (lam * f)) * ub, n, pb, lam, r2)
+    cc = 1.0 / (lam * r1) ** 2 / (lam * r2) ** 2
+    ref = cc * np.conj(uc)[:, :, None, None] * uc[None, None, :, :]
+    wc, _ = O.image_through_lens(wa, n, p, lam, r1, f, r2, geo, a)
+    assert rel(wc, ref) < 1e-12
+
+
 def test_q_algebra():
     n, p, z = 64, 20e-6, 0.3
     beta = 1.7
