@@ -233,6 +233,12 @@ def extras(wolf, wl, args):
     out["c64_farfield_ms"] = round(tff, 4)
     out["c64_adjoint_ms"] = round(tadj, 4)
     out["adjoint_over_forward"] = round(tadj / t64, 3)
+    # Two-stage imaging (lens plane at 0.4 m, f = 0.2 m, image at 0.4 m, circular pupil), in place:
+    # two operator launches, the lens phase and pupil folded into the second one.
+    pb = lam * 0.4 / (n * p)
+    timg = time_op(lambda: wolf.image_through_lens(o, p, lam, 0.4, 0.2, 0.4, wolf.GEO_CIRCLE, 0.3 * n * pb, out=o))
+    out["c64_imaging_ms"] = round(timg, 4)
+    out["c64_imaging_achieved_GBps"] = round(2 * 32.0 * elems / (timg * 1e-3) / 1e9, 1)
     # Copy ceiling: read + write of the same 2 GiB array.
     tcp = time_op(lambda: o.copy_(w))
     out["copy_ceiling_GBps"] = round(2 * w.numel() * 8 / (tcp * 1e-3) / 1e9, 1)

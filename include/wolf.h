@@ -123,6 +123,26 @@ WOLF_API wolf_status wolf_propagate_farfield(const void* w_in, void* w_out, int3
                                              double* out_pitch_m, void* stream);
 
 /*
+ * wolf_propagate_lens -- a thin lens at the input plane, then Fresnel propagation by z_m
+ * (Sec. 2.2: lens transmission T(x) = P(x) q*(f, x), W+ = T*(x1) W- T(x2); the second stage of
+ * eq. WC_imaging). With wolf_propagate_fresnel from the source plane A to the lens plane B (distance
+ * R1) and this call from B (its pitch is the out_pitch of the first call) to C (distance R2), the
+ * pair is the two-stage imaging system of eqs. WA_imaging and WC_imaging, with no approximation.
+ *   focal_m          focal length f (negative: diverging lens); 0 = no lens phase (pupil only).
+ *   pupil_geometry   WOLF_GEO_NONE (P = 1), WOLF_GEO_CIRCLE (P = 1 for |x| <= r) or WOLF_GEO_SQUARE
+ *                    (P = 1 for |x|, |y| <= r), decided on the input grid in pixel units with the
+ *                    rule of the source geometry. P is real (no aberration phase).
+ *   pupil_radius_m   r (> 0) when pupil_geometry != WOLF_GEO_NONE.
+ * Other arguments, layout, in-place use and errors as wolf_propagate_fresnel. The lens phase only
+ * changes the source-side chirp of the operator (q*(f) q(z) is one chirp), and the pupil is applied
+ * while the first pass loads its input, so the call costs one propagation.
+ */
+WOLF_API wolf_status wolf_propagate_lens(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                         double wavelength_m, double focal_m, int32_t pupil_geometry,
+                                         double pupil_radius_m, double z_m, int32_t kind, int32_t dtype,
+                                         double* out_pitch_m, void* stream);
+
+/*
  * wolf_propagate_adjoint -- adjoint of the Fresnel (farfield = 0) or far-field (farfield = 1)
  * propagation, for the real inner product Re sum conj(a) b. It is the derivative operator of the
  * paper's propagation (eq. W_general).

@@ -30,7 +30,8 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_spectral_density", "wolf_degree_of_coherence", "wolf_propagate_batch", "wolf_chirp_table",
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
-            "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes"]
+            "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
+            "wolf_propagate_lens"]
 
 
 class WolfError(RuntimeError):
@@ -63,6 +64,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_build_source": [ctypes.POINTER(_Source), i32, f64, i32, vp, vp],
         "wolf_propagate_fresnel": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_farfield": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
+        "wolf_propagate_lens": [vp, vp, i32, f64, f64, f64, i32, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_adjoint": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_propagate_adjoint_diag": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_spectral_density": [vp, i32, i32, vp, vp],
@@ -196,6 +198,35 @@ def propagate_farfield(w: torch.Tensor, pitch: float, wavelength: float, z: floa
 
 def propagate(w, pitch, wavelength, z, farfield=False, kind=SECONDARY, out=None):
     return (propagate_farfield if farfield else propagate_fresnel)(w, pitch, wavelength, z, kind, out)
+
+
+def propagate_lens(w: torch.Tensor, pitch: float, wavelength: float, focal: float, z: float,
+                   pupil_geometry: int = GEO_NONE, pupil_radius: float = 0.0, kind: int = SECONDARY,
+                   out: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, float]:
+    """Thin lens T = P q*(f) at the plane of w (pitch `pitch`), then Fresnel propagation by z
+    (Sec. 2.2). focal = 0: pupil only. Returns (W, dx)."""
+    lib = load()
+    n = _csd(w, "w")
+    if out is None:
+        out = torch.empty_like(w)
+    else:
+        _csd(out, "out")
+        if out.dtype != w.dtype or out.shape != w.shape:
+            raise ValueError("out must match w in shape and dtype")
+    dx = ctypes.c_double(0.0)
+    _check(lib.wolf_propagate_lens(_ptr(w), _ptr(out), n, pitch, wavelength, focal, pupil_geometry, pupil_radius,
+                                   z, kind, _code(w.dtype), ctypes.byref(dx), _stream()), "wolf_propagate_lens")
+    return out, dx.value
+
+
+def image_through_lens(w: torch.Tensor, pitch: float, wavelength: float, r1: float, focal: float, r2: float,
+                       pupil_geometry: int = GEO_NONE, pupil_radius: float = 0.0, kind: int = SECONDARY,
+                       out: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, float]:
+    """Source plane -> lens plane (Fresnel, r1) -> thin lens with pupil -> image plane (Fresnel, r2):
+    eqs. WA_imaging and WC_imaging. Two operator launches; the second runs in place on `out`.
+    The pupil radius is in metres on the lens plane. Returns (W_C, pitch at the image plane)."""
+    wb, pb = propagate_fresnel(w, pitch, wavelength, r1, kind, out)
+    return propagate_lens(wb, pb, wavelength, focal, r2, pupil_geometry, pupil_radius, kind, out=wb)
 
 
 def propagate_adjoint(g: torch.Tensor, pitch: float, wavelength: float, z: float, farfield: bool = False,

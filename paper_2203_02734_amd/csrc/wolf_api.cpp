@@ -141,8 +141,18 @@ wolf::OperatorTables make_op(int32_t n, double pitch, double lam, double z, bool
     op.sign2 = +1;
   }
   op.scale = c * pitch * pitch * pitch * pitch;
+  op.pupil = wolf::Pupil{0, 0};
   return op;
 }
+
+// A thin lens T = P q*(f, x) at the input plane (Sec. 2.2): W+ = T*(x1) W T(x2) before a Fresnel
+// propagation. q*(f) times the source chirp q(z) is one chirp q(z f / (f - z)) (eqs. qprop), so the
+// lens only changes the source-side chirp rate; the pupil is applied while the input is loaded.
+struct LensSpec {
+  double focal_m;  // 0: no lens phase
+  int32_t pupil_geometry;
+  double pupil_radius_m;
+};
 
 // The batch extracts S and mu(P, .) without an N^4 output where the observables pass fits.
 bool batch_uses_observables(int32_t n, int32_t dtype) {
@@ -263,18 +273,38 @@ wolf_status run_operator(const T* in, T* out, int32_t n, int32_t dtype, const wo
 
 wolf_status propagate_common(const void* w_in, void* w_out, int32_t n, double pitch, double lam, double z,
                              bool farfield, int32_t kind, int32_t dtype, bool adjoint, double* out_pitch,
-                             void* stream, const char* who) {
+                             void* stream, const char* who, const LensSpec* lens = nullptr) {
   if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d is not a power of two in [2, 256]", who, n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype %d", who, dtype);
   if (!pos_finite(pitch) || !pos_finite(lam) || !pos_finite(z))
     return fail(WOLF_EINVAL, "%s: pitch, wavelength and z must be finite and > 0", who);
   if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind %d", who, kind);
+  if (lens) {
+    if (!std::isfinite(lens->focal_m)) return fail(WOLF_EINVAL, "%s: focal_m must be finite (0 = no lens phase)", who);
+    if (lens->pupil_geometry != WOLF_GEO_NONE && lens->pupil_geometry != WOLF_GEO_CIRCLE &&
+        lens->pupil_geometry != WOLF_GEO_SQUARE)
+      return fail(WOLF_EINVAL, "%s: pupil_geometry must be NONE, CIRCLE or SQUARE", who);
+    if (lens->pupil_geometry != WOLF_GEO_NONE &&
+        (!pos_finite(lens->pupil_radius_m) || lens->pupil_radius_m / pitch > 1e6))
+      return fail(WOLF_EINVAL, "%s: pupil_radius_m must be finite, > 0 and < 1e6 pixels", who);
+  }
   const size_t bytes = n4(n) * elem_bytes(dtype);
   wolf_status s;
   if ((s = check_buf(w_in, bytes, "input")) != WOLF_OK) return s;
   if ((s = check_buf(w_out, bytes, "output")) != WOLF_OK) return s;
   if (partial_overlap(w_in, w_out, bytes)) return fail(WOLF_EINVAL, "%s: input and output partly overlap", who);
-  const wolf::OperatorTables op = make_op(n, pitch, lam, z, farfield, kind, adjoint);
+  wolf::OperatorTables op = make_op(n, pitch, lam, z, farfield, kind, adjoint);
+  if (lens) {
+    if (lens->focal_m != 0.0) {
+      const double a = pitch * pitch * (1.0 / z - 1.0 / lens->focal_m) / lam;
+      op.pre1.alpha = a;
+      op.pre2.alpha = a;
+    }
+    if (lens->pupil_geometry != WOLF_GEO_NONE) {
+      const double rho = lens->pupil_radius_m / pitch;
+      op.pupil = wolf::Pupil{lens->pupil_geometry, (long long)std::floor(rho * rho * (1.0 + 1e-9))};
+    }
+  }
   if (out_pitch) *out_pitch = lam * z / ((double)n * pitch);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == WOLF_C64)
@@ -317,6 +347,15 @@ WOLF_API wolf_status wolf_propagate_farfield(const void* w_in, void* w_out, int3
                                              double* out_pitch_m, void* stream) {
   return propagate_common(w_in, w_out, n, pitch_m, wavelength_m, z_m, true, kind, dtype, false, out_pitch_m,
                           stream, "wolf_propagate_farfield");
+}
+
+WOLF_API wolf_status wolf_propagate_lens(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                         double wavelength_m, double focal_m, int32_t pupil_geometry,
+                                         double pupil_radius_m, double z_m, int32_t kind, int32_t dtype,
+                                         double* out_pitch_m, void* stream) {
+  const LensSpec lens{focal_m, pupil_geometry, pupil_radius_m};
+  return propagate_common(w_in, w_out, n, pitch_m, wavelength_m, z_m, false, kind, dtype, false, out_pitch_m,
+                          stream, "wolf_propagate_lens", &lens);
 }
 
 WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32_t n, double pitch_m,

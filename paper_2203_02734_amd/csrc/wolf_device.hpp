@@ -121,6 +121,22 @@ struct Chirp {
   int checker;     // 1: fold (-1)^n in
 };
 
+// Aperture at the input plane of an operator (the pupil of a thin lens there, Sec. 2.2).
+// geo: 0 none, 1 circle (di^2 + dj^2 <= thr), 2 square (di^2 <= thr and dj^2 <= thr), with
+// di = i - N/2, dj = j - N/2 in pixels and thr = floor((r / pitch)^2 (1 + 1e-9)): the same integer
+// decision as the source geometry.
+struct Pupil {
+  int geo;
+  long long thr;
+};
+
+__host__ __device__ __forceinline__ bool pupil_pass(const Pupil& pu, int i, int j, int N) {
+  const long long di = (long long)i - N / 2, dj = (long long)j - N / 2;
+  if (pu.geo == 1) return di * di + dj * dj <= pu.thr;
+  if (pu.geo == 2) return di * di <= pu.thr && dj * dj <= pu.thr;
+  return true;
+}
+
 // pi * r (r already reduced to [-1, 1]) -> (cos, sin) in FP64.
 __device__ __forceinline__ void sincospi_reduced(double r, double* s, double* c) { sincospi(r, s, c); }
 

@@ -182,6 +182,25 @@ __device__ __forceinline__ void slab_load(const T* in, T* v, int tid) {
   }
 }
 
+// Zero the loaded values outside the pupil (pu.geo != 0), in the layout of slab_load.
+template <class T, int N, int VT = 1>
+__device__ __forceinline__ void slab_mask(const Pupil& pu, T* v, int tid) {
+  using S = Split<N>;
+  using R = typename real_of<T>::type;
+  constexpr int N1 = S::N1, N2 = S::N2;
+  constexpr int NTR = N2 * N / VT;
+  if (pu.geo == 0) return;
+#pragma unroll
+  for (int vt = 0; vt < VT; ++vt) {
+    const int id = tid + vt * NTR;
+    const int c = id % N;
+    const int t = id / N;
+#pragma unroll
+    for (int a = 0; a < N1; ++a)
+      if (!pupil_pass(pu, N2 * a + t, c, N)) v[vt * N1 + a] = T{(R)0, (R)0};
+  }
+}
+
 template <class T, int N, int SIGN, bool ROW_POST, int VT>
 __device__ __forceinline__ void slab_transform_loaded(T* v, T* buf, const T* tpre, const T* tpost, const T* tw,
                                                       const T scal, T* u, int tid);
@@ -303,8 +322,9 @@ __device__ __forceinline__ void slab_transform_loaded(T* v, T* buf, const T* tpr
 
 template <class T, int N, int SIGN>
 __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T* dst, Chirp pre, Chirp post,
-                                                               Chirp slab_pre) {
+                                                               Chirp slab_pre, Pupil pu) {
   using S = Split<N>;
+  using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
   constexpr int NT = N2 * N;
   constexpr int SP = slab_stride<N>();
@@ -312,18 +332,21 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
   __shared__ T tpre[N], tpost[N], tw[N], sc[2];
 
   const long long p1 = blockIdx.x;
+  const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
   for (int i = threadIdx.x; i < N; i += NT) {
     tpre[i] = chirp_entry<T>(pre, i, N);
     tpost[i] = chirp_entry<T>(post, i, N);
     tw[i] = twiddle_entry<T, SIGN>(i, N);
   }
-  if (threadIdx.x < 2) {
-    const int idx = threadIdx.x == 0 ? (int)(p1 / N) : (int)(p1 % N);
-    sc[threadIdx.x] = chirp_entry<T>(slab_pre, idx, N);
-  }
+  if (threadIdx.x < 2) sc[threadIdx.x] = chirp_entry<T>(slab_pre, threadIdx.x == 0 ? a1 : b1, N);
   __syncthreads();
+  T v[N1];
+  slab_load<T, N>(src + p1 * N * N, v, (int)threadIdx.x);
+  slab_mask<T, N>(pu, v, (int)threadIdx.x);
+  T scal = cmul(sc[0], sc[1]);
+  if (!pupil_pass(pu, a1, b1, N)) scal = T{(R)0, (R)0};
   T u[N1];
-  slab_transform<T, N, SIGN>(src + p1 * N * N, buf, tpre, tpost, tw, cmul(sc[0], sc[1]), u, (int)threadIdx.x);
+  slab_transform_loaded<T, N, SIGN, true, 1>(v, buf, tpre, tpost, tw, scal, u, (int)threadIdx.x);
   T* out = dst + p1 * N * N;
   const int t = threadIdx.x % N2;
   const int r = threadIdx.x / N2;
@@ -343,8 +366,9 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
 // current one, so the loads of one slab overlap the arithmetic of the previous one.
 template <class T, int N, int SIGN>
 __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T* dst, long long slabs, Chirp pre,
-                                                                Chirp post, Chirp slab_pre) {
+                                                                Chirp post, Chirp slab_pre, Pupil pu) {
   using S = Split<N>;
+  using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
   constexpr int NT = N2 * N;
   constexpr int SP = slab_stride<N>();
@@ -369,8 +393,11 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T
     T nxt[N1];
     if (pn < slabs) slab_load<T, N>(src + pn * nn, nxt, tid);
     T u[N1];
-    slab_transform_loaded<T, N, SIGN, true, 1>(cur, buf, tpre, tpost, tw,
-                                               cmul(tpre1[(int)(p1 / N)], tpre1[(int)(p1 % N)]), u, tid);
+    const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
+    slab_mask<T, N>(pu, cur, tid);
+    T scal = cmul(tpre1[a1], tpre1[b1]);
+    if (!pupil_pass(pu, a1, b1, N)) scal = T{(R)0, (R)0};
+    slab_transform_loaded<T, N, SIGN, true, 1>(cur, buf, tpre, tpost, tw, scal, u, tid);
     __syncthreads();  // buf is reused by the next slab
     T* out = dst + p1 * nn;
     const int t = tid % N2;
@@ -545,7 +572,7 @@ template <class T, int N> constexpr long long slab_resident_wgs() {
 
 template <class T, int N, int SIGN>
 static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chirp& pre, const Chirp& post,
-                                const Chirp& slab_pre, int mode, hipStream_t st) {
+                                const Chirp& slab_pre, const Pupil& pu, int mode, hipStream_t st) {
   if constexpr (slab_lds_bytes<T, N>() > kMaxLds) {
     return hipErrorInvalidValue;
   } else {
@@ -553,10 +580,10 @@ static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chi
     if (mode == 2) {
       const long long g = slabs < slab_resident_wgs<T, N>() ? slabs : slab_resident_wgs<T, N>();
       hipLaunchKernelGGL((k_slab_fft2p<T, N, SIGN>), dim3((unsigned)g), dim3(Split<N>::N2 * N), 0, st, src, dst,
-                         slabs, pre, post, slab_pre);
+                         slabs, pre, post, slab_pre, pu);
     } else {
       hipLaunchKernelGGL((k_slab_fft2<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N), 0, st, src, dst,
-                         pre, post, slab_pre);
+                         pre, post, slab_pre, pu);
     }
     return hipGetLastError();
   }
@@ -592,10 +619,33 @@ hipError_t launch_row_pass(int n, const T* src, T* dst, long long rows, int sign
 
 template <class T>
 hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slabs, int sign, const Chirp& pre,
-                            const Chirp& post, const Chirp& slab_pre, int mode, hipStream_t st) {
-  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, mode, st))) }
-  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, mode, st)))
+                            const Chirp& post, const Chirp& slab_pre, const Pupil& pu, int mode, hipStream_t st) {
+  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, pu, mode, st))) }
+  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, pu, mode, st)))
 }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_apply_pupil(const T* in, T* out, int n, Pupil pu) {
+  using R = typename real_of<T>::type;
+  const long long nn = (long long)n * n, total = nn * nn;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long p1 = e / nn, p2 = e - p1 * nn;
+    const bool keep = pupil_pass(pu, (int)(p1 / n), (int)(p1 % n), n) && pupil_pass(pu, (int)(p2 / n), (int)(p2 % n), n);
+    out[e] = keep ? in[e] : T{(R)0, (R)0};
+  }
+}
+
+template <class T>
+hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipStream_t st) {
+  const long long total = (long long)n * n * n * n;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_apply_pupil<T>, dim3((unsigned)blocks), dim3(256), 0, st, in, out, n, pu);
+  return hipGetLastError();
+}
+template hipError_t launch_apply_pupil<float2>(int, const float2*, float2*, const Pupil&, hipStream_t);
+template hipError_t launch_apply_pupil<double2>(int, const double2*, double2*, const Pupil&, hipStream_t);
 
 template <class T> bool slab_pass_supported(int n) {
   switch (n) {
@@ -648,9 +698,15 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   const long long N = n, NN = N * N, NNN = NN * N;
   hipError_t e;
   const Chirp ident{0.0, 1.0, +1, 0};
+  // An input pupil is applied while the slab pass loads; the other schedules apply it first.
+  if (op.pupil.geo != 0 && !plan.fused_slab) {
+    e = launch_apply_pupil<T>(n, in, out, op.pupil, st);
+    if (e != hipSuccess) return e;
+    in = out;
+  }
   // Second-point axes (i2, j2).
   if (plan.fused_slab) {
-    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, plan.fused_slab, st);
+    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, op.pupil, plan.fused_slab, st);
     if (e != hipSuccess) return e;
   } else {
     const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk

@@ -11,10 +11,12 @@ namespace wolf {
 // The propagation operator along its four axes. Axis of the first point (i1, j1) and of the
 // second point (i2, j2): diagonal pre-factor, DFT of sign `sign` (-1 direct, +1 inverse,
 // unnormalised), diagonal post-factor. The real `scale` multiplies the result.
+// `pupil` multiplies the input by P(p1) P(p2) (real 0/1) before the transforms.
 struct OperatorTables {
   Chirp pre1, post1, pre2, post2;
   int sign1, sign2;
   double scale;
+  Pupil pupil;
 };
 
 // Schedule of the passes. fused_slab: one slab pass for (i2, j2). Otherwise a row pass and an
@@ -81,6 +83,9 @@ hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, con
                                    int lookahead, void* counters, hipStream_t st);
 size_t coop_counter_bytes(int n);
 template <class T> bool slab_pass_supported(int n);
+// out[p1; p2] = P(p1) P(p2) in[p1; p2] (in == out allowed).
+template <class T>
+hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipStream_t st);
 int axis_tile_cols(int n);
 int row_pass_rows(int n);  // rows per workgroup of the row pass
 

@@ -17,6 +17,7 @@ import pytest
 import torch
 
 import oracle as O
+from tests.gpu_util import separable_rel
 import wolf_inputs as WI
 
 pytestmark = pytest.mark.gpu
@@ -220,18 +221,7 @@ def test_adjoint_dot_product_gpu(gpu_lib):
 # The GSM source is separable, so the oracle's output is bx[m1, m2] by[n1, n2]. The test forms
 # those products one slab at a time and compares them with the GPU output.
 # ---------------------------------------------------------------------------------------------
-def _separable_rel(w_gpu: torch.Tensor, bx: np.ndarray, by: np.ndarray) -> float:
-    n = w_gpu.shape[0]
-    bxt = torch.from_numpy(bx).cuda()
-    byt = torch.from_numpy(by).cuda()
-    num = 0.0
-    den = 0.0
-    for m1 in range(n):
-        blk = w_gpu[m1].to(torch.complex128)                     # [n1][m2][n2]
-        exp = bxt[m1][None, :, None] * byt[:, None, :]           # [n1][m2][n2] = bx[m1,m2] by[n1,n2]
-        num += torch.sum(torch.abs(blk - exp) ** 2).item()
-        den += torch.sum(torch.abs(exp) ** 2).item()
-    return math.sqrt(num / den)
+_separable_rel = separable_rel
 
 
 @pytest.mark.parametrize("farfield", [False, True])
