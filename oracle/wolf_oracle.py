@@ -31,6 +31,11 @@ Readings taken where the paper is ambiguous:
      S(P1) > tau and S(x) > tau, with tau = floor_rel * max S; mu = 0 elsewhere.
   R7 Incoherent source: Kronecker delta W[p1; p2] = A Y(p1) delta(p1, p2), with no 1/d^2
      factor.
+  R8 Exact free-space kernel (eq. h_free, for the validity check of the approximation eq. approx_L
+     and the Fresnel expansion): h = Lambda(r) exp(i k r) / r with r = sqrt(z^2 + |x - xi|^2).
+     Secondary source at normal incidence: cos(theta_i) = 1 and cos(theta_o) = z / r, so
+     Lambda = (k / (4 pi i)) (1 + z / r); primary: Lambda = 1 / (4 pi). The factor 1/i and the
+     common phase exp(i k z) cancel between h* and h, so they are left out.
 """
 from __future__ import annotations
 
@@ -316,6 +321,45 @@ def propagate_adjoint(g: np.ndarray, n: int, pitch: float, lam: float, z: float,
     out = _sum_axis(out, np.conj(kx).T, 2)  # sum over x2 with h*(x2, xi2)
     out = _sum_axis(out, np.conj(ky).T, 3)
     return s * out
+
+
+# ----------------------------------------------------------------------------------------------
+# Exact free-space kernel (eq. h_free; the check of eq. approx_L and of the Fresnel expansion; R8)
+# ----------------------------------------------------------------------------------------------
+def rs_kernel_matrix(n: int, pitch: float, lam: float, z: float, kind: int = KIND_SECONDARY) -> np.ndarray:
+    """H[(m, n), (i, j)] = |Lambda(r)| exp(i k (r - z)) / r between the output point x_mn (grid of
+    eq. spatial_resolution) and the source point xi_ij, with r = sqrt(z^2 + |x - xi|^2) (R8).
+
+    r - z is computed as rho^2 / (r + z), which has no cancellation.
+    """
+    dx = output_pitch(n, pitch, lam, z)
+    xo, yo = grid_x(n, dx), grid_y(n, dx)
+    xs, ys = grid_x(n, pitch), grid_y(n, pitch)
+    Xo = np.repeat(xo, n)
+    Yo = np.tile(yo, n)
+    Xs = np.repeat(xs, n)
+    Ys = np.tile(ys, n)
+    rho2 = (Xo[:, None] - Xs[None, :]) ** 2 + (Yo[:, None] - Ys[None, :]) ** 2
+    r = np.sqrt(z * z + rho2)
+    if kind == KIND_SECONDARY:
+        amp = (1.0 + z / r) / (2.0 * lam)
+    elif kind == KIND_PRIMARY:
+        amp = np.full_like(r, 1.0 / (4.0 * math.pi))
+    else:
+        raise ValueError("kind")
+    return amp / r * np.exp(2j * math.pi * (rho2 / (r + z)) / lam)
+
+
+def propagate_direct(w: np.ndarray, n: int, pitch: float, lam: float, z: float,
+                     kind: int = KIND_SECONDARY) -> Tuple[np.ndarray, float]:
+    """eq. (W_general) with the exact kernel of eq. (h_free), summed directly on the grids (no
+    approximation eq. approx_L, no Fresnel expansion): W_B = d^4 conj(H) W_A H^T with H from
+    rs_kernel_matrix. The output grid is that of the Fresnel operator, for element-wise comparison.
+    Returns (W_B, dx)."""
+    h = rs_kernel_matrix(n, pitch, lam, z, kind)
+    wm = w.reshape(n * n, n * n)
+    out = pitch ** 4 * (np.conj(h) @ wm @ h.T)
+    return out.reshape(n, n, n, n), output_pitch(n, pitch, lam, z)
 
 
 # ----------------------------------------------------------------------------------------------

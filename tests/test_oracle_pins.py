@@ -276,6 +276,62 @@ def test_imaging_coherent_source_with_pupil_matches_field_optics(geo):
     assert rel(wc, ref) < 1e-12
 
 
+# ---------------------------------------------------------------------------------------------
+# Exact free-space kernel (eq. h_free) against the Fresnel operator (eqs. approx_L, W_fresnel).
+# With equal source and output pitch d = sqrt(lambda z / N), the grids span rho ~ sqrt(N lambda z),
+# so every term that the Fresnel expansion drops shrinks like 1/z: the phase -k rho^4 / (8 z^3) and
+# the amplitude terms of Lambda(r)/r. Expanding h to the next order,
+#   h ~ (1/(lambda z)) (1 - 3 rho^2 / (4 z^2)) exp(i k (rho^2/(2z) - rho^4/(8 z^3)))   (secondary)
+#   h ~ (1/(4 pi z)) (1 - rho^2 / (2 z^2)) ...                                          (primary)
+# must leave an error that shrinks like 1/z^2.
+# Catches: a wrong conjugation or grid in the direct sum (an O(1) difference), a wrong scale or
+# obliquity factor (a difference that does not shrink at these rates), a lost or wrong phase term.
+# ---------------------------------------------------------------------------------------------
+def _next_order_kernel_sum(w, n, p, lam, z, kind):
+    dx = lam * z / (n * p)
+    c = np.arange(n) - n / 2
+    xo, yo, xs, ys = dx * c, -dx * c, p * c, -p * c
+    Xo, Yo, Xs, Ys = np.repeat(xo, n), np.tile(yo, n), np.repeat(xs, n), np.tile(ys, n)
+    rho2 = (Xo[:, None] - Xs[None, :]) ** 2 + (Yo[:, None] - Ys[None, :]) ** 2
+    k = 2 * math.pi / lam
+    if kind == O.KIND_SECONDARY:
+        amp = (1 - 0.75 * rho2 / z ** 2) / (lam * z)
+    else:
+        amp = (1 - 0.5 * rho2 / z ** 2) / (4 * math.pi * z)
+    h = amp * np.exp(1j * k * (rho2 / (2 * z) - rho2 ** 2 / (8 * z ** 3)))
+    m = w.reshape(n * n, n * n)
+    return (p ** 4 * (np.conj(h) @ m @ h.T)).reshape(n, n, n, n)
+
+
+@pytest.mark.parametrize("kind", [O.KIND_SECONDARY, O.KIND_PRIMARY])
+def test_direct_kernel_converges_to_fresnel(kind):
+    n = 8
+    w = WI.random_hermitian_psd(n, seed=33)
+    e1, e2 = [], []
+    for z in (2e-3, 4e-3, 8e-3, 16e-3):
+        p = math.sqrt(LAM * z / n)
+        wd, dxd = O.propagate_direct(w, n, p, LAM, z, kind)
+        wf, dxf = O.propagate(w, n, p, LAM, z, False, kind)
+        assert abs(dxd / p - 1) < 1e-12 and dxd == dxf
+        e1.append(rel(wd, wf))
+        e2.append(rel(wd, _next_order_kernel_sum(w, n, p, LAM, z, kind)))
+    assert e1[0] < 1e-2
+    for a, b in zip(e1, e1[1:]):
+        assert 0.45 < b / a < 0.55, e1          # Fresnel error ~ 1/z
+    for a, b in zip(e2, e2[1:]):
+        assert 0.22 < b / a < 0.28, e2          # next-order error ~ 1/z^2
+
+
+def test_direct_kernel_is_hermitian_and_psd():
+    """h* W h keeps a Hermitian non-negative definite W so (eq. W_general holds for any kernel)."""
+    n, p, z = 4, 20e-6, 3e-3
+    w = WI.random_hermitian_psd(n, seed=34)
+    wd, _ = O.propagate_direct(w, n, p, LAM, z)
+    m = wd.reshape(n * n, n * n)
+    assert np.abs(m - m.conj().T).max() < 1e-12 * np.abs(m).max()
+    assert np.linalg.eigvalsh(m).min() > -1e-12 * np.abs(m).max()
+
+
 def test_q_algebra():
     n, p, z = 64, 20e-6, 0.3
     beta = 1.7
