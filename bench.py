@@ -161,6 +161,7 @@ def main():
     if not args.no_extras:
         detail.update(extras(wolf, wl, args))
         detail.update(batch_and_fit(wolf, args))
+        detail.update(direct_check(wolf))
     if args.big:
         detail.update(big(wolf, args))
 
@@ -321,6 +322,46 @@ def batch_and_fit(wolf, args):
     out["fit64_backward_ms"] = round(g, 4)
     out["fit64_backward_over_forward"] = round(g / f, 3)
     return out
+
+
+def direct_check(wolf):
+    """Exact-kernel direct sum (the validity check of the Fresnel approximation), N = 64 GSM source at
+    z = 20 mm: two dense complex products of size N^2 = 4096 (8 N^6 real flops each)."""
+    import torch
+
+    import wolf_inputs as WI
+
+    out = {}
+    n, p, z = 64, 20e-6, 0.02
+    src = WI.gsm_small()[0].source
+    flops = 2 * 8.0 * float(n * n) ** 3
+    for dt, tag in ((torch.complex128, "c128"), (torch.complex64, "c64")):
+        w = wolf.build_source(src, n, p, dt)
+        o = torch.empty_like(w)
+        work = torch.empty(int(wolf.load().wolf_direct_work_bytes(n, 1 if dt == torch.complex128 else 0)),
+                           dtype=torch.uint8, device="cuda")
+        wolf.propagate_direct(w, p, wolf_lam(), z, out=o, work=work)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            wolf.propagate_direct(w, p, wolf_lam(), z, out=o, work=work)
+        b.record()
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b) / 3
+        out[f"direct64_{tag}_ms"] = round(t, 3)
+        out[f"direct64_{tag}_TFLOPs"] = round(flops / (t * 1e-3) / 1e12, 2)
+        del w, o, work
+    w = wolf.build_source(src, n, p, torch.complex128)
+    out["fresnel_validity_n64_z20mm"] = wolf.fresnel_validity(w, p, wolf_lam(), z)
+    del w
+    torch.cuda.empty_cache()
+    return out
+
+
+def wolf_lam():
+    import wolf_inputs as WI
+    return WI.LAMBDA_HENE
 
 
 def big(wolf, args):

@@ -143,6 +143,29 @@ WOLF_API wolf_status wolf_propagate_lens(const void* w_in, void* w_out, int32_t 
                                          double* out_pitch_m, void* stream);
 
 /*
+ * wolf_propagate_direct -- the validity check of the Fresnel propagation: eq. (W_general) with the
+ * exact free-space kernel of eq. (h_free), h = Lambda(r) exp(i k r) / r, r = sqrt(z^2 + |x - xi|^2),
+ * summed directly over the grids, without the approximation Lambda/r ~ Lambda/R (eq. approx_L) and
+ * without the Fresnel expansion of r. Secondary source: Lambda = (k / 4 pi i)(1 + z / r) (normal
+ * incidence); primary: Lambda = 1 / (4 pi). The output grid is that of wolf_propagate_fresnel with
+ * the same arguments (pitch lambda z / (N pitch_m)), so the two results compare element by element;
+ * their difference is the error of the Fresnel approximation for this source and distance.
+ * The kernel does not separate into x and y: the cost is two dense complex products of size N^2
+ * (2 N^6 complex multiply-adds), meant for N <= 64 (N = 128 is accepted).
+ *   w_in, w_out   device N^4 complex of `dtype`; w_in == w_out is allowed (partial overlap is not).
+ *   work          device scratch of wolf_direct_work_bytes(n, dtype) bytes (two N^4 arrays),
+ *                 overwritten, not overlapping w_in or w_out.
+ *   out_pitch_m   optional host output.
+ * Returns WOLF_EUNSUPPORTED for N > 128.
+ */
+WOLF_API wolf_status wolf_propagate_direct(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                           double wavelength_m, double z_m, int32_t kind, int32_t dtype, void* work,
+                                           double* out_pitch_m, void* stream);
+
+/* Bytes of the work buffer of wolf_propagate_direct; -1 if (n, dtype) is not supported. */
+WOLF_API int64_t wolf_direct_work_bytes(int32_t n, int32_t dtype);
+
+/*
  * wolf_propagate_adjoint -- adjoint of the Fresnel (farfield = 0) or far-field (farfield = 1)
  * propagation, for the real inner product Re sum conj(a) b. It is the derivative operator of the
  * paper's propagation (eq. W_general).

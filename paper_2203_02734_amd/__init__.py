@@ -31,7 +31,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
             "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
-            "wolf_propagate_lens"]
+            "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes"]
 
 
 class WolfError(RuntimeError):
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_propagate_fresnel": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_farfield": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_lens": [vp, vp, i32, f64, f64, f64, i32, f64, f64, i32, i32, pd, vp],
+        "wolf_propagate_direct": [vp, vp, i32, f64, f64, f64, i32, i32, vp, pd, vp],
         "wolf_propagate_adjoint": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_propagate_adjoint_diag": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_spectral_density": [vp, i32, i32, vp, vp],
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wolf_fit_work_bytes.restype = ctypes.c_int64
     lib.wolf_batch_work_bytes.argtypes = [i32, i32]
     lib.wolf_batch_work_bytes.restype = ctypes.c_int64
+    lib.wolf_direct_work_bytes.argtypes = [i32, i32]
+    lib.wolf_direct_work_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -227,6 +230,42 @@ def image_through_lens(w: torch.Tensor, pitch: float, wavelength: float, r1: flo
     The pupil radius is in metres on the lens plane. Returns (W_C, pitch at the image plane)."""
     wb, pb = propagate_fresnel(w, pitch, wavelength, r1, kind, out)
     return propagate_lens(wb, pb, wavelength, focal, r2, pupil_geometry, pupil_radius, kind, out=wb)
+
+
+def propagate_direct(w: torch.Tensor, pitch: float, wavelength: float, z: float, kind: int = SECONDARY,
+                     out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, float]:
+    """Direct sum with the exact free-space kernel (eq. h_free), on the output grid of
+    propagate_fresnel: the reference for the error of the Fresnel approximation. Returns (W_B, dx)."""
+    lib = load()
+    n = _csd(w, "w")
+    if out is None:
+        out = torch.empty_like(w)
+    else:
+        _csd(out, "out")
+        if out.dtype != w.dtype or out.shape != w.shape:
+            raise ValueError("out must match w in shape and dtype")
+    nbytes = int(lib.wolf_direct_work_bytes(n, _code(w.dtype)))
+    if nbytes < 0:
+        raise WolfError(EUNSUPPORTED, "wolf_direct_work_bytes", f"N={n} unsupported")
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=w.device)
+    dx = ctypes.c_double(0.0)
+    _check(lib.wolf_propagate_direct(_ptr(w), _ptr(out), n, pitch, wavelength, z, kind, _code(w.dtype), _ptr(work),
+                                     ctypes.byref(dx), _stream()), "wolf_propagate_direct")
+    return out, dx.value
+
+
+def fresnel_validity(w: torch.Tensor, pitch: float, wavelength: float, z: float, kind: int = SECONDARY) -> dict:
+    """Error of the Fresnel propagation of w against the exact-kernel direct sum (eqs. h_free,
+    approx_L): relative L2 distance of W_B and of S_B, and the largest difference of S_B relative
+    to max S_B. Both propagations run in the library; the norms are taken on the device."""
+    wd, _ = propagate_direct(w, pitch, wavelength, z, kind)
+    wf, _ = propagate_fresnel(w, pitch, wavelength, z, kind)
+    sd, sf = spectral_density(wd), spectral_density(wf)
+    d = {"rel_l2_w": float(torch.linalg.vector_norm(wf - wd) / torch.linalg.vector_norm(wd)),
+         "rel_l2_s": float(torch.linalg.vector_norm(sf - sd) / torch.linalg.vector_norm(sd)),
+         "max_s_rel": float((sf - sd).abs().max() / sd.abs().max())}
+    return d
 
 
 def propagate_adjoint(g: torch.Tensor, pitch: float, wavelength: float, z: float, farfield: bool = False,

@@ -358,6 +358,40 @@ WOLF_API wolf_status wolf_propagate_lens(const void* w_in, void* w_out, int32_t 
                           stream, "wolf_propagate_lens", &lens);
 }
 
+WOLF_API int64_t wolf_direct_work_bytes(int32_t n, int32_t dtype) {
+  if (!supported_n(n) || n > 128 || (dtype != WOLF_C64 && dtype != WOLF_C128)) return -1;
+  return (int64_t)wolf::direct_work_bytes(n, (int)elem_bytes(dtype));
+}
+
+WOLF_API wolf_status wolf_propagate_direct(const void* w_in, void* w_out, int32_t n, double pitch_m,
+                                           double wavelength_m, double z_m, int32_t kind, int32_t dtype, void* work,
+                                           double* out_pitch_m, void* stream) {
+  const char* who = "wolf_propagate_direct";
+  if (!supported_n(n) || n > 128) return fail(WOLF_EUNSUPPORTED, "%s: N=%d (powers of two up to 128)", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  if (!pos_finite(pitch_m) || !pos_finite(wavelength_m) || !pos_finite(z_m))
+    return fail(WOLF_EINVAL, "%s: pitch, wavelength and z must be finite and > 0", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind", who);
+  const size_t bytes = n4(n) * elem_bytes(dtype), wb = wolf::direct_work_bytes(n, (int)elem_bytes(dtype));
+  wolf_status s;
+  if ((s = check_buf(w_in, bytes, "w_in")) != WOLF_OK) return s;
+  if ((s = check_buf(w_out, bytes, "w_out")) != WOLF_OK) return s;
+  if ((s = check_buf(work, wb, "work")) != WOLF_OK) return s;
+  if (partial_overlap(w_in, w_out, bytes) || intervals_overlap(work, wb, w_in, bytes) ||
+      intervals_overlap(work, wb, w_out, bytes))
+    return fail(WOLF_EINVAL, "%s: buffers overlap", who);
+  if (out_pitch_m) *out_pitch_m = wavelength_m * z_m / ((double)n * pitch_m);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int primary = kind == WOLF_PRIMARY ? 1 : 0;
+  const hipError_t e =
+      dtype == WOLF_C64
+          ? wolf::launch_direct<float2>(n, (const float2*)w_in, (float2*)w_out, work, pitch_m, wavelength_m, z_m,
+                                        primary, st)
+          : wolf::launch_direct<double2>(n, (const double2*)w_in, (double2*)w_out, work, pitch_m, wavelength_m, z_m,
+                                         primary, st);
+  return launched(e, who);
+}
+
 WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32_t n, double pitch_m,
                                             double wavelength_m, double z_m, int32_t farfield, int32_t kind,
                                             int32_t dtype, void* stream) {

@@ -89,6 +89,12 @@ hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipSt
 int axis_tile_cols(int n);
 int row_pass_rows(int n);  // rows per workgroup of the row pass
 
+// Direct sum with the exact free-space kernel (wolf_direct.hip). work: direct_work_bytes(n, elem).
+template <class T>
+hipError_t launch_direct(int n, const T* in, T* out, void* work, double pitch, double lam, double z, int primary,
+                         hipStream_t st);
+size_t direct_work_bytes(int n, int elem);
+
 // Source description after host-side validation and unit conversion.
 struct SourceParams {
   int model;
