@@ -74,9 +74,12 @@ def grid_y(n: int, pitch: float) -> np.ndarray:
     return pitch * (n / 2 - np.arange(n, dtype=np.float64))
 
 
-def output_pitch(n: int, pitch: float, lam: float, z: float) -> float:
-    """Sec. 3.3, eq. (spatial_resolution): dx = 2 pi c R / (omega N dxi) = lambda R / (N dxi)."""
-    return lam * z / (n * pitch)
+def output_pitch(n: int, pitch: float, lam: float, z: float, n_fft: Optional[int] = None) -> float:
+    """Sec. 3.3, eq. (spatial_resolution): dx = 2 pi c R / (omega N dxi) = lambda R / (N dxi).
+
+    With zero padding to n_fft points, N in this relation is n_fft (Sec. 3.3, the remark on zero
+    padding): the output grid is finer, and the result is cropped back to N points."""
+    return lam * z / ((n if n_fft is None else n_fft) * pitch)
 
 
 def fresnel_number(a: float, lam: float, z: float) -> float:
@@ -110,14 +113,17 @@ def coupling_constant(lam: float, z: float, kind: int = KIND_SECONDARY) -> float
     raise ValueError("kind")
 
 
-def kernel_1d(n: int, pitch: float, lam: float, z: float, farfield: bool, axis: str) -> np.ndarray:
+def kernel_1d(n: int, pitch: float, lam: float, z: float, farfield: bool, axis: str,
+              n_fft: Optional[int] = None) -> np.ndarray:
     """One axis factor K[m, i] of the propagation kernel h(x, xi), on the output and source grids.
 
     Fresnel (eqs. h_free, approx_L, W_fresnel): h(x, xi) = exp(i pi |x - xi|^2 / (lambda R)).
     Far field (eq. W_farfield, q(R, xi) set to 1): h(x, xi) = exp(i pi |x|^2 / (lambda R)) exp(-2 pi i x.xi / (lambda R)).
     Both factorise into an x factor times a y factor. The constant amplitude Lambda / R is in C.
+    n_fft: the output pitch of zero padding to n_fft points (see output_pitch); the N output samples
+    are the central ones of the padded grid, at the same centred coordinates.
     """
-    dx = output_pitch(n, pitch, lam, z)
+    dx = output_pitch(n, pitch, lam, z, n_fft)
     if axis == "x":
         xo, xs = grid_x(n, dx), grid_x(n, pitch)
     else:
@@ -223,21 +229,22 @@ def _sum_axis(w: np.ndarray, k: np.ndarray, axis: int) -> np.ndarray:
 
 
 def propagate(w: np.ndarray, n: int, pitch: float, lam: float, z: float, farfield: bool = False,
-              kind: int = KIND_SECONDARY) -> Tuple[np.ndarray, float]:
+              kind: int = KIND_SECONDARY, n_fft: Optional[int] = None) -> Tuple[np.ndarray, float]:
     """W_B(x1, x2) = C d^4 sum_{xi1, xi2} h*(x1, xi1) W_A(xi1, xi2) h(x2, xi2) (eq. W_general, R1, R2).
 
     The four source coordinates (xi1, eta1, xi2, eta2) are summed one at a time, each against
     its own axis factor of h. h factorises into an x factor and a y factor (see kernel_1d).
+    Any even n is allowed; n_fft (>= n) selects the output grid of zero padding (output_pitch).
     Returns (W_B, dx), where dx is the output pitch of eq. (spatial_resolution).
     """
-    kx = kernel_1d(n, pitch, lam, z, farfield, "x")
-    ky = kernel_1d(n, pitch, lam, z, farfield, "y")
+    kx = kernel_1d(n, pitch, lam, z, farfield, "x", n_fft)
+    ky = kernel_1d(n, pitch, lam, z, farfield, "y", n_fft)
     s = coupling_constant(lam, z, kind) * pitch ** 4
     out = _sum_axis(w, kx, 2)              # sum over xi2 with h(x2, xi2)
     out = _sum_axis(out, ky, 3)            # sum over eta2
     out = _sum_axis(out, np.conj(kx), 0)   # sum over xi1 with h*(x1, xi1)
     out = _sum_axis(out, np.conj(ky), 1)   # sum over eta1
-    return s * out, output_pitch(n, pitch, lam, z)
+    return s * out, output_pitch(n, pitch, lam, z, n_fft)
 
 
 def propagate_matrix(w: np.ndarray, n: int, pitch: float, lam: float, z: float,
@@ -295,13 +302,14 @@ def propagate_alg2(w: np.ndarray, n: int, pitch: float, lam: float, z: float,
 
 
 def propagate_separable(wx: np.ndarray, wy: np.ndarray, n: int, pitch: float, lam: float, z: float,
-                        farfield: bool = False, kind: int = KIND_SECONDARY) -> Tuple[np.ndarray, np.ndarray]:
+                        farfield: bool = False, kind: int = KIND_SECONDARY,
+                        n_fft: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
     """For W_A[i1, j1, i2, j2] = wx[i1, i2] wy[j1, j2], the operator of `propagate` gives
     W_B = bx[m1, m2] by[n1, n2], with bx = C d^4 conj(Kx) wx Kx^T and by = conj(Ky) wy Ky^T.
     This is the same sum with the x and y coordinates summed separately.
     """
-    kx = kernel_1d(n, pitch, lam, z, farfield, "x")
-    ky = kernel_1d(n, pitch, lam, z, farfield, "y")
+    kx = kernel_1d(n, pitch, lam, z, farfield, "x", n_fft)
+    ky = kernel_1d(n, pitch, lam, z, farfield, "y", n_fft)
     s = coupling_constant(lam, z, kind) * pitch ** 4
     return s * (np.conj(kx) @ wx @ kx.T), np.conj(ky) @ wy @ ky.T
 

@@ -332,6 +332,42 @@ def test_direct_kernel_is_hermitian_and_psd():
     assert np.linalg.eigvalsh(m).min() > -1e-12 * np.abs(m).max()
 
 
+# ---------------------------------------------------------------------------------------------
+# Zero padding (Sec. 3.3): the paper pads the N x N array to N_z x N_z, transforms, and crops back,
+# with N_z in the relation of eq. (spatial_resolution). Done literally here: embed the N^4 source in
+# an N_z^4 zero array, propagate that at size N_z, crop the central N^4. The oracle's definition with
+# n_fft = N_z must give the same array. N need not be a power of two.
+# Catches: N instead of N_z in dx, an off-by-one crop (centre), padding on the wrong axes.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,nz", [(4, 8), (6, 10), (6, 16), (10, 10)])
+@pytest.mark.parametrize("farfield", [False, True])
+def test_zero_padding_equals_embed_propagate_crop(n, nz, farfield):
+    p, z = 20e-6, 0.05
+    w = WI.random_hermitian_psd(n, seed=40 + n)
+    s0 = (nz - n) // 2
+    big = np.zeros((nz,) * 4, dtype=np.complex128)
+    sl = slice(s0, s0 + n)
+    big[sl, sl, sl, sl] = w
+    wb_big, dx_big = O.propagate(big, nz, p, LAM, z, farfield)
+    got, dx = O.propagate(w, n, p, LAM, z, farfield, n_fft=nz)
+    assert dx == dx_big == LAM * z / (nz * p)
+    assert rel(got, wb_big[sl, sl, sl, sl]) < 1e-12
+
+
+@pytest.mark.parametrize("n,nz", [(96, 96), (120, 240), (100, 256)])
+def test_gsm_closed_form_non_power_of_two(n, nz):
+    """GSM (separable) at N = 96, 100, 120, with and without padding, against the re-derived closed
+    form: nothing in the definition needs N or N_z to be a power of two."""
+    p, z, ss, sg = 20e-6, 0.5, 0.1e-3, 0.05e-3
+    bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, ss, sg, "x"), O.gsm_axis_factor(n, p, ss, sg, "y"),
+                                   n, p, LAM, z, n_fft=nz)
+    dx = O.output_pitch(n, p, LAM, z, nz)
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    cx = CF.gsm_axis_closed_form(X[:, None], X[None, :], ss, sg, LAM, z, False)
+    cy = CF.gsm_axis_closed_form(Y[:, None], Y[None, :], ss, sg, LAM, z, False)
+    assert rel(np.kron(bx, by), np.kron(cx, cy)) < 1e-8
+
+
 def test_q_algebra():
     n, p, z = 64, 20e-6, 0.3
     beta = 1.7
