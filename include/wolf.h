@@ -166,6 +166,25 @@ WOLF_API wolf_status wolf_propagate_direct(const void* w_in, void* w_out, int32_
 WOLF_API int64_t wolf_direct_work_bytes(int32_t n, int32_t dtype);
 
 /*
+ * wolf_propagate_padded -- Fresnel or far-field propagation (eqs. W_fresnel, W_farfield) for any
+ * even N and with zero padding (Sec. 3.3): the N-point axes are padded to n_fft points for the
+ * transform and the result is cropped back to the central N points, so the output pitch is
+ * lambda z / (n_fft pitch_m) (eq. spatial_resolution with n_fft in place of N). n_fft = N gives the
+ * plain operator for N that are not powers of two (e.g. the paper's N = 200 examples, padded to
+ * n_fft = 512). Each axis is a dense N x N product with the exact centred kernel
+ * e^{-+2 pi i (k - N/2)(n - N/2) / n_fft} (four passes; no FFT, so the cost is 32 N real flops per
+ * element; the power-of-two entry points are faster where they apply).
+ *   n          even, 2..256.   n_fft   N..2048.
+ *   w_in, w_out   device N^4 complex; w_in == w_out allowed (partial overlap is not).
+ *   work       device N^4 complex of `dtype`, overwritten; must not overlap w_in or w_out.
+ *   farfield   0 Fresnel, 1 far field.   kind, dtype, out_pitch_m as wolf_propagate_fresnel.
+ * The source builder and the observables accept any even N as well.
+ */
+WOLF_API wolf_status wolf_propagate_padded(const void* w_in, void* w_out, int32_t n, int32_t n_fft, double pitch_m,
+                                           double wavelength_m, double z_m, int32_t farfield, int32_t kind, int32_t dtype,
+                                           void* work, double* out_pitch_m, void* stream);
+
+/*
  * wolf_propagate_adjoint -- adjoint of the Fresnel (farfield = 0) or far-field (farfield = 1)
  * propagation, for the real inner product Re sum conj(a) b. It is the derivative operator of the
  * paper's propagation (eq. W_general).

@@ -194,7 +194,10 @@ def build_source(spec, n: int, pitch: float) -> np.ndarray:
         else:
             raise ValueError("model")
         amp = amp * geo
-        inv2g2 = 0.0 if math.isinf(spec.sigma_g_m) else 1.0 / (2.0 * spec.sigma_g_m ** 2)
+        # The Gaussian degree of coherence belongs to the GSM and MAP models only; a coherent source
+        # has mu = 1 whatever sigma_g says (Sec. 5.1).
+        uses_g = spec.model in (MODEL_GSM, MODEL_MAP) and not math.isinf(spec.sigma_g_m)
+        inv2g2 = 1.0 / (2.0 * spec.sigma_g_m ** 2) if uses_g else 0.0
         dX = X[:, :, None, None] - X[None, None, :, :]
         dY = Y[:, :, None, None] - Y[None, None, :, :]
         mu = np.exp(-(dX ** 2 + dY ** 2) * inv2g2)

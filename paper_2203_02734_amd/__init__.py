@@ -31,7 +31,8 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_output_pitch", "wolf_status_string", "wolf_last_error_message", "wolf_version",
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
             "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
-            "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes"]
+            "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes",
+            "wolf_propagate_padded"]
 
 
 class WolfError(RuntimeError):
@@ -66,6 +67,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_propagate_farfield": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_lens": [vp, vp, i32, f64, f64, f64, i32, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_direct": [vp, vp, i32, f64, f64, f64, i32, i32, vp, pd, vp],
+        "wolf_propagate_padded": [vp, vp, i32, i32, f64, f64, f64, i32, i32, i32, vp, pd, vp],
         "wolf_propagate_adjoint": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_propagate_adjoint_diag": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_spectral_density": [vp, i32, i32, vp, vp],
@@ -266,6 +268,28 @@ def fresnel_validity(w: torch.Tensor, pitch: float, wavelength: float, z: float,
          "rel_l2_s": float(torch.linalg.vector_norm(sf - sd) / torch.linalg.vector_norm(sd)),
          "max_s_rel": float((sf - sd).abs().max() / sd.abs().max())}
     return d
+
+
+def propagate_padded(w: torch.Tensor, pitch: float, wavelength: float, z: float, n_fft: Optional[int] = None,
+                     farfield: bool = False, kind: int = SECONDARY, out: Optional[torch.Tensor] = None,
+                     work: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, float]:
+    """Propagation for any even N, with zero padding of the transform to n_fft points and the result
+    cropped back to N (Sec. 3.3; n_fft = N by default). Returns (W_B, dx), dx = lambda z / (n_fft pitch)."""
+    lib = load()
+    n = _csd(w, "w")
+    if out is None:
+        out = torch.empty_like(w)
+    else:
+        _csd(out, "out")
+        if out.dtype != w.dtype or out.shape != w.shape:
+            raise ValueError("out must match w in shape and dtype")
+    if work is None:
+        work = torch.empty_like(w)
+    dx = ctypes.c_double(0.0)
+    _check(lib.wolf_propagate_padded(_ptr(w), _ptr(out), n, n if n_fft is None else int(n_fft), pitch, wavelength, z,
+                                     int(bool(farfield)), kind, _code(w.dtype), _ptr(work), ctypes.byref(dx),
+                                     _stream()), "wolf_propagate_padded")
+    return out, dx.value
 
 
 def propagate_adjoint(g: torch.Tensor, pitch: float, wavelength: float, z: float, farfield: bool = False,

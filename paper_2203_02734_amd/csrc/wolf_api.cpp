@@ -30,6 +30,8 @@ wolf_status fail(wolf_status s, const char* fmt, ...) {
 }
 
 bool supported_n(int32_t n) { return n >= 2 && n <= 256 && (n & (n - 1)) == 0; }
+// Sizes that the source builder, the observables and wolf_propagate_padded accept: any even N.
+bool even_n(int32_t n) { return n >= 2 && n <= 256 && n % 2 == 0; }
 bool pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
 size_t elem_bytes(int32_t dtype) { return dtype == WOLF_C64 ? 8 : 16; }
 size_t real_bytes(int32_t dtype) { return dtype == WOLF_C64 ? 4 : 8; }
@@ -392,6 +394,51 @@ WOLF_API wolf_status wolf_propagate_direct(const void* w_in, void* w_out, int32_
   return launched(e, who);
 }
 
+WOLF_API wolf_status wolf_propagate_padded(const void* w_in, void* w_out, int32_t n, int32_t n_fft, double pitch_m,
+                                           double wavelength_m, double z_m, int32_t farfield, int32_t kind, int32_t dtype,
+                                           void* work, double* out_pitch_m, void* stream) {
+  const char* who = "wolf_propagate_padded";
+  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d (even, 2..256)", who, n);
+  if (!wolf::dense_supported(n, n_fft)) return fail(WOLF_EUNSUPPORTED, "%s: n_fft=%d (N..2048)", who, n_fft);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  if (!pos_finite(pitch_m) || !pos_finite(wavelength_m) || !pos_finite(z_m))
+    return fail(WOLF_EINVAL, "%s: pitch, wavelength and z must be finite and > 0", who);
+  if (farfield != 0 && farfield != 1) return fail(WOLF_EINVAL, "%s: farfield must be 0 or 1", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind", who);
+  const size_t bytes = n4(n) * elem_bytes(dtype);
+  wolf_status s;
+  if ((s = check_buf(w_in, bytes, "w_in")) != WOLF_OK) return s;
+  if ((s = check_buf(w_out, bytes, "w_out")) != WOLF_OK) return s;
+  if ((s = check_buf(work, bytes, "work")) != WOLF_OK) return s;
+  if (partial_overlap(w_in, w_out, bytes) || intervals_overlap(work, bytes, w_in, bytes) ||
+      intervals_overlap(work, bytes, w_out, bytes))
+    return fail(WOLF_EINVAL, "%s: buffers overlap", who);
+  // Tables of the dense passes: chirps on the N-point grids, no (-1)^n (the centring is exact in
+  // the kernel index), output pitch lambda z / (n_fft pitch).
+  const double dx = wavelength_m * z_m / ((double)n_fft * pitch_m);
+  const double c = kind == WOLF_PRIMARY ? 1.0 / ((4.0 * M_PI * z_m) * (4.0 * M_PI * z_m))
+                                        : 1.0 / ((wavelength_m * z_m) * (wavelength_m * z_m));
+  const double a_src = farfield ? 0.0 : pitch_m * pitch_m / (wavelength_m * z_m);
+  const double a_out = dx * dx / (wavelength_m * z_m);
+  wolf::OperatorTables op;
+  op.pre2 = wolf::Chirp{a_src, 1.0, +1, 0};
+  op.post2 = wolf::Chirp{a_out, 1.0, +1, 0};
+  op.sign2 = -1;
+  op.pre1 = wolf::Chirp{a_src, 1.0, -1, 0};
+  op.post1 = wolf::Chirp{a_out, 1.0, -1, 0};
+  op.sign1 = +1;
+  op.scale = c * pitch_m * pitch_m * pitch_m * pitch_m;
+  op.pupil = wolf::Pupil{0, 0};
+  if (out_pitch_m) *out_pitch_m = dx;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e =
+      dtype == WOLF_C64
+          ? wolf::launch_operator_dense<float2>(n, n_fft, (const float2*)w_in, (float2*)w_out, (float2*)work, op, st)
+          : wolf::launch_operator_dense<double2>(n, n_fft, (const double2*)w_in, (double2*)w_out, (double2*)work, op,
+                                                 st);
+  return launched(e, who);
+}
+
 WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32_t n, double pitch_m,
                                             double wavelength_m, double z_m, int32_t farfield, int32_t kind,
                                             int32_t dtype, void* stream) {
@@ -403,7 +450,7 @@ WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32
 WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double pitch_m, int32_t dtype, void* w_out,
                                        void* stream) {
   if (src == nullptr) return fail(WOLF_EINVAL, "wolf_build_source: null source");
-  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_build_source: N=%d unsupported", n);
+  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_build_source: N=%d (even, 2..256)", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_build_source: bad dtype");
   if (!pos_finite(pitch_m)) return fail(WOLF_EINVAL, "wolf_build_source: pitch must be finite and > 0");
   if (src->model < 0 || src->model > 3) return fail(WOLF_EINVAL, "wolf_build_source: bad model %d", src->model);
@@ -455,7 +502,7 @@ WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double
 }
 
 WOLF_API wolf_status wolf_spectral_density(const void* w, int32_t n, int32_t dtype, void* s_out, void* stream) {
-  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_spectral_density: N=%d unsupported", n);
+  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_spectral_density: N=%d (even, 2..256)", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_spectral_density: bad dtype");
   wolf_status s;
   if ((s = check_buf(w, n4(n) * elem_bytes(dtype), "w")) != WOLF_OK) return s;
@@ -469,7 +516,7 @@ WOLF_API wolf_status wolf_spectral_density(const void* w, int32_t n, int32_t dty
 
 WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp,
                                               double s_floor_rel, void* mu_out, void* stream) {
-  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_degree_of_coherence: N=%d unsupported", n);
+  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_degree_of_coherence: N=%d (even, 2..256)", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_degree_of_coherence: bad dtype");
   const bool full = ip == -1 && jp == -1;
   if (!full && (ip < 0 || ip >= n || jp < 0 || jp >= n))
@@ -496,7 +543,7 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
 
 WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double wavelength_m, double z_m, int32_t dtype,
                                       void* out, void* stream) {
-  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_chirp_table: N=%d unsupported", n);
+  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_chirp_table: N=%d (even, 2..256)", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_chirp_table: bad dtype");
   if (!pos_finite(pitch_m) || !pos_finite(wavelength_m) || !pos_finite(z_m))
     return fail(WOLF_EINVAL, "wolf_chirp_table: pitch, wavelength and z must be finite and > 0");

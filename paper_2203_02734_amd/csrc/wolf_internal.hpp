@@ -89,6 +89,13 @@ hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipSt
 int axis_tile_cols(int n);
 int row_pass_rows(int n);  // rows per workgroup of the row pass
 
+// The operator for any even N and transform length N_z >= N (zero padding and crop), as four dense
+// axis passes (wolf_dense.hip). work: N^4 elements. Tables without the (-1)^n centring factor.
+bool dense_supported(int n, int nz);
+template <class T>
+hipError_t launch_operator_dense(int n, int nz, const T* in, T* out, T* work, const OperatorTables& op,
+                                 hipStream_t st);
+
 // Direct sum with the exact free-space kernel (wolf_direct.hip). work: direct_work_bytes(n, elem).
 template <class T>
 hipError_t launch_direct(int n, const T* in, T* out, void* work, double pitch, double lam, double z, int primary,

@@ -60,7 +60,11 @@ __global__ __launch_bounds__(256) void k_build_source(T* __restrict__ w, int n, 
   T* slab = w + (long long)p1 * nn;
   if (sp.model == 3) {  // incoherent: Kronecker delta in (p1, p2)
     for (long long e = threadIdx.x; e < nn; e += blockDim.x) slab[e] = T{(R)0, (R)0};
-    if (threadIdx.x == 0) slab[p1] = T{am1, (R)0};
+    __syncthreads();  // every zero of this slab is written before the diagonal entry
+    if (threadIdx.x == 0) {
+      __threadfence_block();
+      slab[p1] = T{am1, (R)0};
+    }
     return;
   }
   for (long long e = threadIdx.x; e < nn; e += blockDim.x) {

@@ -65,13 +65,20 @@ def test_output_pitch_matches_paper_relation(lib):
 
 
 @pytest.mark.parametrize("n", [0, 1, 3, 12, 200, 512, -4])
-def test_unsupported_sizes(lib, n):
+def test_unsupported_sizes_fft_path(lib, n):
+    """The FFT-based operator takes powers of two in [2, 256]."""
     assert lib.wolf_propagate_fresnel(None, None, n, 1e-5, 5e-7, 0.1, 0, 0, None, None) == -2
     assert lib.wolf_propagate_farfield(None, None, n, 1e-5, 5e-7, 0.1, 0, 0, None, None) == -2
     assert lib.wolf_propagate_adjoint(None, None, n, 1e-5, 5e-7, 0.1, 0, 0, 0, None) == -2
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 5, 258, 512, -4])
+def test_unsupported_sizes_any_even(lib, n):
+    """The builder, the observables and the padded operator take any even N in [2, 256]."""
     assert lib.wolf_spectral_density(None, n, 0, None, None) == -2
     assert lib.wolf_degree_of_coherence(None, n, 0, 0, 0, 1e-12, None, None) == -2
     assert lib.wolf_chirp_table(n, 1e-5, 5e-7, 0.1, 0, None, None) == -2
+    assert lib.wolf_propagate_padded(None, None, n, 512, 1e-5, 5e-7, 0.1, 0, 0, 0, None, None, None) == -2
 
 
 @pytest.mark.parametrize("args", [

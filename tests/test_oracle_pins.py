@@ -170,6 +170,19 @@ def test_primary_source_scale():
 # van Cittert-Zernike form holds exactly. The annulus mu follows the Bessel form to pixel accuracy.
 # Catches: the chirp applied on the output side only, or a wrong sign in the x1 - x2 dependence.
 # ---------------------------------------------------------------------------------------------
+def test_coherent_source_is_rank_one_whatever_sigma_g():
+    """A coherent source (Sec. 5.1) has |mu| = 1: W = A Y(p1) Y(p2) is rank one, and sigma_g (a GSM
+    and MAP parameter) does not enter. Catches: the Gaussian mu applied to the coherent model."""
+    n, p = 10, 20e-6
+    w = O.build_source(spec(model=O.MODEL_COHERENT, amplitude=1.3, sigma_g_m=0.04e-3, geometry=O.GEO_CIRCLE,
+                            geo_r0_m=3.5 * p), n, p)
+    ev = np.linalg.eigvalsh(w.reshape(n * n, n * n))
+    assert ev[-2] < 1e-12 * ev[-1]
+    s = O.spectral_density(w)
+    mu = O.degree_of_coherence(w, n // 2, n // 2, 1e-12)
+    assert np.allclose(np.abs(mu)[s > 0], 1.0, atol=1e-14)
+
+
 def test_incoherent_source_identities():
     n, p, z = 16, 20e-6, 0.2
     sp = spec(model=O.MODEL_INCOHERENT, amplitude=2.0, geometry=O.GEO_ANNULUS, geo_r0_m=6 * p,
