@@ -162,6 +162,7 @@ def main():
         detail.update(extras(wolf, wl, args))
         detail.update(batch_and_fit(wolf, args))
         detail.update(direct_check(wolf))
+        detail.update(padded_check(wolf))
     if args.big:
         detail.update(big(wolf, args))
 
@@ -357,6 +358,39 @@ def direct_check(wolf):
     del w
     torch.cuda.empty_cache()
     return out
+
+
+def padded_check(wolf):
+    """The paper's example size: N = 200 (not a power of two), transform padded to N_z = 512, GSM
+    source, Fresnel z = 0.5 m, complex64, in place (1.6e9 elements; 12.8 GB + a 12.8 GB work array).
+    Four dense axis passes: 4 x N complex multiply-adds = 32 N real flops per element."""
+    import types
+
+    import torch
+
+    import wolf_inputs as WI
+
+    n, nz, p, z = 200, 512, 20e-6, 0.5
+    src = types.SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=0.1e-3, sigma_g_m=0.05e-3,
+                                geometry=WI.GEO_NONE, geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None,
+                                lens_focal_m=0.0, wavelength_m=0.0)
+    w = wolf.build_source(src, n, p, torch.complex64)
+    work = torch.empty_like(w)
+    wolf.propagate_padded(w, p, wolf_lam(), z, nz, out=w, work=work)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(2):
+        wolf.propagate_padded(w, p, wolf_lam(), z, nz, out=w, work=work)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / 2
+    elems = float(n) ** 4
+    flops = 32.0 * n * elems
+    del w, work
+    torch.cuda.empty_cache()
+    return {"padded200_512_c64_ms": round(t, 2), "padded200_512_elems_per_s": elems / (t * 1e-3),
+            "padded200_512_TFLOPs": round(flops / (t * 1e-3) / 1e12, 2)}
 
 
 def wolf_lam():

@@ -239,6 +239,23 @@ def test_full_size_gsm128(gpu_lib, farfield, dtype):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("farfield,dtype", [(False, torch.complex64), (True, torch.complex64),
+                                             (False, torch.complex128)])
+def test_full_size_gsm256(gpu_lib, farfield, dtype):
+    """N = 256 (2^32 elements: 34 GB in complex64, 69 GB in complex128), in place, every entry against
+    the separable oracle. At this size the slab does not fit the LDS, so the row and axis passes run."""
+    wl = WI.gsm256()[1 if farfield else 0]
+    n, p, z = wl.n, wl.pitch_m, wl.z_m
+    sp = wl.source
+    w = gpu_lib.build_source(sp, n, p, dtype)
+    gpu_lib.propagate(w, p, LAM, z, farfield, out=w)
+    bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x"),
+                                   O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y"), n, p, LAM, z, farfield)
+    assert _separable_rel(w, bx, by) < TOL[dtype]
+    del w
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------------------------------------
 # Every pass schedule gives the same operator (fused slab or row + i2 passes; any chunking).
 # ---------------------------------------------------------------------------------------------
