@@ -83,7 +83,7 @@ def timed_steps(fn, steps, warmup, marks):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; run it with --gpus 1 "
+        print("bench.py: measures one GPU only; run it with --gpus 1 "
               "(multi-GPU sharding of the CSD propagation is described, not built).", file=sys.stderr)
         sys.exit(2)
 

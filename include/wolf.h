@@ -308,7 +308,7 @@ WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double waveleng
  *   coop_wgs    > 0: the first-point axes run as one cooperative pass (one HBM sweep) on a persistent
  *               grid of coop_wgs workgroups (a multiple of 8). Each 128 B-wide column tile is
  *               transformed along j1 and then i1 by the workgroups of one XCD, through that XCD's L2.
- *               Needs 32 <= N <= 128. 0: two passes, chunked by col_chunk. This build disables the
+ *               Needs 32 <= N <= 128. 0: two passes, chunked by col_chunk. The library disables the
  *               cooperative pass: coop_wgs > 0 returns WOLF_EUNSUPPORTED.
  *   coop_lookahead  tiles whose phase A may run ahead of phase B on an XCD (1..8).
  * wolf_set_plan with fused_slab = slab_chunk = col_chunk = -1 restores the built-in default.
