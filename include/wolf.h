@@ -300,7 +300,9 @@ WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double waveleng
  *   fused_slab  1: one pass does both second-point axes, one N x N slab per workgroup in LDS
  *                  (needs N^2 elements <= 160 KB of LDS). 2: the same pass on a persistent grid
  *                  (as many workgroups as are resident), each loading the next slab into the L2
- *                  while it transforms the current one. 0: a row pass and an i2 pass instead.
+ *                  while it transforms the current one. 3: one slab per workgroup with its exchanges
+ *                  through a buffer of N/2 rows (32 <= N <= 128; two resident workgroups per CU in
+ *                  complex64, and it fits complex128 at N = 128). 0: a row pass and an i2 pass instead.
  *   slab_chunk  slabs per chunk of the row + i2 pass pair (0 = all). A power-of-two divisor of N^2.
  *   col_chunk   columns m2 per chunk of the j1 + i1 pass pair (0 = all). A power-of-two divisor
  *               of N^2 and a multiple of the axis tile. Chunks of tens of MB let the second pass of

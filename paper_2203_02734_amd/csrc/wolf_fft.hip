@@ -361,6 +361,139 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
   }
 }
 
+// Slab pass with half the LDS of k_slab_fft2. The column exchange runs for the two column halves in
+// turn, and the transposition to rows plus the row exchange for the two row halves in turn, each
+// through a buffer of N/2 rows. At N = 128 that buffer is 70 KB in complex64, so two workgroups are
+// resident per CU (one loads while the other computes), and 139 KB in complex128, which fits where
+// the whole slab (256 KB) does not. Thread tid plays (t1, c) = (tid / H, tid % H + H vt) in the column
+// phase and (t2, r) = (tid % N2, tid / N2 + H h) in the row phase, with H = N/2.
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <class T, int N> constexpr size_t half_lds_bytes() {
+  return sizeof(T) * ((size_t)(N / 2) * slab_stride<N>() + 3 * N + 2);
+}
+
+// Two resident workgroups per CU where the LDS allows it (complex64): waves per SIMD for the register
+// budget (512 VGPRs per SIMD lane shared by the resident waves).
+template <class T, int N> constexpr int half_waves_per_simd() {
+  constexpr int waves = (Split<N>::N2 * N / 2 + 63) / 64 / 4;
+  return (2 * half_lds_bytes<T, N>() <= kMaxLds ? 2 : 1) * (waves < 1 ? 1 : waves);
+}
+
+template <class T, int N, int SIGN>
+__global__ __launch_bounds__(Split<N>::N2 * N / 2) __attribute__((amdgpu_waves_per_eu(half_waves_per_simd<T, N>())))
+void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pupil pu) {
+  using S = Split<N>;
+  using R = typename real_of<T>::type;
+  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
+  constexpr int H = N / 2;
+  constexpr int NT = N2 * H;
+  constexpr int SP = slab_stride<N>();
+  static_assert(H % N1 == 0 && SP >= N, "half slab layout");
+  __shared__ T buf[H * SP];
+  __shared__ T tpre[N], tpost[N], tw[N], sc[2];
+
+  const long long p1 = blockIdx.x;
+  const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
+  for (int i = threadIdx.x; i < N; i += NT) {
+    tpre[i] = chirp_entry<T>(pre, i, N);
+    tpost[i] = chirp_entry<T>(post, i, N);
+    tw[i] = twiddle_entry<T, SIGN>(i, N);
+  }
+  if (threadIdx.x < 2) sc[threadIdx.x] = chirp_entry<T>(slab_pre, threadIdx.x == 0 ? a1 : b1, N);
+  const int tid = threadIdx.x;
+  const int t1 = tid / H, cl = tid % H;
+  const T* in = src + p1 * N * N;
+  __syncthreads();  // tables
+  T scal = cmul(sc[0], sc[1]);
+  if (!pupil_pass(pu, a1, b1, N)) scal = T{(R)0, (R)0};
+
+  // Column phase, one column half at a time: buffer X[(k1 N2 + t1)][cl] of N x H entries. The loads
+  // of a half are issued when it starts; the other resident workgroup hides their latency.
+  T w[2][N1];
+#pragma unroll
+  for (int vt = 0; vt < 2; ++vt) {
+    const int c = cl + H * vt;
+    T v[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[a] = in[(N2 * a + t1) * N + c];
+    if (pu.geo != 0) {
+#pragma unroll
+      for (int a = 0; a < N1; ++a)
+        if (!pupil_pass(pu, N2 * a + t1, c, N)) v[a] = T{(R)0, (R)0};
+    }
+    const T cst = cmul(tpre[c], scal);
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[a] = cmul(v[a], tpre[N2 * a + t1]);
+    dft_reg<N1, SIGN>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t1) * H + cl] = cmul(v[k1], tw[(t1 * k1) & (N - 1)]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t1 + N2 * q;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) w[vt][q * N2 + n2] = buf[(k1 * N2 + n2) * H + cl];
+      dft_reg<N2, SIGN>(&w[vt][q * N2]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int k = t1 + N2 * q + N1 * k2;
+        w[vt][q * N2 + k2] = cmul(w[vt][q * N2 + k2], cmul(tpost[k], cst));
+      }
+  }
+
+  // Row phase, one row half at a time: rows k in [H h, H h + H) are written to the buffer (row
+  // k - H h, stride SP), transformed by threads (t2, rl), and stored.
+  const int t2 = tid % N2, rl = tid / N2;
+  T* out = dst + p1 * N * N;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int vt = 0; vt < 2; ++vt)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          // k = t1 + N2 q + N1 k2 with t1 + N2 q < N1, so k / H = k2 / (H / N1): fixed at compile time.
+          if ((k2 * N1) / H != h) continue;
+          const int k = t1 + N2 * q + N1 * k2;
+          buf[(k - H * h) * SP + cl + H * vt] = w[vt][q * N2 + k2];
+        }
+    __syncthreads();
+    T x[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) x[a] = buf[rl * SP + N2 * a + t2];
+    dft_reg<N1, SIGN>(x);
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) buf[rl * SP + k1 * (N2 + 1) + t2] = cmul(x[k1], tw[(t2 * k1) & (N - 1)]);
+    __syncthreads();
+    T u[N1];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t2 + N2 * q;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[q * N2 + n2] = buf[rl * SP + k1 * (N2 + 1) + n2];
+      dft_reg<N2, SIGN>(&u[q * N2]);
+    }
+    const int r = rl + H * h;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t2 + N2 * q;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int k = k1 + N1 * k2;
+        out[r * N + k] = cmul(u[q * N2 + k2], tpost[k]);
+      }
+    }
+    __syncthreads();  // the next half reuses the buffer
+  }
+}
+
 // Persistent form of the slab pass: each workgroup takes every gridDim-th slab and keeps its
 // tables. The raw values of its next slab are loaded into registers while it transforms the
 // current one, so the loads of one slab overlap the arithmetic of the previous one.
@@ -512,7 +645,6 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_obs(const T* src, Chi
 // ---------------------------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------------------------
-constexpr size_t kMaxLds = 160 * 1024;
 
 template <int N> constexpr int axis_cols() {
   constexpr int c = 256 / Split<N>::N2;
@@ -573,10 +705,19 @@ template <class T, int N> constexpr long long slab_resident_wgs() {
 template <class T, int N, int SIGN>
 static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chirp& pre, const Chirp& post,
                                 const Chirp& slab_pre, const Pupil& pu, int mode, hipStream_t st) {
+  if (slabs > 0x7fffffffll) return hipErrorInvalidValue;
+  if (mode == 3) {
+    if constexpr (N >= 32 && N <= 128 && half_lds_bytes<T, N>() <= kMaxLds) {
+      hipLaunchKernelGGL((k_slab_half<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N / 2), 0, st, src,
+                         dst, pre, post, slab_pre, pu);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if constexpr (slab_lds_bytes<T, N>() > kMaxLds) {
     return hipErrorInvalidValue;
   } else {
-    if (slabs > 0x7fffffffll) return hipErrorInvalidValue;
     if (mode == 2) {
       const long long g = slabs < slab_resident_wgs<T, N>() ? slabs : slab_resident_wgs<T, N>();
       hipLaunchKernelGGL((k_slab_fft2p<T, N, SIGN>), dim3((unsigned)g), dim3(Split<N>::N2 * N), 0, st, src, dst,
@@ -660,6 +801,17 @@ template <class T> bool slab_pass_supported(int n) {
     default: return false;
   }
 }
+
+template <class T> bool half_slab_supported(int n) {
+  switch (n) {
+    case 32: return half_lds_bytes<T, 32>() <= kMaxLds;
+    case 64: return half_lds_bytes<T, 64>() <= kMaxLds;
+    case 128: return half_lds_bytes<T, 128>() <= kMaxLds;
+    default: return false;
+  }
+}
+template bool half_slab_supported<float2>(int);
+template bool half_slab_supported<double2>(int);
 
 int row_pass_rows(int n) {
   switch (n) {

@@ -23,7 +23,8 @@ struct OperatorTables {
 // i2 pass run over chunks of `slab_chunk` slabs. The j1 and i1 passes run over chunks of
 // `col_chunk` columns m2 (0 = all).
 struct Plan {
-  int fused_slab;  // 0: row pass + i2 axis pass; 1: one slab per workgroup; 2: persistent slab pass
+  int fused_slab;  // 0: row pass + i2 axis pass; 1: one slab per workgroup; 2: persistent slab pass;
+                   // 3: one slab per workgroup through a half-size LDS buffer
   long long slab_chunk;
   long long col_chunk;
   int coop;        // 1: first-point axes in one cooperative pass (wolf_coop.hip); col_chunk unused
@@ -83,6 +84,7 @@ hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, con
                                    int lookahead, void* counters, hipStream_t st);
 size_t coop_counter_bytes(int n);
 template <class T> bool slab_pass_supported(int n);
+template <class T> bool half_slab_supported(int n);  // plan fused_slab = 3
 // out[p1; p2] = P(p1) P(p2) in[p1; p2] (in == out allowed).
 template <class T>
 hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipStream_t st);

@@ -268,7 +268,7 @@ def test_all_schedules_agree(gpu_lib, dtype):
     nn = n * n
     c = 256 // 4 if 256 // 4 < n else n       # axis tile at N = 32 (N2 = 4)
     plans = [(1, 0, 0, 0, 1), (1, 0, c, 0, 1), (1, 0, nn // 2, 0, 1), (0, 0, 0, 0, 1), (0, nn // 4, c, 0, 1),
-             (0, 2, nn // 8, 0, 1), (2, 0, 0, 0, 1), (2, 0, c, 0, 1)]
+             (0, 2, nn // 8, 0, 1), (2, 0, 0, 0, 1), (2, 0, c, 0, 1), (3, 0, 0, 0, 1), (3, 0, c, 0, 1)]
     try:
         for plan in plans:
             gpu_lib.set_plan(n, dtype, *plan)
@@ -304,6 +304,36 @@ def test_persistent_slab_pass_matches_per_slab(gpu_lib, n, dtype):
     torch.cuda.synchronize()
     d = float(torch.linalg.vector_norm(outs[1] - outs[0]) / torch.linalg.vector_norm(outs[0]))
     assert d <= (1e-6 if dtype == torch.complex64 else 1e-14), d
+
+
+@pytest.mark.parametrize("n,dtype", [(32, torch.complex64), (64, torch.complex64), (128, torch.complex64),
+                                     (32, torch.complex128), (64, torch.complex128)])
+def test_half_buffer_slab_pass_matches_per_slab(gpu_lib, n, dtype):
+    """The slab pass through a half-size LDS buffer (fused_slab = 3) does the same arithmetic as the
+    whole-slab pass: the outputs agree to rounding."""
+    p, z = 20e-6, 0.5
+    if n == 128:
+        w = gpu_lib.build_source(WI.gsm128().source, n, p, dtype)
+    else:
+        w = dev(WI.random_complex((n, n, n, n), seed=61 + n), dtype)
+    nn = n * n
+    outs = []
+    try:
+        for mode in (1, 3):
+            gpu_lib.set_plan(n, dtype, mode, 0, nn, 0, 1)
+            got, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
+            outs.append(got)
+    finally:
+        gpu_lib.set_plan(n, dtype)
+    torch.cuda.synchronize()
+    d = float(torch.linalg.vector_norm(outs[1] - outs[0]) / torch.linalg.vector_norm(outs[0]))
+    assert d <= (1e-6 if dtype == torch.complex64 else 1e-14), d
+
+
+def test_complex128_n128_uses_the_half_buffer_slab_pass(gpu_lib):
+    """complex128 at N = 128: the whole slab (256 KB) does not fit the LDS; the default plan takes the
+    half-buffer slab pass (3 sweeps instead of 4). Full-size parity is test_full_size_gsm128."""
+    assert gpu_lib.get_plan(128, torch.complex128)["fused_slab"] == 3
 
 
 COOP_SKIP = ("the cooperative first-point pass is disabled: its cross-workgroup wait did not complete "
