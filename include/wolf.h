@@ -171,12 +171,14 @@ WOLF_API int64_t wolf_direct_work_bytes(int32_t n, int32_t dtype);
  * transform and the result is cropped back to the central N points, so the output pitch is
  * lambda z / (n_fft pitch_m) (eq. spatial_resolution with n_fft in place of N). n_fft = N gives the
  * plain operator for N that are not powers of two (e.g. the paper's N = 200 examples, padded to
- * n_fft = 512). Each axis is a dense N x N product with the exact centred kernel
- * e^{-+2 pi i (k - N/2)(n - N/2) / n_fft} (four passes; no FFT, so the cost is 32 N real flops per
- * element; the power-of-two entry points are faster where they apply).
+ * n_fft = 512). Four passes, one per axis. A power-of-two n_fft (<= 1024) takes zero-padded FFTs of
+ * n_fft points per line (the N inputs at the centre, the N central outputs kept). Any other n_fft
+ * takes dense N x N products with the exact centred kernel e^{-+2 pi i (k - N/2)(n - N/2) / n_fft}
+ * (32 N real flops per element).
  *   n          even, 2..256.   n_fft   N..2048.
  *   w_in, w_out   device N^4 complex; w_in == w_out allowed (partial overlap is not).
- *   work       device N^4 complex of `dtype`, overwritten; must not overlap w_in or w_out.
+ *   work       device N^4 complex of `dtype` (used by the dense passes), overwritten; must not
+ *              overlap w_in or w_out.
  *   farfield   0 Fresnel, 1 far field.   kind, dtype, out_pitch_m as wolf_propagate_fresnel.
  * The source builder and the observables accept any even N as well.
  */

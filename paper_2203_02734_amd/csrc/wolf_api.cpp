@@ -434,22 +434,31 @@ WOLF_API wolf_status wolf_propagate_padded(const void* w_in, void* w_out, int32_
                                         : 1.0 / ((wavelength_m * z_m) * (wavelength_m * z_m));
   const double a_src = farfield ? 0.0 : pitch_m * pitch_m / (wavelength_m * z_m);
   const double a_out = dx * dx / (wavelength_m * z_m);
+  // A power-of-two n_fft takes zero-padded FFTs (the centring as (-1)^n in the tables); any other
+  // n_fft the dense passes (the centring exact in the kernel index, no (-1)^n).
+  const bool fft = wolf::pad_fft_supported(n, n_fft);
+  const int chk = fft ? 1 : 0;
   wolf::OperatorTables op;
-  op.pre2 = wolf::Chirp{a_src, 1.0, +1, 0};
-  op.post2 = wolf::Chirp{a_out, 1.0, +1, 0};
+  op.pre2 = wolf::Chirp{a_src, 1.0, +1, chk};
+  op.post2 = wolf::Chirp{a_out, 1.0, +1, chk};
   op.sign2 = -1;
-  op.pre1 = wolf::Chirp{a_src, 1.0, -1, 0};
-  op.post1 = wolf::Chirp{a_out, 1.0, -1, 0};
+  op.pre1 = wolf::Chirp{a_src, 1.0, -1, chk};
+  op.post1 = wolf::Chirp{a_out, 1.0, -1, chk};
   op.sign1 = +1;
   op.scale = c * pitch_m * pitch_m * pitch_m * pitch_m;
   op.pupil = wolf::Pupil{0, 0};
   if (out_pitch_m) *out_pitch_m = dx;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const hipError_t e =
-      dtype == WOLF_C64
-          ? wolf::launch_operator_dense<float2>(n, n_fft, (const float2*)w_in, (float2*)w_out, (float2*)work, op, st)
-          : wolf::launch_operator_dense<double2>(n, n_fft, (const double2*)w_in, (double2*)w_out, (double2*)work, op,
-                                                 st);
+  hipError_t e;
+  if (fft)
+    e = dtype == WOLF_C64 ? wolf::launch_operator_padfft<float2>(n, n_fft, (const float2*)w_in, (float2*)w_out, op, st)
+                          : wolf::launch_operator_padfft<double2>(n, n_fft, (const double2*)w_in, (double2*)w_out, op,
+                                                                  st);
+  else
+    e = dtype == WOLF_C64
+            ? wolf::launch_operator_dense<float2>(n, n_fft, (const float2*)w_in, (float2*)w_out, (float2*)work, op, st)
+            : wolf::launch_operator_dense<double2>(n, n_fft, (const double2*)w_in, (double2*)w_out, (double2*)work, op,
+                                                   st);
   return launched(e, who);
 }
 

@@ -186,6 +186,147 @@ hipError_t launch_operator_dense(int n, int nz, const T* in, T* out, T* work, co
   return launch_dense_axis<T, true>(work, out, d, op.sign1, op.pre1, op.post1, op.scale, st);
 }
 
+// ---------------------------------------------------------------------------------------------
+// The same operator with a zero-padded FFT when N_z is a power of two (<= 1024). Per line, the N
+// inputs sit at positions n + s (s = (N_z - N)/2) of an N_z-point transform, the rest are zeros,
+// and the outputs at positions k + s are kept. With the centring factors on the padded indices,
+//   e^{SIGN 2 pi i (k - N/2)(n - N/2)/N_z} = e^{SIGN 2 pi i k' n'/N_z} (-1)^{k'} (-1)^{n'} (-1)^{N_z/2},
+// k' = k + s, n' = n + s; (-1)^{n'} (-1)^{k'} = (-1)^{n + k}, which the checkerboarded chirps on the
+// N-point grids carry, and (-1)^{N_z/2} cancels over the four axes. The transform is the split
+// N_z = N1 N2 of the slab and axis passes. A workgroup owns C lines (one LDS exchange) and loops
+// over tiles of lines; it reads its lines before a barrier and writes them after, so dst may be src.
+// ---------------------------------------------------------------------------------------------
+// Lines of one pass: `outer` blocks (stride outer_stride) of ncols lines each (stride col_stride);
+// the transformed axis has stride axis_stride. tiles_per_outer and tiles are filled at launch.
+struct PadJob {
+  long long outer, outer_stride, axis_stride, col_stride, ncols;
+  int n, s;
+  Chirp pre, post;
+  long long tiles_per_outer, tiles;
+};
+
+template <int NZ> constexpr int pad_cols() {
+  constexpr int c = 256 / Split<NZ>::N2;
+  return c;
+}
+
+template <class T, int NZ, int SIGN>
+__global__ __launch_bounds__(256) void k_axis_pad(const T* src, T* dst, PadJob j) {
+  using S = Split<NZ>;
+  using R = typename real_of<T>::type;
+  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
+  constexpr int C = pad_cols<NZ>();
+  static_assert(N2 * C == 256, "threads");
+  __shared__ T xch[NZ * C];
+  __shared__ T tpre[kDenseMaxN], tpost[kDenseMaxN], tw[NZ];
+  const int n = j.n, sft = j.s;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    tpre[i] = chirp_entry<T>(j.pre, i, n);
+    tpost[i] = chirp_entry<T>(j.post, i, n);
+  }
+  for (int i = threadIdx.x; i < NZ; i += 256) tw[i] = twiddle_entry<T, SIGN>(i, NZ);
+  __syncthreads();
+  const int c = threadIdx.x % C;
+  const int t = threadIdx.x / C;
+  const long long as = j.axis_stride;
+  const T zero{(R)0, (R)0};
+  for (long long tile = blockIdx.x; tile < j.tiles; tile += gridDim.x) {
+    const long long o = tile / j.tiles_per_outer;
+    const long long col = (tile - o * j.tiles_per_outer) * C + c;
+    const bool valid = col < j.ncols;
+    const long long base = o * j.outer_stride + col * j.col_stride;
+    T v[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int m = N2 * a + t - sft;
+      v[a] = (valid && m >= 0 && m < n) ? cmul(src[base + (long long)m * as], tpre[m]) : zero;
+    }
+    dft_reg<N1, SIGN>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) xch[(k1 * N2 + t) * C + c] = cmul(v[k1], tw[(t * k1) & (NZ - 1)]);
+    __syncthreads();
+    T u[N1];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t + N2 * q;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[q * N2 + n2] = xch[(k1 * N2 + n2) * C + c];
+      dft_reg<N2, SIGN>(&u[q * N2]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k1 = t + N2 * q;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int m = k1 + N1 * k2 - sft;
+        if (valid && m >= 0 && m < n) dst[base + (long long)m * as] = cmul(u[q * N2 + k2], tpost[m]);
+      }
+    }
+    __syncthreads();  // xch is reused by the next tile
+  }
+}
+
+template <class T, int NZ>
+static hipError_t launch_pad_nz(const T* src, T* dst, PadJob j, int sign, hipStream_t st) {
+  constexpr int C = pad_cols<NZ>();
+  j.tiles_per_outer = (j.ncols + C - 1) / C;
+  j.tiles = j.outer * j.tiles_per_outer;
+  const long long grid = j.tiles < 4096 ? j.tiles : 4096;
+  if (grid < 1) return hipSuccess;
+  if (sign < 0)
+    hipLaunchKernelGGL((k_axis_pad<T, NZ, -1>), dim3((unsigned)grid), dim3(256), 0, st, src, dst, j);
+  else
+    hipLaunchKernelGGL((k_axis_pad<T, NZ, +1>), dim3((unsigned)grid), dim3(256), 0, st, src, dst, j);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_pad_axis(int nz, const T* src, T* dst, const PadJob& j, int sign, hipStream_t st) {
+  switch (nz) {
+    case 2: return launch_pad_nz<T, 2>(src, dst, j, sign, st);
+    case 4: return launch_pad_nz<T, 4>(src, dst, j, sign, st);
+    case 8: return launch_pad_nz<T, 8>(src, dst, j, sign, st);
+    case 16: return launch_pad_nz<T, 16>(src, dst, j, sign, st);
+    case 32: return launch_pad_nz<T, 32>(src, dst, j, sign, st);
+    case 64: return launch_pad_nz<T, 64>(src, dst, j, sign, st);
+    case 128: return launch_pad_nz<T, 128>(src, dst, j, sign, st);
+    case 256: return launch_pad_nz<T, 256>(src, dst, j, sign, st);
+    case 512: return launch_pad_nz<T, 512>(src, dst, j, sign, st);
+    case 1024: return launch_pad_nz<T, 1024>(src, dst, j, sign, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool pad_fft_supported(int n, int nz) {
+  return n >= 2 && n <= kDenseMaxN && n % 2 == 0 && nz >= n && nz <= 1024 && (nz & (nz - 1)) == 0;
+}
+
+// Four passes: j2 (lines along the contiguous axis, line stride N), i2, j1, i1. The first reads `in`
+// and writes `out`; the others work in place on `out`. The tables carry the (-1)^n centring.
+template <class T>
+hipError_t launch_operator_padfft(int n, int nz, const T* in, T* out, const OperatorTables& op, hipStream_t st) {
+  if (!pad_fft_supported(n, nz)) return hipErrorInvalidValue;
+  const long long N = n, NN = N * N, NNN = NN * N;
+  const int sft = (nz - n) / 2;
+  Chirp post1 = op.post1;
+  post1.scale = op.scale;
+  hipError_t e;
+  // PadJob{outer, outer_stride, axis_stride, col_stride, ncols, n, s, pre, post}
+  const PadJob j2{1, 0, 1, N, NNN, n, sft, op.pre2, op.post2, 0, 0};     // contiguous axis: lines of N
+  const PadJob i2{NN, NN, N, 1, N, n, sft, op.pre2, op.post2, 0, 0};    // stride N, N^2 blocks of N lines
+  const PadJob j1{N, NNN, NN, 1, NN, n, sft, op.pre1, op.post1, 0, 0};  // stride N^2, N blocks of N^2 lines
+  const PadJob i1{1, 0, NNN, 1, NNN, n, sft, op.pre1, post1, 0, 0};     // stride N^3, N^3 lines
+  if ((e = launch_pad_axis<T>(nz, in, out, j2, op.sign2, st)) != hipSuccess) return e;
+  if ((e = launch_pad_axis<T>(nz, out, out, i2, op.sign2, st)) != hipSuccess) return e;
+  if ((e = launch_pad_axis<T>(nz, out, out, j1, op.sign1, st)) != hipSuccess) return e;
+  return launch_pad_axis<T>(nz, out, out, i1, op.sign1, st);
+}
+
+template hipError_t launch_operator_padfft<float2>(int, int, const float2*, float2*, const OperatorTables&,
+                                                   hipStream_t);
+template hipError_t launch_operator_padfft<double2>(int, int, const double2*, double2*, const OperatorTables&,
+                                                    hipStream_t);
+
 template hipError_t launch_operator_dense<float2>(int, int, const float2*, float2*, float2*, const OperatorTables&,
                                                   hipStream_t);
 template hipError_t launch_operator_dense<double2>(int, int, const double2*, double2*, double2*,

@@ -71,31 +71,70 @@ template <int SIGN, class T> __device__ __forceinline__ T twiddle16(T b, int j16
   return T{b.x * c - b.y * s, b.x * s + b.y * c};
 }
 
-// In-register DFT of length R <= 16: X[k] = sum_n v[n] e^{SIGN 2 pi i n k / R}, natural order in
-// and out. Iterative radix-2 decimation in time on bit-reversed input; fully unrolled.
+// cos and sin of 2 pi j / 32, j = 0..15, to 21 digits (the odd twiddles of the 32-point DFT).
+__device__ constexpr double kCos32[16] = {
+    1.0, 0.980785280403230449126, 0.923879532511286756128, 0.831469612302545237079,
+    0.707106781186547524401, 0.555570233019602224743, 0.382683432365089771728, 0.195090322016128267848,
+    0.0, -0.195090322016128267848, -0.382683432365089771728, -0.555570233019602224743,
+    -0.707106781186547524401, -0.831469612302545237079, -0.923879532511286756128, -0.980785280403230449126};
+__device__ constexpr double kSin32[16] = {
+    0.0, 0.195090322016128267848, 0.382683432365089771728, 0.555570233019602224743,
+    0.707106781186547524401, 0.831469612302545237079, 0.923879532511286756128, 0.980785280403230449126,
+    1.0, 0.980785280403230449126, 0.923879532511286756128, 0.831469612302545237079,
+    0.707106781186547524401, 0.555570233019602224743, 0.382683432365089771728, 0.195090322016128267848};
+
+template <int R, int SIGN, class T> __device__ __forceinline__ void dft_reg(T* v);
+
+// 32-point DFT from two 16-point DFTs of the even and odd samples (one radix-2 step).
+template <int SIGN, class T> __device__ __forceinline__ void dft_reg32(T* v) {
+  using R = typename real_of<T>::type;
+  T e[16], o[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    e[i] = v[2 * i];
+    o[i] = v[2 * i + 1];
+  }
+  dft_reg<16, SIGN>(e);
+  dft_reg<16, SIGN>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const R c = (R)kCos32[k];
+    const R s = (R)(SIGN * kSin32[k]);
+    const T b = T{o[k].x * c - o[k].y * s, o[k].x * s + o[k].y * c};
+    v[k] = cadd(e[k], b);
+    v[k + 16] = csub(e[k], b);
+  }
+}
+
+// In-register DFT of length R <= 32: X[k] = sum_n v[n] e^{SIGN 2 pi i n k / R}, natural order in
+// and out. Iterative radix-2 decimation in time on bit-reversed input (R <= 16), fully unrolled;
+// R = 32 takes one more radix-2 step over two 16-point DFTs.
 template <int R, int SIGN, class T> __device__ __forceinline__ void dft_reg(T* v) {
-  static_assert(R >= 1 && R <= 16 && (R & (R - 1)) == 0, "radix");
-  if constexpr (R == 1) return;
-  constexpr int L = ilog2(R);
-  T w[R];
+  static_assert(R >= 1 && R <= 32 && (R & (R - 1)) == 0, "radix");
+  if constexpr (R == 32) {
+    dft_reg32<SIGN>(v);
+  } else if constexpr (R > 1) {
+    constexpr int L = ilog2(R);
+    T w[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) w[i] = v[bitrev(i, L)];
+    for (int i = 0; i < R; ++i) w[i] = v[bitrev(i, L)];
 #pragma unroll
-  for (int s = 1; s <= L; ++s) {
-    const int m = 1 << s, h = m >> 1;
+    for (int s = 1; s <= L; ++s) {
+      const int m = 1 << s, h = m >> 1;
 #pragma unroll
-    for (int k = 0; k < R; k += m) {
+      for (int k = 0; k < R; k += m) {
 #pragma unroll
-      for (int j = 0; j < h; ++j) {
-        const T a = w[k + j];
-        const T b = twiddle16<SIGN>(w[k + j + h], j * (16 / m));
-        w[k + j] = cadd(a, b);
-        w[k + j + h] = csub(a, b);
+        for (int j = 0; j < h; ++j) {
+          const T a = w[k + j];
+          const T b = twiddle16<SIGN>(w[k + j + h], j * (16 / m));
+          w[k + j] = cadd(a, b);
+          w[k + j + h] = csub(a, b);
+        }
       }
     }
-  }
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = w[i];
+    for (int i = 0; i < R; ++i) v[i] = w[i];
+  }
 }
 
 // Split of a length-N DFT across N2 threads holding N1 elements each (N = N1 N2, N1 >= N2).

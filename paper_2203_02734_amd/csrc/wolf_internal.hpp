@@ -94,6 +94,11 @@ int row_pass_rows(int n);  // rows per workgroup of the row pass
 // The operator for any even N and transform length N_z >= N (zero padding and crop), as four dense
 // axis passes (wolf_dense.hip). work: N^4 elements. Tables without the (-1)^n centring factor.
 bool dense_supported(int n, int nz);
+// The same operator with zero-padded FFTs, for a power-of-two N_z <= 1024 (in -> out, then in place).
+// Tables with the (-1)^n centring factor.
+bool pad_fft_supported(int n, int nz);
+template <class T>
+hipError_t launch_operator_padfft(int n, int nz, const T* in, T* out, const OperatorTables& op, hipStream_t st);
 template <class T>
 hipError_t launch_operator_dense(int n, int nz, const T* in, T* out, T* work, const OperatorTables& op,
                                  hipStream_t st);

@@ -91,10 +91,12 @@ def test_source_builder_even_n(gpu_lib, model):
     assert rel(got, O.build_source(sp, n, p)) < 1e-14
 
 
-@pytest.mark.parametrize("n,nz,dtype", [(200, 512, torch.complex64), (96, 192, torch.complex128)])
+@pytest.mark.parametrize("n,nz,dtype", [(200, 512, torch.complex64), (96, 192, torch.complex128),
+                                        (100, 256, torch.complex128), (200, 200, torch.complex64)])
 def test_padded_full_size_gsm(gpu_lib, n, nz, dtype):
-    """The paper's example size: N = 200 padded to N_z = 512 (complex64, 1.6e9 elements), and N = 96
-    padded to 192 in complex128, GSM source, against the separable oracle with the same padding."""
+    """The paper's example size: N = 200 padded to N_z = 512 (complex64, 1.6e9 elements; zero-padded
+    FFTs), N = 200 unpadded (dense passes), N = 96 padded to 192 (dense) and N = 100 padded to 256
+    (FFTs) in complex128, GSM source, against the separable oracle with the same padding."""
     p, z, ss, sg = 20e-6, 0.5, 0.1e-3, 0.05e-3
     sp = SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=ss, sigma_g_m=sg, geometry=WI.GEO_NONE,
                          geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None, lens_focal_m=0.0,
