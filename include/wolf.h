@@ -171,10 +171,11 @@ WOLF_API int64_t wolf_direct_work_bytes(int32_t n, int32_t dtype);
  * transform and the result is cropped back to the central N points, so the output pitch is
  * lambda z / (n_fft pitch_m) (eq. spatial_resolution with n_fft in place of N). n_fft = N gives the
  * plain operator for N that are not powers of two (e.g. the paper's N = 200 examples, padded to
- * n_fft = 512). Four passes, one per axis. A power-of-two n_fft (<= 1024) takes zero-padded FFTs of
- * n_fft points per line (the N inputs at the centre, the N central outputs kept). Any other n_fft
- * takes dense N x N products with the exact centred kernel e^{-+2 pi i (k - N/2)(n - N/2) / n_fft}
- * (32 N real flops per element).
+ * n_fft = 512). Four passes, one per axis. An n_fft that is a power of two (<= 1024) or one of 6, 10,
+ * 12, 20, 24, 36, 48, 72, 80, 96, 100, 144, 192, 200 takes zero-padded FFTs of n_fft points per line
+ * (the N inputs at the centre, the N central outputs kept; mixed radices 2, 3, 5 for the listed
+ * lengths). Any other n_fft takes dense N x N products with the exact centred kernel
+ * e^{-+2 pi i (k - N/2)(n - N/2) / n_fft} (32 N real flops per element).
  *   n          even, 2..256.   n_fft   N..2048.
  *   w_in, w_out   device N^4 complex; w_in == w_out allowed (partial overlap is not).
  *   work       device N^4 complex of `dtype` (used by the dense passes), overwritten; must not

@@ -75,6 +75,22 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[r][c] = zero;
     for (int n0 = 0; n0 < n; n0 += TK) {
+      T raw[4];  // this thread's four elements of the array tile, all loads issued first
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        if constexpr (COLS) {
+          const int kk = e / TN, jj = e % TN;
+          const long long gc = j0 + jj;
+          const int gn = n0 + kk;
+          raw[q] = load_or_first(in, gc < d.S && gn < n, base + (long long)gn * d.S + gc);
+        } else {
+          const int ii = e / TK, kk = e % TK;
+          const long long gi = i0 + ii;
+          const int gn = n0 + kk;
+          raw[q] = load_or_first(in, gi < d.rows && gn < n, gi * n + gn);
+        }
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = tid + 256 * q;
@@ -85,7 +101,8 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
         if constexpr (COLS) {
           if (gi < n && gn < n) v = tw[dense_index((int)gi, gn, c0, nz)];
         } else {
-          if (gi < d.rows && gn < n) v = cmul(in[gi * n + gn], tpre[gn]);
+          const T x = cmul(raw[q], tpre[gn < n ? gn : 0]);
+          v = keep_or_zero(gi < d.rows && gn < n, x);
         }
         As[kk][ii] = v;
       }
@@ -97,7 +114,8 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
           const int kk = e / TN, jj = e % TN;
           const long long gc = j0 + jj;
           const int gn = n0 + kk;
-          if (gc < d.S && gn < n) v = cmul(in[base + (long long)gn * d.S + gc], tpre[gn]);
+          const T x = cmul(raw[q], tpre[gn < n ? gn : 0]);
+          v = keep_or_zero(gc < d.S && gn < n, x);
           Bs[kk][jj] = v;
         } else {
           const int jj = e / TK, kk = e % TK;
@@ -205,29 +223,76 @@ struct PadJob {
   long long tiles_per_outer, tiles;
 };
 
-template <int NZ> constexpr int pad_cols() {
-  constexpr int c = 256 / Split<NZ>::N2;
-  return c;
+// Split of an N_z-point line transform over L2 threads that hold L1 = Q L2 elements each
+// (N_z = Q L2^2), and the C lines of a workgroup (L2 C <= 256 threads, at most one wavefront per
+// SIMD). Powers of two take the split of the slab and axis passes and C = 256 / L2. Other lengths
+// take the largest L2 with L1 <= 32 (the register DFTs) and C = 8 floor(32 / L2), a multiple of 8
+// lines so that a tile of neighbouring lines spans whole 64-byte segments.
+__host__ __device__ constexpr int line_l2(int lz) {
+  if (is_pow2(lz)) return lz >> ((ilog2(lz) + 1) / 2);  // Split<lz>::N2
+  for (int l2 = 32; l2 >= 1; --l2)
+    if (lz % (l2 * l2) == 0 && (lz / (l2 * l2)) * l2 <= 32) return l2;
+  return 0;
+}
+__host__ __device__ constexpr int line_cols(int l2) { return 8 * (32 / l2); }
+template <int NZ> struct LineCfg {
+  static constexpr int L2 = line_l2(NZ);
+  static constexpr int L1 = NZ / L2;
+  static constexpr int Q = L1 / L2;
+  static constexpr int C = is_pow2(NZ) ? 256 / L2 : line_cols(L2);
+  static constexpr int kThreads = L2 * C;
+  static_assert(L2 >= 1 && L1 == Q * L2 && L1 <= 32 && kThreads <= 256, "line split");
+};
+
+// Lane layout and exchange buffer of a pass. The exchange runs in Q / G phases: in phase p the
+// buffer holds the first-stage outputs k1 in [p G N2, (p + 1) G N2) of the C lines, G N2 x N2 x C
+// entries. G = Q is one exchange; G = 1 takes a factor Q less LDS (more workgroups per CU) for
+// Q - 1 more barriers and registers that hold the inputs across the phases.
+//   !CONTIG (a strided axis; neighbouring lines are contiguous): lanes run across the C lines,
+//           c = tid % C; entry (k1l, n2, c) at k1l (N2 C + C) + n2 C + c.
+//   CONTIG (the contiguous axis): lanes run along the line, t = tid % N2, so each load and store
+//           covers whole lines of memory; entry at c G N2 (N2 + 1) + k1l (N2 + 1) + n2.
+// The paddings (C entries per k1l, one per N2) keep the writes and the reads of a phase free of
+// bank conflicts beyond the two passes that 64 eight-byte accesses need.
+template <int NZ, bool CONTIG, int G> struct PadLayout {
+  static constexpr int N2 = LineCfg<NZ>::L2;
+  static constexpr int C = LineCfg<NZ>::C;
+  static constexpr int kSize = CONTIG ? C * G * N2 * (N2 + 1) : G * N2 * (N2 * C + C);
+  static __device__ __forceinline__ int at(int k1l, int n2, int c) {
+    return CONTIG ? c * (G * N2 * (N2 + 1)) + k1l * (N2 + 1) + n2 : k1l * (N2 * C + C) + n2 * C + c;
+  }
+};
+
+template <class T, int NZ, int G> constexpr size_t pad_lds_bytes() {
+  return (PadLayout<NZ, false, G>::kSize + 2 * kDenseMaxN + NZ) * sizeof(T);
 }
 
-template <class T, int NZ, int SIGN>
-__global__ __launch_bounds__(256) void k_axis_pad(const T* src, T* dst, PadJob j) {
-  using S = Split<NZ>;
+// One exchange unless phases let more workgroups share a CU and the inputs are few enough (L1 <= 16)
+// to stay in registers across the phases; with complex64 the single exchange already fits as many
+// workgroups as the registers allow (measured register counts of the unrolled kernels).
+template <class T, int NZ> constexpr int pad_groups() {
+  using S = LineCfg<NZ>;
+  constexpr bool phases_fit_more = kMaxLds / pad_lds_bytes<T, NZ, S::Q>() < kMaxLds / pad_lds_bytes<T, NZ, 1>();
+  return (sizeof(T) == 16 && S::L1 <= 16 && phases_fit_more) ? 1 : S::Q;
+}
+
+template <class T, int NZ, int SIGN, bool CONTIG>
+__global__ __launch_bounds__(LineCfg<NZ>::kThreads) void k_axis_pad(const T* src, T* dst, PadJob j) {
+  using S = LineCfg<NZ>;
   using R = typename real_of<T>::type;
-  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
-  constexpr int C = pad_cols<NZ>();
-  static_assert(N2 * C == 256, "threads");
-  __shared__ T xch[NZ * C];
+  constexpr int N1 = S::L1, N2 = S::L2, Q = S::Q, C = S::C, NT = S::kThreads, G = pad_groups<T, NZ>();
+  using L = PadLayout<NZ, CONTIG, G>;
+  __shared__ T xch[L::kSize];
   __shared__ T tpre[kDenseMaxN], tpost[kDenseMaxN], tw[NZ];
   const int n = j.n, sft = j.s;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < n; i += NT) {
     tpre[i] = chirp_entry<T>(j.pre, i, n);
     tpost[i] = chirp_entry<T>(j.post, i, n);
   }
-  for (int i = threadIdx.x; i < NZ; i += 256) tw[i] = twiddle_entry<T, SIGN>(i, NZ);
+  for (int i = threadIdx.x; i < NZ; i += NT) tw[i] = twiddle_entry<T, SIGN>(i, NZ);
   __syncthreads();
-  const int c = threadIdx.x % C;
-  const int t = threadIdx.x / C;
+  const int t = CONTIG ? (int)threadIdx.x % N2 : (int)threadIdx.x / C;
+  const int c = CONTIG ? (int)threadIdx.x / N2 : (int)threadIdx.x % C;
   const long long as = j.axis_stride;
   const T zero{(R)0, (R)0};
   for (long long tile = blockIdx.x; tile < j.tiles; tile += gridDim.x) {
@@ -239,66 +304,91 @@ __global__ __launch_bounds__(256) void k_axis_pad(const T* src, T* dst, PadJob j
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
       const int m = N2 * a + t - sft;
-      v[a] = (valid && m >= 0 && m < n) ? cmul(src[base + (long long)m * as], tpre[m]) : zero;
-    }
-    dft_reg<N1, SIGN>(v);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) xch[(k1 * N2 + t) * C + c] = cmul(v[k1], tw[(t * k1) & (NZ - 1)]);
-    __syncthreads();
-    T u[N1];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int k1 = t + N2 * q;
-#pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) u[q * N2 + n2] = xch[(k1 * N2 + n2) * C + c];
-      dft_reg<N2, SIGN>(&u[q * N2]);
+      v[a] = load_or_first(src, valid && m >= 0 && m < n, base + (long long)m * as);
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int k1 = t + N2 * q;
+    for (int a = 0; a < N1; ++a) {
+      const int m = N2 * a + t - sft;
+      const bool ok = valid && m >= 0 && m < n;
+      const T x = cmul(v[a], tpre[ok ? m : 0]);
+      v[a] = keep_or_zero(ok, x);
+    }
+    dft_any<N1, SIGN>(v);
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int m = k1 + N1 * k2 - sft;
-        if (valid && m >= 0 && m < n) dst[base + (long long)m * as] = cmul(u[q * N2 + k2], tpost[m]);
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], tw[t * k1]);  // t k1 < N_z
+    // Every load of the tile has been consumed here, so the stores below may overwrite src.
+#pragma unroll
+    for (int p = 0; p < Q / G; ++p) {
+#pragma unroll
+      for (int k1l = 0; k1l < G * N2; ++k1l) xch[L::at(k1l, t, c)] = v[p * G * N2 + k1l];
+      __syncthreads();
+      T u[G][N2];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) u[g][n2] = xch[L::at(t + N2 * g, n2, c)];
+      __syncthreads();  // the buffer is rewritten by the next phase or tile
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        dft_any<N2, SIGN>(u[g]);
+        const int k1 = t + N2 * (p * G + g);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const int m = k1 + N1 * k2 - sft;
+          if (valid && m >= 0 && m < n) dst[base + (long long)m * as] = cmul(u[g][k2], tpost[m]);
+        }
       }
     }
-    __syncthreads();  // xch is reused by the next tile
   }
+}
+
+template <class T, int NZ, bool CONTIG>
+static hipError_t launch_pad_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
+  if (sign < 0)
+    hipLaunchKernelGGL((k_axis_pad<T, NZ, -1, CONTIG>), dim3(grid), dim3(LineCfg<NZ>::kThreads), 0, st, src, dst, j);
+  else
+    hipLaunchKernelGGL((k_axis_pad<T, NZ, +1, CONTIG>), dim3(grid), dim3(LineCfg<NZ>::kThreads), 0, st, src, dst, j);
+  return hipGetLastError();
 }
 
 template <class T, int NZ>
 static hipError_t launch_pad_nz(const T* src, T* dst, PadJob j, int sign, hipStream_t st) {
-  constexpr int C = pad_cols<NZ>();
+  constexpr int C = LineCfg<NZ>::C;
   j.tiles_per_outer = (j.ncols + C - 1) / C;
   j.tiles = j.outer * j.tiles_per_outer;
   const long long grid = j.tiles < 4096 ? j.tiles : 4096;
   if (grid < 1) return hipSuccess;
-  if (sign < 0)
-    hipLaunchKernelGGL((k_axis_pad<T, NZ, -1>), dim3((unsigned)grid), dim3(256), 0, st, src, dst, j);
-  else
-    hipLaunchKernelGGL((k_axis_pad<T, NZ, +1>), dim3((unsigned)grid), dim3(256), 0, st, src, dst, j);
-  return hipGetLastError();
+  return j.axis_stride == 1 ? launch_pad_nzc<T, NZ, true>(src, dst, j, sign, (unsigned)grid, st)
+                            : launch_pad_nzc<T, NZ, false>(src, dst, j, sign, (unsigned)grid, st);
 }
+
+// Transform lengths of the FFT passes besides the powers of two 2 .. 1024: even N_z = Q L2^2 with
+// odd factors 3, 5, 7 and L1 = Q L2 <= 32 (N_z = 200 is the 20 x 10 split).
+#define WOLF_MIXED_LINES(X) X(6) X(10) X(12) X(20) X(24) X(36) X(48) X(72) X(80) X(96) X(100) X(144) X(192) X(200)
 
 template <class T>
 static hipError_t launch_pad_axis(int nz, const T* src, T* dst, const PadJob& j, int sign, hipStream_t st) {
+#define WOLF_LINE_CASE(L) \
+  case L: return launch_pad_nz<T, L>(src, dst, j, sign, st);
   switch (nz) {
-    case 2: return launch_pad_nz<T, 2>(src, dst, j, sign, st);
-    case 4: return launch_pad_nz<T, 4>(src, dst, j, sign, st);
-    case 8: return launch_pad_nz<T, 8>(src, dst, j, sign, st);
-    case 16: return launch_pad_nz<T, 16>(src, dst, j, sign, st);
-    case 32: return launch_pad_nz<T, 32>(src, dst, j, sign, st);
-    case 64: return launch_pad_nz<T, 64>(src, dst, j, sign, st);
-    case 128: return launch_pad_nz<T, 128>(src, dst, j, sign, st);
-    case 256: return launch_pad_nz<T, 256>(src, dst, j, sign, st);
-    case 512: return launch_pad_nz<T, 512>(src, dst, j, sign, st);
-    case 1024: return launch_pad_nz<T, 1024>(src, dst, j, sign, st);
+    WOLF_LINE_CASE(2) WOLF_LINE_CASE(4) WOLF_LINE_CASE(8) WOLF_LINE_CASE(16) WOLF_LINE_CASE(32) WOLF_LINE_CASE(64)
+    WOLF_LINE_CASE(128) WOLF_LINE_CASE(256) WOLF_LINE_CASE(512) WOLF_LINE_CASE(1024)
+    WOLF_MIXED_LINES(WOLF_LINE_CASE)
     default: return hipErrorInvalidValue;
   }
+#undef WOLF_LINE_CASE
+}
+
+static bool line_length_supported(int nz) {
+  if (nz >= 2 && nz <= 1024 && is_pow2(nz)) return true;
+#define WOLF_LINE_MATCH(L) if (nz == L) return true;
+  WOLF_MIXED_LINES(WOLF_LINE_MATCH)
+#undef WOLF_LINE_MATCH
+  return false;
 }
 
 bool pad_fft_supported(int n, int nz) {
-  return n >= 2 && n <= kDenseMaxN && n % 2 == 0 && nz >= n && nz <= 1024 && (nz & (nz - 1)) == 0;
+  return n >= 2 && n <= kDenseMaxN && n % 2 == 0 && nz >= n && line_length_supported(nz);
 }
 
 // Four passes: j2 (lines along the contiguous axis, line stride N), i2, j1, i1. The first reads `in`

@@ -21,6 +21,9 @@
 
 namespace wolf {
 
+// LDS of one gfx950 compute unit, shared by the workgroups resident on it.
+constexpr size_t kMaxLds = 160 * 1024;
+
 // ---------------------------------------------------------------------------------------------
 // Complex helpers on float2 / double2 (interleaved re, im: the layout of torch complex64/128).
 // ---------------------------------------------------------------------------------------------
@@ -137,6 +140,150 @@ template <int R, int SIGN, class T> __device__ __forceinline__ void dft_reg(T* v
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Mixed-radix register DFTs (lengths whose odd factors are 3, 5 and 7).
+// Their twiddles are compile-time constants: cos and sin of 2 pi j / R, with the angle reduced
+// exactly in integers to [0, pi/4] (quadrant, then the complement within it) and the Taylor series
+// of sin and cos summed there in double (12 terms at |x| <= pi/4 are below the rounding level).
+// ---------------------------------------------------------------------------------------------
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double ct_sin_series(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k <= 12; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double ct_cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k <= 12; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+// cos (want_sin false) or sin of 2 pi j / R. With 4j = qR + r, 0 <= r < R, the angle is
+// q pi/2 + (pi/2) r/R; for 2r > R the within-quadrant angle is taken as the complement.
+constexpr double ct_trig(long long j, long long r_len, bool want_sin) {
+  j %= r_len;
+  if (j < 0) j += r_len;
+  const long long q = (4 * j) / r_len;
+  long long r = 4 * j - q * r_len;
+  bool swap = false;
+  if (2 * r > r_len) {
+    r = r_len - r;
+    swap = true;
+  }
+  const double x = (kPi / 2.0) * (double)r / (double)r_len;
+  double c = ct_cos_series(x), s = ct_sin_series(x);
+  if (swap) {
+    const double t = c;
+    c = s;
+    s = t;
+  }
+  for (long long k = 0; k < q; ++k) {  // a quarter turn maps (c, s) to (-s, c)
+    const double t = c;
+    c = -s;
+    s = t;
+  }
+  return want_sin ? s : c;
+}
+
+template <int R> struct RootTable {
+  double c[R], s[R];
+  constexpr RootTable() : c{}, s{} {
+    for (int j = 0; j < R; ++j) {
+      c[j] = ct_trig(j, R, false);
+      s[j] = ct_trig(j, R, true);
+    }
+  }
+};
+template <int R> __device__ constexpr RootTable<R> kRoots{};
+
+__host__ __device__ constexpr bool is_pow2(int r) { return r >= 1 && (r & (r - 1)) == 0; }
+__host__ __device__ constexpr int smallest_odd_factor(int r) {
+  for (int p = 3; p <= r; p += 2)
+    if (r % p == 0) return p;
+  return 1;
+}
+
+// b * e^{SIGN 2 pi i e / R} for a compile-time e once the callers are unrolled.
+template <int R, int SIGN, class T> __device__ __forceinline__ T twiddle_ct(T b, int e) {
+  using Rt = typename real_of<T>::type;
+  if (e % R == 0) return b;
+  const Rt c = (Rt)kRoots<R>.c[e % R];
+  const Rt s = (Rt)(SIGN * kRoots<R>.s[e % R]);
+  return T{b.x * c - b.y * s, b.x * s + b.y * c};
+}
+
+// P-point DFT, P odd, from the (P-1)/2 sums and differences of mirrored samples:
+//   X[k]     = x0 + sum_j (x_j + x_{P-j}) cos(2 pi jk/P) + SIGN i sum_j (x_j - x_{P-j}) sin(2 pi jk/P),
+//   X[P - k] = the same with -SIGN,   j, k = 1 .. (P-1)/2.
+template <int P, int SIGN, class T> __device__ __forceinline__ void dft_odd(T* v) {
+  using Rt = typename real_of<T>::type;
+  constexpr int H = (P - 1) / 2;
+  T sm[H], df[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    sm[j] = cadd(v[j + 1], v[P - 1 - j]);
+    df[j] = csub(v[j + 1], v[P - 1 - j]);
+  }
+  T y[P];
+  y[0] = v[0];
+#pragma unroll
+  for (int j = 0; j < H; ++j) y[0] = cadd(y[0], sm[j]);
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    T a = v[0], b{(Rt)0, (Rt)0};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const Rt c = (Rt)kRoots<P>.c[(j * k) % P];
+      const Rt s = (Rt)kRoots<P>.s[(j * k) % P];
+      a = T{a.x + sm[j - 1].x * c, a.y + sm[j - 1].y * c};
+      b = T{b.x + df[j - 1].x * s, b.y + df[j - 1].y * s};
+    }
+    // SIGN i b = SIGN (-b.y, b.x)
+    y[k] = T{a.x - (Rt)SIGN * b.y, a.y + (Rt)SIGN * b.x};
+    y[P - k] = T{a.x + (Rt)SIGN * b.y, a.y - (Rt)SIGN * b.x};
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) v[k] = y[k];
+}
+
+// In-register DFT of length R (odd factors 3, 5, 7; power-of-two part <= 32), natural order in and
+// out. R = P M with P the smallest odd factor: the M-point DFTs of the P decimated sequences
+// x[P m + r], the twiddles e^{SIGN 2 pi i r k'/R}, then P-point DFTs across r:
+//   X[k' + M k''] = sum_r e^{SIGN 2 pi i r k''/P} (e^{SIGN 2 pi i r k'/R} Y_r[k']).
+template <int R, int SIGN, class T> __device__ __forceinline__ void dft_any(T* v) {
+  if constexpr (is_pow2(R)) {
+    dft_reg<R, SIGN>(v);
+  } else if constexpr (smallest_odd_factor(R) == R) {
+    dft_odd<R, SIGN>(v);
+  } else {
+    constexpr int P = smallest_odd_factor(R), M = R / P;
+    T sub[P][M];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) sub[r][m] = v[P * m + r];
+      dft_any<M, SIGN>(sub[r]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < M; ++k1) {
+      T t[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) t[r] = twiddle_ct<R, SIGN>(sub[r][k1], r * k1);
+      dft_odd<P, SIGN>(t);
+#pragma unroll
+      for (int k2 = 0; k2 < P; ++k2) v[k1 + M * k2] = t[k2];
+    }
+  }
+}
+
 // Split of a length-N DFT across N2 threads holding N1 elements each (N = N1 N2, N1 >= N2).
 template <int N> struct Split {
   static constexpr int L = ilog2(N);
@@ -211,6 +358,20 @@ template <class T, int SIGN> __device__ __forceinline__ T twiddle_entry(int j, i
   double s, c;
   sincospi((double)(SIGN * 2) * (double)j / (double)N, &s, &c);
   return T{(R)c, (R)s};
+}
+
+// ok ? a : 0, component by component (a select of whole structs can be lowered through scratch memory).
+template <class T> __device__ __forceinline__ T keep_or_zero(bool ok, T a) {
+  using R = typename real_of<T>::type;
+  return T{ok ? a.x : (R)0, ok ? a.y : (R)0};
+}
+
+// p[ok ? i : 0]: every lane loads, lanes outside the data read element 0 (a valid address) and are
+// zeroed by the caller. Without a branch around each load the compiler issues all of a thread's
+// loads before it waits on the first; a conditional load whose value is used in its own branch is
+// waited on at once.
+template <class T> __device__ __forceinline__ T load_or_first(const T* p, bool ok, long long i) {
+  return p[ok ? i : 0];
 }
 
 // Monotone map of a double to an unsigned 64-bit key (for atomicMax over reals) and back.

@@ -42,8 +42,11 @@ __global__ __launch_bounds__(256) void k_rs_kernel(T* __restrict__ h, int n, dou
 // columns tx + 16 c (r, c < 4), so that the LDS reads of a wavefront are broadcasts (A) or
 // consecutive (B), and the stores are 16 consecutive elements. The k dimension is staged through
 // LDS 16 at a time. Out-of-range elements load as zero and are not stored (NN < 64).
+// complex128 tiles need about 200 registers: at most two waves per SIMD, rather than spills.
+template <class T> constexpr int cgemm_max_waves() { return sizeof(T) == 16 ? 2 : 8; }
+
 template <class T, bool CONJ_A, bool B_TRANS>
-__global__ __launch_bounds__(256) void k_cgemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, cgemm_max_waves<T>()))) void k_cgemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
                                                int nn, double alpha) {
   using R = typename real_of<T>::type;
   constexpr int TM = 64, TN = 64, TK = 16;
@@ -59,12 +62,33 @@ __global__ __launch_bounds__(256) void k_cgemm(const T* __restrict__ A, const T*
     for (int c = 0; c < 4; ++c) acc[r][c] = T{(R)0, (R)0};
   const T zero{(R)0, (R)0};
   for (long long k0 = 0; k0 < nn; k0 += TK) {
+    // All eight loads are issued before any is used (out-of-range lanes read element 0, then zero).
+    T ra[4], rb[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int ii = e / TK, kk = e % TK;
       const long long gi = i0 + ii, gk = k0 + kk;
-      T v = (gi < nn && gk < nn) ? A[gi * nn + gk] : zero;
+      ra[q] = load_or_first(A, gi < nn && gk < nn, gi * nn + gk);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      if constexpr (B_TRANS) {
+        const int jj = e / TK, kk = e % TK;
+        const long long gj = j0 + jj, gk = k0 + kk;
+        rb[q] = load_or_first(B, gj < nn && gk < nn, gj * nn + gk);
+      } else {
+        const int kk = e / TN, jj = e % TN;
+        const long long gj = j0 + jj, gk = k0 + kk;
+        rb[q] = load_or_first(B, gj < nn && gk < nn, gk * nn + gj);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int ii = e / TK, kk = e % TK;
+      T v = keep_or_zero(i0 + ii < nn && k0 + kk < nn, ra[q]);
       if constexpr (CONJ_A) v.y = -v.y;
       As[kk][ii] = v;
     }
@@ -73,12 +97,10 @@ __global__ __launch_bounds__(256) void k_cgemm(const T* __restrict__ A, const T*
       const int e = tid + 256 * q;
       if constexpr (B_TRANS) {
         const int jj = e / TK, kk = e % TK;
-        const long long gj = j0 + jj, gk = k0 + kk;
-        Bs[kk][jj] = (gj < nn && gk < nn) ? B[gj * nn + gk] : zero;
+        Bs[kk][jj] = keep_or_zero(j0 + jj < nn && k0 + kk < nn, rb[q]);
       } else {
         const int kk = e / TN, jj = e % TN;
-        const long long gj = j0 + jj, gk = k0 + kk;
-        Bs[kk][jj] = (gj < nn && gk < nn) ? B[gk * nn + gj] : zero;
+        Bs[kk][jj] = keep_or_zero(j0 + jj < nn && k0 + kk < nn, rb[q]);
       }
     }
     __syncthreads();

@@ -367,8 +367,6 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
 // resident per CU (one loads while the other computes), and 139 KB in complex128, which fits where
 // the whole slab (256 KB) does not. Thread tid plays (t1, c) = (tid / H, tid % H + H vt) in the column
 // phase and (t2, r) = (tid % N2, tid / N2 + H h) in the row phase, with H = N/2.
-constexpr size_t kMaxLds = 160 * 1024;
-
 template <class T, int N> constexpr size_t half_lds_bytes() {
   return sizeof(T) * ((size_t)(N / 2) * slab_stride<N>() + 3 * N + 2);
 }
