@@ -10,6 +10,7 @@
 //   dL/dsg   = sum_{p, q} Re(conj(G_A[p; q]) W_A[p; q]) |xi_p - xi_q|^2 / sg^3
 // The row sums R come from one workgroup per slab. The column sums K are accumulated by workgroups
 // that each own a group of slabs, then reduced over the groups.
+#include "wolf_device.hpp"
 #include "wolf_internal.hpp"
 
 namespace wolf {
@@ -24,7 +25,9 @@ __global__ __launch_bounds__(256) void k_diag_embed(const typename real_of<T>::t
   for (long long e = threadIdx.x; e < nn; e += blockDim.x) slab[e] = T{e == p1 ? g[p1] : (R)0, (R)0};
 }
 
-// Per-group partials: rows[p1] (one per slab), colpart[group][q], sgpart[group].
+// Per-group partials: rows[p1] (one per slab), colpart[group][q], sgpart[group]. A thread owns the
+// columns q = k 256 + tid; it issues the loads of 16 columns before it uses any. The row sum of a slab
+// is reduced by a butterfly within each wavefront and then over the four wavefronts in order.
 template <class T, int COLS_PER_THREAD>
 __global__ __launch_bounds__(256) void k_fit_partials(const T* __restrict__ ga, const float* __restrict__ imap, int n,
                                                       double inv2g2_px, int slabs_per_group,
@@ -32,11 +35,12 @@ __global__ __launch_bounds__(256) void k_fit_partials(const T* __restrict__ ga, 
                                                       typename real_of<T>::type* __restrict__ colpart,
                                                       double* __restrict__ sgpart) {
   using R = typename real_of<T>::type;
-  __shared__ R red[256];
+  constexpr int CH = COLS_PER_THREAD < 16 ? COLS_PER_THREAD : 16;
+  __shared__ R red[2][4];  // wavefront sums of the row, double-buffered by slab parity
   __shared__ double redd[256];
   __shared__ R gx[256];  // exp(-d^2 pitch^2 / (2 sg^2)) for d = 0..N-1; mu_g = gx[|di|] gx[|dj|]
   const long long nn = (long long)n * n;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   for (int d = tid; d < n; d += blockDim.x) gx[d] = (R)exp(-(double)d * (double)d * inv2g2_px);
   __syncthreads();
   R colacc[COLS_PER_THREAD];
@@ -51,29 +55,37 @@ __global__ __launch_bounds__(256) void k_fit_partials(const T* __restrict__ ga, 
     const T* row = ga + p * nn;
     R racc = (R)0;
 #pragma unroll
-    for (int k = 0; k < COLS_PER_THREAD; ++k) {
-      const long long q = (long long)k * 256 + tid;
-      if (q < nn) {
+    for (int k0 = 0; k0 < COLS_PER_THREAD; k0 += CH) {
+      T gv[CH];
+      float im[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const long long q = (long long)(k0 + k) * 256 + tid;
+        gv[k] = load_or_first(row, q < nn, q);
+        im[k] = load_or_first(imap, q < nn, q);
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const long long q = (long long)(k0 + k) * 256 + tid;
+        const bool ok = q < nn;
         const int qi = (int)(q / n), qj = (int)(q % n);
         const int di = pi - qi, dj = pj - qj;
         const double d2 = (double)(di * di + dj * dj);
-        const R mu = gx[di < 0 ? -di : di] * gx[dj < 0 ? -dj : dj];
-        const R aq = sqrt((R)imap[q]);
-        const T gv = row[q];
-        const R w = gv.x * aq * mu;                  // Re(conj(G) a(q) mu), a and mu real
+        const int ai = di < 0 ? -di : di, aj = dj < 0 ? -dj : dj;
+        const R mu = gx[ok ? ai : 0] * gx[ok ? aj : 0];
+        const R aq = sqrt((R)im[k]);
+        const R gre = ok ? gv[k].x : (R)0;
+        const R w = gre * aq * mu;                   // Re(conj(G) a(q) mu), a and mu real
         racc += w;
-        colacc[k] += gv.x * ap * mu;                 // contribution to K(q)
+        colacc[k0 + k] += gre * ap * mu;             // contribution to K(q)
         sgacc += (double)(w * ap) * d2;              // Re(conj(G) W_A) |d|^2 in pixel units
       }
     }
-    red[tid] = racc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off);
+    if (lane == 0) red[s & 1][wave] = racc;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (tid < h) red[tid] += red[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) rows[p] = red[0];
-    __syncthreads();
+    if (tid == 0) rows[p] = ((red[s & 1][0] + red[s & 1][1]) + red[s & 1][2]) + red[s & 1][3];
   }
 #pragma unroll
   for (int k = 0; k < COLS_PER_THREAD; ++k) {
@@ -89,6 +101,9 @@ __global__ __launch_bounds__(256) void k_fit_partials(const T* __restrict__ ga, 
   if (tid == 0) sgpart[group] = redd[0];
 }
 
+// dL/dI from the row sums and the column partials, and dL/dsg from the group partials. A workgroup
+// owns 32 columns; its eight slices of 32 threads each add every eighth group in order, and the slices
+// are combined in order. Workgroup 0 also adds the sg partials: 256 strided sums, then a fixed tree.
 template <class T>
 __global__ __launch_bounds__(256) void k_fit_finish(const float* __restrict__ imap, int n, int groups,
                                                     const typename real_of<T>::type* __restrict__ rows,
@@ -96,18 +111,36 @@ __global__ __launch_bounds__(256) void k_fit_finish(const float* __restrict__ im
                                                     const double* __restrict__ sgpart, double sg_scale,
                                                     float* __restrict__ d_imap, double* __restrict__ d_sigma) {
   using R = typename real_of<T>::type;
+  __shared__ R part[8][32];
+  __shared__ double sred[256];
   const long long nn = (long long)n * n;
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cx = threadIdx.x % 32, sl = threadIdx.x / 32;
+  const long long q = (long long)blockIdx.x * 32 + cx;
+  R k = (R)0;
   if (q < nn) {
-    R k = (R)0;
-    for (int g = 0; g < groups; ++g) k += colpart[(long long)g * nn + q];
-    const R a = sqrt((R)imap[q]);
-    d_imap[q] = (float)((rows[q] + k) / ((R)2 * a));
+#pragma unroll 8
+    for (int g = sl; g < groups; g += 8) k += colpart[(long long)g * nn + q];  // loads in flight, sums in order
   }
-  if (q == 0) {
+  part[sl][cx] = k;
+  if (blockIdx.x == 0) {
     double t = 0.0;
-    for (int g = 0; g < groups; ++g) t += sgpart[g];
-    *d_sigma = t * sg_scale;
+    for (int g = threadIdx.x; g < groups; g += 256) t += sgpart[g];
+    sred[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (sl == 0 && q < nn) {
+    R kk = part[0][cx];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) kk += part[j][cx];
+    const R a = sqrt((R)imap[q]);
+    d_imap[q] = (float)((rows[q] + kk) / ((R)2 * a));
+  }
+  if (blockIdx.x == 0) {
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) sred[threadIdx.x] += sred[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *d_sigma = sred[0] * sg_scale;
   }
 }
 
@@ -137,7 +170,7 @@ hipError_t launch_fit_gradient(int n, const T* ga, const float* imap, double inv
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fit_finish<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, imap, n, groups,
+  hipLaunchKernelGGL(k_fit_finish<T>, dim3((unsigned)((nn + 31) / 32)), dim3(256), 0, st, imap, n, groups,
                      (const R*)rows, (const R*)colpart, (const double*)sgpart, sg_scale, d_imap, d_sigma);
   return hipGetLastError();
 }
