@@ -36,10 +36,12 @@ def parse():
     ap.add_argument("--big", action="store_true", help="also time the N=256 complex64 workload (34 GB)")
     ap.add_argument("--plan", default="auto",
                     help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or 'fused,slab_chunk,col_chunk'")
-    ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None, choices=["propagate", "batch"],
+    ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None,
+                    choices=["propagate", "batch", "padded"],
                     help="run one untimed invocation for a counter run and exit: 'propagate' (build, in-place "
-                         "propagation, then a 2 GiB runtime copy of known size for calibration) or 'batch' "
-                         "(the 64-pair observables batch)")
+                         "propagation, then a 2 GiB runtime copy of known size for calibration), 'batch' "
+                         "(the 64-pair observables batch) or 'padded' (N = 200 complex64 in place, padded to "
+                         "N_z = 512, then unpadded)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="rocprofv3 FETCH/WRITE summary for the current kernels (optional)")
     return ap.parse_args()
@@ -115,6 +117,15 @@ def main():
         wolf.propagate_fresnel(w, p, lam, z, out=w)
         cal = torch.empty_like(w)
         cal.copy_(w)  # calibration: 2 GiB read + 2 GiB write by the runtime's copy kernel
+        torch.cuda.synchronize()
+        print("pmc sample done", flush=True)
+        return
+    if args.pmc_sample == "padded":
+        del w
+        torch.cuda.empty_cache()
+        n2, p2, z2, w2 = padded_source(wolf)
+        for nz in (512, 200):
+            wolf.propagate_padded(w2, p2, wolf_lam(), z2, nz, out=w2)
         torch.cuda.synchronize()
         print("pmc sample done", flush=True)
         return
@@ -362,12 +373,8 @@ def direct_check(wolf):
     return out
 
 
-def padded_check(wolf):
-    """The paper's example size: N = 200 (not a power of two), GSM source, Fresnel z = 0.5 m, complex64,
-    in place (1.6e9 elements, 12.8 GB). Padded to N_z = 512 (Secs. 5.1, 5.2): four zero-padded FFT
-    passes. Unpadded (N_z = 200, Secs. 5.3, 5.4): four 20 x 10 mixed-radix FFT passes. Both move 64 B
-    per element (the operator needs 32 B/element). For comparison the dense passes, which any other
-    N_z takes (here N_z = 210), with a 12.8 GB work array, 32 N real flops per element."""
+def padded_source(wolf):
+    """The N = 200 GSM source of the padded workload (complex64, 12.8 GB), with its pitch and distance."""
     import types
 
     import torch
@@ -378,7 +385,18 @@ def padded_check(wolf):
     src = types.SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=0.1e-3, sigma_g_m=0.05e-3,
                                 geometry=WI.GEO_NONE, geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None,
                                 lens_focal_m=0.0, wavelength_m=0.0)
-    w = wolf.build_source(src, n, p, torch.complex64)
+    return n, p, z, wolf.build_source(src, n, p, torch.complex64)
+
+
+def padded_check(wolf):
+    """The paper's example size: N = 200 (not a power of two), GSM source, Fresnel z = 0.5 m, complex64,
+    in place (1.6e9 elements, 12.8 GB). Padded to N_z = 512 (Secs. 5.1, 5.2): four zero-padded FFT
+    passes. Unpadded (N_z = 200, Secs. 5.3, 5.4): four 20 x 10 mixed-radix FFT passes. Both move 64 B
+    per element (the operator needs 32 B/element). For comparison the dense passes, which any other
+    N_z takes (here N_z = 210), with a 12.8 GB work array, 32 N real flops per element."""
+    import torch
+
+    n, p, z, w = padded_source(wolf)
     work = torch.empty_like(w)
     elems = float(n) ** 4
     out = {}
