@@ -226,20 +226,24 @@ struct PadJob {
 // Split of an N_z-point line transform over L2 threads that hold L1 = Q L2 elements each
 // (N_z = Q L2^2), and the C lines of a workgroup (L2 C <= 256 threads, at most one wavefront per
 // SIMD). Powers of two take the split of the slab and axis passes and C = 256 / L2. Other lengths
-// take the largest L2 with L1 <= 32 (the register DFTs) and C = 8 floor(32 / L2), a multiple of 8
-// lines so that a tile of neighbouring lines spans whole 64-byte segments.
+// take the largest L2 with L1 <= 32 (the register DFTs); C is a multiple of 16 lines in complex64
+// (16 max(1, floor(16 / L2))) and of 8 lines in complex128 (8 floor(32 / L2)), so that a tile of
+// neighbouring lines spans whole 128-byte memory lines (tiles that split lines between workgroups,
+// which run on different XCDs, took 27 ms instead of 23 ms at N = 200 in complex64).
 __host__ __device__ constexpr int line_l2(int lz) {
   if (is_pow2(lz)) return lz >> ((ilog2(lz) + 1) / 2);  // Split<lz>::N2
   for (int l2 = 32; l2 >= 1; --l2)
     if (lz % (l2 * l2) == 0 && (lz / (l2 * l2)) * l2 <= 32) return l2;
   return 0;
 }
-__host__ __device__ constexpr int line_cols(int l2) { return 8 * (32 / l2); }
-template <int NZ> struct LineCfg {
+__host__ __device__ constexpr int line_cols(int l2, int elem_bytes) {
+  return elem_bytes == 8 ? 16 * (16 / l2 > 1 ? 16 / l2 : 1) : 8 * (32 / l2);
+}
+template <class T, int NZ> struct LineCfg {
   static constexpr int L2 = line_l2(NZ);
   static constexpr int L1 = NZ / L2;
   static constexpr int Q = L1 / L2;
-  static constexpr int C = is_pow2(NZ) ? 256 / L2 : line_cols(L2);
+  static constexpr int C = is_pow2(NZ) ? 256 / L2 : line_cols(L2, (int)sizeof(T));
   static constexpr int kThreads = L2 * C;
   static_assert(L2 >= 1 && L1 == Q * L2 && L1 <= 32 && kThreads <= 256, "line split");
 };
@@ -254,9 +258,9 @@ template <int NZ> struct LineCfg {
 //           covers whole lines of memory; entry at c G N2 (N2 + 1) + k1l (N2 + 1) + n2.
 // The paddings (C entries per k1l, one per N2) keep the writes and the reads of a phase free of
 // bank conflicts beyond the two passes that 64 eight-byte accesses need.
-template <int NZ, bool CONTIG, int G> struct PadLayout {
-  static constexpr int N2 = LineCfg<NZ>::L2;
-  static constexpr int C = LineCfg<NZ>::C;
+template <class T, int NZ, bool CONTIG, int G> struct PadLayout {
+  static constexpr int N2 = LineCfg<T, NZ>::L2;
+  static constexpr int C = LineCfg<T, NZ>::C;
   static constexpr int kSize = CONTIG ? C * G * N2 * (N2 + 1) : G * N2 * (N2 * C + C);
   static __device__ __forceinline__ int at(int k1l, int n2, int c) {
     return CONTIG ? c * (G * N2 * (N2 + 1)) + k1l * (N2 + 1) + n2 : k1l * (N2 * C + C) + n2 * C + c;
@@ -264,24 +268,24 @@ template <int NZ, bool CONTIG, int G> struct PadLayout {
 };
 
 template <class T, int NZ, int G> constexpr size_t pad_lds_bytes() {
-  return (PadLayout<NZ, false, G>::kSize + 2 * kDenseMaxN + NZ) * sizeof(T);
+  return (PadLayout<T, NZ, false, G>::kSize + 2 * kDenseMaxN + NZ) * sizeof(T);
 }
 
 // One exchange unless phases let more workgroups share a CU and the inputs are few enough (L1 <= 16)
 // to stay in registers across the phases; with complex64 the single exchange already fits as many
 // workgroups as the registers allow (measured register counts of the unrolled kernels).
 template <class T, int NZ> constexpr int pad_groups() {
-  using S = LineCfg<NZ>;
+  using S = LineCfg<T, NZ>;
   constexpr bool phases_fit_more = kMaxLds / pad_lds_bytes<T, NZ, S::Q>() < kMaxLds / pad_lds_bytes<T, NZ, 1>();
   return (sizeof(T) == 16 && S::L1 <= 16 && phases_fit_more) ? 1 : S::Q;
 }
 
 template <class T, int NZ, int SIGN, bool CONTIG>
-__global__ __launch_bounds__(LineCfg<NZ>::kThreads) void k_axis_pad(const T* src, T* dst, PadJob j) {
-  using S = LineCfg<NZ>;
+__global__ __launch_bounds__((LineCfg<T, NZ>::kThreads)) void k_axis_pad(const T* src, T* dst, PadJob j) {
+  using S = LineCfg<T, NZ>;
   using R = typename real_of<T>::type;
   constexpr int N1 = S::L1, N2 = S::L2, Q = S::Q, C = S::C, NT = S::kThreads, G = pad_groups<T, NZ>();
-  using L = PadLayout<NZ, CONTIG, G>;
+  using L = PadLayout<T, NZ, CONTIG, G>;
   __shared__ T xch[L::kSize];
   __shared__ T tpre[kDenseMaxN], tpost[kDenseMaxN], tw[NZ];
   const int n = j.n, sft = j.s;
@@ -345,15 +349,15 @@ __global__ __launch_bounds__(LineCfg<NZ>::kThreads) void k_axis_pad(const T* src
 template <class T, int NZ, bool CONTIG>
 static hipError_t launch_pad_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
   if (sign < 0)
-    hipLaunchKernelGGL((k_axis_pad<T, NZ, -1, CONTIG>), dim3(grid), dim3(LineCfg<NZ>::kThreads), 0, st, src, dst, j);
+    hipLaunchKernelGGL((k_axis_pad<T, NZ, -1, CONTIG>), dim3(grid), dim3(LineCfg<T, NZ>::kThreads), 0, st, src, dst, j);
   else
-    hipLaunchKernelGGL((k_axis_pad<T, NZ, +1, CONTIG>), dim3(grid), dim3(LineCfg<NZ>::kThreads), 0, st, src, dst, j);
+    hipLaunchKernelGGL((k_axis_pad<T, NZ, +1, CONTIG>), dim3(grid), dim3(LineCfg<T, NZ>::kThreads), 0, st, src, dst, j);
   return hipGetLastError();
 }
 
 template <class T, int NZ>
 static hipError_t launch_pad_nz(const T* src, T* dst, PadJob j, int sign, hipStream_t st) {
-  constexpr int C = LineCfg<NZ>::C;
+  constexpr int C = LineCfg<T, NZ>::C;
   j.tiles_per_outer = (j.ncols + C - 1) / C;
   j.tiles = j.outer * j.tiles_per_outer;
   const long long grid = j.tiles < 4096 ? j.tiles : 4096;
