@@ -2,6 +2,7 @@
 // No exception crosses this layer. Every entry point returns a wolf_status.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -156,15 +157,21 @@ struct LensSpec {
   double pupil_radius_m;
 };
 
-// The batch extracts S and mu(P, .) without an N^4 output where the observables pass fits.
-bool batch_uses_observables(int32_t n, int32_t dtype) {
+// The batch extracts S and mu(P, .) without an N^4 output. In the far field, where the observables
+// pass fits, one slab-transform pass serves every pair; otherwise the sums over the first point are
+// shared contractions of all pairs (wolf_pairs.hip).
+bool batch_uses_observables(int32_t n, int32_t dtype, bool farfield) {
+  if (!farfield) return false;
   return dtype == WOLF_C64 ? wolf::obs_supported<float2>(n) : wolf::obs_supported<double2>(n);
 }
 
 size_t batch_work_bytes(int32_t n, int32_t dtype) {
-  if (batch_uses_observables(n, dtype))
-    return dtype == WOLF_C64 ? wolf::obs_work_bytes<float2>(n) : wolf::obs_work_bytes<double2>(n);
-  return n4(n) * elem_bytes(dtype);
+  size_t b = dtype == WOLF_C64 ? wolf::pair_work_bytes<float2>(n) : wolf::pair_work_bytes<double2>(n);
+  if (batch_uses_observables(n, dtype, true)) {
+    const size_t o = dtype == WOLF_C64 ? wolf::obs_work_bytes<float2>(n) : wolf::obs_work_bytes<double2>(n);
+    if (o > b) b = o;
+  }
+  return b;
 }
 
 template <class T>
@@ -183,6 +190,44 @@ hipError_t record_obs_pairs(int32_t n, const T* w_src, double pitch, int32_t n_p
       e = wolf::launch_obs_emit<T>(n, sums, op, weight[k], ip, jp, floor_rel, s_out + k * nn, mu_out + k * nn, st);
   }
   return e;
+}
+
+// Groups of up to 64 pairs: their raw sums from one pair-sums pass, then one emit per pair. In the far
+// field the sums do not depend on (lambda, z): one group of one chirp-free entry serves every pair.
+template <class T>
+hipError_t record_pair_groups(int32_t n, const T* w_src, double pitch, int32_t n_pairs, const double* lam,
+                              const double* z, const double* weight, bool farfield, int32_t kind, int32_t ip, int32_t jp,
+                              double floor_rel, void* work, typename wolf::real_of<T>::type* s_out, T* mu_out,
+                              hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  constexpr int G = wolf::kPairGroup;
+  std::vector<wolf::ObsSums<T>> sums(G);
+  double a_src[G];
+  hipError_t e = hipSuccess;
+  for (int k0 = 0; k0 < n_pairs && e == hipSuccess; k0 += G) {
+    const int cnt = farfield ? 1 : std::min(G, n_pairs - k0);
+    for (int k = 0; k < cnt; ++k) a_src[k] = farfield ? 0.0 : pitch * pitch / (lam[k0 + k] * z[k0 + k]);
+    if (k0 == 0 || !farfield) e = wolf::launch_pair_sums<T>(n, w_src, a_src, cnt, ip, jp, work, sums.data(), st);
+    const int last = farfield ? n_pairs : std::min(n_pairs, k0 + G);
+    for (int k = k0; k < last && e == hipSuccess; ++k) {
+      const wolf::OperatorTables op = make_op(n, pitch, lam[k], z[k], farfield, kind, false);
+      e = wolf::launch_obs_emit<T>(n, sums[farfield ? 0 : k - k0], op, weight[k], ip, jp, floor_rel, s_out + k * nn,
+                                   mu_out + k * nn, st);
+    }
+    if (farfield) break;
+  }
+  return e;
+}
+
+hipError_t record_batch_pairs(int32_t n, const void* w_src, double pitch, int32_t n_pairs, const double* lam,
+                              const double* z, const double* weight, bool farfield, int32_t kind, int32_t dtype,
+                              int32_t ip, int32_t jp, double floor_rel, void* work, void* s_out, void* mu_out,
+                              hipStream_t st) {
+  if (dtype == WOLF_C64)
+    return record_pair_groups<float2>(n, (const float2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
+                                      floor_rel, work, (float*)s_out, (float2*)mu_out, st);
+  return record_pair_groups<double2>(n, (const double2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
+                                     floor_rel, work, (double*)s_out, (double2*)mu_out, st);
 }
 
 hipError_t record_batch_observables(int32_t n, const void* w_src, double pitch, int32_t n_pairs, const double* lam,
@@ -599,7 +644,7 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "%s: s_floor_rel must be >= 0", who);
   const size_t eb = elem_bytes(dtype), big = n4(n) * eb, nn = (size_t)n * n;
   wolf_status s;
-  const bool obs = batch_uses_observables(n, dtype);
+  const bool obs = batch_uses_observables(n, dtype, farfield == 1);
   const size_t wb = batch_work_bytes(n, dtype);
   if ((s = check_buf(w_src, big, "w_src")) != WOLF_OK) return s;
   if ((s = check_buf(work, wb, "work")) != WOLF_OK) return s;
@@ -645,24 +690,9 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
     if (obs && e == hipSuccess) e = record_batch_observables(n, w_src, pitch_m, n_pairs, wavelength_m, z_m, weight,
                                                              farfield == 1, kind, dtype, ip, jp, s_floor_rel, work,
                                                              s_out, mu_out, cap);
-    for (int k = 0; k < n_pairs && e == hipSuccess && !obs; ++k) {
-      wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m[k], z_m[k], farfield == 1, kind, false);
-      op.scale *= weight[k];
-      if (dtype == WOLF_C64) {
-        e = wolf::launch_operator<float2>(n, (const float2*)w_src, (float2*)work, op, plan, scratch, cap);
-        if (e == hipSuccess) e = wolf::launch_spectral_density<float2>(n, (const float2*)work, (float*)s_out + k * nn, cap);
-        if (e == hipSuccess)
-          e = wolf::launch_coherence<float2>(n, (const float2*)work, ip, jp, s_floor_rel, (float2*)mu_out + k * nn,
-                                             scratch, cap);
-      } else {
-        e = wolf::launch_operator<double2>(n, (const double2*)w_src, (double2*)work, op, plan, scratch, cap);
-        if (e == hipSuccess)
-          e = wolf::launch_spectral_density<double2>(n, (const double2*)work, (double*)s_out + k * nn, cap);
-        if (e == hipSuccess)
-          e = wolf::launch_coherence<double2>(n, (const double2*)work, ip, jp, s_floor_rel, (double2*)mu_out + k * nn,
-                                              scratch, cap);
-      }
-    }
+    if (!obs && e == hipSuccess) e = record_batch_pairs(n, w_src, pitch_m, n_pairs, wavelength_m, z_m, weight,
+                                                        farfield == 1, kind, dtype, ip, jp, s_floor_rel, work, s_out,
+                                                        mu_out, cap);
     const hipError_t e_end = hipStreamEndCapture(cap, &graph);
     if (e == hipSuccess) e = e_end;
     hipGraphExec_t exec = nullptr;

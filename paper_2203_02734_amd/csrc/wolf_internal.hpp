@@ -78,6 +78,15 @@ hipError_t launch_obs_sums(int n, const T* src, const OperatorTables& op, int pi
 template <class T>
 hipError_t launch_obs_emit(int n, const ObsSums<T>& sums, const OperatorTables& op, double weight, int pi, int pj,
                            double floor_rel, typename real_of<T>::type* s_out, T* mu_out, hipStream_t st);
+// The same sums for groups of up to kPairGroup Fresnel pairs at once (wolf_pairs.hip): the first-point
+// contractions are shared by the pairs of a group, so the source is read twice per group. a_src[k] is
+// the source chirp rate pitch^2 / (lambda z) of pair k (0 in the far field); out[k] receives pair k's
+// sums, which live in `work` (pair_work_bytes) until the next call.
+constexpr int kPairGroup = 64;
+template <class T> size_t pair_work_bytes(int n);
+template <class T>
+hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, int pi, int pj, void* work,
+                            ObsSums<T>* out, hipStream_t st);
 template <class T> bool coop_supported(int n);
 template <class T>
 hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,

@@ -1,0 +1,377 @@
+// Observables of many (lambda, z) pairs from one read of the source: the sums that S and the row
+// W_B[P; .] need are contractions over the first point that every pair shares (eq. W_fresnel).
+//
+// With the operator's checkerboarded tables u1 = pre1, u2 = pre2 (per axis; they carry the source
+// chirp of each pair and the (-1)^n centring), the raw sums of S and of the row are
+//   s0[m] = Re sum_d e^{+2 pi i <m, d>/N} D[d],  D[d] = sum_{p1} u1(p1) u2(p1 - d) W[p1; p1 - d]
+//   b0[m] = sum_{p2} e^{-2 pi i <m, p2>/N} u2(p2) R[p2],  R[p2] = sum_{p1} e^{+2 pi i <P, p1>/N} u1(p1) W[p1; p2]
+// (indices mod N, 2D products of the axis tables). S = s w s0 and W_B[P; m] = s w post1(P) post2(m) b0[m]:
+// on the diagonal m1 = m2 = m the post-factors cancel and the two exponentials depend on p1 - p2 only.
+// Both sums are dense contractions over p1 with pair-dependent weights:
+//   R = C W with C[k][p1] = ci_k[a] cj_k[b] (a complex GEMM, pairs x N^2 x N^2), and
+//   D[k][(di, dj)] = sum_b B_k^{dj}[b] sum_a A_k^{di}[a] W[a, b; a - di, b - dj] with A = u1[a] u2[a - di],
+//   B = u1[b] u2[b - dj]: for each di and b a GEMM over a (pairs x N x N).
+// The source is read twice in all, whatever the number of pairs; then two N x N DFTs per pair.
+#include "wolf_device.hpp"
+#include "wolf_internal.hpp"
+
+namespace wolf {
+
+constexpr int kPairTile = kPairGroup;  // pairs per group (rows of the GEMM tiles)
+constexpr int kPairSplitK = 16;  // chunks of p1 in the row sums R (partials summed in FP64)
+
+struct PairGroup {
+  int count;                 // pairs in this group (<= kPairTile)
+  double a_src[kPairTile];   // source chirp rate of each pair (0 in the far field)
+};
+
+// Tables of one group, FP64-built: u1, u2 (pre1, pre2 of each pair), ci = e^{2 pi i P_i a/N} u1[a],
+// cj = e^{2 pi i P_j b/N} u1[b]; each kPairTile x N. Pairs beyond the count get zero tables.
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_tables(PairGroup g, int n, int pi, int pj, T* u1, T* u2, T* ci, T* cj) {
+  using R = typename real_of<T>::type;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kPairTile * n) return;
+  const int k = e / n, a = e % n;
+  if (k >= g.count) {
+    const T z{(R)0, (R)0};
+    u1[e] = z; u2[e] = z; ci[e] = z; cj[e] = z;
+    return;
+  }
+  const Chirp c1{g.a_src[k], 1.0, -1, 1}, c2{g.a_src[k], 1.0, +1, 1};
+  const double2 v1 = chirp_entry<double2>(c1, a, n), v2 = chirp_entry<double2>(c2, a, n);
+  double si, co, sj, cjx;
+  sincospi(2.0 * (double)((pi * a) % n) / (double)n, &si, &co);
+  sincospi(2.0 * (double)((pj * a) % n) / (double)n, &sj, &cjx);
+  const double2 wi = cmul(double2{co, si}, v1), wj = cmul(double2{cjx, sj}, v1);
+  u1[e] = T{(R)v1.x, (R)v1.y};
+  u2[e] = T{(R)v2.x, (R)v2.y};
+  ci[e] = T{(R)wi.x, (R)wi.y};
+  cj[e] = T{(R)wj.x, (R)wj.y};
+}
+
+// Row sums: part[s][k][p2] = sum_{p1 in chunk s} ci[k][a] cj[k][b] W[p1][p2]. A workgroup computes a
+// tile of 64 pairs x 64 columns p2, 4 x 4 per thread; p1 is staged through LDS 16 at a time: the A
+// operand is generated from the tables, the W rows are 64 contiguous elements (512 bytes in complex64).
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_rows(const T* __restrict__ w, int n, const T* __restrict__ ci,
+                                                   const T* __restrict__ cj, long long chunk, T* __restrict__ part) {
+  using R = typename real_of<T>::type;
+  constexpr int TM = kPairTile, TN = 64, TK = 16;
+  __shared__ T As[TK][TM + 1];
+  __shared__ T Bs[TK][TN + 1];
+  const long long nn = (long long)n * n;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const long long j0 = (long long)blockIdx.x * TN;
+  const long long s = blockIdx.y;
+  const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
+  const T zero{(R)0, (R)0};
+  T acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = zero;
+  for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
+    T rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // W rows: kk = e / 64, jj = e % 64
+      const int e = tid + 256 * q;
+      const int kk = e / TN, jj = e % TN;
+      const long long p1 = k0 + kk, p2 = j0 + jj;
+      rb[q] = load_or_first(w, p1 < p_end && p2 < nn, p1 * nn + p2);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // A: As[kk][k] = ci[k][a] cj[k][b], p1 = k0 + kk = a n + b
+      const int e = tid + 256 * q;
+      const int k = e / TK, kk = e % TK;
+      const long long p1 = k0 + kk;
+      const bool ok = p1 < p_end;
+      const int a = ok ? (int)(p1 / n) : 0, b = ok ? (int)(p1 % n) : 0;
+      As[kk][k] = keep_or_zero(ok, cmul(ci[k * n + a], cj[k * n + b]));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / TN, jj = e % TN;
+      Bs[kk][jj] = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[r][c].x += av[r].x * bv[c].x - av[r].y * bv[c].y;
+          acc[r][c].y += av[r].x * bv[c].y + av[r].y * bv[c].x;
+        }
+    }
+    __syncthreads();
+  }
+  T* out = part + s * kPairTile * nn;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const long long j = j0 + tx + 16 * c;
+      if (j < nn) out[(long long)(ty + 16 * r) * nn + j] = acc[r][c];
+    }
+}
+
+// Difference sums: part[sb][k][di n + dj] = sum_{b in chunk sb} B_k^{dj}[b] sum_a A_k^{di}[a]
+// W[a, b; a - di, b - dj]. A workgroup owns di, 64 values of dj and a chunk of b; for each b the
+// sum over a is a 64 x 64 x N GEMM (the W operand: for each a, 64 consecutive columns b - dj of one
+// row, read backwards, wrapping at N), then the B factors are applied and summed over b.
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int n, const T* __restrict__ u1,
+                                                    const T* __restrict__ u2, int bchunk, T* __restrict__ part) {
+  using R = typename real_of<T>::type;
+  constexpr int TM = kPairTile, TN = 64, TK = 16;
+  __shared__ T As[TK][TM + 1];
+  __shared__ T Bs[TK][TN + 1];
+  const long long nn = (long long)n * n;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int dj0 = blockIdx.x * TN, di = blockIdx.y;
+  const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
+  const T zero{(R)0, (R)0};
+  T dacc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dacc[r][c] = zero;
+  for (int b = b_begin; b < b_end; ++b) {
+    T g[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) g[r][c] = zero;
+    for (int a0 = 0; a0 < n; a0 += TK) {
+      T rb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // Bs[kk][jj] = W[a, b; a - di, b - dj], a = a0 + kk, dj = dj0 + jj
+        const int e = tid + 256 * q;
+        const int kk = e / TN, jj = e % TN;
+        const int a = a0 + kk, dj = dj0 + jj;
+        const int a2 = (a - di + n) % n, b2 = ((b - dj) % n + n) % n;
+        rb[q] = load_or_first(w, a < n && dj < n, ((long long)a * n + b) * nn + (long long)a2 * n + b2);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // As[kk][k] = u1[k][a] u2[k][a - di]
+        const int e = tid + 256 * q;
+        const int k = e / TK, kk = e % TK;
+        const int a = a0 + kk;
+        const bool ok = a < n;
+        const int ac = ok ? a : 0;
+        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + (ac - di + n) % n]));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        const int kk = e / TN, jj = e % TN;
+        Bs[kk][jj] = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            g[r][c].x += av[r].x * bv[c].x - av[r].y * bv[c].y;
+            g[r][c].y += av[r].x * bv[c].y + av[r].y * bv[c].x;
+          }
+      }
+      __syncthreads();
+    }
+    // B_k^{dj}[b] = u1[k][b] u2[k][b - dj]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = ty + 16 * r;
+      const T ub = u1[k * n + b];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int dj = dj0 + tx + 16 * c;
+        const int b2 = ((b - dj) % n + n) % n;
+        const T f = cmul(ub, u2[k * n + b2]);
+        const T t = cmul(f, g[r][c]);
+        dacc[r][c].x += t.x;
+        dacc[r][c].y += t.y;
+      }
+    }
+  }
+  T* out = part + (long long)blockIdx.z * kPairTile * nn;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int dj = dj0 + tx + 16 * c;
+      if (dj < n) out[(long long)(ty + 16 * r) * nn + (long long)di * n + dj] = dacc[r][c];
+    }
+}
+
+// out[k][i] = f(k, i) sum_s part[s][k][i], summed in FP64 in the order of s; f = u2[k][i / n] u2[k][i % n]
+// when u2 is given (the row sums), else 1.
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_sum(const T* __restrict__ part, int parts, int n,
+                                                  const T* __restrict__ u2, T* __restrict__ out) {
+  using R = typename real_of<T>::type;
+  const long long nn = (long long)n * n, total = (long long)kPairTile * nn;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  double2 acc{0.0, 0.0};
+#pragma unroll 8
+  for (int s = 0; s < parts; ++s) {
+    const T v = part[(long long)s * total + e];
+    acc.x += (double)v.x;
+    acc.y += (double)v.y;
+  }
+  if (u2 != nullptr) {
+    const long long k = e / nn, i = e - k * nn;
+    const T f = cmul(u2[k * n + i / n], u2[k * n + i % n]);
+    acc = cmul(acc, double2{(double)f.x, (double)f.y});
+  }
+  out[e] = T{(R)acc.x, (R)acc.y};
+}
+
+// One axis of the 2D DFT of every pair's N x N array, stored transposed:
+// out[k][m][i] = sum_p e^{SIGN 2 pi i m p / N} in[k][i][p]. Applied twice it gives the 2D DFT in natural
+// order. One workgroup per row (k, i): the row and the N roots (FP64-built) are staged in LDS.
+template <class T, int SIGN>
+__global__ __launch_bounds__(256) void k_pair_dft(const T* __restrict__ in, int n, T* __restrict__ out) {
+  using R = typename real_of<T>::type;
+  __shared__ T row[256], tw[256];
+  const long long nn = (long long)n * n;
+  const long long k = blockIdx.x / n, i = blockIdx.x % n;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    row[p] = in[k * nn + i * n + p];
+    tw[p] = twiddle_entry<T, SIGN>(p, n);
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < n; m += blockDim.x) {
+    T acc{(R)0, (R)0};
+    int idx = 0;
+    for (int p = 0; p < n; ++p) {
+      const T t = cmul(tw[idx], row[p]);
+      acc.x += t.x;
+      acc.y += t.y;
+      idx += m;
+      if (idx >= n) idx -= n;
+    }
+    out[k * nn + (long long)m * n + i] = acc;
+  }
+}
+
+// s0[k][m] = Re z[k][m] and key[k] = order key of max_m s0[k][m] (one workgroup per pair; fixed order).
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_s0(const T* __restrict__ z, int n, typename real_of<T>::type* s0,
+                                                 unsigned long long* key) {
+  using R = typename real_of<T>::type;
+  __shared__ double red[256];
+  const long long nn = (long long)n * n;
+  const long long k = blockIdx.x;
+  double mx = -INFINITY;
+  for (long long m = threadIdx.x; m < nn; m += blockDim.x) {
+    const R v = z[k * nn + m].x;
+    s0[k * nn + m] = v;
+    mx = fmax(mx, (double)v);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) key[k] = order_key(red[0]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Work layout (per group of kPairTile pairs), in elements of T unless noted.
+// ---------------------------------------------------------------------------------------------
+static int pair_tiles_j(int n) { return (n + 63) / 64; }
+static int pair_bsplit(int n) {
+  int sb = 1024 / (pair_tiles_j(n) * n);
+  if (sb < 4) sb = 4;
+  if (sb > n) sb = n;
+  return sb;
+}
+
+template <class T> size_t pair_work_bytes(int n) {
+  using R = typename real_of<T>::type;
+  const size_t nn = (size_t)n * n, g = (size_t)kPairTile * nn;
+  const size_t elems = 4 * (size_t)kPairTile * n + (size_t)kPairSplitK * g + (size_t)pair_bsplit(n) * g + 3 * g;
+  return elems * sizeof(T) + g * sizeof(R) + kPairTile * sizeof(unsigned long long) + 256;
+}
+
+template <class T>
+hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, int pi, int pj, void* work,
+                            ObsSums<T>* out, hipStream_t st) {
+  using R = typename real_of<T>::type;
+  if (count < 1 || count > kPairTile) return hipErrorInvalidValue;
+  const long long nn = (long long)n * n, g = (long long)kPairTile * nn;
+  T* base = reinterpret_cast<T*>(work);
+  T* u1 = base;
+  T* u2 = u1 + kPairTile * n;
+  T* ci = u2 + kPairTile * n;
+  T* cj = ci + kPairTile * n;
+  T* part_r = cj + kPairTile * n;
+  const int sb = pair_bsplit(n);
+  T* part_d = part_r + (long long)kPairSplitK * g;
+  T* buf_d = part_d + (long long)sb * g;  // D, then the 2D DFT of D
+  T* buf_t = buf_d + g;                   // transposed intermediate of the DFTs
+  T* buf_r = buf_t + g;                   // u2 R, then b0
+  R* s0 = reinterpret_cast<R*>(buf_r + g);
+  unsigned long long* key = reinterpret_cast<unsigned long long*>(
+      (reinterpret_cast<uintptr_t>(s0 + g) + 7) & ~(uintptr_t)7);
+
+  PairGroup pg{};
+  pg.count = count;
+  for (int k = 0; k < count; ++k) pg.a_src[k] = a_src[k];
+  hipLaunchKernelGGL(k_pair_tables<T>, dim3((unsigned)((kPairTile * n + 255) / 256)), dim3(256), 0, st, pg, n, pi, pj,
+                     u1, u2, ci, cj);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
+  hipLaunchKernelGGL(k_pair_rows<T>, dim3((unsigned)((nn + 63) / 64), kPairSplitK), dim3(256), 0, st, w, n,
+                     (const T*)ci, (const T*)cj, chunk, part_r);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int bchunk = (n + sb - 1) / sb;
+  hipLaunchKernelGGL(k_pair_diffs<T>, dim3((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb), dim3(256), 0, st, w,
+                     n, (const T*)u1, (const T*)u2, bchunk, part_d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const unsigned sum_blocks = (unsigned)((g + 255) / 256);
+  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n,
+                     (const T*)u2, buf_r);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_d, sb, n, (const T*)nullptr,
+                     buf_d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const unsigned rows = (unsigned)(kPairTile * n);
+  // s0 = Re F D F^T with the + sign; b0 = F* (u2 R) F*^T.
+  hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_d, n, buf_t);
+  hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_d);
+  hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_r, n, buf_t);
+  hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_r);
+  hipLaunchKernelGGL(k_pair_s0<T>, dim3((unsigned)count), dim3(256), 0, st, (const T*)buf_d, n, s0, key);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k = 0; k < count; ++k) out[k] = ObsSums<T>{s0 + k * nn, buf_r + k * nn, key + k};
+  return hipSuccess;
+}
+
+template size_t pair_work_bytes<float2>(int);
+template size_t pair_work_bytes<double2>(int);
+template hipError_t launch_pair_sums<float2>(int, const float2*, const double*, int, int, int, void*, ObsSums<float2>*,
+                                             hipStream_t);
+template hipError_t launch_pair_sums<double2>(int, const double2*, const double*, int, int, int, void*,
+                                              ObsSums<double2>*, hipStream_t);
+
+}  // namespace wolf
