@@ -306,8 +306,9 @@ def batch_and_fit(wolf, args):
         t = a.elapsed_time(b) / reps
         out[f"{tag}_ms"] = round(t, 3)
         out[f"{tag}_pairs_per_s"] = round(k / (t * 1e-3), 1)
-    # Fresnel: one read of the source per pair (8 B per element).
-    out["batch64_source_read_GBps"] = round(k * n ** 4 * 8 / (out["batch64_ms"] * 1e-3) / 1e9, 1)
+    # Fresnel: two contractions over the first point shared by the 64 pairs, 8 real flops per complex
+    # multiply-add, 64 pairs x N^4 multiply-adds each.
+    out["batch64_contraction_TFLOPs"] = round(2 * 8 * k * n ** 4 / (out["batch64_ms"] * 1e-3) / 1e12, 2)
     del w0, work
     torch.cuda.empty_cache()
 

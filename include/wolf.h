@@ -239,10 +239,12 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
  * at wavelength lambda[k] (Sec. 2.1, eqs. W_fresnel / W_farfield), and S_k (Algorithm 4) and
  * mu_k(P1, .) (Algorithm 5) are written to s_out[k] and mu_out[k]. No propagated N^4 array is
  * returned.
- * Where the observables pass fits (complex64 N <= 128, complex128 N <= 64) the propagated CSD
- * is never stored: S and the row W_B[P1; .] are summed straight from the slab transforms of the
- * source, one read of w_src per pair. In the far field the source-side factors do not depend on
- * (lambda, z), so a single read serves every pair. Elsewhere each pair is propagated into `work`.
+ * The propagated CSD is never stored. On the diagonal it depends on the source only through sums
+ * along the difference coordinate p1 - p2, and the row W_B[P1; .] through a weighted sum over the
+ * first point; with the source chirps of the pairs as weights both are dense contractions that
+ * groups of up to 64 pairs share (two reads of w_src per group, then two N x N DFTs per pair). In the
+ * far field the source-side factors do not depend on (lambda, z): one set of sums serves every pair
+ * (from the slab-transform observables pass where it fits: complex64 N <= 128, complex128 N <= 64).
  * The first call for a given shape records the sequence of launches in a hipGraph; later calls
  * with the same shape replay it.
  *   w_src          device N^4, read only.
@@ -258,7 +260,8 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
 
 /*
  * wolf_batch_work_bytes -- bytes of the `work` buffer that wolf_propagate_batch needs for (n, dtype):
- * per-workgroup partial sums when the observables pass fits, else one N^4 array. -1 if (n, dtype)
+ * the partial sums of one group of 64 pairs (16 + up to 32 N^2 x 64 complex chunks), three N^2 x 64
+ * buffers and the tables (about 190 MB at N = 128 complex64); never an N^4 array. -1 if (n, dtype)
  * is not supported.
  */
 WOLF_API int64_t wolf_batch_work_bytes(int32_t n, int32_t dtype);

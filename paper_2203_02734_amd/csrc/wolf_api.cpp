@@ -208,11 +208,18 @@ hipError_t record_pair_groups(int32_t n, const T* w_src, double pitch, int32_t n
     const int cnt = farfield ? 1 : std::min(G, n_pairs - k0);
     for (int k = 0; k < cnt; ++k) a_src[k] = farfield ? 0.0 : pitch * pitch / (lam[k0 + k] * z[k0 + k]);
     if (k0 == 0 || !farfield) e = wolf::launch_pair_sums<T>(n, w_src, a_src, cnt, ip, jp, work, sums.data(), st);
+    // In the far field every pair reads the one set of sums; emit in launches of up to G pairs.
     const int last = farfield ? n_pairs : std::min(n_pairs, k0 + G);
-    for (int k = k0; k < last && e == hipSuccess; ++k) {
-      const wolf::OperatorTables op = make_op(n, pitch, lam[k], z[k], farfield, kind, false);
-      e = wolf::launch_obs_emit<T>(n, sums[farfield ? 0 : k - k0], op, weight[k], ip, jp, floor_rel, s_out + k * nn,
-                                   mu_out + k * nn, st);
+    for (int e0 = k0; e0 < last && e == hipSuccess; e0 += G) {
+      const int ecnt = std::min(G, last - e0);
+      double c[G], a_out[G];
+      for (int k = 0; k < ecnt; ++k) {
+        const wolf::OperatorTables op = make_op(n, pitch, lam[e0 + k], z[e0 + k], farfield, kind, false);
+        c[k] = op.scale * weight[e0 + k];
+        a_out[k] = op.post2.alpha;
+      }
+      e = wolf::launch_pair_emit<T>(n, sums[farfield ? 0 : e0 - k0], farfield, ecnt, c, a_out, ip, jp, floor_rel,
+                                    s_out + e0 * nn, mu_out + e0 * nn, st);
     }
     if (farfield) break;
   }

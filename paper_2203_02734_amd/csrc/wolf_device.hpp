@@ -384,4 +384,28 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
   return __longlong_as_double((long long)b);
 }
 
+// One output point m of the observables: S[m] = c s0[m]; mu(P, m) = post1[P_i] post1[P_j] post2[m_i]
+// post2[m_j] b0[m] / sqrt(s0[P] s0[m]) where both s0 exceed floor * max s0 (key: order key of the
+// maximum) and c > 0, else 0. The factor c cancels in mu. Phases in FP64.
+template <class T, class R>
+__device__ __forceinline__ void emit_observables(const R* s0, const T* b0, unsigned long long key, int n, int pi, int pj,
+                                                 long long m, double c, const Chirp& post1, const Chirp& post2,
+                                                 double floor_rel, R* s_out, T* mu_out) {
+  const int mi = (int)(m / n), mj = (int)(m - (long long)mi * n);
+  const R sm = s0[m];
+  s_out[m] = (R)(c * (double)sm);
+  const R tau = (R)(floor_rel * key_value(key));
+  const R sp = s0[(long long)pi * n + pj];
+  T out{(R)0, (R)0};
+  if (c > 0.0 && sp > tau && sm > tau) {
+    const double2 ph = cmul(cmul(chirp_entry<double2>(post1, pi, n), chirp_entry<double2>(post1, pj, n)),
+                            cmul(chirp_entry<double2>(post2, mi, n), chirp_entry<double2>(post2, mj, n)));
+    const T f{(R)ph.x, (R)ph.y};
+    const R d = sqrt(sp) * sqrt(sm);
+    const T v = cmul(f, b0[m]);
+    out = T{v.x / d, v.y / d};
+  }
+  mu_out[m] = out;
+}
+
 }  // namespace wolf

@@ -965,32 +965,14 @@ __global__ __launch_bounds__(256) void k_obs_reduce(const typename real_of<T>::t
 
 __global__ void k_obs_clear_key(unsigned long long* key) { *key = 0ull; }
 
-// S = c s0; mu(P, m) = post1[P_i] post1[P_j] post2[m_i] post2[m_j] b0[m] / sqrt(s0[P] s0[m]) where
-// both s0 exceed floor * max s0 (and c > 0), 0 elsewhere. The factor s c cancels in mu.
+// S = c s0 and mu(P, .) from the raw sums (emit_observables).
 template <class T>
 __global__ __launch_bounds__(256) void k_obs_emit(const typename real_of<T>::type* __restrict__ s0,
                                                   const T* __restrict__ b0, const unsigned long long* key, int n, int pi,
                                                   int pj, double c, Chirp post1, Chirp post2, double floor_rel,
                                                   typename real_of<T>::type* __restrict__ s_out, T* __restrict__ mu_out) {
-  using R = typename real_of<T>::type;
-  const long long nn = (long long)n * n;
   const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nn) return;
-  const int mi = (int)(m / n), mj = (int)(m - (long long)mi * n);
-  const R sm = s0[m];
-  s_out[m] = (R)(c * (double)sm);
-  const R tau = (R)(floor_rel * key_value(*key));
-  const R sp = s0[(long long)pi * n + pj];
-  T out{(R)0, (R)0};
-  if (c > 0.0 && sp > tau && sm > tau) {
-    const double2 ph = cmul(cmul(chirp_entry<double2>(post1, pi, n), chirp_entry<double2>(post1, pj, n)),
-                            cmul(chirp_entry<double2>(post2, mi, n), chirp_entry<double2>(post2, mj, n)));
-    const T f{(R)ph.x, (R)ph.y};
-    const R d = sqrt(sp) * sqrt(sm);
-    const T v = cmul(f, b0[m]);
-    out = T{v.x / d, v.y / d};
-  }
-  mu_out[m] = out;
+  if (m < (long long)n * n) emit_observables(s0, b0, *key, n, pi, pj, m, c, post1, post2, floor_rel, s_out, mu_out);
 }
 
 template <class T, int N, int SIGN>

@@ -87,6 +87,13 @@ template <class T> size_t pair_work_bytes(int n);
 template <class T>
 hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, int pi, int pj, void* work,
                             ObsSums<T>* out, hipStream_t st);
+// S and mu(P, .) of `count` (<= kPairGroup) pairs in one launch from the sums of launch_pair_sums (pair
+// k reads sums + k N^2, or the first pair's sums for all when shared): c[k] = s weight, a_out[k] the
+// output chirp rate; pair k writes s_out + k N^2 and mu_out + k N^2.
+template <class T>
+hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int count, const double* c,
+                            const double* a_out, int pi, int pj, double floor_rel, typename real_of<T>::type* s_out,
+                            T* mu_out, hipStream_t st);
 template <class T> bool coop_supported(int n);
 template <class T>
 hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
   __shared__ T Bs[TK][TN + 1];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const int dj0 = blockIdx.x * TN, di = blockIdx.y;
+  const int dj0 = blockIdx.x * TN, di = blockIdx.y, nm = n - 1;  // N is a power of two
   const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
   const T zero{(R)0, (R)0};
   T dacc[4][4];
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
         const int e = tid + 256 * q;
         const int kk = e / TN, jj = e % TN;
         const int a = a0 + kk, dj = dj0 + jj;
-        const int a2 = (a - di + n) % n, b2 = ((b - dj) % n + n) % n;
+        const int a2 = (a - di) & nm, b2 = (b - dj) & nm;
         rb[q] = load_or_first(w, a < n && dj < n, ((long long)a * n + b) * nn + (long long)a2 * n + b2);
       }
 #pragma unroll
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
         const int a = a0 + kk;
         const bool ok = a < n;
         const int ac = ok ? a : 0;
-        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + (ac - di + n) % n]));
+        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ((ac - di) & nm)]));
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -201,8 +201,7 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int dj = dj0 + tx + 16 * c;
-        const int b2 = ((b - dj) % n + n) % n;
-        const T f = cmul(ub, u2[k * n + b2]);
+        const T f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
         const T t = cmul(f, g[r][c]);
         dacc[r][c].x += t.x;
         dacc[r][c].y += t.y;
@@ -269,6 +268,29 @@ __global__ __launch_bounds__(256) void k_pair_dft(const T* __restrict__ in, int 
     }
     out[k * nn + (long long)m * n + i] = acc;
   }
+}
+
+// S and mu(P, .) of up to kPairTile pairs in one launch (emit_observables), from the raw sums of pair
+// k (shared: the same sums for every pair, in the far field).
+struct PairEmit {
+  int count;
+  double c[kPairTile];      // s * weight of each pair
+  double a_out[kPairTile];  // output chirp rate of each pair
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_emit(const typename real_of<T>::type* __restrict__ s0,
+                                                   const T* __restrict__ b0, const unsigned long long* key, int shared,
+                                                   int n, int pi, int pj, PairEmit pe, double floor_rel,
+                                                   typename real_of<T>::type* __restrict__ s_out, T* __restrict__ mu_out) {
+  const long long nn = (long long)n * n;
+  const int k = blockIdx.y;
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nn || k >= pe.count) return;
+  const long long so = shared ? 0 : k * nn;
+  const Chirp post1{pe.a_out[k], 1.0, -1, 1}, post2{pe.a_out[k], 1.0, +1, 1};
+  emit_observables(s0 + so, b0 + so, key[shared ? 0 : k], n, pi, pj, m, pe.c[k], post1, post2, floor_rel,
+                   s_out + k * nn, mu_out + k * nn);
 }
 
 // s0[k][m] = Re z[k][m] and key[k] = order key of max_m s0[k][m] (one workgroup per pair; fixed order).
@@ -367,11 +389,33 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   return hipSuccess;
 }
 
+template <class T>
+hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int count, const double* c,
+                            const double* a_out, int pi, int pj, double floor_rel, typename real_of<T>::type* s_out,
+                            T* mu_out, hipStream_t st) {
+  if (count < 1 || count > kPairTile) return hipErrorInvalidValue;
+  PairEmit pe{};
+  pe.count = count;
+  for (int k = 0; k < count; ++k) {
+    pe.c[k] = c[k];
+    pe.a_out[k] = a_out[k];
+  }
+  const long long nn = (long long)n * n;
+  hipLaunchKernelGGL(k_pair_emit<T>, dim3((unsigned)((nn + 255) / 256), (unsigned)count), dim3(256), 0, st,
+                     (const typename real_of<T>::type*)sums.s0, (const T*)sums.b0,
+                     (const unsigned long long*)sums.key, shared ? 1 : 0, n, pi, pj, pe, floor_rel, s_out, mu_out);
+  return hipGetLastError();
+}
+
 template size_t pair_work_bytes<float2>(int);
 template size_t pair_work_bytes<double2>(int);
 template hipError_t launch_pair_sums<float2>(int, const float2*, const double*, int, int, int, void*, ObsSums<float2>*,
                                              hipStream_t);
 template hipError_t launch_pair_sums<double2>(int, const double2*, const double*, int, int, int, void*,
                                               ObsSums<double2>*, hipStream_t);
+template hipError_t launch_pair_emit<float2>(int, const ObsSums<float2>&, bool, int, const double*, const double*, int,
+                                             int, double, float*, float2*, hipStream_t);
+template hipError_t launch_pair_emit<double2>(int, const ObsSums<double2>&, bool, int, const double*, const double*,
+                                              int, int, double, double*, double2*, hipStream_t);
 
 }  // namespace wolf
