@@ -218,6 +218,205 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// complex64: the two contractions on the matrix cores (v_mfma_f32_16x16x4f32, 2x the FP32 vector
+// rate without packed math). A workgroup's 64 x 64 complex tile is four 32 x 32 wavefront blocks of
+// 2 x 2 MFMA tiles; a complex product is four real ones (re re - im im, re im + im re). Operands are
+// staged in LDS as separate re / im planes [16][kLdm]: lane l of a 16 x 16 x 4 step reads
+// A[k 4 + l / 16][row l % 16] and B[k 4 + l / 16][col l % 16], and holds D[4 (l / 16) + i][l % 16];
+// with the row stride of 80 floats the four k rows of a step fall on distinct banks.
+// ---------------------------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kLdm = 80;
+
+struct CTile {
+  v4f re[2][2], im[2][2];
+};
+
+__device__ __forceinline__ void ctile_zero(CTile& c) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      c.re[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+      c.im[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+// c += A B over the 16 staged values of the contraction index, for the wavefront block at (row0, col0).
+__device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], const float (*ai)[kLdm],
+                                             const float (*br)[kLdm], const float (*bi)[kLdm], int row0, int col0,
+                                             int lane) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int kk = ks * 4 + lane / 16, l16 = lane % 16;
+    float xr[2], xi[2], xn[2], yr[2], yi[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      xr[r] = ar[kk][row0 + 16 * r + l16];
+      xi[r] = ai[kk][row0 + 16 * r + l16];
+      xn[r] = -xi[r];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      yr[q] = br[kk][col0 + 16 * q + l16];
+      yi[q] = bi[kk][col0 + 16 * q + l16];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        c.re[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yr[q], c.re[r][q], 0, 0, 0);
+        c.re[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xn[r], yi[q], c.re[r][q], 0, 0, 0);
+        c.im[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yi[q], c.im[r][q], 0, 0, 0);
+        c.im[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[r], yr[q], c.im[r][q], 0, 0, 0);
+      }
+  }
+}
+
+// k_pair_rows on the matrix cores (same partial sums and layout).
+__global__ __launch_bounds__(256) void k_pair_rows_mfma(const float2* __restrict__ w, int n,
+                                                        const float2* __restrict__ ci, const float2* __restrict__ cj,
+                                                        long long chunk, float2* __restrict__ part) {
+  constexpr int TK = 16;
+  __shared__ float ar[TK][kLdm], ai[TK][kLdm], br[TK][kLdm], bi[TK][kLdm];
+  const long long nn = (long long)n * n;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
+  const long long j0 = (long long)blockIdx.x * 64;
+  const long long s = blockIdx.y;
+  const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
+  CTile acc;
+  ctile_zero(acc);
+  for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
+    float2 rb[4], ra[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // element e: contraction row kk = e / 64, column or pair e % 64
+      const int e = tid + 256 * q;
+      const int kk = e / 64, jj = e % 64;
+      const long long p1 = k0 + kk, p2 = j0 + jj;
+      rb[q] = load_or_first(w, p1 < p_end && p2 < nn, p1 * nn + p2);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / 64, k = e % 64;
+      const long long p1 = k0 + kk;
+      const bool ok = p1 < p_end;
+      const int a = ok ? (int)(p1 / n) : 0, b = ok ? (int)(p1 % n) : 0;
+      ra[q] = keep_or_zero(ok, cmul(ci[k * n + a], cj[k * n + b]));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / 64, jj = e % 64;
+      const float2 v = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
+      ar[kk][jj] = ra[q].x;
+      ai[kk][jj] = ra[q].y;
+      br[kk][jj] = v.x;
+      bi[kk][jj] = v.y;
+    }
+    __syncthreads();
+    ctile_mfma16(acc, ar, ai, br, bi, row0, col0, lane);
+    __syncthreads();
+  }
+  float2* out = part + s * kPairTile * nn;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const long long j = j0 + col0 + 16 * q + lane % 16;
+        if (j < nn) out[k * nn + j] = float2{acc.re[r][q][i], acc.im[r][q][i]};
+      }
+}
+
+// k_pair_diffs on the matrix cores (same partial sums and layout).
+__global__ __launch_bounds__(256) void k_pair_diffs_mfma(const float2* __restrict__ w, int n,
+                                                         const float2* __restrict__ u1, const float2* __restrict__ u2,
+                                                         int bchunk, float2* __restrict__ part) {
+  constexpr int TK = 16;
+  __shared__ float ar[TK][kLdm], ai[TK][kLdm], br[TK][kLdm], bi[TK][kLdm];
+  const long long nn = (long long)n * n;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
+  const int dj0 = blockIdx.x * 64, di = blockIdx.y, nm = n - 1;  // N is a power of two
+  const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
+  float dre[2][2][4], dim[2][2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
+  for (int b = b_begin; b < b_end; ++b) {
+    CTile g;
+    ctile_zero(g);
+    for (int a0 = 0; a0 < n; a0 += TK) {
+      float2 rb[4], ra[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // W[a, b; a - di, b - dj], a = a0 + kk, dj = dj0 + jj
+        const int e = tid + 256 * q;
+        const int kk = e / 64, jj = e % 64;
+        const int a = a0 + kk, dj = dj0 + jj;
+        rb[q] = load_or_first(w, a < n && dj < n,
+                              ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // A[kk][k] = u1[k][a] u2[k][a - di]
+        const int e = tid + 256 * q;
+        const int kk = e / 64, k = e % 64;
+        const int a = a0 + kk;
+        const bool ok = a < n;
+        const int ac = ok ? a : 0;
+        ra[q] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ((ac - di) & nm)]));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        const int kk = e / 64, jj = e % 64;
+        const float2 v = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
+        ar[kk][jj] = ra[q].x;
+        ai[kk][jj] = ra[q].y;
+        br[kk][jj] = v.x;
+        bi[kk][jj] = v.y;
+      }
+      __syncthreads();
+      ctile_mfma16(g, ar, ai, br, bi, row0, col0, lane);
+      __syncthreads();
+    }
+    // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj], on the outputs this lane holds
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const float2 ub = u1[k * n + b];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int dj = dj0 + col0 + 16 * q + lane % 16;
+          const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
+          const float gr = g.re[r][q][i], gi = g.im[r][q][i];
+          dre[r][q][i] += f.x * gr - f.y * gi;
+          dim[r][q][i] += f.x * gi + f.y * gr;
+        }
+      }
+  }
+  float2* out = part + (long long)blockIdx.z * kPairTile * nn;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const int dj = dj0 + col0 + 16 * q + lane % 16;
+        if (dj < n) out[k * nn + (long long)di * n + dj] = float2{dre[r][q][i], dim[r][q][i]};
+      }
+}
+
 // out[k][i] = f(k, i) sum_s part[s][k][i], summed in FP64 in the order of s; f = u2[k][i / n] u2[k][i % n]
 // when u2 is given (the row sums), else 1.
 template <class T>
@@ -363,12 +562,17 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
-  hipLaunchKernelGGL(k_pair_rows<T>, dim3((unsigned)((nn + 63) / 64), kPairSplitK), dim3(256), 0, st, w, n,
-                     (const T*)ci, (const T*)cj, chunk, part_r);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int bchunk = (n + sb - 1) / sb;
-  hipLaunchKernelGGL(k_pair_diffs<T>, dim3((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb), dim3(256), 0, st, w,
-                     n, (const T*)u1, (const T*)u2, bchunk, part_d);
+  const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK), grid_d((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb);
+  if constexpr (sizeof(T) == 8) {  // complex64: matrix cores
+    hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+  } else {
+    hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned sum_blocks = (unsigned)((g + 255) / 256);
   hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n,
