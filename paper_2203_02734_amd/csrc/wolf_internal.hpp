@@ -104,7 +104,7 @@ template <class T> bool half_slab_supported(int n);  // plan fused_slab = 3
 // out[p1; p2] = P(p1) P(p2) in[p1; p2] (in == out allowed).
 template <class T>
 hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipStream_t st);
-int axis_tile_cols(int n);
+int axis_tile_cols(int n, int elem_bytes);  // columns of an axis-pass tile
 int row_pass_rows(int n);  // rows per workgroup of the row pass
 
 // The operator for any even N and transform length N_z >= N (zero padding and crop), as four dense
