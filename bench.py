@@ -217,8 +217,12 @@ def kernels_sha() -> str:
 
 
 def extras(wolf, wl, args):
-    """complex128 speedup, far field, adjoint ratio and a copy-kernel ceiling (same N=128 source)."""
+    """complex128 speedup, far field, adjoint ratio and a copy-kernel ceiling (same N=128 source); the
+    relative L2 error of the complex64 result against the complex128 one, here and on the N = 64 top-hat
+    source with a thin lens (f = 0.2 m, Fresnel z = 0.2 m)."""
     import torch
+
+    import wolf_inputs as WI
 
     n, p, lam, z = wl.n, wl.pitch_m, wl.wavelength_m, wl.z_m
     elems = n ** 4
@@ -241,6 +245,7 @@ def extras(wolf, wl, args):
     w = wolf.build_source(wl.source, n, p, torch.complex64)
     o = torch.empty_like(w)
     t64 = time_op(lambda: wolf.propagate_fresnel(w, p, lam, z, out=o))
+    kept64 = o.clone()  # the complex64 Fresnel result, compared with complex128 below
     tff = time_op(lambda: wolf.propagate_farfield(w, p, lam, z, out=o))
     tadj = time_op(lambda: wolf.propagate_adjoint(w, p, lam, z, out=o))
     out["extras_mode"] = "out of place (w_in != w_out)"
@@ -267,8 +272,18 @@ def extras(wolf, wl, args):
     out["c128_propagate_elems_per_s"] = elems / (t128 * 1e-3)
     out["c128_achieved_GBps"] = round(64.0 * elems / (t128 * 1e-3) / 1e9, 1)
     out["c64_speedup_over_c128"] = round(t128 / t64, 3)
-    del w, o
+    out["c64_rel_l2_vs_c128"] = float(torch.linalg.vector_norm(kept64.to(torch.complex128) - o) /
+                                      torch.linalg.vector_norm(o))
+    del w, o, kept64
     torch.cuda.empty_cache()
+    t = WI.tophat_lens64()
+    r = {}
+    for dt in (torch.complex64, torch.complex128):
+        r[dt] = wolf.propagate_fresnel(wolf.build_source(t.source, t.n, t.pitch_m, dt), t.pitch_m, t.wavelength_m,
+                                       t.z_m)[0]
+    out["tophat_lens64_c64_rel_l2_vs_c128"] = float(
+        torch.linalg.vector_norm(r[torch.complex64].to(torch.complex128) - r[torch.complex128]) /
+        torch.linalg.vector_norm(r[torch.complex128]))
     return out
 
 
