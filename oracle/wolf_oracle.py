@@ -114,7 +114,7 @@ def coupling_constant(lam: float, z: float, kind: int = KIND_SECONDARY) -> float
 
 
 def kernel_1d(n: int, pitch: float, lam: float, z: float, farfield: bool, axis: str,
-              n_fft: Optional[int] = None) -> np.ndarray:
+              n_fft: Optional[int] = None, out_pitch: Optional[float] = None) -> np.ndarray:
     """One axis factor K[m, i] of the propagation kernel h(x, xi), on the output and source grids.
 
     Fresnel (eqs. h_free, approx_L, W_fresnel): h(x, xi) = exp(i pi |x - xi|^2 / (lambda R)).
@@ -122,8 +122,10 @@ def kernel_1d(n: int, pitch: float, lam: float, z: float, farfield: bool, axis: 
     Both factorise into an x factor times a y factor. The constant amplitude Lambda / R is in C.
     n_fft: the output pitch of zero padding to n_fft points (see output_pitch); the N output samples
     are the central ones of the padded grid, at the same centred coordinates.
+    out_pitch: any other output pitch (the same centred coordinates, out_pitch (i - N/2)); eq. (W_general)
+    holds at any observation point, the grid of eq. (spatial_resolution) is only the FFT's.
     """
-    dx = output_pitch(n, pitch, lam, z, n_fft)
+    dx = out_pitch if out_pitch is not None else output_pitch(n, pitch, lam, z, n_fft)
     if axis == "x":
         xo, xs = grid_x(n, dx), grid_x(n, pitch)
     else:
@@ -232,22 +234,24 @@ def _sum_axis(w: np.ndarray, k: np.ndarray, axis: int) -> np.ndarray:
 
 
 def propagate(w: np.ndarray, n: int, pitch: float, lam: float, z: float, farfield: bool = False,
-              kind: int = KIND_SECONDARY, n_fft: Optional[int] = None) -> Tuple[np.ndarray, float]:
+              kind: int = KIND_SECONDARY, n_fft: Optional[int] = None,
+              out_pitch: Optional[float] = None) -> Tuple[np.ndarray, float]:
     """W_B(x1, x2) = C d^4 sum_{xi1, xi2} h*(x1, xi1) W_A(xi1, xi2) h(x2, xi2) (eq. W_general, R1, R2).
 
     The four source coordinates (xi1, eta1, xi2, eta2) are summed one at a time, each against
     its own axis factor of h. h factorises into an x factor and a y factor (see kernel_1d).
     Any even n is allowed; n_fft (>= n) selects the output grid of zero padding (output_pitch).
-    Returns (W_B, dx), where dx is the output pitch of eq. (spatial_resolution).
+    out_pitch: evaluate on the grid of that pitch instead (see kernel_1d).
+    Returns (W_B, dx), where dx is the output pitch of eq. (spatial_resolution), or out_pitch.
     """
-    kx = kernel_1d(n, pitch, lam, z, farfield, "x", n_fft)
-    ky = kernel_1d(n, pitch, lam, z, farfield, "y", n_fft)
+    kx = kernel_1d(n, pitch, lam, z, farfield, "x", n_fft, out_pitch)
+    ky = kernel_1d(n, pitch, lam, z, farfield, "y", n_fft, out_pitch)
     s = coupling_constant(lam, z, kind) * pitch ** 4
     out = _sum_axis(w, kx, 2)              # sum over xi2 with h(x2, xi2)
     out = _sum_axis(out, ky, 3)            # sum over eta2
     out = _sum_axis(out, np.conj(kx), 0)   # sum over xi1 with h*(x1, xi1)
     out = _sum_axis(out, np.conj(ky), 1)   # sum over eta1
-    return s * out, output_pitch(n, pitch, lam, z, n_fft)
+    return s * out, (out_pitch if out_pitch is not None else output_pitch(n, pitch, lam, z, n_fft))
 
 
 def propagate_matrix(w: np.ndarray, n: int, pitch: float, lam: float, z: float,
@@ -450,6 +454,20 @@ def degree_of_coherence(w: np.ndarray, ip: int, jp: int, floor_rel: float = 1e-1
             if s[i, j] > tau:
                 mu[i, j] = w[ip, jp, i, j] / math.sqrt(s0 * s[i, j])
     return mu
+
+
+def polychromatic(w: np.ndarray, n: int, pitch: float, lams, zs, weights, out_pitch: float,
+                  farfield: bool = False, kind: int = KIND_SECONDARY, ip: int = 0, jp: int = 0,
+                  floor_rel: float = 1e-12) -> Tuple[np.ndarray, np.ndarray]:
+    """Polychromatic light from one source, read as R17: the CSD at each frequency propagates on its
+    own (eq. W_general at wavelength lams[k] and distance zs[k]); on a common output grid of pitch
+    out_pitch the weighted CSDs add, W(x1, x2) = sum_k weights[k] W_k(x1, x2), and S and mu follow from
+    the sum (Algorithms 4-5). Returns (S, mu(P1, .))."""
+    total = None
+    for lam, z, wk in zip(lams, zs, weights):
+        wb, _ = propagate(w, n, pitch, lam, z, farfield, kind, out_pitch=out_pitch)
+        total = wk * wb if total is None else total + wk * wb
+    return spectral_density(total), degree_of_coherence(total, ip, jp, floor_rel)
 
 
 def degree_of_coherence_full(w: np.ndarray, floor_rel: float = 1e-12) -> np.ndarray:

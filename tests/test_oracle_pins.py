@@ -554,3 +554,44 @@ def test_degree_of_coherence_floor():
     assert np.array_equal(np.abs(mu) > 0, y > 0)
     assert np.allclose(mu[y > 0], 1.0)
     assert not O.degree_of_coherence(w, 0, 0).any()       # P1 outside the source: mu = 0
+
+
+# ---------------------------------------------------------------------------------------------
+# Any output grid, and the polychromatic sum on a common grid (R17). The closed form holds at any
+# observation point. Catches: the output pitch entering the chirp or the DFT frequency wrongly.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_gsm_closed_form_any_output_grid(farfield):
+    n, p, ss, sg, z = 64, 20e-6, 0.08e-3, 0.12e-3, 0.3     # the window holds the source to e^-16
+    w = O.build_source(spec(sigma_s_m=ss, sigma_g_m=sg), n, p)
+    dx = 0.73 * O.output_pitch(n, p, LAM, z)          # not the FFT grid
+    wb, d = O.propagate(w, n, p, LAM, z, farfield, out_pitch=dx)
+    assert d == dx
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    cx = CF.gsm_axis_closed_form(X[:, None], X[None, :], ss, sg, LAM, z, farfield)
+    cy = CF.gsm_axis_closed_form(Y[:, None], Y[None, :], ss, sg, LAM, z, farfield)
+    assert rel(wb, cx[:, None, :, None] * cy[None, :, None, :]) < 1e-9
+
+
+def test_polychromatic_sum_of_closed_forms():
+    """Three wavelengths at one distance on a common grid: S and the mu row of the weighted sum of the
+    closed-form CSDs. The source fits the window to e^-16 and the grid is the FFT grid of the shortest
+    wavelength, so that no kernel is sampled beyond its Nyquist rate."""
+    n, p, ss, sg, z = 32, 20e-6, 0.04e-3, 0.06e-3, 0.2
+    lams, zs, ws = [500e-9, 600e-9, 700e-9], [z, z, z], [0.5, 1.0, 0.8]
+    dx = O.output_pitch(n, p, 500e-9, z)
+    w = O.build_source(spec(sigma_s_m=ss, sigma_g_m=sg), n, p)
+    ip, jp = 14, 17
+    s, mu = O.polychromatic(w, n, p, lams, zs, ws, dx, ip=ip, jp=jp, floor_rel=1e-6)
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    tot = 0
+    for lam, wk in zip(lams, ws):
+        cx = CF.gsm_axis_closed_form(X[:, None], X[None, :], ss, sg, lam, z, False)
+        cy = CF.gsm_axis_closed_form(Y[:, None], Y[None, :], ss, sg, lam, z, False)
+        tot = tot + wk * cx[:, None, :, None] * cy[None, :, None, :]
+    sr = np.real(np.einsum("ijij->ij", tot))
+    assert rel(s, sr) < 1e-9
+    row = tot[ip, jp]
+    mur = row / np.sqrt(sr[ip, jp] * sr)
+    mur[sr <= 1e-6 * sr.max()] = 0
+    assert rel(mu, mur) < 1e-8
