@@ -259,6 +259,31 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
                                           double s_floor_rel, void* work, void* s_out, void* mu_out, void* stream);
 
 /*
+ * wolf_propagate_polychromatic -- polychromatic light from one source on a common output grid
+ * (the paper's Sec. 6 names polychromatic light as future work). The CSD at each frequency
+ * propagates on its own (eq. W_general at wavelength_m[k] and distance z_m[k], Fresnel or far
+ * field); on the output grid x = out_pitch_m (i - N/2), y = out_pitch_m (N/2 - j), which need not be
+ * any pair's FFT grid, the weighted CSDs add: W = sum_k weight[k] W_k. s_out receives S of the sum
+ * (Algorithm 4) and mu_out mu(P1, .) of the sum (Algorithm 5, floor s_floor_rel * max S).
+ * The sums over the first point are shared by groups of 64 pairs as in wolf_propagate_batch, and
+ * the DFTs of the FFT grid become chirp-z transforms at frequency out_pitch pitch / (lambda z);
+ * the difference-coordinate sums then keep both signs of the offset.
+ *   w_src          device N^4, read only.
+ *   wavelength_m, z_m, weight   host arrays of n_pairs (> 0, > 0, >= 0); out_pitch_m > 0.
+ *   work           device scratch of wolf_polychromatic_work_bytes(n, dtype) bytes (overwritten).
+ *   s_out          device N*N real; mu_out: device N*N complex.
+ */
+WOLF_API wolf_status wolf_propagate_polychromatic(const void* w_src, int32_t n, double pitch_m, int32_t n_pairs,
+                                                  const double* wavelength_m, const double* z_m, const double* weight,
+                                                  double out_pitch_m, int32_t farfield, int32_t kind, int32_t dtype,
+                                                  int32_t ip, int32_t jp, double s_floor_rel, void* work, void* s_out,
+                                                  void* mu_out, void* stream);
+
+/* Bytes of the work buffer of wolf_propagate_polychromatic (about 250 MB at N = 128 complex64); -1
+ * if (n, dtype) is not supported. */
+WOLF_API int64_t wolf_polychromatic_work_bytes(int32_t n, int32_t dtype);
+
+/*
  * wolf_batch_work_bytes -- bytes of the `work` buffer that wolf_propagate_batch needs for (n, dtype):
  * the partial sums of one group of 64 pairs (16 + up to 32 N^2 x 64 complex chunks), three N^2 x 64
  * buffers and the tables (about 190 MB at N = 128 complex64); never an N^4 array. -1 if (n, dtype)

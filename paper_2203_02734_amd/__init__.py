@@ -32,7 +32,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
             "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
             "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes",
-            "wolf_propagate_padded"]
+            "wolf_propagate_padded", "wolf_propagate_polychromatic", "wolf_polychromatic_work_bytes"]
 
 
 class WolfError(RuntimeError):
@@ -73,6 +73,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_spectral_density": [vp, i32, i32, vp, vp],
         "wolf_degree_of_coherence": [vp, i32, i32, i32, i32, f64, vp, vp],
         "wolf_propagate_batch": [vp, i32, f64, i32, pd, pd, pd, i32, i32, i32, i32, i32, f64, vp, vp, vp, vp],
+        "wolf_propagate_polychromatic": [vp, i32, f64, i32, pd, pd, pd, f64, i32, i32, i32, i32, i32, f64, vp, vp, vp,
+                                         vp],
         "wolf_chirp_table": [i32, f64, f64, f64, i32, vp, vp],
         "wolf_set_plan": [i32, i32, i32, ctypes.c_int64, ctypes.c_int64, i32, i32],
         "wolf_get_plan": [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64),
@@ -99,6 +101,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wolf_batch_work_bytes.restype = ctypes.c_int64
     lib.wolf_direct_work_bytes.argtypes = [i32, i32]
     lib.wolf_direct_work_bytes.restype = ctypes.c_int64
+    lib.wolf_polychromatic_work_bytes.argtypes = [i32, i32]
+    lib.wolf_polychromatic_work_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -376,6 +380,38 @@ def propagate_batch(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights,
                                     ww.ctypes.data_as(pd), int(bool(farfield)), kind, _code(w_src.dtype), ip, jp,
                                     floor_rel, _ptr(work), _ptr(s), _ptr(mu), _stream()), "wolf_propagate_batch")
     return s, mu
+
+
+def propagate_polychromatic(w_src: torch.Tensor, pitch: float, wavelengths, zs, weights, out_pitch: float,
+                            farfield: bool = False, kind: int = SECONDARY, ip: int = 0, jp: int = 0,
+                            floor_rel: float = 1e-12, work: Optional[torch.Tensor] = None):
+    """Polychromatic light on a common output grid of pitch out_pitch: S and mu(P1, .) of
+    sum_k weights[k] W_k, W_k the source propagated at (wavelengths[k], zs[k]). Returns (S, mu), N x N each."""
+    lib = load()
+    n = _csd(w_src, "w_src")
+    lam = np.ascontiguousarray(wavelengths, dtype=np.float64)
+    zz = np.ascontiguousarray(zs, dtype=np.float64)
+    ww = np.ascontiguousarray(weights, dtype=np.float64)
+    if not (lam.shape == zz.shape == ww.shape and lam.ndim == 1):
+        raise ValueError("wavelengths, zs and weights must be 1D arrays of the same length")
+    if work is None:
+        work = torch.empty(polychromatic_work_bytes(n, w_src.dtype), dtype=torch.uint8, device=w_src.device)
+    s = torch.empty((n, n), dtype=_real(w_src.dtype), device=w_src.device)
+    mu = torch.empty((n, n), dtype=w_src.dtype, device=w_src.device)
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(lib.wolf_propagate_polychromatic(_ptr(w_src), n, pitch, lam.shape[0], lam.ctypes.data_as(pd),
+                                            zz.ctypes.data_as(pd), ww.ctypes.data_as(pd), float(out_pitch),
+                                            int(bool(farfield)), kind, _code(w_src.dtype), ip, jp, floor_rel,
+                                            _ptr(work), _ptr(s), _ptr(mu), _stream()), "wolf_propagate_polychromatic")
+    return s, mu
+
+
+def polychromatic_work_bytes(n: int, dtype: torch.dtype) -> int:
+    """Bytes of the `work` buffer that propagate_polychromatic needs for (n, dtype)."""
+    b = int(load().wolf_polychromatic_work_bytes(n, _code(dtype)))
+    if b < 0:
+        raise WolfError(EUNSUPPORTED, "wolf_polychromatic_work_bytes", f"N={n} unsupported")
+    return b
 
 
 def batch_work_bytes(n: int, dtype: torch.dtype) -> int:

@@ -726,6 +726,62 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   return launched(hipGraphLaunch(hit->exec, st), who);
 }
 
+WOLF_API wolf_status wolf_propagate_polychromatic(const void* w_src, int32_t n, double pitch_m, int32_t n_pairs,
+                                                  const double* wavelength_m, const double* z_m, const double* weight,
+                                                  double out_pitch_m, int32_t farfield, int32_t kind, int32_t dtype,
+                                                  int32_t ip, int32_t jp, double s_floor_rel, void* work, void* s_out,
+                                                  void* mu_out, void* stream) {
+  const char* who = "wolf_propagate_polychromatic";
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d unsupported", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  if (!pos_finite(pitch_m) || !pos_finite(out_pitch_m)) return fail(WOLF_EINVAL, "%s: pitches must be finite and > 0", who);
+  if (n_pairs < 1 || n_pairs > 4096) return fail(WOLF_EINVAL, "%s: n_pairs must be in [1, 4096]", who);
+  if (!wavelength_m || !z_m || !weight) return fail(WOLF_EINVAL, "%s: null parameter array", who);
+  for (int k = 0; k < n_pairs; ++k) {
+    if (!pos_finite(wavelength_m[k]) || !pos_finite(z_m[k]) || !std::isfinite(weight[k]) || weight[k] < 0)
+      return fail(WOLF_EINVAL, "%s: pair %d needs lambda > 0, z > 0, weight >= 0", who, k);
+  }
+  if (farfield != 0 && farfield != 1) return fail(WOLF_EINVAL, "%s: farfield must be 0 or 1", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind", who);
+  if (ip < 0 || ip >= n || jp < 0 || jp >= n) return fail(WOLF_EINVAL, "%s: (ip, jp) out of range", who);
+  if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "%s: s_floor_rel must be >= 0", who);
+  const size_t eb = elem_bytes(dtype), big = n4(n) * eb, nn = (size_t)n * n;
+  const size_t wb = dtype == WOLF_C64 ? wolf::poly_work_bytes<float2>(n) : wolf::poly_work_bytes<double2>(n);
+  const size_t s_bytes = nn * real_bytes(dtype), mu_bytes = nn * eb;
+  wolf_status s;
+  if ((s = check_buf(w_src, big, "w_src")) != WOLF_OK) return s;
+  if ((s = check_buf(work, wb, "work")) != WOLF_OK) return s;
+  if ((s = check_buf(s_out, s_bytes, "s_out")) != WOLF_OK) return s;
+  if ((s = check_buf(mu_out, mu_bytes, "mu_out")) != WOLF_OK) return s;
+  if (intervals_overlap(w_src, big, work, wb) || intervals_overlap(s_out, s_bytes, mu_out, mu_bytes) ||
+      intervals_overlap(s_out, s_bytes, w_src, big) || intervals_overlap(s_out, s_bytes, work, wb) ||
+      intervals_overlap(mu_out, mu_bytes, w_src, big) || intervals_overlap(mu_out, mu_bytes, work, wb))
+    return fail(WOLF_EINVAL, "%s: buffers overlap", who);
+  std::vector<double> alpha(n_pairs), beta(n_pairs), gamma(n_pairs), coef(n_pairs);
+  for (int k = 0; k < n_pairs; ++k) {
+    const double lz = wavelength_m[k] * z_m[k];
+    alpha[k] = farfield ? 0.0 : pitch_m * pitch_m / lz;
+    beta[k] = out_pitch_m * pitch_m / lz;
+    gamma[k] = out_pitch_m * out_pitch_m / lz;
+    const double c = kind == WOLF_PRIMARY ? 1.0 / ((4.0 * M_PI * z_m[k]) * (4.0 * M_PI * z_m[k])) : 1.0 / (lz * lz);
+    coef[k] = weight[k] * c * pitch_m * pitch_m * pitch_m * pitch_m;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == WOLF_C64)
+    e = wolf::launch_poly<float2>(n, (const float2*)w_src, n_pairs, alpha.data(), beta.data(), gamma.data(),
+                                  coef.data(), ip, jp, s_floor_rel, work, (float*)s_out, (float2*)mu_out, st);
+  else
+    e = wolf::launch_poly<double2>(n, (const double2*)w_src, n_pairs, alpha.data(), beta.data(), gamma.data(),
+                                   coef.data(), ip, jp, s_floor_rel, work, (double*)s_out, (double2*)mu_out, st);
+  return launched(e, who);
+}
+
+WOLF_API int64_t wolf_polychromatic_work_bytes(int32_t n, int32_t dtype) {
+  if (!supported_n(n) || (dtype != WOLF_C64 && dtype != WOLF_C128)) return -1;
+  return (int64_t)(dtype == WOLF_C64 ? wolf::poly_work_bytes<float2>(n) : wolf::poly_work_bytes<double2>(n));
+}
+
 WOLF_API int64_t wolf_batch_work_bytes(int32_t n, int32_t dtype) {
   if (!supported_n(n) || (dtype != WOLF_C64 && dtype != WOLF_C128)) return -1;
   return (int64_t)batch_work_bytes(n, dtype);

@@ -94,6 +94,14 @@ template <class T>
 hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int count, const double* c,
                             const double* a_out, int pi, int pj, double floor_rel, typename real_of<T>::type* s_out,
                             T* mu_out, hipStream_t st);
+// Polychromatic S and mu(P, .) on a common output grid (wolf_pairs.hip): alpha[k], beta[k], gamma[k] are the
+// source chirp rate, the DFT frequency and the output chirp rate of pair k on that grid, coef[k] its weight
+// times s; the pairs run in groups of kPairGroup, and the sums are written to s_out, mu_out (N^2 each).
+template <class T> size_t poly_work_bytes(int n);
+template <class T>
+hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, const double* beta, const double* gamma,
+                       const double* coef, int pi, int pj, double floor_rel, void* work,
+                       typename real_of<T>::type* s_out, T* mu_out, hipStream_t st);
 template <class T> bool coop_supported(int n);
 template <class T>
 hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,

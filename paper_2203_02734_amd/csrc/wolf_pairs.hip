@@ -516,6 +516,247 @@ __global__ __launch_bounds__(256) void k_pair_s0(const T* __restrict__ z, int n,
 }
 
 // ---------------------------------------------------------------------------------------------
+// Polychromatic sums on a common output grid of any pitch (the chirp-z form of the same sums).
+// With the plain chirp t_k[a] = e^{i pi alpha_k (a - c)^2} (alpha_k = pitch^2 / (lambda_k z_k), 0 in the far
+// field) and the DFT frequency beta_k = out_pitch pitch / (lambda_k z_k) (1/N on the FFT grid):
+//   S_k(m)     = s_k Re sum_{d in [-N, N)^2} e^{+2 pi i beta_k <m - c, d>} D_k[d],
+//   D_k[d]     = sum_{p1 : p1 - d in [0, N)^2} conj(T_k[p1]) T_k[p1 - d] W[p1; p1 - d]   (no wrap),
+//   W_k[P; m]  = s_k conj(tau_k(P)) tau_k(m) sum_{p2} e^{-2 pi i beta_k <m - c, p2 - c>} T_k[p2] R_k[p2],
+//   R_k[p2]    = sum_{p1} e^{+2 pi i beta_k <P - c, p1 - c>} conj(T_k[p1]) W[p1; p2],
+// tau_k(m) = e^{i pi gamma_k (m - c)^2}, gamma_k = out_pitch^2 / (lambda_k z_k); then S = sum_k w_k S_k and
+// W[P; .] = sum_k w_k W_k[P; .] (R17). The output grid no longer has the period N of the DFT, so the
+// difference sums keep both signs of d: bins d in [-N, N), index d + N.
+// ---------------------------------------------------------------------------------------------
+struct PolyGroup {
+  int count;
+  double alpha[kPairTile];  // source chirp rate of each pair
+  double beta[kPairTile];   // DFT frequency of each pair on the common grid
+  double gamma[kPairTile];  // output chirp rate of each pair on the common grid
+  double c[kPairTile];      // weight * s of each pair
+};
+
+// u1 = conj(t), u2 = t, ci = e^{2 pi i beta (P_i - c)(a - c)} conj(t[a]), cj likewise with P_j (FP64-built).
+template <class T>
+__global__ __launch_bounds__(256) void k_poly_tables(PolyGroup g, int n, int pi, int pj, T* u1, T* u2, T* ci, T* cj) {
+  using R = typename real_of<T>::type;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kPairTile * n) return;
+  const int k = e / n, a = e % n, c = n / 2;
+  if (k >= g.count) {
+    const T z{(R)0, (R)0};
+    u1[e] = z; u2[e] = z; ci[e] = z; cj[e] = z;
+    return;
+  }
+  const double2 t = chirp_entry<double2>(Chirp{g.alpha[k], 1.0, +1, 0}, a, n);
+  const double2 tc{t.x, -t.y};
+  double pr = g.beta[k] * (double)(pi - c) * (double)(a - c);
+  double ps = g.beta[k] * (double)(pj - c) * (double)(a - c);
+  pr -= rint(pr);
+  ps -= rint(ps);
+  double si, co, sj, cjx;
+  sincospi(2.0 * pr, &si, &co);
+  sincospi(2.0 * ps, &sj, &cjx);
+  const double2 wi = cmul(double2{co, si}, tc), wj = cmul(double2{cjx, sj}, tc);
+  u1[e] = T{(R)tc.x, (R)tc.y};
+  u2[e] = T{(R)t.x, (R)t.y};
+  ci[e] = T{(R)wi.x, (R)wi.y};
+  cj[e] = T{(R)wj.x, (R)wj.y};
+}
+
+// Difference sums without wrap: part[z][k][(di + N) 2N + dj + N] = sum_{b} B_k^{dj}[b] sum_a A_k^{di}[a]
+// W[a, b; a - di, b - dj] over a - di, b - dj in [0, N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj].
+// A workgroup owns di, 64 values of dj and a chunk of the b range that reaches its tile.
+template <class T>
+__global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int n, const T* __restrict__ u1,
+                                                    const T* __restrict__ u2, int bchunk, T* __restrict__ part) {
+  using R = typename real_of<T>::type;
+  constexpr int TM = kPairTile, TN = 64, TK = 16;
+  __shared__ T As[TK][TM + 1];
+  __shared__ T Bs[TK][TN + 1];
+  const long long nn = (long long)n * n, bins = 4 * nn;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int di = (int)blockIdx.y - n, dj0 = (int)blockIdx.x * TN - n;
+  const int a_lo = di > 0 ? di : 0, a_hi = di < 0 ? n + di : n;
+  int b_lo = dj0 > 0 ? dj0 : 0, b_hi = dj0 + TN - 1 + n;
+  if (b_hi > n) b_hi = n;
+  b_lo += (int)blockIdx.z * bchunk;
+  if (b_lo + bchunk < b_hi) b_hi = b_lo + bchunk;
+  const T zero{(R)0, (R)0};
+  T dacc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dacc[r][q] = zero;
+  for (int b = b_lo; b < b_hi; ++b) {
+    T g[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[r][q] = zero;
+    for (int a0 = a_lo; a0 < a_hi; a0 += TK) {
+      T rb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // Bs[kk][jj] = W[a, b; a - di, b - dj]
+        const int e = tid + 256 * q;
+        const int kk = e / TN, jj = e % TN;
+        const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
+        const bool ok = a < a_hi && dj < n && bq >= 0 && bq < n;
+        rb[q] = load_or_first(w, ok, ((long long)a * n + b) * nn + (long long)(a - di) * n + bq);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // As[kk][k] = u1[k][a] u2[k][a - di]
+        const int e = tid + 256 * q;
+        const int k = e / TK, kk = e % TK;
+        const int a = a0 + kk;
+        const bool ok = a < a_hi;
+        const int ac = ok ? a : a_lo;
+        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ac - di]));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        const int kk = e / TN, jj = e % TN;
+        const int dj = dj0 + jj, bq = b - dj;
+        Bs[kk][jj] = keep_or_zero(a0 + kk < a_hi && dj < n && bq >= 0 && bq < n, rb[q]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q] = Bs[kk][tx + 16 * q];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            g[r][q].x += av[r].x * bv[q].x - av[r].y * bv[q].y;
+            g[r][q].y += av[r].x * bv[q].y + av[r].y * bv[q].x;
+          }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = ty + 16 * r;
+      const T ub = u1[k * n + b];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int bq = b - (dj0 + tx + 16 * q);
+        const bool ok = bq >= 0 && bq < n;
+        const T f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
+        const T t = cmul(f, g[r][q]);
+        dacc[r][q].x += t.x;
+        dacc[r][q].y += t.y;
+      }
+    }
+  }
+  T* out = part + (long long)blockIdx.z * kPairTile * bins;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int dj = dj0 + tx + 16 * q;
+      if (dj < n) out[(long long)(ty + 16 * r) * bins + (long long)(di + n) * (2 * n) + dj + n] = dacc[r][q];
+    }
+}
+
+// One axis of a chirp-z transform of every pair's array, stored transposed:
+// out[k][m][i] = sum_{p < len} e^{SIGN 2 pi i beta_k (m - c)(p - off)} in[k][i][p], m < N, i < rows. The
+// factors come from an FP64 recurrence along p (one FP64 product per term); sums in FP64.
+template <class T, int SIGN>
+__global__ __launch_bounds__(256) void k_poly_czt(const T* __restrict__ in, int n, int rows, int len, int off,
+                                                  PolyGroup g, T* __restrict__ out) {
+  using R = typename real_of<T>::type;
+  __shared__ T row[512];
+  const int k = blockIdx.x / rows, i = blockIdx.x % rows, c = n / 2;
+  const long long inb = ((long long)k * rows + i) * len;
+  for (int p = threadIdx.x; p < len; p += blockDim.x) row[p] = in[inb + p];
+  __syncthreads();
+  const double beta = k < g.count ? g.beta[k] : 0.0;
+  for (int m = threadIdx.x; m < n; m += blockDim.x) {
+    double f0 = (double)SIGN * beta * (double)(m - c) * (double)(0 - off);
+    double fs = (double)SIGN * beta * (double)(m - c);
+    f0 -= rint(f0);
+    fs -= rint(fs);
+    double s0, c0, s1, c1;
+    sincospi(2.0 * f0, &s0, &c0);
+    sincospi(2.0 * fs, &s1, &c1);
+    double2 wv{c0, s0};
+    const double2 rot{c1, s1};
+    double2 acc{0.0, 0.0};
+    for (int p = 0; p < len; ++p) {
+      const T v = row[p];
+      acc.x += wv.x * (double)v.x - wv.y * (double)v.y;
+      acc.y += wv.x * (double)v.y + wv.y * (double)v.x;
+      wv = cmul(wv, rot);
+    }
+    out[((long long)k * n + m) * rows + i] = T{(R)acc.x, (R)acc.y};
+  }
+}
+
+// S(m) (+)= sum_k c_k Re zd_k[m]; W(m) (+)= sum_k c_k conj(tau_k(P)) tau_k(m) zr_k[m], in FP64, pairs in order.
+template <class T>
+__global__ __launch_bounds__(256) void k_poly_combine(const T* __restrict__ zd, const T* __restrict__ zr, int n,
+                                                      int pi, int pj, PolyGroup g, int first, double* s_acc,
+                                                      double2* w_acc) {
+  const long long nn = (long long)n * n;
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nn) return;
+  const int mi = (int)(m / n), mj = (int)(m % n);
+  double s = 0.0;
+  double2 wr{0.0, 0.0};
+  for (int k = 0; k < g.count; ++k) {
+    const Chirp ch{g.gamma[k], 1.0, +1, 0};
+    const double2 tp = cmul(chirp_entry<double2>(ch, pi, n), chirp_entry<double2>(ch, pj, n));
+    const double2 tm = cmul(chirp_entry<double2>(ch, mi, n), chirp_entry<double2>(ch, mj, n));
+    const double2 ph = cmul(double2{tp.x, -tp.y}, tm);
+    const T d = zd[k * nn + m], r = zr[k * nn + m];
+    s += g.c[k] * (double)d.x;
+    const double2 v = cmul(ph, double2{(double)r.x, (double)r.y});
+    wr.x += g.c[k] * v.x;
+    wr.y += g.c[k] * v.y;
+  }
+  if (first) {
+    s_acc[m] = s;
+    w_acc[m] = wr;
+  } else {
+    s_acc[m] += s;
+    w_acc[m] = double2{w_acc[m].x + wr.x, w_acc[m].y + wr.y};
+  }
+}
+
+// S and mu(P, .) from the sums: one workgroup, the maximum of S by a fixed tree.
+template <class T>
+__global__ __launch_bounds__(1024) void k_poly_mu(const double* __restrict__ s_acc, const double2* __restrict__ w_acc,
+                                                  int n, int pi, int pj, double floor_rel,
+                                                  typename real_of<T>::type* __restrict__ s_out, T* __restrict__ mu_out) {
+  using R = typename real_of<T>::type;
+  __shared__ double red[1024];
+  const long long nn = (long long)n * n;
+  double mx = -INFINITY;
+  for (long long m = threadIdx.x; m < nn; m += blockDim.x) mx = fmax(mx, s_acc[m]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double tau = floor_rel * red[0], sp = s_acc[(long long)pi * n + pj];
+  for (long long m = threadIdx.x; m < nn; m += blockDim.x) {
+    const double sm = s_acc[m];
+    s_out[m] = (R)sm;
+    T o{(R)0, (R)0};
+    if (sp > tau && sm > tau) {
+      const double d = sqrt(sp) * sqrt(sm);
+      o = T{(R)(w_acc[m].x / d), (R)(w_acc[m].y / d)};
+    }
+    mu_out[m] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Work layout (per group of kPairTile pairs), in elements of T unless noted.
 // ---------------------------------------------------------------------------------------------
 static int pair_tiles_j(int n) { return (n + 63) / 64; }
@@ -610,6 +851,100 @@ hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int coun
                      (const unsigned long long*)sums.key, shared ? 1 : 0, n, pi, pj, pe, floor_rel, s_out, mu_out);
   return hipGetLastError();
 }
+
+// Work of the polychromatic sums, per group (elements of T unless noted): tables 4 x 64 N, row-sum
+// partials 16 x 64 N^2, difference-sum partials sb x 64 x 4N^2, D 64 x 4N^2, T R 64 N^2, transform
+// intermediate 64 x 2N^2, the two transformed arrays 64 N^2 each; then S and W[P; .] in FP64 (N^2 each).
+static int poly_tiles_j(int n) { return (2 * n + 63) / 64; }
+static int poly_bsplit(int n) {
+  int sb = 1024 / (poly_tiles_j(n) * 2 * n);
+  if (sb < 1) sb = 1;
+  if (sb > n) sb = n;
+  return sb;
+}
+
+template <class T> size_t poly_work_bytes(int n) {
+  const size_t nn = (size_t)n * n, g = (size_t)kPairTile * nn;
+  const size_t elems = 4 * (size_t)kPairTile * n + (size_t)kPairSplitK * g + (size_t)poly_bsplit(n) * 4 * g + 4 * g +
+                       g + 2 * g + 2 * g;
+  return elems * sizeof(T) + nn * (sizeof(double) + sizeof(double2)) + 512;
+}
+
+template <class T>
+hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, const double* beta, const double* gamma,
+                       const double* coef, int pi, int pj, double floor_rel, void* work,
+                       typename real_of<T>::type* s_out, T* mu_out, hipStream_t st) {
+  const long long nn = (long long)n * n, g = (long long)kPairTile * nn;
+  T* base = reinterpret_cast<T*>(work);
+  T* u1 = base;
+  T* u2 = u1 + kPairTile * n;
+  T* ci = u2 + kPairTile * n;
+  T* cj = ci + kPairTile * n;
+  T* part_r = cj + kPairTile * n;
+  const int sb = poly_bsplit(n);
+  T* part_d = part_r + (long long)kPairSplitK * g;
+  T* dfull = part_d + (long long)sb * 4 * g;
+  T* rr = dfull + 4 * g;
+  T* tmp = rr + g;
+  T* zd = tmp + 2 * g;
+  T* zr = zd + g;
+  double* s_acc = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(zr + g) + 15) & ~(uintptr_t)15);
+  double2* w_acc = reinterpret_cast<double2*>(s_acc + nn);
+  hipError_t e = hipSuccess;
+  for (int k0 = 0; k0 < n_pairs; k0 += kPairTile) {
+    PolyGroup pg{};
+    pg.count = n_pairs - k0 < kPairTile ? n_pairs - k0 : kPairTile;
+    for (int k = 0; k < pg.count; ++k) {
+      pg.alpha[k] = alpha[k0 + k];
+      pg.beta[k] = beta[k0 + k];
+      pg.gamma[k] = gamma[k0 + k];
+      pg.c[k] = coef[k0 + k];
+    }
+    hipLaunchKernelGGL(k_poly_tables<T>, dim3((unsigned)((kPairTile * n + 255) / 256)), dim3(256), 0, st, pg, n, pi,
+                       pj, u1, u2, ci, cj);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
+    const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK);
+    if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+    else
+      hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int bchunk = (n + sb - 1) / sb;
+    hipLaunchKernelGGL(k_poly_diffs<T>, dim3((unsigned)poly_tiles_j(n), (unsigned)(2 * n), (unsigned)sb), dim3(256), 0,
+                       st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
+                       kPairSplitK, n, (const T*)u2, rr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d, sb,
+                       2 * n, (const T*)nullptr, dfull);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // S: the + transform of D over [-N, N)^2 (offset N); the row: the - transform of T R (offset N/2).
+    hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(kPairTile * 2 * n)), dim3(256), 0, st, (const T*)dfull, n,
+                       2 * n, 2 * n, n, pg, tmp);
+    hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(kPairTile * n)), dim3(256), 0, st, (const T*)tmp, n, n,
+                       2 * n, n, pg, zd);
+    hipLaunchKernelGGL((k_poly_czt<T, -1>), dim3((unsigned)(kPairTile * n)), dim3(256), 0, st, (const T*)rr, n, n, n,
+                       n / 2, pg, tmp);
+    hipLaunchKernelGGL((k_poly_czt<T, -1>), dim3((unsigned)(kPairTile * n)), dim3(256), 0, st, (const T*)tmp, n, n, n,
+                       n / 2, pg, zr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_poly_combine<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const T*)zd,
+                       (const T*)zr, n, pi, pj, pg, k0 == 0 ? 1 : 0, s_acc, w_acc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_poly_mu<T>, dim3(1), dim3(1024), 0, st, (const double*)s_acc, (const double2*)w_acc, n, pi, pj,
+                     floor_rel, s_out, mu_out);
+  return hipGetLastError();
+}
+
+template size_t poly_work_bytes<float2>(int);
+template size_t poly_work_bytes<double2>(int);
+template hipError_t launch_poly<float2>(int, const float2*, int, const double*, const double*, const double*,
+                                        const double*, int, int, double, void*, float*, float2*, hipStream_t);
+template hipError_t launch_poly<double2>(int, const double2*, int, const double*, const double*, const double*,
+                                         const double*, int, int, double, void*, double*, double2*, hipStream_t);
 
 template size_t pair_work_bytes<float2>(int);
 template size_t pair_work_bytes<double2>(int);
