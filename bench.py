@@ -324,6 +324,23 @@ def batch_and_fit(wolf, args):
     # Fresnel: two contractions over the first point shared by the 64 pairs, 8 real flops per complex
     # multiply-add, 64 pairs x N^4 multiply-adds each.
     out["batch64_contraction_TFLOPs"] = round(2 * 8 * k * n ** 4 / (out["batch64_ms"] * 1e-3) / 1e12, 2)
+    # Polychromatic sum on a common grid (the FFT grid of 500 nm): the 16 wavelengths at z = 0.5 m, and all
+    # 64 pairs, S and mu(P1, .) of the weighted sum.
+    pwork = torch.empty(wolf.polychromatic_work_bytes(n, torch.complex64), dtype=torch.uint8, device="cuda")
+    dxc = 500e-9 * 0.5 / (n * p)
+    for tag, sel in (("poly16", pairs["z"] == 0.5), ("poly64", pairs["z"] > 0)):
+        args3 = (pairs["wavelength"][sel], pairs["z"][sel], pairs["weight"][sel])
+        run = lambda: wolf.propagate_polychromatic(w0, p, *args3, dxc, ip=wl.probe[0], jp=wl.probe[1], work=pwork)
+        run()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        out[f"{tag}_common_grid_ms"] = round(a.elapsed_time(b) / 3, 3)
+    del pwork
     del w0, work
     torch.cuda.empty_cache()
 

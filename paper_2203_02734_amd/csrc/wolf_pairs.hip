@@ -527,6 +527,9 @@ __global__ __launch_bounds__(256) void k_pair_s0(const T* __restrict__ z, int n,
 // W[P; .] = sum_k w_k W_k[P; .] (R17). The output grid no longer has the period N of the DFT, so the
 // difference sums keep both signs of d: bins d in [-N, N), index d + N.
 // ---------------------------------------------------------------------------------------------
+// Offset d_i of grid row y, heaviest first: 0, -1, 1, -2, 2, ..., -N (a row's work is N - |d_i|).
+__device__ __forceinline__ int poly_offset(int y) { return (y & 1) ? -((y + 1) >> 1) : (y >> 1); }
+
 struct PolyGroup {
   int count;
   double alpha[kPairTile];  // source chirp rate of each pair
@@ -575,7 +578,7 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
   __shared__ T Bs[TK][TN + 1];
   const long long nn = (long long)n * n, bins = 4 * nn;
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const int di = (int)blockIdx.y - n, dj0 = (int)blockIdx.x * TN - n;
+  const int di = poly_offset((int)blockIdx.y), dj0 = (int)blockIdx.x * TN - n;
   const int a_lo = di > 0 ? di : 0, a_hi = di < 0 ? n + di : n;
   int b_lo = dj0 > 0 ? dj0 : 0, b_hi = dj0 + TN - 1 + n;
   if (b_hi > n) b_hi = n;
@@ -660,6 +663,95 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
       const int dj = dj0 + tx + 16 * q;
       if (dj < n) out[(long long)(ty + 16 * r) * bins + (long long)(di + n) * (2 * n) + dj + n] = dacc[r][q];
     }
+}
+
+// k_poly_diffs on the matrix cores (complex64; same partial sums and layout).
+__global__ __launch_bounds__(256) void k_poly_diffs_mfma(const float2* __restrict__ w, int n,
+                                                         const float2* __restrict__ u1, const float2* __restrict__ u2,
+                                                         int bchunk, float2* __restrict__ part) {
+  constexpr int TK = 16;
+  __shared__ float ar[TK][kLdm], ai[TK][kLdm], br[TK][kLdm], bi[TK][kLdm];
+  const long long nn = (long long)n * n, bins = 4 * nn;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
+  const int di = poly_offset((int)blockIdx.y), dj0 = (int)blockIdx.x * 64 - n;
+  const int a_lo = di > 0 ? di : 0, a_hi = di < 0 ? n + di : n;
+  int b_lo = dj0 > 0 ? dj0 : 0, b_hi = dj0 + 63 + n;
+  if (b_hi > n) b_hi = n;
+  b_lo += (int)blockIdx.z * bchunk;
+  if (b_lo + bchunk < b_hi) b_hi = b_lo + bchunk;
+  float dre[2][2][4], dim[2][2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
+  for (int b = b_lo; b < b_hi; ++b) {
+    CTile g;
+    ctile_zero(g);
+    for (int a0 = a_lo; a0 < a_hi; a0 += TK) {
+      float2 rb[4], ra[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // W[a, b; a - di, b - dj], a = a0 + kk, dj = dj0 + jj
+        const int e = tid + 256 * q;
+        const int kk = e / 64, jj = e % 64;
+        const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
+        const bool ok = a < a_hi && dj < n && bq >= 0 && bq < n;
+        rb[q] = load_or_first(w, ok, ((long long)a * n + b) * nn + (long long)(a - di) * n + bq);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // A[kk][k] = u1[k][a] u2[k][a - di]
+        const int e = tid + 256 * q;
+        const int kk = e / 64, k = e % 64;
+        const int a = a0 + kk;
+        const bool ok = a < a_hi;
+        const int ac = ok ? a : a_lo;
+        ra[q] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ac - di]));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        const int kk = e / 64, jj = e % 64;
+        const int dj = dj0 + jj, bq = b - dj;
+        const float2 v = keep_or_zero(a0 + kk < a_hi && dj < n && bq >= 0 && bq < n, rb[q]);
+        ar[kk][jj] = ra[q].x;
+        ai[kk][jj] = ra[q].y;
+        br[kk][jj] = v.x;
+        bi[kk][jj] = v.y;
+      }
+      __syncthreads();
+      ctile_mfma16(g, ar, ai, br, bi, row0, col0, lane);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const float2 ub = u1[k * n + b];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int bq = b - (dj0 + col0 + 16 * q + lane % 16);
+          const bool ok = bq >= 0 && bq < n;
+          const float2 f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
+          const float gr = g.re[r][q][i], gi = g.im[r][q][i];
+          dre[r][q][i] += f.x * gr - f.y * gi;
+          dim[r][q][i] += f.x * gi + f.y * gr;
+        }
+      }
+  }
+  float2* out = part + (long long)blockIdx.z * kPairTile * bins;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const int dj = dj0 + col0 + 16 * q + lane % 16;
+        if (dj < n) out[k * bins + (long long)(di + n) * (2 * n) + dj + n] = float2{dre[r][q][i], dim[r][q][i]};
+      }
 }
 
 // One axis of a chirp-z transform of every pair's array, stored transposed:
@@ -857,8 +949,8 @@ hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int coun
 // intermediate 64 x 2N^2, the two transformed arrays 64 N^2 each; then S and W[P; .] in FP64 (N^2 each).
 static int poly_tiles_j(int n) { return (2 * n + 63) / 64; }
 static int poly_bsplit(int n) {
-  int sb = 1024 / (poly_tiles_j(n) * 2 * n);
-  if (sb < 1) sb = 1;
+  int sb = 4096 / (poly_tiles_j(n) * 2 * n);  // enough workgroups to even out rows of unequal work
+  if (sb < 4) sb = 4;
   if (sb > n) sb = n;
   return sb;
 }
@@ -911,8 +1003,11 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bchunk = (n + sb - 1) / sb;
-    hipLaunchKernelGGL(k_poly_diffs<T>, dim3((unsigned)poly_tiles_j(n), (unsigned)(2 * n), (unsigned)sb), dim3(256), 0,
-                       st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+    const dim3 grid_d((unsigned)poly_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
+    if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+    else
+      hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
                        kPairSplitK, n, (const T*)u2, rr);
