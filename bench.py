@@ -40,7 +40,8 @@ def parse():
                     choices=["propagate", "batch", "padded"],
                     help="run one untimed invocation for a counter run and exit: 'propagate' (build, in-place "
                          "propagation, then a 2 GiB runtime copy of known size for calibration), 'batch' "
-                         "(the 64-pair observables batch) or 'padded' (N = 200 complex64 in place, padded to "
+                         "(the 64-pair observables batch, then the 16-wavelength sum at z = 0.5 m on the FFT grid of "
+                         "500 nm) or 'padded' (N = 200 complex64 in place, padded to "
                          "N_z = 512, then unpadded)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="rocprofv3 FETCH/WRITE summary for the current kernels (optional)")
@@ -133,6 +134,9 @@ def main():
         pairs = WI.polychromatic_pairs()
         wolf.build_source(wl.source, n, p, out=w)
         wolf.propagate_batch(w, p, pairs["wavelength"], pairs["z"], pairs["weight"], ip=ip, jp=jp)
+        sel = pairs["z"] == 0.5
+        wolf.propagate_polychromatic(w, p, pairs["wavelength"][sel], pairs["z"][sel], pairs["weight"][sel],
+                                     500e-9 * 0.5 / (n * p), ip=ip, jp=jp)
         torch.cuda.synchronize()
         print("pmc sample done", flush=True)
         return
