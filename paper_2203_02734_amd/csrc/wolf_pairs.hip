@@ -26,16 +26,28 @@ struct PairGroup {
 };
 
 // Tables of one group, FP64-built: u1, u2 (pre1, pre2 of each pair), ci = e^{2 pi i P_i a/N} u1[a],
-// cj = e^{2 pi i P_j b/N} u1[b]; each kPairTile x N. Pairs beyond the count get zero tables.
+// cj = e^{2 pi i P_j b/N} u1[b]; each kPairTile x N. Pairs beyond the count get zero tables. The
+// matrix-core kernels read the same four tables transposed (tr: [4][N][kPairTile]), so that the 64
+// pairs of one index are 512 contiguous bytes.
 template <class T>
-__global__ __launch_bounds__(256) void k_pair_tables(PairGroup g, int n, int pi, int pj, T* u1, T* u2, T* ci, T* cj) {
+__device__ __forceinline__ void store_tables(T* u1, T* u2, T* ci, T* cj, T* tr, int n, int k, int a, T v1, T v2,
+                                             T vi, T vj) {
+  const int e = k * n + a;
+  const long long t = (long long)a * kPairTile + k, q = (long long)n * kPairTile;
+  u1[e] = v1; u2[e] = v2; ci[e] = vi; cj[e] = vj;
+  tr[t] = v1; tr[q + t] = v2; tr[2 * q + t] = vi; tr[3 * q + t] = vj;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pair_tables(PairGroup g, int n, int pi, int pj, T* u1, T* u2, T* ci, T* cj,
+                                                     T* tr) {
   using R = typename real_of<T>::type;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kPairTile * n) return;
   const int k = e / n, a = e % n;
   if (k >= g.count) {
     const T z{(R)0, (R)0};
-    u1[e] = z; u2[e] = z; ci[e] = z; cj[e] = z;
+    store_tables(u1, u2, ci, cj, tr, n, k, a, z, z, z, z);
     return;
   }
   const Chirp c1{g.a_src[k], 1.0, -1, 1}, c2{g.a_src[k], 1.0, +1, 1};
@@ -44,10 +56,8 @@ __global__ __launch_bounds__(256) void k_pair_tables(PairGroup g, int n, int pi,
   sincospi(2.0 * (double)((pi * a) % n) / (double)n, &si, &co);
   sincospi(2.0 * (double)((pj * a) % n) / (double)n, &sj, &cjx);
   const double2 wi = cmul(double2{co, si}, v1), wj = cmul(double2{cjx, sj}, v1);
-  u1[e] = T{(R)v1.x, (R)v1.y};
-  u2[e] = T{(R)v2.x, (R)v2.y};
-  ci[e] = T{(R)wi.x, (R)wi.y};
-  cj[e] = T{(R)wj.x, (R)wj.y};
+  store_tables(u1, u2, ci, cj, tr, n, k, a, T{(R)v1.x, (R)v1.y}, T{(R)v2.x, (R)v2.y}, T{(R)wi.x, (R)wi.y},
+               T{(R)wj.x, (R)wj.y});
 }
 
 // Row sums: part[s][k][p2] = sum_{p1 in chunk s} ci[k][a] cj[k][b] W[p1][p2]. A workgroup computes a
@@ -86,7 +96,8 @@ __global__ __launch_bounds__(256) void k_pair_rows(const T* __restrict__ w, int 
       const int k = e / TK, kk = e % TK;
       const long long p1 = k0 + kk;
       const bool ok = p1 < p_end;
-      const int a = ok ? (int)(p1 / n) : 0, b = ok ? (int)(p1 % n) : 0;
+      const int pi = ok ? (int)p1 : 0;  // p1 < N^2 fits an int: 32-bit division
+      const int a = pi / n, b = pi - a * n;
       As[kk][k] = keep_or_zero(ok, cmul(ci[k * n + a], cj[k * n + b]));
     }
 #pragma unroll
@@ -274,51 +285,63 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], 
   }
 }
 
-// k_pair_rows on the matrix cores (same partial sums and layout).
+// k_pair_rows on the matrix cores (same partial sums and layout). The operands of step s + 1 are
+// loaded from HBM while the matrix cores work on step s, and staged into the second LDS buffer after
+// it: one barrier per step.
 __global__ __launch_bounds__(256) void k_pair_rows_mfma(const float2* __restrict__ w, int n,
-                                                        const float2* __restrict__ ci, const float2* __restrict__ cj,
+                                                        const float2* __restrict__ cit, const float2* __restrict__ cjt,
                                                         long long chunk, float2* __restrict__ part) {
   constexpr int TK = 16;
-  __shared__ float ar[TK][kLdm], ai[TK][kLdm], br[TK][kLdm], bi[TK][kLdm];
+  __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
   const long long j0 = (long long)blockIdx.x * 64;
   const long long s = blockIdx.y;
   const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
-  CTile acc;
-  ctile_zero(acc);
-  for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
-    float2 rb[4], ra[4];
+  // Element e = tid + 256 q of a step: contraction row kk = e / 64, and column (or pair) e % 64.
+  float2 rb[4], ca[4], cb[4];
+  auto fetch = [&](long long k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {  // element e: contraction row kk = e / 64, column or pair e % 64
+    for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int kk = e / 64, jj = e % 64;
       const long long p1 = k0 + kk, p2 = j0 + jj;
-      rb[q] = load_or_first(w, p1 < p_end && p2 < nn, p1 * nn + p2);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, k = e % 64;
-      const long long p1 = k0 + kk;
       const bool ok = p1 < p_end;
-      const int a = ok ? (int)(p1 / n) : 0, b = ok ? (int)(p1 % n) : 0;
-      ra[q] = keep_or_zero(ok, cmul(ci[k * n + a], cj[k * n + b]));
+      rb[q] = load_or_first(w, ok && p2 < nn, p1 * nn + p2);
+      const int pi = ok ? (int)p1 : 0;  // p1 < N^2 fits an int: 32-bit division
+      const int a = pi / n, b = pi - a * n;
+      ca[q] = cit[a * kPairTile + jj];
+      cb[q] = cjt[b * kPairTile + jj];
     }
+  };
+  auto stage = [&](int buf, long long k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int kk = e / 64, jj = e % 64;
-      const float2 v = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
-      ar[kk][jj] = ra[q].x;
-      ai[kk][jj] = ra[q].y;
-      br[kk][jj] = v.x;
-      bi[kk][jj] = v.y;
+      const bool ok = k0 + kk < p_end;
+      const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
+      const float2 v = keep_or_zero(ok && j0 + jj < nn, rb[q]);
+      ar[buf][kk][jj] = a.x;
+      ai[buf][kk][jj] = a.y;
+      br[buf][kk][jj] = v.x;
+      bi[buf][kk][jj] = v.y;
     }
+  };
+  CTile acc;
+  ctile_zero(acc);
+  fetch(p_begin);
+  stage(0, p_begin);
+  __syncthreads();
+  int buf = 0;
+  for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
+    const bool more = k0 + TK < p_end;
+    if (more) fetch(k0 + TK);
+    ctile_mfma16(acc, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    if (more) stage(buf ^ 1, k0 + TK);
     __syncthreads();
-    ctile_mfma16(acc, ar, ai, br, bi, row0, col0, lane);
-    __syncthreads();
+    buf ^= 1;
   }
   float2* out = part + s * kPairTile * nn;
 #pragma unroll
@@ -333,12 +356,16 @@ __global__ __launch_bounds__(256) void k_pair_rows_mfma(const float2* __restrict
       }
 }
 
-// k_pair_diffs on the matrix cores (same partial sums and layout).
+// k_pair_diffs on the matrix cores (same partial sums and layout). The steps (b, a0) run in one
+// sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b the wavefront block
+// folds its G tile into D.
 __global__ __launch_bounds__(256) void k_pair_diffs_mfma(const float2* __restrict__ w, int n,
                                                          const float2* __restrict__ u1, const float2* __restrict__ u2,
-                                                         int bchunk, float2* __restrict__ part) {
+                                                         const float2* __restrict__ u1t,
+                                                         const float2* __restrict__ u2t, int bchunk,
+                                                         float2* __restrict__ part) {
   constexpr int TK = 16;
-  __shared__ float ar[TK][kLdm], ai[TK][kLdm], br[TK][kLdm], bi[TK][kLdm];
+  __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
@@ -351,58 +378,74 @@ __global__ __launch_bounds__(256) void k_pair_diffs_mfma(const float2* __restric
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  for (int b = b_begin; b < b_end; ++b) {
-    CTile g;
-    ctile_zero(g);
-    for (int a0 = 0; a0 < n; a0 += TK) {
-      float2 rb[4], ra[4];
+  // Element e = tid + 256 q of a step: a = a0 + e / 64; column dj = dj0 + e % 64, or pair e % 64.
+  float2 rb[4], ca[4], cb[4];
+  auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] and the tables of A = u1[a] u2[a - di]
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {  // W[a, b; a - di, b - dj], a = a0 + kk, dj = dj0 + jj
-        const int e = tid + 256 * q;
-        const int kk = e / 64, jj = e % 64;
-        const int a = a0 + kk, dj = dj0 + jj;
-        rb[q] = load_or_first(w, a < n && dj < n,
-                              ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // A[kk][k] = u1[k][a] u2[k][a - di]
-        const int e = tid + 256 * q;
-        const int kk = e / 64, k = e % 64;
-        const int a = a0 + kk;
-        const bool ok = a < n;
-        const int ac = ok ? a : 0;
-        ra[q] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ((ac - di) & nm)]));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        const int kk = e / 64, jj = e % 64;
-        const float2 v = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
-        ar[kk][jj] = ra[q].x;
-        ai[kk][jj] = ra[q].y;
-        br[kk][jj] = v.x;
-        bi[kk][jj] = v.y;
-      }
-      __syncthreads();
-      ctile_mfma16(g, ar, ai, br, bi, row0, col0, lane);
-      __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / 64, jj = e % 64;
+      const int a = a0 + kk, dj = dj0 + jj;
+      const bool ok = a < n;
+      rb[q] = load_or_first(w, ok && dj < n,
+                            ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
+      const int ac = ok ? a : 0;
+      ca[q] = u1t[ac * kPairTile + jj];
+      cb[q] = u2t[((ac - di) & nm) * kPairTile + jj];
     }
-    // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj], on the outputs this lane holds
+  };
+  auto stage = [&](int buf, int a0) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / 64, jj = e % 64;
+      const bool ok = a0 + kk < n;
+      const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
+      const float2 v = keep_or_zero(ok && dj0 + jj < n, rb[q]);
+      ar[buf][kk][jj] = a.x;
+      ai[buf][kk][jj] = a.y;
+      br[buf][kk][jj] = v.x;
+      bi[buf][kk][jj] = v.y;
+    }
+  };
+  if (b_begin < b_end) {
+    fetch(b_begin, 0);
+    stage(0, 0);
+  }
+  __syncthreads();
+  CTile g;
+  ctile_zero(g);
+  int buf = 0;
+  for (int b = b_begin, a0 = 0; b < b_end;) {
+    const bool last_a = a0 + TK >= n;
+    const int nb = last_a ? b + 1 : b, na = last_a ? 0 : a0 + TK;
+    const bool more = nb < b_end;
+    if (more) fetch(nb, na);
+    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    if (last_a) {
+      // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj], on the outputs this lane holds
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = row0 + 16 * r + 4 * (lane / 16) + i;
-        const float2 ub = u1[k * n + b];
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int dj = dj0 + col0 + 16 * q + lane % 16;
-          const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
-          const float gr = g.re[r][q][i], gi = g.im[r][q][i];
-          dre[r][q][i] += f.x * gr - f.y * gi;
-          dim[r][q][i] += f.x * gi + f.y * gr;
+        for (int i = 0; i < 4; ++i) {
+          const int k = row0 + 16 * r + 4 * (lane / 16) + i;
+          const float2 ub = u1[k * n + b];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int dj = dj0 + col0 + 16 * q + lane % 16;
+            const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
+            const float gr = g.re[r][q][i], gi = g.im[r][q][i];
+            dre[r][q][i] += f.x * gr - f.y * gi;
+            dim[r][q][i] += f.x * gi + f.y * gr;
+          }
         }
-      }
+      ctile_zero(g);
+    }
+    if (more) stage(buf ^ 1, na);
+    __syncthreads();
+    buf ^= 1;
+    b = nb;
+    a0 = na;
   }
   float2* out = part + (long long)blockIdx.z * kPairTile * nn;
 #pragma unroll
@@ -540,14 +583,15 @@ struct PolyGroup {
 
 // u1 = conj(t), u2 = t, ci = e^{2 pi i beta (P_i - c)(a - c)} conj(t[a]), cj likewise with P_j (FP64-built).
 template <class T>
-__global__ __launch_bounds__(256) void k_poly_tables(PolyGroup g, int n, int pi, int pj, T* u1, T* u2, T* ci, T* cj) {
+__global__ __launch_bounds__(256) void k_poly_tables(PolyGroup g, int n, int pi, int pj, T* u1, T* u2, T* ci, T* cj,
+                                                     T* tr) {
   using R = typename real_of<T>::type;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kPairTile * n) return;
   const int k = e / n, a = e % n, c = n / 2;
   if (k >= g.count) {
     const T z{(R)0, (R)0};
-    u1[e] = z; u2[e] = z; ci[e] = z; cj[e] = z;
+    store_tables(u1, u2, ci, cj, tr, n, k, a, z, z, z, z);
     return;
   }
   const double2 t = chirp_entry<double2>(Chirp{g.alpha[k], 1.0, +1, 0}, a, n);
@@ -560,10 +604,8 @@ __global__ __launch_bounds__(256) void k_poly_tables(PolyGroup g, int n, int pi,
   sincospi(2.0 * pr, &si, &co);
   sincospi(2.0 * ps, &sj, &cjx);
   const double2 wi = cmul(double2{co, si}, tc), wj = cmul(double2{cjx, sj}, tc);
-  u1[e] = T{(R)tc.x, (R)tc.y};
-  u2[e] = T{(R)t.x, (R)t.y};
-  ci[e] = T{(R)wi.x, (R)wi.y};
-  cj[e] = T{(R)wj.x, (R)wj.y};
+  store_tables(u1, u2, ci, cj, tr, n, k, a, T{(R)tc.x, (R)tc.y}, T{(R)t.x, (R)t.y}, T{(R)wi.x, (R)wi.y},
+               T{(R)wj.x, (R)wj.y});
 }
 
 // Difference sums without wrap: part[z][k][(di + N) 2N + dj + N] = sum_{b} B_k^{dj}[b] sum_a A_k^{di}[a]
@@ -665,12 +707,15 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
     }
 }
 
-// k_poly_diffs on the matrix cores (complex64; same partial sums and layout).
+// k_poly_diffs on the matrix cores (complex64; same partial sums and layout), double-buffered like
+// k_pair_diffs_mfma.
 __global__ __launch_bounds__(256) void k_poly_diffs_mfma(const float2* __restrict__ w, int n,
                                                          const float2* __restrict__ u1, const float2* __restrict__ u2,
-                                                         int bchunk, float2* __restrict__ part) {
+                                                         const float2* __restrict__ u1t,
+                                                         const float2* __restrict__ u2t, int bchunk,
+                                                         float2* __restrict__ part) {
   constexpr int TK = 16;
-  __shared__ float ar[TK][kLdm], ai[TK][kLdm], br[TK][kLdm], bi[TK][kLdm];
+  __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n, bins = 4 * nn;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
@@ -687,59 +732,75 @@ __global__ __launch_bounds__(256) void k_poly_diffs_mfma(const float2* __restric
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  for (int b = b_lo; b < b_hi; ++b) {
-    CTile g;
-    ctile_zero(g);
-    for (int a0 = a_lo; a0 < a_hi; a0 += TK) {
-      float2 rb[4], ra[4];
+  float2 rb[4], ca[4], cb[4];
+  auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj], a = a0 + e / 64, dj = dj0 + e % 64
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {  // W[a, b; a - di, b - dj], a = a0 + kk, dj = dj0 + jj
-        const int e = tid + 256 * q;
-        const int kk = e / 64, jj = e % 64;
-        const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
-        const bool ok = a < a_hi && dj < n && bq >= 0 && bq < n;
-        rb[q] = load_or_first(w, ok, ((long long)a * n + b) * nn + (long long)(a - di) * n + bq);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // A[kk][k] = u1[k][a] u2[k][a - di]
-        const int e = tid + 256 * q;
-        const int kk = e / 64, k = e % 64;
-        const int a = a0 + kk;
-        const bool ok = a < a_hi;
-        const int ac = ok ? a : a_lo;
-        ra[q] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ac - di]));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        const int kk = e / 64, jj = e % 64;
-        const int dj = dj0 + jj, bq = b - dj;
-        const float2 v = keep_or_zero(a0 + kk < a_hi && dj < n && bq >= 0 && bq < n, rb[q]);
-        ar[kk][jj] = ra[q].x;
-        ai[kk][jj] = ra[q].y;
-        br[kk][jj] = v.x;
-        bi[kk][jj] = v.y;
-      }
-      __syncthreads();
-      ctile_mfma16(g, ar, ai, br, bi, row0, col0, lane);
-      __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / 64, jj = e % 64;
+      const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
+      const bool ok = a < a_hi;
+      rb[q] = load_or_first(w, ok && dj < n && bq >= 0 && bq < n,
+                            ((long long)a * n + b) * nn + (long long)(a - di) * n + bq);
+      const int ac = ok ? a : a_lo;  // A[kk][k] = u1[k][a] u2[k][a - di]
+      ca[q] = u1t[ac * kPairTile + jj];
+      cb[q] = u2t[(ac - di) * kPairTile + jj];
     }
+  };
+  auto stage = [&](int buf, int b, int a0) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / 64, jj = e % 64;
+      const int dj = dj0 + jj, bq = b - dj;
+      const bool ok = a0 + kk < a_hi;
+      const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
+      const float2 v = keep_or_zero(ok && dj < n && bq >= 0 && bq < n, rb[q]);
+      ar[buf][kk][jj] = a.x;
+      ai[buf][kk][jj] = a.y;
+      br[buf][kk][jj] = v.x;
+      bi[buf][kk][jj] = v.y;
+    }
+  };
+  const bool any = b_lo < b_hi && a_lo < a_hi;
+  if (any) {
+    fetch(b_lo, a_lo);
+    stage(0, b_lo, a_lo);
+  }
+  __syncthreads();
+  CTile g;
+  ctile_zero(g);
+  int buf = 0;
+  for (int b = b_lo, a0 = a_lo; any && b < b_hi;) {
+    const bool last_a = a0 + TK >= a_hi;
+    const int nb = last_a ? b + 1 : b, na = last_a ? a_lo : a0 + TK;
+    const bool more = nb < b_hi;
+    if (more) fetch(nb, na);
+    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    if (last_a) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = row0 + 16 * r + 4 * (lane / 16) + i;
-        const float2 ub = u1[k * n + b];
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int bq = b - (dj0 + col0 + 16 * q + lane % 16);
-          const bool ok = bq >= 0 && bq < n;
-          const float2 f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
-          const float gr = g.re[r][q][i], gi = g.im[r][q][i];
-          dre[r][q][i] += f.x * gr - f.y * gi;
-          dim[r][q][i] += f.x * gi + f.y * gr;
+        for (int i = 0; i < 4; ++i) {
+          const int k = row0 + 16 * r + 4 * (lane / 16) + i;
+          const float2 ub = u1[k * n + b];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int bq = b - (dj0 + col0 + 16 * q + lane % 16);
+            const bool ok = bq >= 0 && bq < n;
+            const float2 f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
+            const float gr = g.re[r][q][i], gi = g.im[r][q][i];
+            dre[r][q][i] += f.x * gr - f.y * gi;
+            dim[r][q][i] += f.x * gi + f.y * gr;
+          }
         }
-      }
+      ctile_zero(g);
+    }
+    if (more) stage(buf ^ 1, nb, na);
+    __syncthreads();
+    buf ^= 1;
+    b = nb;
+    a0 = na;
   }
   float2* out = part + (long long)blockIdx.z * kPairTile * bins;
 #pragma unroll
@@ -862,7 +923,7 @@ static int pair_bsplit(int n) {
 template <class T> size_t pair_work_bytes(int n) {
   using R = typename real_of<T>::type;
   const size_t nn = (size_t)n * n, g = (size_t)kPairTile * nn;
-  const size_t elems = 4 * (size_t)kPairTile * n + (size_t)kPairSplitK * g + (size_t)pair_bsplit(n) * g + 3 * g;
+  const size_t elems = 8 * (size_t)kPairTile * n + (size_t)kPairSplitK * g + (size_t)pair_bsplit(n) * g + 3 * g;
   return elems * sizeof(T) + g * sizeof(R) + kPairTile * sizeof(unsigned long long) + 256;
 }
 
@@ -877,7 +938,9 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   T* u2 = u1 + kPairTile * n;
   T* ci = u2 + kPairTile * n;
   T* cj = ci + kPairTile * n;
-  T* part_r = cj + kPairTile * n;
+  T* tr = cj + kPairTile * n;  // u1, u2, ci, cj transposed
+  const long long tq = (long long)kPairTile * n;
+  T* part_r = tr + 4 * tq;
   const int sb = pair_bsplit(n);
   T* part_d = part_r + (long long)kPairSplitK * g;
   T* buf_d = part_d + (long long)sb * g;  // D, then the 2D DFT of D
@@ -891,16 +954,18 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   pg.count = count;
   for (int k = 0; k < count; ++k) pg.a_src[k] = a_src[k];
   hipLaunchKernelGGL(k_pair_tables<T>, dim3((unsigned)((kPairTile * n + 255) / 256)), dim3(256), 0, st, pg, n, pi, pj,
-                     u1, u2, ci, cj);
+                     u1, u2, ci, cj, tr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
   const int bchunk = (n + sb - 1) / sb;
   const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK), grid_d((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb);
   if constexpr (sizeof(T) == 8) {  // complex64: matrix cores
-    hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+    hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)(tr + 2 * tq),
+                       (const T*)(tr + 3 * tq), chunk, part_r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+    hipLaunchKernelGGL(k_pair_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
+                       (const T*)(tr + tq), bchunk, part_d);
   } else {
     hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -944,7 +1009,7 @@ hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int coun
   return hipGetLastError();
 }
 
-// Work of the polychromatic sums, per group (elements of T unless noted): tables 4 x 64 N, row-sum
+// Work of the polychromatic sums, per group (elements of T unless noted): tables 8 x 64 N, row-sum
 // partials 16 x 64 N^2, difference-sum partials sb x 64 x 4N^2, D 64 x 4N^2, T R 64 N^2, transform
 // intermediate 64 x 2N^2, the two transformed arrays 64 N^2 each; then S and W[P; .] in FP64 (N^2 each).
 static int poly_tiles_j(int n) { return (2 * n + 63) / 64; }
@@ -957,7 +1022,7 @@ static int poly_bsplit(int n) {
 
 template <class T> size_t poly_work_bytes(int n) {
   const size_t nn = (size_t)n * n, g = (size_t)kPairTile * nn;
-  const size_t elems = 4 * (size_t)kPairTile * n + (size_t)kPairSplitK * g + (size_t)poly_bsplit(n) * 4 * g + 4 * g +
+  const size_t elems = 8 * (size_t)kPairTile * n + (size_t)kPairSplitK * g + (size_t)poly_bsplit(n) * 4 * g + 4 * g +
                        g + 2 * g + 2 * g;
   return elems * sizeof(T) + nn * (sizeof(double) + sizeof(double2)) + 512;
 }
@@ -972,7 +1037,9 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
   T* u2 = u1 + kPairTile * n;
   T* ci = u2 + kPairTile * n;
   T* cj = ci + kPairTile * n;
-  T* part_r = cj + kPairTile * n;
+  T* tr = cj + kPairTile * n;  // u1, u2, ci, cj transposed
+  const long long tq = (long long)kPairTile * n;
+  T* part_r = tr + 4 * tq;
   const int sb = poly_bsplit(n);
   T* part_d = part_r + (long long)kPairSplitK * g;
   T* dfull = part_d + (long long)sb * 4 * g;
@@ -993,19 +1060,21 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       pg.c[k] = coef[k0 + k];
     }
     hipLaunchKernelGGL(k_poly_tables<T>, dim3((unsigned)((kPairTile * n + 255) / 256)), dim3(256), 0, st, pg, n, pi,
-                       pj, u1, u2, ci, cj);
+                       pj, u1, u2, ci, cj, tr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
     const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK);
     if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+      hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)(tr + 2 * tq),
+                         (const T*)(tr + 3 * tq), chunk, part_r);
     else
       hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bchunk = (n + sb - 1) / sb;
     const dim3 grid_d((unsigned)poly_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
     if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+      hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
+                         (const T*)(tr + tq), bchunk, part_d);
     else
       hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
