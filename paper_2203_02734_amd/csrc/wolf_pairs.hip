@@ -232,7 +232,8 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
 // ---------------------------------------------------------------------------------------------
 // complex64: the two contractions on the matrix cores (v_mfma_f32_16x16x4f32, 2x the FP32 vector
 // rate without packed math). A workgroup's 64 x 64 complex tile is four 32 x 32 wavefront blocks of
-// 2 x 2 MFMA tiles; a complex product is four real ones (re re - im im, re im + im re). Operands are
+// 2 x 2 MFMA tiles. A complex product takes three real ones (the 3M form): T1 = Ar Br, T2 = Ai Bi and
+// T3 = (Ar + Ai)(Br + Bi) are accumulated apart, then re = T1 - T2 and im = T3 - T1 - T2. Operands are
 // staged in LDS as separate re / im planes [16][kLdm]: lane l of a 16 x 16 x 4 step reads
 // A[k 4 + l / 16][row l % 16] and B[k 4 + l / 16][col l % 16], and holds D[4 (l / 16) + i][l % 16];
 // with the row stride of 80 floats the four k rows of a step fall on distinct banks.
@@ -241,7 +242,11 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kLdm = 80;
 
 struct CTile {
-  v4f re[2][2], im[2][2];
+  v4f t1[2][2], t2[2][2], t3[2][2];
+  __device__ __forceinline__ float re(int r, int q, int i) const { return t1[r][q][i] - t2[r][q][i]; }
+  __device__ __forceinline__ float im(int r, int q, int i) const {
+    return t3[r][q][i] - t1[r][q][i] - t2[r][q][i];
+  }
 };
 
 __device__ __forceinline__ void ctile_zero(CTile& c) {
@@ -249,8 +254,9 @@ __device__ __forceinline__ void ctile_zero(CTile& c) {
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      c.re[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
-      c.im[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+      c.t1[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+      c.t2[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+      c.t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 }
 
@@ -261,26 +267,26 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], 
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
     const int kk = ks * 4 + lane / 16, l16 = lane % 16;
-    float xr[2], xi[2], xn[2], yr[2], yi[2];
+    float xr[2], xi[2], xs[2], yr[2], yi[2], ys[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       xr[r] = ar[kk][row0 + 16 * r + l16];
       xi[r] = ai[kk][row0 + 16 * r + l16];
-      xn[r] = -xi[r];
+      xs[r] = xr[r] + xi[r];
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       yr[q] = br[kk][col0 + 16 * q + l16];
       yi[q] = bi[kk][col0 + 16 * q + l16];
+      ys[q] = yr[q] + yi[q];
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        c.re[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yr[q], c.re[r][q], 0, 0, 0);
-        c.re[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xn[r], yi[q], c.re[r][q], 0, 0, 0);
-        c.im[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yi[q], c.im[r][q], 0, 0, 0);
-        c.im[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[r], yr[q], c.im[r][q], 0, 0, 0);
+        c.t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yr[q], c.t1[r][q], 0, 0, 0);
+        c.t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[r], yi[q], c.t2[r][q], 0, 0, 0);
+        c.t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], c.t3[r][q], 0, 0, 0);
       }
   }
 }
@@ -288,7 +294,7 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], 
 // k_pair_rows on the matrix cores (same partial sums and layout). The operands of step s + 1 are
 // loaded from HBM while the matrix cores work on step s, and staged into the second LDS buffer after
 // it: one barrier per step.
-__global__ __launch_bounds__(256) void k_pair_rows_mfma(const float2* __restrict__ w, int n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rows_mfma(const float2* __restrict__ w, int n,
                                                         const float2* __restrict__ cit, const float2* __restrict__ cjt,
                                                         long long chunk, float2* __restrict__ part) {
   constexpr int TK = 16;
@@ -352,14 +358,14 @@ __global__ __launch_bounds__(256) void k_pair_rows_mfma(const float2* __restrict
       for (int i = 0; i < 4; ++i) {
         const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
         const long long j = j0 + col0 + 16 * q + lane % 16;
-        if (j < nn) out[k * nn + j] = float2{acc.re[r][q][i], acc.im[r][q][i]};
+        if (j < nn) out[k * nn + j] = float2{acc.re(r, q, i), acc.im(r, q, i)};
       }
 }
 
 // k_pair_diffs on the matrix cores (same partial sums and layout). The steps (b, a0) run in one
 // sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b the wavefront block
 // folds its G tile into D.
-__global__ __launch_bounds__(256) void k_pair_diffs_mfma(const float2* __restrict__ w, int n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_diffs_mfma(const float2* __restrict__ w, int n,
                                                          const float2* __restrict__ u1, const float2* __restrict__ u2,
                                                          const float2* __restrict__ u1t,
                                                          const float2* __restrict__ u2t, int bchunk,
@@ -434,7 +440,7 @@ __global__ __launch_bounds__(256) void k_pair_diffs_mfma(const float2* __restric
           for (int q = 0; q < 2; ++q) {
             const int dj = dj0 + col0 + 16 * q + lane % 16;
             const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
-            const float gr = g.re[r][q][i], gi = g.im[r][q][i];
+            const float gr = g.re(r, q, i), gi = g.im(r, q, i);
             dre[r][q][i] += f.x * gr - f.y * gi;
             dim[r][q][i] += f.x * gi + f.y * gr;
           }
@@ -709,7 +715,7 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
 
 // k_poly_diffs on the matrix cores (complex64; same partial sums and layout), double-buffered like
 // k_pair_diffs_mfma.
-__global__ __launch_bounds__(256) void k_poly_diffs_mfma(const float2* __restrict__ w, int n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_poly_diffs_mfma(const float2* __restrict__ w, int n,
                                                          const float2* __restrict__ u1, const float2* __restrict__ u2,
                                                          const float2* __restrict__ u1t,
                                                          const float2* __restrict__ u2t, int bchunk,
@@ -789,7 +795,7 @@ __global__ __launch_bounds__(256) void k_poly_diffs_mfma(const float2* __restric
             const int bq = b - (dj0 + col0 + 16 * q + lane % 16);
             const bool ok = bq >= 0 && bq < n;
             const float2 f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
-            const float gr = g.re[r][q][i], gi = g.im[r][q][i];
+            const float gr = g.re(r, q, i), gi = g.im(r, q, i);
             dre[r][q][i] += f.x * gr - f.y * gi;
             dim[r][q][i] += f.x * gi + f.y * gr;
           }
