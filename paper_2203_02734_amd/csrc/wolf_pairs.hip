@@ -261,9 +261,10 @@ __device__ __forceinline__ void ctile_zero(CTile& c) {
 }
 
 // c += A B over the 16 staged values of the contraction index, for the wavefront block at (row0, col0).
+// Bit q of `cols` (wavefront-uniform) enables the 16 columns col0 + 16 q; a disabled block is left as is.
 __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], const float (*ai)[kLdm],
                                              const float (*br)[kLdm], const float (*bi)[kLdm], int row0, int col0,
-                                             int lane) {
+                                             int lane, int cols = 3) {
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
     const int kk = ks * 4 + lane / 16, l16 = lane % 16;
@@ -281,13 +282,15 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], 
       ys[q] = yr[q] + yi[q];
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int q = 0; q < 2; ++q) {
+      if (!((cols >> q) & 1)) continue;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int r = 0; r < 2; ++r) {
         c.t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yr[q], c.t1[r][q], 0, 0, 0);
         c.t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[r], yi[q], c.t2[r][q], 0, 0, 0);
         c.t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], c.t3[r][q], 0, 0, 0);
       }
+    }
   }
 }
 
@@ -782,7 +785,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nb = last_a ? b + 1 : b, na = last_a ? a_lo : a0 + TK;
     const bool more = nb < b_hi;
     if (more) fetch(nb, na);
-    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    // Column blocks with no dj in (b - N, b] hold no term of this b: skip their products.
+    int cols = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c0 = dj0 + col0 + 16 * q;
+      if (c0 <= b && c0 + 15 > b - n) cols |= 1 << q;
+    }
+    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane, __builtin_amdgcn_readfirstlane(cols));
     if (last_a) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
