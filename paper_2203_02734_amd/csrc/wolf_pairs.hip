@@ -303,23 +303,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   constexpr int TK = 16;
   __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n;
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
   const long long j0 = (long long)blockIdx.x * 64;
   const long long s = blockIdx.y;
   const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
-  // Element e = tid + 256 q of a step: contraction row kk = e / 64, and column (or pair) e % 64.
+  const int lg = __builtin_ctz((unsigned)n);
+  // Element q of a thread in a step: contraction row kk = wv + 4 q (one per wavefront), and column (or
+  // pair) jj = lane.
   float2 rb[4], ca[4], cb[4];
   auto fetch = [&](long long k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, jj = e % 64;
+      const int kk = wv + 4 * q, jj = lane;
       const long long p1 = k0 + kk, p2 = j0 + jj;
       const bool ok = p1 < p_end;
       rb[q] = load_or_first(w, ok && p2 < nn, p1 * nn + p2);
-      const int pi = ok ? (int)p1 : 0;  // p1 < N^2 fits an int: 32-bit division
-      const int a = pi / n, b = pi - a * n;
+      const int pi = ok ? (int)p1 : 0;  // p1 < N^2, N a power of two
+      const int a = pi >> lg, b = pi & (n - 1);
       ca[q] = cit[a * kPairTile + jj];
       cb[q] = cjt[b * kPairTile + jj];
     }
@@ -327,8 +329,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   auto stage = [&](int buf, long long k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, jj = e % 64;
+      const int kk = wv + 4 * q, jj = lane;
       const bool ok = k0 + kk < p_end;
       const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
       const float2 v = keep_or_zero(ok && j0 + jj < nn, rb[q]);
@@ -376,7 +377,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int TK = 16;
   __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n;
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
   const int dj0 = blockIdx.x * 64, di = blockIdx.y, nm = n - 1;  // N is a power of two
   const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
@@ -387,13 +389,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  // Element e = tid + 256 q of a step: a = a0 + e / 64; column dj = dj0 + e % 64, or pair e % 64.
+  // Element q of a thread in a step: a = a0 + wv + 4 q (one per wavefront); column dj = dj0 + lane, or pair lane.
   float2 rb[4], ca[4], cb[4];
   auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] and the tables of A = u1[a] u2[a - di]
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, jj = e % 64;
+      const int kk = wv + 4 * q, jj = lane;
       const int a = a0 + kk, dj = dj0 + jj;
       const bool ok = a < n;
       rb[q] = load_or_first(w, ok && dj < n,
@@ -406,8 +407,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   auto stage = [&](int buf, int a0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, jj = e % 64;
+      const int kk = wv + 4 * q, jj = lane;
       const bool ok = a0 + kk < n;
       const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
       const float2 v = keep_or_zero(ok && dj0 + jj < n, rb[q]);
@@ -726,7 +726,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int TK = 16;
   __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n, bins = 4 * nn;
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
   const int di = poly_offset((int)blockIdx.y), dj0 = (int)blockIdx.x * 64 - n;
   const int a_lo = di > 0 ? di : 0, a_hi = di < 0 ? n + di : n;
@@ -742,11 +743,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
   float2 rb[4], ca[4], cb[4];
-  auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj], a = a0 + e / 64, dj = dj0 + e % 64
+  auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj], a = a0 + wv + 4 q, dj = dj0 + lane
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, jj = e % 64;
+      const int kk = wv + 4 * q, jj = lane;
       const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
       const bool ok = a < a_hi;
       rb[q] = load_or_first(w, ok && dj < n && bq >= 0 && bq < n,
@@ -759,8 +759,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   auto stage = [&](int buf, int b, int a0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / 64, jj = e % 64;
+      const int kk = wv + 4 * q, jj = lane;
       const int dj = dj0 + jj, bq = b - dj;
       const bool ok = a0 + kk < a_hi;
       const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
