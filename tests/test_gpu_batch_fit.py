@@ -75,6 +75,57 @@ def test_batch_sizes_vs_oracle(gpu_lib, n, dtype, farfield):
         assert rel(host(mu[k]), O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor)
 
 
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_batch_two_groups_vs_oracle(gpu_lib, farfield, dtype):
+    """70 pairs, a full group of 64 and a group of 6 (the last group's tables pad with zero pairs), each
+    pair against the oracle; random Hermitian source at N = 8, random wavelengths, distances, weights."""
+    n, p = 8, 20e-6
+    w = WI.random_hermitian_psd(n, seed=91)
+    g = WI.rng(92)
+    lam = g.uniform(450e-9, 750e-9, 70)
+    zs = g.uniform(0.05, 2.0, 70)
+    ws = g.uniform(0.1, 1.5, 70)
+    ip, jp = 3, 6
+    floor = 1e-4 if dtype == torch.complex64 else 1e-8
+    s, mu = gpu_lib.propagate_batch(torch.from_numpy(w).to(dtype).cuda(), p, lam, zs, ws, farfield=farfield,
+                                    ip=ip, jp=jp, floor_rel=floor)
+    s, mu = host(s), host(mu)
+    for k in range(70):
+        wb, _ = O.propagate(ws[k] * w, n, p, lam[k], zs[k], farfield)
+        assert rel(s[k], O.spectral_density(wb)) < TOL[dtype], k
+        assert rel(mu[k], O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor), k
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_batch_gsm_separable_large(gpu_lib, n):
+    """complex64 GSM at N = 64 and at the largest N (256: a 34 GB source, 65536-row contractions), three
+    pairs against the separable oracle: S and the mu row."""
+    if n == 256:
+        wl = WI.gsm256()[0]
+        p, sp = wl.pitch_m, wl.source
+    else:
+        p, sp = 20e-6, WI.SourceSpec(model=WI.MODEL_GSM, sigma_s_m=0.1e-3, sigma_g_m=0.05e-3)
+    lam = np.array([500e-9, 632.8e-9, 700e-9])
+    zs = np.array([0.3, 1.0, 0.6])
+    ws = np.array([1.0, 0.4, 0.8])
+    ip, jp, floor = n // 2, n // 2 - 3, 1e-4
+    w0 = gpu_lib.build_source(sp, n, p, torch.complex64)
+    s, mu = gpu_lib.propagate_batch(w0, p, lam, zs, ws, ip=ip, jp=jp, floor_rel=floor)
+    s, mu = host(s), host(mu)
+    del w0
+    torch.cuda.empty_cache()
+    wx = O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x")
+    wy = O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y")
+    for k in range(3):
+        bx, by = O.propagate_separable(ws[k] * wx, wy, n, p, lam[k], zs[k])
+        sr = np.real(np.diag(bx)[:, None] * np.diag(by)[None, :])
+        mur = bx[ip][:, None] * by[jp][None, :] / np.sqrt(sr[ip, jp] * sr)
+        mur[sr <= floor * sr.max()] = 0
+        assert rel(s[k], sr) < 1e-5, k
+        assert rel(mu[k], mur) < 1e-5 / math.sqrt(floor), k
+
+
 def test_batch_work_bytes(gpu_lib):
     """No N^4 work array at any size: per-group partial sums of 64 pairs (16 row-sum chunks and the
     difference-sum chunks), three N^2 buffers per pair and the tables."""

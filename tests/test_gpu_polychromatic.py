@@ -46,6 +46,26 @@ def test_polychromatic_vs_oracle(gpu_lib, n, dtype, farfield):
     assert rel(host(mu), mur) < TOL[dtype] / math.sqrt(floor)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_polychromatic_two_groups_vs_oracle(gpu_lib, dtype):
+    """70 pairs (a group of 64, then 6 whose sums add to the first group's in FP64), random Hermitian
+    source at N = 8, random wavelengths, distances and weights, a common grid of no pair's pitch."""
+    n, p = 8, 20e-6
+    w = WI.random_hermitian_psd(n, seed=93)
+    g = WI.rng(94)
+    lam = g.uniform(450e-9, 750e-9, 70)
+    zs = g.uniform(0.05, 0.2, 70)
+    ws = g.uniform(0.0, 1.0, 70)
+    dxp = 0.9 * O.output_pitch(n, p, 600e-9, 0.1)
+    ip, jp = 2, 5
+    floor = 1e-4 if dtype == torch.complex64 else 1e-8
+    s, mu = gpu_lib.propagate_polychromatic(torch.from_numpy(w).to(dtype).cuda(), p, lam, zs, ws, dxp, ip=ip,
+                                            jp=jp, floor_rel=floor)
+    sr, mur = O.polychromatic(w, n, p, lam, zs, ws, dxp, False, ip=ip, jp=jp, floor_rel=floor)
+    assert rel(host(s), sr) < TOL[dtype]
+    assert rel(host(mu), mur) < TOL[dtype] / math.sqrt(floor)
+
+
 @pytest.mark.parametrize("farfield", [False, True])
 def test_single_pair_on_its_fft_grid_equals_batch(gpu_lib, farfield):
     """One pair on its own FFT grid (pitch lambda z / (N pitch)): the chirp-z transforms reduce to
