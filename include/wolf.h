@@ -243,8 +243,8 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
  * along the difference coordinate p1 - p2, and the row W_B[P1; .] through a weighted sum over the
  * first point; with the source chirps of the pairs as weights both are dense contractions that
  * groups of up to 64 pairs share (two reads of w_src per group, then two N x N DFTs per pair). In the
- * far field the source-side factors do not depend on (lambda, z): one set of sums serves every pair
- * (from the slab-transform observables pass where it fits: complex64 N <= 128, complex128 N <= 64).
+ * far field the source-side factors do not depend on (lambda, z): one set of sums serves every pair,
+ * and a group of one entry (the far field, or a single pair) takes one pass over w_src.
  * The first call for a given shape records the sequence of launches in a hipGraph; later calls
  * with the same shape replay it.
  *   w_src          device N^4, read only.

@@ -157,39 +157,11 @@ struct LensSpec {
   double pupil_radius_m;
 };
 
-// The batch extracts S and mu(P, .) without an N^4 output. In the far field, where the observables
-// pass fits, one slab-transform pass serves every pair; otherwise the sums over the first point are
-// shared contractions of all pairs (wolf_pairs.hip).
-bool batch_uses_observables(int32_t n, int32_t dtype, bool farfield) {
-  if (!farfield) return false;
-  return dtype == WOLF_C64 ? wolf::obs_supported<float2>(n) : wolf::obs_supported<double2>(n);
-}
-
+// The batch extracts S and mu(P, .) without an N^4 output: the sums over the first point are shared
+// contractions of all pairs of a group (wolf_pairs.hip); a group of one entry (the far field, whose
+// sums every pair shares, or a single pair) takes one HBM-bound pass.
 size_t batch_work_bytes(int32_t n, int32_t dtype) {
-  size_t b = dtype == WOLF_C64 ? wolf::pair_work_bytes<float2>(n) : wolf::pair_work_bytes<double2>(n);
-  if (batch_uses_observables(n, dtype, true)) {
-    const size_t o = dtype == WOLF_C64 ? wolf::obs_work_bytes<float2>(n) : wolf::obs_work_bytes<double2>(n);
-    if (o > b) b = o;
-  }
-  return b;
-}
-
-template <class T>
-hipError_t record_obs_pairs(int32_t n, const T* w_src, double pitch, int32_t n_pairs, const double* lam, const double* z,
-                            const double* weight, bool farfield, int32_t kind, int32_t ip, int32_t jp, double floor_rel,
-                            void* work, typename wolf::real_of<T>::type* s_out, T* mu_out, hipStream_t st) {
-  const size_t nn = (size_t)n * n;
-  wolf::ObsSums<T> sums{};
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < n_pairs && e == hipSuccess; ++k) {
-    const wolf::OperatorTables op = make_op(n, pitch, lam[k], z[k], farfield, kind, false);
-    // In the far field the source side carries no chirp: the raw sums do not depend on (lambda, z),
-    // and one pass over the source serves every pair.
-    if (k == 0 || !farfield) e = wolf::launch_obs_sums<T>(n, w_src, op, ip, jp, work, &sums, st);
-    if (e == hipSuccess)
-      e = wolf::launch_obs_emit<T>(n, sums, op, weight[k], ip, jp, floor_rel, s_out + k * nn, mu_out + k * nn, st);
-  }
-  return e;
+  return dtype == WOLF_C64 ? wolf::pair_work_bytes<float2>(n) : wolf::pair_work_bytes<double2>(n);
 }
 
 // Groups of up to 64 pairs: their raw sums from one pair-sums pass, then one emit per pair. In the far
@@ -235,17 +207,6 @@ hipError_t record_batch_pairs(int32_t n, const void* w_src, double pitch, int32_
                                       floor_rel, work, (float*)s_out, (float2*)mu_out, st);
   return record_pair_groups<double2>(n, (const double2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
                                      floor_rel, work, (double*)s_out, (double2*)mu_out, st);
-}
-
-hipError_t record_batch_observables(int32_t n, const void* w_src, double pitch, int32_t n_pairs, const double* lam,
-                                    const double* z, const double* weight, bool farfield, int32_t kind, int32_t dtype,
-                                    int32_t ip, int32_t jp, double floor_rel, void* work, void* s_out, void* mu_out,
-                                    hipStream_t st) {
-  if (dtype == WOLF_C64)
-    return record_obs_pairs<float2>(n, (const float2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
-                                    floor_rel, work, (float*)s_out, (float2*)mu_out, st);
-  return record_obs_pairs<double2>(n, (const double2*)w_src, pitch, n_pairs, lam, z, weight, farfield, kind, ip, jp,
-                                   floor_rel, work, (double*)s_out, (double2*)mu_out, st);
 }
 
 struct BatchGraph {
@@ -657,7 +618,6 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
   if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "%s: s_floor_rel must be >= 0", who);
   const size_t eb = elem_bytes(dtype), big = n4(n) * eb, nn = (size_t)n * n;
   wolf_status s;
-  const bool obs = batch_uses_observables(n, dtype, farfield == 1);
   const size_t wb = batch_work_bytes(n, dtype);
   if ((s = check_buf(w_src, big, "w_src")) != WOLF_OK) return s;
   if ((s = check_buf(work, wb, "work")) != WOLF_OK) return s;
@@ -668,18 +628,14 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
       intervals_overlap(s_out, s_bytes, w_src, big) || intervals_overlap(s_out, s_bytes, work, wb) ||
       intervals_overlap(mu_out, mu_bytes, w_src, big) || intervals_overlap(mu_out, mu_bytes, work, wb))
     return fail(WOLF_EINVAL, "%s: buffers overlap", who);
-  void* scratch = nullptr;
-  if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(WOLF_EDEVICE, "%s: hipGetDevice failed", who);
-  const wolf::Plan plan = plan_for(n, dtype);
 
   // Key of the recorded graph: every argument that a kernel sees.
   std::vector<double> key = {(double)dev, (double)n, pitch_m, (double)n_pairs, (double)farfield, (double)kind,
                              (double)dtype, (double)ip, (double)jp, s_floor_rel,
                              (double)(uintptr_t)w_src, (double)(uintptr_t)work, (double)(uintptr_t)s_out,
-                             (double)(uintptr_t)mu_out, (double)(uintptr_t)scratch, (double)obs, (double)plan.fused_slab,
-                             (double)plan.slab_chunk, (double)plan.col_chunk};
+                             (double)(uintptr_t)mu_out};
   for (int k = 0; k < n_pairs; ++k) {
     key.push_back(wavelength_m[k]);
     key.push_back(z_m[k]);
@@ -700,12 +656,8 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
       return fail(WOLF_EDEVICE, "%s: cannot create the capture stream", who);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (obs && e == hipSuccess) e = record_batch_observables(n, w_src, pitch_m, n_pairs, wavelength_m, z_m, weight,
-                                                             farfield == 1, kind, dtype, ip, jp, s_floor_rel, work,
-                                                             s_out, mu_out, cap);
-    if (!obs && e == hipSuccess) e = record_batch_pairs(n, w_src, pitch_m, n_pairs, wavelength_m, z_m, weight,
-                                                        farfield == 1, kind, dtype, ip, jp, s_floor_rel, work, s_out,
-                                                        mu_out, cap);
+    if (e == hipSuccess) e = record_batch_pairs(n, w_src, pitch_m, n_pairs, wavelength_m, z_m, weight, farfield == 1,
+                                                kind, dtype, ip, jp, s_floor_rel, work, s_out, mu_out, cap);
     const hipError_t e_end = hipStreamEndCapture(cap, &graph);
     if (e == hipSuccess) e = e_end;
     hipGraphExec_t exec = nullptr;

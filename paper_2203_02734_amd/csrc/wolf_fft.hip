@@ -158,12 +158,11 @@ template <class T, int N> constexpr size_t slab_lds_bytes() {
   return sizeof(T) * ((size_t)N * slab_stride<N>() + 3 * N + 2);
 }
 
-// The 2D transform of one slab, shared by the slab pass and the observables pass. The work is
+// The 2D transform of one slab, shared by the slab passes. The work is
 // laid out for N2 N virtual threads; each real thread runs VT of them (virtual id = tid + vt NT / VT).
 // `tid` is the real thread id. On return, virtual thread (t, r) = (id % N2, id / N2) holds in u[vt N1 + q N2 + k2] the transformed
 // value of row r at column k = t + N2 q + N1 k2, before the column post-factor tpost[k]. The row
 // post-factor tpost[r] is applied only if ROW_POST.
-template <class T, int N> constexpr int slab_lines() { return (N * N * (int)sizeof(T) + 127) / 128; }
 
 // Raw loads of one slab for the column phase: virtual thread (t, c) takes rows n = N2 a + t of
 // column c into v[vt N1 + a].
@@ -199,30 +198,6 @@ __device__ __forceinline__ void slab_mask(const Pupil& pu, T* v, int tid) {
     for (int a = 0; a < N1; ++a)
       if (!pupil_pass(pu, N2 * a + t, c, N)) v[vt * N1 + a] = T{(R)0, (R)0};
   }
-}
-
-template <class T, int N, int SIGN, bool ROW_POST, int VT>
-__device__ __forceinline__ void slab_transform_loaded(T* v, T* buf, const T* tpre, const T* tpost, const T* tw,
-                                                      const T scal, T* u, int tid);
-
-template <class T, int N, int SIGN, bool ROW_POST = true, int VT = 1, int PFT = 0>
-__device__ __forceinline__ void slab_transform(const T* in, T* buf, const T* tpre, const T* tpost, const T* tw,
-                                               const T scal, T* u, int tid, const T* next = nullptr,
-                                               uint32_t* pf = nullptr) {
-  constexpr int NTR = Split<N>::N2 * N / VT;  // real threads
-  T v[VT * Split<N>::N1];
-  slab_load<T, N, VT>(in, v, tid);
-  // Touch one dword of each 128-byte line of the next slab: the lines travel to the L2 while this
-  // slab is transformed. The caller keeps pf[] live until the end of its iteration.
-  if constexpr (PFT > 0) {
-    const uint32_t* nx = reinterpret_cast<const uint32_t*>(next);
-#pragma unroll
-    for (int l = 0; l < PFT; ++l) {
-      const int line = tid + l * NTR;
-      pf[l] = (nx != nullptr && line < slab_lines<T, N>()) ? nx[line * 32] : 0u;
-    }
-  }
-  slab_transform_loaded<T, N, SIGN, ROW_POST, VT>(v, buf, tpre, tpost, tw, scal, u, tid);
 }
 
 // The transform of a slab whose raw values slab_load put in v (v is overwritten).
@@ -547,98 +522,6 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// Observables pass. For the forward operator the post-factors of the two points cancel on the
-// diagonal: post1[k] post2[k] = q*(x_k) q(x_k) (-1)^{2k} = 1. With Z[p1; m] the slab transform of
-// slab p1 = (a, b) before any post-factor and w1 = e^{sign1 2 pi i / N},
-//   S(m)      = s Re sum_p1 w1^(m_i a + m_j b) Z[p1; m]
-//   W_B[P; m] = s post1[P_i] post1[P_j] post2[m_i] post2[m_j] sum_p1 w1^(P_i a + P_j b) Z[p1; m].
-// Each workgroup takes every gridDim-th slab and keeps the two raw sums for all N^2 columns m in
-// registers; no N^4 array is written. k_obs_reduce adds the per-workgroup partials; k_obs_emit
-// applies s, the weight and the post-factors, so one set of raw sums serves every (lambda, z)
-// whose pre-factors are the same (the far field, where the source side carries no chirp).
-// ---------------------------------------------------------------------------------------------
-template <class T, int N, int SIGN>
-__global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_obs(const T* src, Chirp pre,
-                                                                               Chirp slab_pre, int pi, int pj,
-                                                                               typename real_of<T>::type* s_part,
-                                                                               T* b_part) {
-  using R = typename real_of<T>::type;
-  using S = Split<N>;
-  constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
-  constexpr int VT = 1;
-  constexpr int NTR = N2 * N / VT;
-  constexpr int SP = slab_stride<N>();
-  constexpr int PFT = (slab_lines<T, N>() + NTR - 1) / NTR;
-  __shared__ T buf[N * SP];
-  __shared__ T tpre[N], tw[N], tw1[N], tpre1[N];
-  for (int i = threadIdx.x; i < N; i += NTR) {
-    tpre[i] = chirp_entry<T>(pre, i, N);
-    tw[i] = twiddle_entry<T, SIGN>(i, N);
-    tw1[i] = twiddle_entry<T, -SIGN>(i, N);
-    tpre1[i] = chirp_entry<T>(slab_pre, i, N);
-  }
-  __syncthreads();
-  R sacc[VT * N1];
-  T bacc[VT * N1];
-#pragma unroll
-  for (int i = 0; i < VT * N1; ++i) {
-    sacc[i] = (R)0;
-    bacc[i] = T{(R)0, (R)0};
-  }
-  const long long nn = (long long)N * N;
-  for (long long p1 = blockIdx.x; p1 < nn; p1 += gridDim.x) {
-    const int a = (int)(p1 / N), b = (int)(p1 % N);
-    T u[VT * N1];
-    // An opaque copy of the thread id: the addresses derived from it are recomputed per slab
-    // instead of being held (and spilled) across the loop next to the raw sums.
-    int tid = (int)threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    const long long pn = p1 + gridDim.x;
-    uint32_t pf[PFT];
-    slab_transform<T, N, SIGN, false, VT, PFT>(src + p1 * nn, buf, tpre, tpre, tw, cmul(tpre1[a], tpre1[b]), u, tid,
-                                               pn < nn ? src + pn * nn : nullptr, pf);
-    const T cb = tw1[(pi * a + pj * b) & (N - 1)];
-#pragma unroll
-    for (int vt = 0; vt < VT; ++vt) {
-      const int id = tid + vt * NTR;
-      const int t = id % N2;
-      const int r = id / N2;
-      const int base = r * a + t * b;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-#pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-          const int i = vt * N1 + q * N2 + k2;
-          const T co = tw1[(base + (N2 * q + N1 * k2) * b) & (N - 1)];
-          const T v = u[i];
-          sacc[i] += co.x * v.x - co.y * v.y;
-          bacc[i] = cadd(bacc[i], cmul(cb, v));
-        }
-      }
-    }
-#pragma unroll
-    for (int l = 0; l < PFT; ++l) asm volatile("" ::"v"(pf[l]));
-    __syncthreads();  // buf is reused by the next slab
-  }
-  R* sp = s_part + (long long)blockIdx.x * nn;
-  T* bp = b_part + (long long)blockIdx.x * nn;
-#pragma unroll
-  for (int vt = 0; vt < VT; ++vt) {
-    const int id = threadIdx.x + vt * NTR;
-    const int t = id % N2;
-    const int r = id / N2;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-#pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int k = t + N2 * q + N1 * k2;
-        sp[r * N + k] = sacc[vt * N1 + q * N2 + k2];
-        bp[r * N + k] = bacc[vt * N1 + q * N2 + k2];
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------------------------
 // Launchers.
@@ -900,166 +783,6 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   }
   return hipSuccess;
 }
-
-// ---------------------------------------------------------------------------------------------
-// Observables pass launch, reduction and emission.
-// ---------------------------------------------------------------------------------------------
-template <class T> int obs_parts(int n) {
-  const long long nn = (long long)n * n;
-  long long g = 256;  // one workgroup per CU (the slab buffer takes most of the LDS at N = 128)
-  if (g > nn) g = nn;
-  return (int)g;
-}
-
-template <class T> size_t obs_work_bytes(int n) {
-  using R = typename real_of<T>::type;
-  const size_t nn = (size_t)n * n;
-  return ((size_t)obs_parts<T>(n) + 1) * nn * (sizeof(R) + sizeof(T)) + 256;
-}
-template size_t obs_work_bytes<float2>(int);
-template size_t obs_work_bytes<double2>(int);
-
-// Sum of the per-workgroup partials. A block covers 64 columns m with 4 threads each; thread q adds
-// the partials g = q, q + 4, ... (four independent chains), and the four sums are combined in a
-// fixed order, so the result does not depend on scheduling.
-template <class T>
-__global__ __launch_bounds__(256) void k_obs_reduce(const typename real_of<T>::type* __restrict__ s_part,
-                                                    const T* __restrict__ b_part, int parts, long long nn,
-                                                    typename real_of<T>::type* __restrict__ s0, T* __restrict__ b0,
-                                                    unsigned long long* key) {
-  using R = typename real_of<T>::type;
-  __shared__ R ss[4][64];
-  __shared__ T sb[4][64];
-  __shared__ unsigned long long red[64];
-  const int lane = threadIdx.x % 64, q = threadIdx.x / 64;
-  const long long m = (long long)blockIdx.x * 64 + lane;
-  R sv[4] = {(R)0, (R)0, (R)0, (R)0};
-  T bv[4] = {T{(R)0, (R)0}, T{(R)0, (R)0}, T{(R)0, (R)0}, T{(R)0, (R)0}};
-  if (m < nn) {
-    int g = q;
-    for (; g + 12 < parts; g += 16) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        sv[u] += s_part[(long long)(g + 4 * u) * nn + m];
-        bv[u] = cadd(bv[u], b_part[(long long)(g + 4 * u) * nn + m]);
-      }
-    }
-    for (; g < parts; g += 4) {
-      sv[0] += s_part[(long long)g * nn + m];
-      bv[0] = cadd(bv[0], b_part[(long long)g * nn + m]);
-    }
-  }
-  ss[q][lane] = (sv[0] + sv[1]) + (sv[2] + sv[3]);
-  sb[q][lane] = cadd(cadd(bv[0], bv[1]), cadd(bv[2], bv[3]));
-  __syncthreads();
-  if (q == 0) {
-    unsigned long long kk = 0ull;
-    if (m < nn) {
-      const R s = (ss[0][lane] + ss[1][lane]) + (ss[2][lane] + ss[3][lane]);
-      s0[m] = s;
-      b0[m] = cadd(cadd(sb[0][lane], sb[1][lane]), cadd(sb[2][lane], sb[3][lane]));
-      kk = order_key((double)s);
-    }
-    red[lane] = kk;
-  }
-  __syncthreads();
-  for (int h = 32; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicMax(key, red[0]);
-}
-
-__global__ void k_obs_clear_key(unsigned long long* key) { *key = 0ull; }
-
-// S = c s0 and mu(P, .) from the raw sums (emit_observables).
-template <class T>
-__global__ __launch_bounds__(256) void k_obs_emit(const typename real_of<T>::type* __restrict__ s0,
-                                                  const T* __restrict__ b0, const unsigned long long* key, int n, int pi,
-                                                  int pj, double c, Chirp post1, Chirp post2, double floor_rel,
-                                                  typename real_of<T>::type* __restrict__ s_out, T* __restrict__ mu_out) {
-  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < (long long)n * n) emit_observables(s0, b0, *key, n, pi, pj, m, c, post1, post2, floor_rel, s_out, mu_out);
-}
-
-template <class T, int N, int SIGN>
-static hipError_t launch_obs_n(const T* src, const OperatorTables& op, int pi, int pj, int parts,
-                               typename real_of<T>::type* s_part, T* b_part, hipStream_t st) {
-  if constexpr (slab_lds_bytes<T, N>() + N * sizeof(T) > kMaxLds || Split<N>::N2 * N > 1024) {
-    return hipErrorInvalidValue;
-  } else {
-    hipLaunchKernelGGL((k_slab_obs<T, N, SIGN>), dim3((unsigned)parts), dim3(Split<N>::N2 * N), 0, st,
-                       src, op.pre2,
-                       op.pre1, pi, pj, s_part, b_part);
-    return hipGetLastError();
-  }
-}
-
-template <class T> bool obs_supported(int n) {
-  switch (n) {
-#define WOLF_OBS_CASE(NN) \
-  case NN: return slab_lds_bytes<T, NN>() + NN * sizeof(T) <= kMaxLds && Split<NN>::N2 * NN <= 1024;
-    WOLF_OBS_CASE(2) WOLF_OBS_CASE(4) WOLF_OBS_CASE(8) WOLF_OBS_CASE(16) WOLF_OBS_CASE(32) WOLF_OBS_CASE(64)
-    WOLF_OBS_CASE(128) WOLF_OBS_CASE(256)
-#undef WOLF_OBS_CASE
-    default: return false;
-  }
-}
-template bool obs_supported<float2>(int);
-template bool obs_supported<double2>(int);
-
-// Raw sums of one forward operator's first-point pre-factors and DFTs over `src` (layout in `work`:
-// per-workgroup partials, then s0 (N^2 reals), b0 (N^2 complex), the max key).
-template <class T>
-hipError_t launch_obs_sums(int n, const T* src, const OperatorTables& op, int pi, int pj, void* work, ObsSums<T>* out,
-                           hipStream_t st) {
-  using R = typename real_of<T>::type;
-  if (op.sign2 != -1 || op.sign1 != +1) return hipErrorInvalidValue;  // forward operators only
-  if (!obs_supported<T>(n)) return hipErrorInvalidValue;
-  const long long nn = (long long)n * n;
-  const int parts = obs_parts<T>(n);
-  char* w = reinterpret_cast<char*>(work);
-  R* s_part = reinterpret_cast<R*>(w);
-  T* b_part = reinterpret_cast<T*>(w + (size_t)parts * nn * sizeof(R));
-  char* tail = w + (size_t)parts * nn * (sizeof(R) + sizeof(T));
-  out->s0 = reinterpret_cast<R*>(tail);
-  out->b0 = reinterpret_cast<T*>(tail + (size_t)nn * sizeof(R));
-  out->key = reinterpret_cast<unsigned long long*>(tail + (size_t)nn * (sizeof(R) + sizeof(T)));
-  hipError_t e;
-  switch (n) {
-#define WOLF_OBS_LAUNCH(NN) \
-  case NN: e = launch_obs_n<T, NN, -1>(src, op, pi, pj, parts, s_part, b_part, st); break;
-    WOLF_OBS_LAUNCH(2) WOLF_OBS_LAUNCH(4) WOLF_OBS_LAUNCH(8) WOLF_OBS_LAUNCH(16) WOLF_OBS_LAUNCH(32) WOLF_OBS_LAUNCH(64)
-    WOLF_OBS_LAUNCH(128) WOLF_OBS_LAUNCH(256)
-#undef WOLF_OBS_LAUNCH
-    default: return hipErrorInvalidValue;
-  }
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_obs_clear_key, dim3(1), dim3(1), 0, st, out->key);
-  hipLaunchKernelGGL(k_obs_reduce<T>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, st, (const R*)s_part,
-                     (const T*)b_part, parts, nn, out->s0, out->b0, out->key);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_obs_emit(int n, const ObsSums<T>& sums, const OperatorTables& op, double weight, int pi, int pj,
-                           double floor_rel, typename real_of<T>::type* s_out, T* mu_out, hipStream_t st) {
-  using R = typename real_of<T>::type;
-  const long long nn = (long long)n * n;
-  hipLaunchKernelGGL(k_obs_emit<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const R*)sums.s0,
-                     (const T*)sums.b0, (const unsigned long long*)sums.key, n, pi, pj, weight * op.scale, op.post1,
-                     op.post2, floor_rel, s_out, mu_out);
-  return hipGetLastError();
-}
-
-template hipError_t launch_obs_sums<float2>(int, const float2*, const OperatorTables&, int, int, void*, ObsSums<float2>*,
-                                            hipStream_t);
-template hipError_t launch_obs_sums<double2>(int, const double2*, const OperatorTables&, int, int, void*,
-                                             ObsSums<double2>*, hipStream_t);
-template hipError_t launch_obs_emit<float2>(int, const ObsSums<float2>&, const OperatorTables&, double, int, int, double,
-                                            float*, float2*, hipStream_t);
-template hipError_t launch_obs_emit<double2>(int, const ObsSums<double2>&, const OperatorTables&, double, int, int,
-                                             double, double*, double2*, hipStream_t);
 
 // ---------------------------------------------------------------------------------------------
 // Operator applied to a diagonal input diag(g) (e.g. the gradient of a loss of S = Re diag W).

@@ -64,22 +64,14 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
 template <class T>
 hipError_t launch_operator_diag(int n, const typename real_of<T>::type* g, T* out, const OperatorTables& op,
                                 const Plan& plan, void* counters, hipStream_t st);
-// Observables-only forward propagation: S and mu(P, .) without an N^4 output (k_slab_obs).
+// Raw sums of the observables S and mu(P, .) of one pair, with no N^4 output (wolf_pairs.hip).
 template <class T> struct ObsSums {
   typename real_of<T>::type* s0;  // raw sums for S, N^2
   T* b0;                          // raw sums for the row W_B[P; .], N^2
   unsigned long long* key;        // order key of max s0
 };
-template <class T> bool obs_supported(int n);
-template <class T> size_t obs_work_bytes(int n);
-template <class T>
-hipError_t launch_obs_sums(int n, const T* src, const OperatorTables& op, int pi, int pj, void* work, ObsSums<T>* out,
-                           hipStream_t st);
-template <class T>
-hipError_t launch_obs_emit(int n, const ObsSums<T>& sums, const OperatorTables& op, double weight, int pi, int pj,
-                           double floor_rel, typename real_of<T>::type* s_out, T* mu_out, hipStream_t st);
-// The same sums for groups of up to kPairGroup Fresnel pairs at once (wolf_pairs.hip): the first-point
-// contractions are shared by the pairs of a group, so the source is read twice per group. a_src[k] is
+// The sums for groups of up to kPairGroup pairs at once: the first-point contractions are shared by the
+// pairs of a group, so the source is read twice per group (once for a group of one). a_src[k] is
 // the source chirp rate pitch^2 / (lambda z) of pair k (0 in the far field); out[k] receives pair k's
 // sums, which live in `work` (pair_work_bytes) until the next call.
 constexpr int kPairGroup = 64;

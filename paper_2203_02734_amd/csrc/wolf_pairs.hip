@@ -469,13 +469,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
 }
 
-// out[k][i] = f(k, i) sum_s part[s][k][i], summed in FP64 in the order of s; f = u2[k][i / n] u2[k][i % n]
-// when u2 is given (the row sums), else 1.
+// out[k][i] = f(k, i) sum_s part[s][k][i] (k < kcount), summed in FP64 in the order of s;
+// f = u2[k][i / n] u2[k][i % n] when u2 is given (the row sums), else 1.
 template <class T>
-__global__ __launch_bounds__(256) void k_pair_sum(const T* __restrict__ part, int parts, int n,
+__global__ __launch_bounds__(256) void k_pair_sum(const T* __restrict__ part, int parts, int n, int kcount,
                                                   const T* __restrict__ u2, T* __restrict__ out) {
   using R = typename real_of<T>::type;
-  const long long nn = (long long)n * n, total = (long long)kPairTile * nn;
+  const long long nn = (long long)n * n, total = (long long)kcount * nn;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   double2 acc{0.0, 0.0};
@@ -925,6 +925,79 @@ __global__ __launch_bounds__(1024) void k_poly_mu(const double* __restrict__ s_a
 }
 
 // ---------------------------------------------------------------------------------------------
+// One set of sums (a group of one entry: the far field, whose sums every pair shares, or a single
+// pair). With one row the two contractions are matrix-vector products, bound by HBM, and both come
+// from one pass over the source. A workgroup takes a range of slabs p1 and a block of columns; each
+// thread keeps kOneCols columns i of both raw sums in registers:
+//   R[i] += ci[a] cj[b] W[p1; i]                                  (k_pair_rows with one row)
+//   D[i] += u1[a] u1[b] u2[a - d_i] u2[b - d_j] W[p1; p1 - d], d = i  (k_pair_diffs; indices mod N)
+// The read of a slab for D finds it in the caches after the read for R.
+// ---------------------------------------------------------------------------------------------
+constexpr int kOneThreads = 256, kOneCols = 8;
+
+template <class T>
+__global__ __launch_bounds__(kOneThreads) void k_one_sums(const T* __restrict__ w, int n, const T* __restrict__ u1,
+                                                         const T* __restrict__ u2, const T* __restrict__ ci,
+                                                         const T* __restrict__ cj, int slabs, T* __restrict__ part_r,
+                                                         T* __restrict__ part_d) {
+  using R = typename real_of<T>::type;
+  __shared__ T su2[256];
+  const int nn = n * n, nm = n - 1, lg = __builtin_ctz((unsigned)n);  // N is a power of two
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += kOneThreads) su2[i] = u2[i];
+  __syncthreads();
+  const int c0 = (int)blockIdx.x * kOneThreads * kOneCols + tid;
+  // Column i = c0 + kOneThreads j is d = (di0 + step j, dj0): kOneThreads is a multiple of N.
+  const int di0 = c0 >> lg, dj0 = c0 & nm, step = kOneThreads >> lg;
+  const int p_lo = (int)blockIdx.y * slabs, p_hi = p_lo + slabs < nn ? p_lo + slabs : nn;
+  const T zero{(R)0, (R)0};
+  T r[kOneCols], d[kOneCols];
+#pragma unroll
+  for (int j = 0; j < kOneCols; ++j) r[j] = d[j] = zero;
+  for (int p1 = p_lo; p1 < p_hi; ++p1) {
+    const int a = p1 >> lg, b = p1 & nm;
+    const T cr = cmul(ci[a], cj[b]), cu = cmul(u1[a], u1[b]);
+    const T* slab = w + (long long)p1 * nn;
+    T x[kOneCols];
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const int i = c0 + kOneThreads * j;
+      x[j] = load_or_first(slab, i < nn, i);
+    }
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const T t = cmul(cr, x[j]);
+      r[j].x += t.x;
+      r[j].y += t.y;
+    }
+    const int b2 = (b - dj0) & nm;
+    const T ub = cmul(cu, su2[b2]);
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const int a2 = (a - di0 - step * j) & nm;
+      x[j] = load_or_first(slab, c0 + kOneThreads * j < nn, a2 * n + b2);
+    }
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const int a2 = (a - di0 - step * j) & nm;
+      const T t = cmul(cmul(ub, su2[a2]), x[j]);
+      d[j].x += t.x;
+      d[j].y += t.y;
+    }
+  }
+  T* orr = part_r + (long long)blockIdx.y * nn;
+  T* odd = part_d + (long long)blockIdx.y * nn;
+#pragma unroll
+  for (int j = 0; j < kOneCols; ++j) {
+    const int i = c0 + kOneThreads * j;
+    if (i < nn) {
+      orr[i] = r[j];
+      odd[i] = d[j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Work layout (per group of kPairTile pairs), in elements of T unless noted.
 // ---------------------------------------------------------------------------------------------
 static int pair_tiles_j(int n) { return (n + 63) / 64; }
@@ -972,6 +1045,28 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
                      u1, u2, ci, cj, tr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (count == 1) {  // one row: both sums in one pass, HBM-bound
+    const int ranges = nn < 256 ? (int)nn : 256;  // slab ranges; partials fit: 64 sb >= 256 or nn
+    const int slabs = (int)((nn + ranges - 1) / ranges);
+    const dim3 grid((unsigned)((nn + kOneThreads * kOneCols - 1) / (kOneThreads * kOneCols)), (unsigned)ranges);
+    hipLaunchKernelGGL(k_one_sums<T>, grid, dim3(kOneThreads), 0, st, w, n, (const T*)u1, (const T*)u2,
+                       (const T*)ci, (const T*)cj, slabs, part_r, part_d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((nn + 255) / 256);
+    hipLaunchKernelGGL(k_pair_sum<T>, dim3(blocks), dim3(256), 0, st, (const T*)part_r, ranges, n, 1, (const T*)u2,
+                       buf_r);
+    hipLaunchKernelGGL(k_pair_sum<T>, dim3(blocks), dim3(256), 0, st, (const T*)part_d, ranges, n, 1,
+                       (const T*)nullptr, buf_d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_d, n, buf_t);
+    hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_t, n, buf_d);
+    hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_r, n, buf_t);
+    hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_t, n, buf_r);
+    hipLaunchKernelGGL(k_pair_s0<T>, dim3(1), dim3(256), 0, st, (const T*)buf_d, n, s0, key);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    out[0] = ObsSums<T>{s0, buf_r, key};
+    return hipSuccess;
+  }
   const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
   const int bchunk = (n + sb - 1) / sb;
   const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK), grid_d((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb);
@@ -988,10 +1083,11 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned sum_blocks = (unsigned)((g + 255) / 256);
-  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n,
+  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n, kPairTile,
                      (const T*)u2, buf_r);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_d, sb, n, (const T*)nullptr,
+  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_d, sb, n, kPairTile,
+                     (const T*)nullptr,
                      buf_d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned rows = (unsigned)(kPairTile * n);
@@ -1094,10 +1190,10 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
-                       kPairSplitK, n, (const T*)u2, rr);
+                       kPairSplitK, n, kPairTile, (const T*)u2, rr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d, sb,
-                       2 * n, (const T*)nullptr, dfull);
+                       2 * n, kPairTile, (const T*)nullptr, dfull);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // S: the + transform of D over [-N, N)^2 (offset N); the row: the - transform of T R (offset N/2).
     hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(kPairTile * 2 * n)), dim3(256), 0, st, (const T*)dfull, n,

@@ -139,8 +139,8 @@ def test_batch_work_bytes(gpu_lib):
 
 @pytest.mark.parametrize("farfield", [False, True])
 def test_batch_n128_complex128_full_propagation(gpu_lib, farfield):
-    """complex128 at N = 128 (where the far-field observables pass does not fit), against the separable
-    oracle."""
+    """complex128 at N = 128 (the vector-FMA contractions; in the far field the one-entry pass), against
+    the separable oracle."""
     wl = WI.gsm128()
     n, p = wl.n, wl.pitch_m
     sp = wl.source
