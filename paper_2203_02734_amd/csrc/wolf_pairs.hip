@@ -958,29 +958,25 @@ __global__ __launch_bounds__(kOneThreads) void k_one_sums(const T* __restrict__ 
     const int a = p1 >> lg, b = p1 & nm;
     const T cr = cmul(ci[a], cj[b]), cu = cmul(u1[a], u1[b]);
     const T* slab = w + (long long)p1 * nn;
-    T x[kOneCols];
+    const int b2 = (b - dj0) & nm;
+    T xr[kOneCols], xd[kOneCols];  // both reads of the slab in flight together
 #pragma unroll
     for (int j = 0; j < kOneCols; ++j) {
       const int i = c0 + kOneThreads * j;
-      x[j] = load_or_first(slab, i < nn, i);
+      xr[j] = load_or_first(slab, i < nn, i);
+      xd[j] = load_or_first(slab, i < nn, ((a - di0 - step * j) & nm) * n + b2);
     }
 #pragma unroll
     for (int j = 0; j < kOneCols; ++j) {
-      const T t = cmul(cr, x[j]);
+      const T t = cmul(cr, xr[j]);
       r[j].x += t.x;
       r[j].y += t.y;
     }
-    const int b2 = (b - dj0) & nm;
     const T ub = cmul(cu, su2[b2]);
 #pragma unroll
     for (int j = 0; j < kOneCols; ++j) {
       const int a2 = (a - di0 - step * j) & nm;
-      x[j] = load_or_first(slab, c0 + kOneThreads * j < nn, a2 * n + b2);
-    }
-#pragma unroll
-    for (int j = 0; j < kOneCols; ++j) {
-      const int a2 = (a - di0 - step * j) & nm;
-      const T t = cmul(cmul(ub, su2[a2]), x[j]);
+      const T t = cmul(cmul(ub, su2[a2]), xd[j]);
       d[j].x += t.x;
       d[j].y += t.y;
     }
