@@ -716,25 +716,27 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
     }
 }
 
-// k_poly_diffs on the matrix cores (complex64; same partial sums and layout), double-buffered like
-// k_pair_diffs_mfma.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_poly_diffs_mfma(const float2* __restrict__ w, int n,
-                                                         const float2* __restrict__ u1, const float2* __restrict__ u2,
-                                                         const float2* __restrict__ u1t,
-                                                         const float2* __restrict__ u2t, int bchunk,
-                                                         float2* __restrict__ part) {
+// k_poly_diffs on the matrix cores (complex64; same partial sums and layout). The unfolded sums are
+// taken in the folded order of k_pair_diffs_mfma, with no wasted rows: for a folded offset
+// (d_i, d_j) in [0, N)^2 the folded sum over a and b splits exactly into the unfolded bins. On the first
+// point, a >= d_i belongs to bin d_i and a < d_i to bin d_i - N (the workgroup's half h takes one of the
+// two a ranges); on the second point, b >= d_j belongs to bin d_j and b < d_j to bin d_j - N. As b rises
+// through the workgroup's chunk, a lane's column d_j switches bin once: the lane stores the lower bin's
+// sum when b passes d_j - 1 and writes each of its two bins exactly once.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_poly_diffs_mfma(
+    const float2* __restrict__ w, int n, const float2* __restrict__ u1, const float2* __restrict__ u2,
+    const float2* __restrict__ u1t, const float2* __restrict__ u2t, int bchunk, float2* __restrict__ part) {
   constexpr int TK = 16;
   __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n, bins = 4 * nn;
   const int tid = threadIdx.x, lane = tid % 64;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
   const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
-  const int di = poly_offset((int)blockIdx.y), dj0 = (int)blockIdx.x * 64 - n;
-  const int a_lo = di > 0 ? di : 0, a_hi = di < 0 ? n + di : n;
-  int b_lo = dj0 > 0 ? dj0 : 0, b_hi = dj0 + 63 + n;
-  if (b_hi > n) b_hi = n;
-  b_lo += (int)blockIdx.z * bchunk;
-  if (b_lo + bchunk < b_hi) b_hi = b_lo + bchunk;
+  const int dj0 = blockIdx.x * 64, nm = n - 1;                 // N is a power of two
+  const int h = (int)blockIdx.y & 1, di = (int)blockIdx.y >> 1;  // h = 0: a >= d_i; h = 1: a < d_i
+  const int a_lo = h ? 0 : di, a_hi = h ? di : n;
+  const int b_lo = blockIdx.z * bchunk, b_hi = (b_lo + bchunk < n) ? b_lo + bchunk : n;
+  float2* out = part + (long long)blockIdx.z * kPairTile * bins + (long long)(h ? di : di + n) * (2 * n) + n;
   float dre[2][2][4], dim[2][2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
@@ -742,38 +744,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
+  // Element q of a thread in a step: a = a0 + wv + 4 q (one per wavefront); column dj = dj0 + lane, or pair lane.
   float2 rb[4], ca[4], cb[4];
-  auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj], a = a0 + wv + 4 q, dj = dj0 + lane
+  auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] (indices mod N) and the tables of A
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = wv + 4 * q, jj = lane;
-      const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
+      const int a = a0 + kk, dj = dj0 + jj;
       const bool ok = a < a_hi;
-      rb[q] = load_or_first(w, ok && dj < n && bq >= 0 && bq < n,
-                            ((long long)a * n + b) * nn + (long long)(a - di) * n + bq);
+      rb[q] = load_or_first(w, ok && dj < n,
+                            ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
       const int ac = ok ? a : a_lo;  // A[kk][k] = u1[k][a] u2[k][a - di]
       ca[q] = u1t[ac * kPairTile + jj];
-      cb[q] = u2t[(ac - di) * kPairTile + jj];
+      cb[q] = u2t[((ac - di) & nm) * kPairTile + jj];
     }
   };
-  auto stage = [&](int buf, int b, int a0) {
+  auto stage = [&](int buf, int a0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = wv + 4 * q, jj = lane;
-      const int dj = dj0 + jj, bq = b - dj;
       const bool ok = a0 + kk < a_hi;
       const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
-      const float2 v = keep_or_zero(ok && dj < n && bq >= 0 && bq < n, rb[q]);
+      const float2 v = keep_or_zero(ok && dj0 + jj < n, rb[q]);
       ar[buf][kk][jj] = a.x;
       ai[buf][kk][jj] = a.y;
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
     }
   };
-  const bool any = b_lo < b_hi && a_lo < a_hi;
+  const bool any = a_lo < a_hi && b_lo < b_hi;
   if (any) {
     fetch(b_lo, a_lo);
-    stage(0, b_lo, a_lo);
+    stage(0, a_lo);
   }
   __syncthreads();
   CTile g;
@@ -784,15 +786,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nb = last_a ? b + 1 : b, na = last_a ? a_lo : a0 + TK;
     const bool more = nb < b_hi;
     if (more) fetch(nb, na);
-    // Column blocks with no dj in (b - N, b] hold no term of this b: skip their products.
-    int cols = 0;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c0 = dj0 + col0 + 16 * q;
-      if (c0 <= b && c0 + 15 > b - n) cols |= 1 << q;
-    }
-    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane, __builtin_amdgcn_readfirstlane(cols));
+    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (last_a) {
+      // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj]; at b = dj - 1 the lower bin d_j - N is complete.
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -801,23 +797,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           const float2 ub = u1[k * n + b];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const int bq = b - (dj0 + col0 + 16 * q + lane % 16);
-            const bool ok = bq >= 0 && bq < n;
-            const float2 f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
+            const int dj = dj0 + col0 + 16 * q + lane % 16;
+            const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
             const float gr = g.re(r, q, i), gi = g.im(r, q, i);
             dre[r][q][i] += f.x * gr - f.y * gi;
             dim[r][q][i] += f.x * gi + f.y * gr;
+            if (b == dj - 1 && dj < b_hi && dj < n) {
+              out[(long long)k * bins + dj - n] = float2{dre[r][q][i], dim[r][q][i]};
+              dre[r][q][i] = dim[r][q][i] = 0.f;
+            }
           }
         }
       ctile_zero(g);
     }
-    if (more) stage(buf ^ 1, nb, na);
+    if (more) stage(buf ^ 1, na);
     __syncthreads();
     buf ^= 1;
     b = nb;
     a0 = na;
   }
-  float2* out = part + (long long)blockIdx.z * kPairTile * bins;
+  // Each lane writes both of its bins once: the sum it holds goes to the bin of the chunk's last b; the
+  // other bin was stored at the switch, or has no term in this chunk.
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -826,7 +826,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       for (int i = 0; i < 4; ++i) {
         const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
         const int dj = dj0 + col0 + 16 * q + lane % 16;
-        if (dj < n) out[k * bins + (long long)(di + n) * (2 * n) + dj + n] = float2{dre[r][q][i], dim[r][q][i]};
+        if (dj >= n) continue;
+        const float2 v{dre[r][q][i], dim[r][q][i]}, z{0.f, 0.f};
+        if (!any || dj >= b_hi) {  // every b of the chunk is below dj (or there is no term at all)
+          out[k * bins + dj - n] = v;
+          out[k * bins + dj] = z;
+        } else {
+          out[k * bins + dj] = v;
+          if (dj <= b_lo) out[k * bins + dj - n] = z;  // no b of the chunk is below dj
+        }
       }
 }
 
@@ -1179,9 +1187,10 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bchunk = (n + sb - 1) / sb;
     const dim3 grid_d((unsigned)poly_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
-    if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
-                         (const T*)(tr + tq), bchunk, part_d);
+    if constexpr (sizeof(T) == 8)  // folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of a)
+      hipLaunchKernelGGL(k_poly_diffs_mfma, dim3((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb),
+                         dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr, (const T*)(tr + tq), bchunk,
+                         part_d);
     else
       hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
