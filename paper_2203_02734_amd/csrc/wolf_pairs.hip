@@ -579,9 +579,6 @@ __global__ __launch_bounds__(256) void k_pair_s0(const T* __restrict__ z, int n,
 // W[P; .] = sum_k w_k W_k[P; .] (R17). The output grid no longer has the period N of the DFT, so the
 // difference sums keep both signs of d: bins d in [-N, N), index d + N.
 // ---------------------------------------------------------------------------------------------
-// Offset d_i of grid row y, heaviest first: 0, -1, 1, -2, 2, ..., -N (a row's work is N - |d_i|).
-__device__ __forceinline__ int poly_offset(int y) { return (y & 1) ? -((y + 1) >> 1) : (y >> 1); }
-
 struct PolyGroup {
   int count;
   double alpha[kPairTile];  // source chirp rate of each pair
@@ -618,8 +615,12 @@ __global__ __launch_bounds__(256) void k_poly_tables(PolyGroup g, int n, int pi,
 }
 
 // Difference sums without wrap: part[z][k][(di + N) 2N + dj + N] = sum_{b} B_k^{dj}[b] sum_a A_k^{di}[a]
-// W[a, b; a - di, b - dj] over a - di, b - dj in [0, N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj].
-// A workgroup owns di, 64 values of dj and a chunk of the b range that reaches its tile.
+// W[a, b; a - di, b - dj] over a - di, b - dj in [0, N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj]. They are
+// taken in the folded order of k_pair_diffs: for a folded offset (di, dj) in [0, N)^2 the folded sum
+// splits exactly into the unfolded bins. On the first point a >= di belongs to bin di and a < di to di - N
+// (the workgroup's half h takes one of the two a ranges); on the second point b >= dj belongs to dj and
+// b < dj to dj - N. As b rises through the chunk a thread's column dj switches bin once: the thread
+// stores the lower bin when b passes dj - 1 and writes each of its two bins exactly once.
 template <class T>
 __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int n, const T* __restrict__ u1,
                                                     const T* __restrict__ u2, int bchunk, T* __restrict__ part) {
@@ -628,20 +629,20 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
   __shared__ T As[TK][TM + 1];
   __shared__ T Bs[TK][TN + 1];
   const long long nn = (long long)n * n, bins = 4 * nn;
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const int di = poly_offset((int)blockIdx.y), dj0 = (int)blockIdx.x * TN - n;
-  const int a_lo = di > 0 ? di : 0, a_hi = di < 0 ? n + di : n;
-  int b_lo = dj0 > 0 ? dj0 : 0, b_hi = dj0 + TN - 1 + n;
-  if (b_hi > n) b_hi = n;
-  b_lo += (int)blockIdx.z * bchunk;
-  if (b_lo + bchunk < b_hi) b_hi = b_lo + bchunk;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16, nm = n - 1;  // N is a power of two
+  const int dj0 = (int)blockIdx.x * TN;
+  const int h = (int)blockIdx.y & 1, di = (int)blockIdx.y >> 1;  // h = 0: a >= di; h = 1: a < di
+  const int a_lo = h ? 0 : di, a_hi = h ? di : n;
+  const int b_lo = (int)blockIdx.z * bchunk, b_hi = b_lo + bchunk < n ? b_lo + bchunk : n;
+  T* out = part + (long long)blockIdx.z * kPairTile * bins + (long long)(h ? di : di + n) * (2 * n) + n;
   const T zero{(R)0, (R)0};
   T dacc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) dacc[r][q] = zero;
-  for (int b = b_lo; b < b_hi; ++b) {
+  const bool any = a_lo < a_hi;
+  for (int b = b_lo; any && b < b_hi; ++b) {
     T g[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -650,12 +651,12 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
     for (int a0 = a_lo; a0 < a_hi; a0 += TK) {
       T rb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {  // Bs[kk][jj] = W[a, b; a - di, b - dj]
+      for (int q = 0; q < 4; ++q) {  // Bs[kk][jj] = W[a, b; a - di, b - dj] (indices mod N)
         const int e = tid + 256 * q;
         const int kk = e / TN, jj = e % TN;
-        const int a = a0 + kk, dj = dj0 + jj, bq = b - dj;
-        const bool ok = a < a_hi && dj < n && bq >= 0 && bq < n;
-        rb[q] = load_or_first(w, ok, ((long long)a * n + b) * nn + (long long)(a - di) * n + bq);
+        const int a = a0 + kk, dj = dj0 + jj;
+        rb[q] = load_or_first(w, a < a_hi && dj < n,
+                              ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {  // As[kk][k] = u1[k][a] u2[k][a - di]
@@ -664,14 +665,13 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
         const int a = a0 + kk;
         const bool ok = a < a_hi;
         const int ac = ok ? a : a_lo;
-        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ac - di]));
+        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ((ac - di) & nm)]));
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = tid + 256 * q;
         const int kk = e / TN, jj = e % TN;
-        const int dj = dj0 + jj, bq = b - dj;
-        Bs[kk][jj] = keep_or_zero(a0 + kk < a_hi && dj < n && bq >= 0 && bq < n, rb[q]);
+        Bs[kk][jj] = keep_or_zero(a0 + kk < a_hi && dj0 + jj < n, rb[q]);
       }
       __syncthreads();
 #pragma unroll
@@ -691,28 +691,39 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
       }
       __syncthreads();
     }
+    // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj]; at b = dj - 1 the lower bin dj - N is complete.
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k = ty + 16 * r;
       const T ub = u1[k * n + b];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int bq = b - (dj0 + tx + 16 * q);
-        const bool ok = bq >= 0 && bq < n;
-        const T f = keep_or_zero(ok, cmul(ub, u2[k * n + (ok ? bq : 0)]));
-        const T t = cmul(f, g[r][q]);
+        const int dj = dj0 + tx + 16 * q;
+        const T t = cmul(cmul(ub, u2[k * n + ((b - dj) & nm)]), g[r][q]);
         dacc[r][q].x += t.x;
         dacc[r][q].y += t.y;
+        if (b == dj - 1 && dj < b_hi && dj < n) {
+          out[(long long)k * bins + dj - n] = dacc[r][q];
+          dacc[r][q] = zero;
+        }
       }
     }
   }
-  T* out = part + (long long)blockIdx.z * kPairTile * bins;
+  // Each thread writes both of its bins once (see k_poly_diffs_mfma).
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      const long long k = ty + 16 * r;
       const int dj = dj0 + tx + 16 * q;
-      if (dj < n) out[(long long)(ty + 16 * r) * bins + (long long)(di + n) * (2 * n) + dj + n] = dacc[r][q];
+      if (dj >= n) continue;
+      if (!any || dj >= b_hi) {
+        out[k * bins + dj - n] = dacc[r][q];
+        out[k * bins + dj] = zero;
+      } else {
+        out[k * bins + dj] = dacc[r][q];
+        if (dj <= b_lo) out[k * bins + dj - n] = zero;
+      }
     }
 }
 
@@ -1127,9 +1138,8 @@ hipError_t launch_pair_emit(int n, const ObsSums<T>& sums, bool shared, int coun
 // Work of the polychromatic sums, per group (elements of T unless noted): tables 8 x 64 N, row-sum
 // partials 16 x 64 N^2, difference-sum partials sb x 64 x 4N^2, D 64 x 4N^2, T R 64 N^2, transform
 // intermediate 64 x 2N^2, the two transformed arrays 64 N^2 each; then S and W[P; .] in FP64 (N^2 each).
-static int poly_tiles_j(int n) { return (2 * n + 63) / 64; }
 static int poly_bsplit(int n) {
-  int sb = 4096 / (poly_tiles_j(n) * 2 * n);  // enough workgroups to even out rows of unequal work
+  int sb = 4096 / ((2 * n + 63) / 64 * 2 * n);  // chunks of b: enough workgroups to even out unequal a ranges
   if (sb < 4) sb = 4;
   if (sb > n) sb = n;
   return sb;
@@ -1186,11 +1196,11 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bchunk = (n + sb - 1) / sb;
-    const dim3 grid_d((unsigned)poly_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
-    if constexpr (sizeof(T) == 8)  // folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of a)
-      hipLaunchKernelGGL(k_poly_diffs_mfma, dim3((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb),
-                         dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr, (const T*)(tr + tq), bchunk,
-                         part_d);
+    // Folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks).
+    const dim3 grid_d((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
+    if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
+                         (const T*)(tr + tq), bchunk, part_d);
     else
       hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
