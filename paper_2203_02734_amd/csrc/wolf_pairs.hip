@@ -297,9 +297,9 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], 
 // k_pair_rows on the matrix cores (same partial sums and layout). The operands of step s + 1 are
 // loaded from HBM while the matrix cores work on step s, and staged into the second LDS buffer after
 // it: one barrier per step.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rows_mfma(const float2* __restrict__ w, int n,
-                                                        const float2* __restrict__ cit, const float2* __restrict__ cjt,
-                                                        long long chunk, float2* __restrict__ part) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rows_mfma(
+    const float2* __restrict__ w, int n, const float2* __restrict__ cit, const float2* __restrict__ cjt, long long chunk,
+    float2* __restrict__ part) {
   constexpr int TK = 16;
   __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n;
@@ -369,11 +369,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // k_pair_diffs on the matrix cores (same partial sums and layout). The steps (b, a0) run in one
 // sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b the wavefront block
 // folds its G tile into D.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_diffs_mfma(const float2* __restrict__ w, int n,
-                                                         const float2* __restrict__ u1, const float2* __restrict__ u2,
-                                                         const float2* __restrict__ u1t,
-                                                         const float2* __restrict__ u2t, int bchunk,
-                                                         float2* __restrict__ part) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_diffs_mfma(
+    const float2* __restrict__ w, int n, const float2* __restrict__ u1, const float2* __restrict__ u2,
+    const float2* __restrict__ u1t, const float2* __restrict__ u2t, int bchunk, float2* __restrict__ part) {
   constexpr int TK = 16;
   __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
   const long long nn = (long long)n * n;
