@@ -19,6 +19,7 @@ namespace wolf {
 
 constexpr int kPairTile = kPairGroup;  // pairs per group (rows of the GEMM tiles)
 constexpr int kPairSplitK = 16;  // chunks of p1 in the row sums R (partials summed in FP64)
+constexpr int kOneThreads = 256, kOneCols = 8;  // the one-pass sums of a group of one entry
 
 struct PairGroup {
   int count;                 // pairs in this group (<= kPairTile)
@@ -847,6 +848,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
 }
 
+// The polychromatic sums of a group of one pair in one pass over the source, as k_one_sums: R as there,
+// and the unfolded difference sums D[d], d in [-N, N)^2. The element W[p1; p1 - d] of a thread's folded
+// column d = (d_i, d_j) belongs to the unfolded bin (a >= d_i ? d_i : d_i - N, b >= d_j ? d_j : d_j - N);
+// each thread keeps the four bins of each of its columns. part_d[y][(d_i + N) 2N + d_j + N].
+template <class T>
+__global__ __launch_bounds__(kOneThreads) void k_one_poly_sums(const T* __restrict__ w, int n,
+                                                              const T* __restrict__ u1, const T* __restrict__ u2,
+                                                              const T* __restrict__ ci, const T* __restrict__ cj,
+                                                              int slabs, T* __restrict__ part_r,
+                                                              T* __restrict__ part_d) {
+  using R = typename real_of<T>::type;
+  __shared__ T su2[256];
+  const int nn = n * n, nm = n - 1, lg = __builtin_ctz((unsigned)n);  // N is a power of two
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += kOneThreads) su2[i] = u2[i];
+  __syncthreads();
+  const int c0 = (int)blockIdx.x * kOneThreads * kOneCols + tid;
+  const int di0 = c0 >> lg, dj0 = c0 & nm, step = kOneThreads >> lg;
+  const int p_lo = (int)blockIdx.y * slabs, p_hi = p_lo + slabs < nn ? p_lo + slabs : nn;
+  const T zero{(R)0, (R)0};
+  T r[kOneCols], d[4][kOneCols];  // d[2 (a < d_i) + (b < d_j)][j]
+#pragma unroll
+  for (int j = 0; j < kOneCols; ++j) r[j] = d[0][j] = d[1][j] = d[2][j] = d[3][j] = zero;
+  for (int p1 = p_lo; p1 < p_hi; ++p1) {
+    const int a = p1 >> lg, b = p1 & nm;
+    const T cr = cmul(ci[a], cj[b]), cu = cmul(u1[a], u1[b]);
+    const T* slab = w + (long long)p1 * nn;
+    const int b2 = (b - dj0) & nm;
+    T xr[kOneCols], xd[kOneCols];
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const int i = c0 + kOneThreads * j;
+      xr[j] = load_or_first(slab, i < nn, i);
+      xd[j] = load_or_first(slab, i < nn, ((a - di0 - step * j) & nm) * n + b2);
+    }
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const T t = cmul(cr, xr[j]);
+      r[j].x += t.x;
+      r[j].y += t.y;
+    }
+    const T ub = cmul(cu, su2[b2]);
+    const int lb = b < dj0 ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < kOneCols; ++j) {
+      const int a2 = (a - di0 - step * j) & nm;
+      const T t = cmul(cmul(ub, su2[a2]), xd[j]);
+      const int qd = (a < di0 + step * j ? 2 : 0) + lb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[q][j].x += q == qd ? t.x : (R)0;
+        d[q][j].y += q == qd ? t.y : (R)0;
+      }
+    }
+  }
+  T* orr = part_r + (long long)blockIdx.y * nn;
+  T* odd = part_d + (long long)blockIdx.y * 4 * nn;
+#pragma unroll
+  for (int j = 0; j < kOneCols; ++j) {
+    const int i = c0 + kOneThreads * j;
+    if (i >= nn) continue;
+    orr[i] = r[j];
+    const int di = di0 + step * j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int du = (q & 2) ? di - n : di, ju = (q & 1) ? dj0 - n : dj0;
+      odd[(long long)(du + n) * (2 * n) + ju + n] = d[q][j];
+    }
+  }
+}
+
 // One axis of a chirp-z transform of every pair's array, stored transposed:
 // out[k][m][i] = sum_{p < len} e^{SIGN 2 pi i beta_k (m - c)(p - off)} in[k][i][p], m < N, i < rows. The
 // factors come from an FP64 recurrence along p (one FP64 product per term); sums in FP64.
@@ -950,8 +1022,6 @@ __global__ __launch_bounds__(1024) void k_poly_mu(const double* __restrict__ s_a
 //   D[i] += u1[a] u1[b] u2[a - d_i] u2[b - d_j] W[p1; p1 - d], d = i  (k_pair_diffs; indices mod N)
 // The read of a slab for D finds it in the caches after the read for R.
 // ---------------------------------------------------------------------------------------------
-constexpr int kOneThreads = 256, kOneCols = 8;
-
 template <class T>
 __global__ __launch_bounds__(kOneThreads) void k_one_sums(const T* __restrict__ w, int n, const T* __restrict__ u1,
                                                          const T* __restrict__ u2, const T* __restrict__ ci,
@@ -1103,7 +1173,7 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
                      (const T*)nullptr,
                      buf_d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const unsigned rows = (unsigned)(kPairTile * n);
+  const unsigned rows = (unsigned)(count * n);  // the group's pairs only
   // s0 = Re F D F^T with the + sign; b0 = F* (u2 R) F*^T.
   hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_d, n, buf_t);
   hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_d);
@@ -1185,37 +1255,53 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
     hipLaunchKernelGGL(k_poly_tables<T>, dim3((unsigned)((kPairTile * n + 255) / 256)), dim3(256), 0, st, pg, n, pi,
                        pj, u1, u2, ci, cj, tr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
-    const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK);
-    if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)(tr + 2 * tq),
-                         (const T*)(tr + 3 * tq), chunk, part_r);
-    else
-      hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int bchunk = (n + sb - 1) / sb;
-    // Folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks).
-    const dim3 grid_d((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
-    if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
-                         (const T*)(tr + tq), bchunk, part_d);
-    else
-      hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
-                       kPairSplitK, n, kPairTile, (const T*)u2, rr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d, sb,
-                       2 * n, kPairTile, (const T*)nullptr, dfull);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // S: the + transform of D over [-N, N)^2 (offset N); the row: the - transform of T R (offset N/2).
-    hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(kPairTile * 2 * n)), dim3(256), 0, st, (const T*)dfull, n,
+    if (pg.count == 1) {  // one pair: both sums in one pass, HBM-bound
+      const int ranges = nn < 256 ? (int)nn : 256;  // slab ranges; partials fit: 64 sb >= 256 or nn
+      const int slabs = (int)((nn + ranges - 1) / ranges);
+      const dim3 grid((unsigned)((nn + kOneThreads * kOneCols - 1) / (kOneThreads * kOneCols)), (unsigned)ranges);
+      hipLaunchKernelGGL(k_one_poly_sums<T>, grid, dim3(kOneThreads), 0, st, w, n, (const T*)u1, (const T*)u2,
+                         (const T*)ci, (const T*)cj, slabs, part_r, part_d);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const unsigned blocks = (unsigned)((nn + 255) / 256);
+      hipLaunchKernelGGL(k_pair_sum<T>, dim3(blocks), dim3(256), 0, st, (const T*)part_r, ranges, n, 1,
+                         (const T*)u2, rr);
+      hipLaunchKernelGGL(k_pair_sum<T>, dim3(4 * blocks), dim3(256), 0, st, (const T*)part_d, ranges, 2 * n, 1,
+                         (const T*)nullptr, dfull);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+      const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
+      const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK);
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)(tr + 2 * tq),
+                           (const T*)(tr + 3 * tq), chunk, part_r);
+      else
+        hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const int bchunk = (n + sb - 1) / sb;
+      // Folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks).
+      const dim3 grid_d((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
+                           (const T*)(tr + tq), bchunk, part_d);
+      else
+        hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
+                         kPairSplitK, n, kPairTile, (const T*)u2, rr);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d, sb,
+                         2 * n, kPairTile, (const T*)nullptr, dfull);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // S: the + transform of D over [-N, N)^2 (offset N); the row: the - transform of T R (offset N/2). Only
+    // the group's pairs are transformed.
+    hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(pg.count * 2 * n)), dim3(256), 0, st, (const T*)dfull, n,
                        2 * n, 2 * n, n, pg, tmp);
-    hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(kPairTile * n)), dim3(256), 0, st, (const T*)tmp, n, n,
+    hipLaunchKernelGGL((k_poly_czt<T, +1>), dim3((unsigned)(pg.count * n)), dim3(256), 0, st, (const T*)tmp, n, n,
                        2 * n, n, pg, zd);
-    hipLaunchKernelGGL((k_poly_czt<T, -1>), dim3((unsigned)(kPairTile * n)), dim3(256), 0, st, (const T*)rr, n, n, n,
+    hipLaunchKernelGGL((k_poly_czt<T, -1>), dim3((unsigned)(pg.count * n)), dim3(256), 0, st, (const T*)rr, n, n, n,
                        n / 2, pg, tmp);
-    hipLaunchKernelGGL((k_poly_czt<T, -1>), dim3((unsigned)(kPairTile * n)), dim3(256), 0, st, (const T*)tmp, n, n, n,
+    hipLaunchKernelGGL((k_poly_czt<T, -1>), dim3((unsigned)(pg.count * n)), dim3(256), 0, st, (const T*)tmp, n, n, n,
                        n / 2, pg, zr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_poly_combine<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const T*)zd,

@@ -46,6 +46,24 @@ def test_polychromatic_vs_oracle(gpu_lib, n, dtype, farfield):
     assert rel(host(mu), mur) < TOL[dtype] / math.sqrt(floor)
 
 
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("n", [2, 8, 32])
+def test_polychromatic_single_pair_vs_oracle(gpu_lib, n, dtype, farfield):
+    """One pair (the one-pass sums of a group of one) on a grid that is not its FFT grid, random Hermitian
+    source, probe off-centre."""
+    p = 20e-6
+    w = WI.random_hermitian_psd(n, seed=80 + n)
+    dxp = 1.17 * O.output_pitch(n, p, 560e-9, 0.07)
+    ip, jp = n // 2 - 1, n - 1
+    floor = 1e-4 if dtype == torch.complex64 else 1e-8
+    s, mu = gpu_lib.propagate_polychromatic(torch.from_numpy(w).to(dtype).cuda(), p, [560e-9], [0.07], [0.8], dxp,
+                                            farfield=farfield, ip=ip, jp=jp, floor_rel=floor)
+    sr, mur = O.polychromatic(w, n, p, [560e-9], [0.07], [0.8], dxp, farfield, ip=ip, jp=jp, floor_rel=floor)
+    assert rel(host(s), sr) < TOL[dtype]
+    assert rel(host(mu), mur) < TOL[dtype] / math.sqrt(floor)
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 def test_polychromatic_two_groups_vs_oracle(gpu_lib, dtype):
     """70 pairs (a group of 64, then 6 whose sums add to the first group's in FP64), random Hermitian
