@@ -232,15 +232,23 @@ __global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int
 
 // ---------------------------------------------------------------------------------------------
 // complex64: the two contractions on the matrix cores (v_mfma_f32_16x16x4f32, 2x the FP32 vector
-// rate without packed math). A workgroup's 64 x 64 complex tile is four 32 x 32 wavefront blocks of
-// 2 x 2 MFMA tiles. A complex product takes three real ones (the 3M form): T1 = Ar Br, T2 = Ai Bi and
-// T3 = (Ar + Ai)(Br + Bi) are accumulated apart, then re = T1 - T2 and im = T3 - T1 - T2. Operands are
-// staged in LDS as separate re / im planes [16][kLdm]: lane l of a 16 x 16 x 4 step reads
-// A[k 4 + l / 16][row l % 16] and B[k 4 + l / 16][col l % 16], and holds D[4 (l / 16) + i][l % 16];
-// with the row stride of 80 floats the four k rows of a step fall on distinct banks.
+// rate without packed math). A workgroup's TM x TN complex tile (TM pairs: 64 x 64, or 32 x 128 for a
+// group of at most 32 pairs) is four 32 x 32 wavefront blocks of 2 x 2 MFMA tiles. A complex product
+// takes three real ones (the 3M form): T1 = Ar Br, T2 = Ai Bi and T3 = (Ar + Ai)(Br + Bi) are accumulated
+// apart, then re = T1 - T2 and im = T3 - T1 - T2. Operands are staged in LDS as separate re / im planes
+// [16][width + 16]: lane l of a 16 x 16 x 4 step reads A[k 4 + l / 16][row l % 16] and
+// B[k 4 + l / 16][col l % 16], and holds D[4 (l / 16) + i][l % 16]; with a row stride of 16 mod 64 floats
+// (or 48) the four k rows of a step fall on distinct banks.
 // ---------------------------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int kLdm = 80;
+
+template <int TM> struct MTile {
+  static_assert(TM == 64 || TM == 32, "tile height");
+  static constexpr int TN = 4096 / TM;                 // columns of the workgroup tile
+  static constexpr int WC = TN / 32;                   // wavefront blocks along the columns
+  static constexpr int LDA = TM + 16, LDB = TN + 16;   // LDS row strides of the A and B planes
+  static constexpr int QA = TM * 16 / 256, QB = TN * 16 / 256;  // staged elements per thread and step
+};
 
 struct CTile {
   v4f t1[2][2], t2[2][2], t3[2][2];
@@ -263,8 +271,9 @@ __device__ __forceinline__ void ctile_zero(CTile& c) {
 
 // c += A B over the 16 staged values of the contraction index, for the wavefront block at (row0, col0).
 // Bit q of `cols` (wavefront-uniform) enables the 16 columns col0 + 16 q; a disabled block is left as is.
-__device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], const float (*ai)[kLdm],
-                                             const float (*br)[kLdm], const float (*bi)[kLdm], int row0, int col0,
+template <int LDA, int LDB>
+__device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[LDA], const float (*ai)[LDA],
+                                             const float (*br)[LDB], const float (*bi)[LDB], int row0, int col0,
                                              int lane, int cols = 3) {
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
@@ -295,49 +304,72 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[kLdm], 
   }
 }
 
-// k_pair_rows on the matrix cores (same partial sums and layout). The operands of step s + 1 are
-// loaded from HBM while the matrix cores work on step s, and staged into the second LDS buffer after
-// it: one barrier per step.
+// Staged element q of thread tid in one step of 16 contraction rows kk: the B operand (TN columns) and
+// the A operand (TM pairs). For TM = 64 the row of both is one per wavefront (wavefront-uniform, so its
+// index math runs on the scalar unit); for TM = 32 the B row is, and the A row is per lane.
+template <int TM> struct MStage {
+  static constexpr int TN = MTile<TM>::TN;
+  __device__ __forceinline__ static int b_row(int wv, int q) { return (wv * 64) / TN + (256 / TN) * q; }
+  __device__ __forceinline__ static int b_col(int wv, int lane) { return (wv * 64) % TN + lane; }
+  __device__ __forceinline__ static int a_row(int tid, int wv, int q) {
+    if constexpr (TM == 64) return wv + 4 * q;
+    else return (tid + 256 * q) / TM;
+  }
+  __device__ __forceinline__ static int a_pair(int tid, int lane) {
+    if constexpr (TM == 64) return lane;
+    else return tid % TM;
+  }
+};
+
+// k_pair_rows on the matrix cores (same partial sums and layout) for the first TM pairs. The operands of
+// step s + 1 are loaded from HBM while the matrix cores work on step s, and staged into the second LDS
+// buffer after it: one barrier per step.
+template <int TM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rows_mfma(
     const float2* __restrict__ w, int n, const float2* __restrict__ cit, const float2* __restrict__ cjt, long long chunk,
     float2* __restrict__ part) {
-  constexpr int TK = 16;
-  __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
+  using G = MTile<TM>;
+  using M = MStage<TM>;
+  constexpr int TK = 16, TN = G::TN;
+  __shared__ float ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lane = tid % 64;
-  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
-  const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
-  const long long j0 = (long long)blockIdx.x * 64;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
+  const int row0 = (wv / G::WC) * 32, col0 = (wv % G::WC) * 32;
+  const long long j0 = (long long)blockIdx.x * TN;
   const long long s = blockIdx.y;
   const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
   const int lg = __builtin_ctz((unsigned)n);
-  // Element q of a thread in a step: contraction row kk = wv + 4 q (one per wavefront), and column (or
-  // pair) jj = lane.
-  float2 rb[4], ca[4], cb[4];
+  float2 rb[G::QB], ca[G::QA], cb[G::QA];
   auto fetch = [&](long long k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = wv + 4 * q, jj = lane;
-      const long long p1 = k0 + kk, p2 = j0 + jj;
-      const bool ok = p1 < p_end;
-      rb[q] = load_or_first(w, ok && p2 < nn, p1 * nn + p2);
-      const int pi = ok ? (int)p1 : 0;  // p1 < N^2, N a power of two
-      const int a = pi >> lg, b = pi & (n - 1);
-      ca[q] = cit[a * kPairTile + jj];
-      cb[q] = cjt[b * kPairTile + jj];
+    for (int q = 0; q < G::QB; ++q) {  // W[p1][p2], p1 = k0 + row, p2 = j0 + column
+      const long long p1 = k0 + M::b_row(wv, q), p2 = j0 + M::b_col(wv, lane);
+      rb[q] = load_or_first(w, p1 < p_end && p2 < nn, p1 * nn + p2);
+    }
+#pragma unroll
+    for (int q = 0; q < G::QA; ++q) {  // A[kk][k] = ci[k][a] cj[k][b], p1 = k0 + kk = a N + b
+      const long long p1 = k0 + M::a_row(tid, wv, q);
+      const int k = M::a_pair(tid, lane);
+      const int pi = p1 < p_end ? (int)p1 : 0;  // p1 < N^2, N a power of two
+      ca[q] = cit[(pi >> lg) * kPairTile + k];
+      cb[q] = cjt[(pi & (n - 1)) * kPairTile + k];
     }
   };
   auto stage = [&](int buf, long long k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = wv + 4 * q, jj = lane;
-      const bool ok = k0 + kk < p_end;
-      const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
-      const float2 v = keep_or_zero(ok && j0 + jj < nn, rb[q]);
-      ar[buf][kk][jj] = a.x;
-      ai[buf][kk][jj] = a.y;
+    for (int q = 0; q < G::QB; ++q) {
+      const int kk = M::b_row(wv, q), jj = M::b_col(wv, lane);
+      const float2 v = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < G::QA; ++q) {
+      const int kk = M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
+      const float2 a = keep_or_zero(k0 + kk < p_end, cmul(ca[q], cb[q]));
+      ar[buf][kk][k] = a.x;
+      ai[buf][kk][k] = a.y;
     }
   };
   CTile acc;
@@ -349,7 +381,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
     const bool more = k0 + TK < p_end;
     if (more) fetch(k0 + TK);
-    ctile_mfma16(acc, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    ctile_mfma16<G::LDA, G::LDB>(acc, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (more) stage(buf ^ 1, k0 + TK);
     __syncthreads();
     buf ^= 1;
@@ -367,19 +399,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
 }
 
-// k_pair_diffs on the matrix cores (same partial sums and layout). The steps (b, a0) run in one
-// sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b the wavefront block
-// folds its G tile into D.
+// k_pair_diffs on the matrix cores (same partial sums and layout) for the first TM pairs. The steps
+// (b, a0) run in one sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b the
+// wavefront block folds its G tile into D.
+template <int TM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_diffs_mfma(
     const float2* __restrict__ w, int n, const float2* __restrict__ u1, const float2* __restrict__ u2,
     const float2* __restrict__ u1t, const float2* __restrict__ u2t, int bchunk, float2* __restrict__ part) {
+  using G = MTile<TM>;
+  using M = MStage<TM>;
   constexpr int TK = 16;
-  __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
+  __shared__ float ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lane = tid % 64;
-  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
-  const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
-  const int dj0 = blockIdx.x * 64, di = blockIdx.y, nm = n - 1;  // N is a power of two
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
+  const int row0 = (wv / G::WC) * 32, col0 = (wv % G::WC) * 32;
+  const int dj0 = blockIdx.x * G::TN, di = blockIdx.y, nm = n - 1;  // N is a power of two
   const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
   float dre[2][2][4], dim[2][2][4];
 #pragma unroll
@@ -388,32 +423,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  // Element q of a thread in a step: a = a0 + wv + 4 q (one per wavefront); column dj = dj0 + lane, or pair lane.
-  float2 rb[4], ca[4], cb[4];
+  float2 rb[G::QB], ca[G::QA], cb[G::QA];
   auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] and the tables of A = u1[a] u2[a - di]
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = wv + 4 * q, jj = lane;
-      const int a = a0 + kk, dj = dj0 + jj;
-      const bool ok = a < n;
-      rb[q] = load_or_first(w, ok && dj < n,
+    for (int q = 0; q < G::QB; ++q) {
+      const int a = a0 + M::b_row(wv, q), dj = dj0 + M::b_col(wv, lane);
+      rb[q] = load_or_first(w, a < n && dj < n,
                             ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
-      const int ac = ok ? a : 0;
-      ca[q] = u1t[ac * kPairTile + jj];
-      cb[q] = u2t[((ac - di) & nm) * kPairTile + jj];
+    }
+#pragma unroll
+    for (int q = 0; q < G::QA; ++q) {
+      const int a = a0 + M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
+      const int ac = a < n ? a : 0;
+      ca[q] = u1t[ac * kPairTile + k];
+      cb[q] = u2t[((ac - di) & nm) * kPairTile + k];
     }
   };
   auto stage = [&](int buf, int a0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = wv + 4 * q, jj = lane;
-      const bool ok = a0 + kk < n;
-      const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
-      const float2 v = keep_or_zero(ok && dj0 + jj < n, rb[q]);
-      ar[buf][kk][jj] = a.x;
-      ai[buf][kk][jj] = a.y;
+    for (int q = 0; q < G::QB; ++q) {
+      const int kk = M::b_row(wv, q), jj = M::b_col(wv, lane);
+      const float2 v = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < G::QA; ++q) {
+      const int kk = M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
+      const float2 a = keep_or_zero(a0 + kk < n, cmul(ca[q], cb[q]));
+      ar[buf][kk][k] = a.x;
+      ai[buf][kk][k] = a.y;
     }
   };
   if (b_begin < b_end) {
@@ -429,7 +468,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nb = last_a ? b + 1 : b, na = last_a ? 0 : a0 + TK;
     const bool more = nb < b_end;
     if (more) fetch(nb, na);
-    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    ctile_mfma16<G::LDA, G::LDB>(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (last_a) {
       // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj], on the outputs this lane holds
 #pragma unroll
@@ -732,17 +771,20 @@ __global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int
 // point, a >= d_i belongs to bin d_i and a < d_i to bin d_i - N (the workgroup's half h takes one of the
 // two a ranges); on the second point, b >= d_j belongs to bin d_j and b < d_j to bin d_j - N. As b rises
 // through the workgroup's chunk, a lane's column d_j switches bin once: the lane stores the lower bin's
-// sum when b passes d_j - 1 and writes each of its two bins exactly once.
+// sum when b passes d_j - 1 and writes each of its two bins exactly once. For the first TM pairs.
+template <int TM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_poly_diffs_mfma(
     const float2* __restrict__ w, int n, const float2* __restrict__ u1, const float2* __restrict__ u2,
     const float2* __restrict__ u1t, const float2* __restrict__ u2t, int bchunk, float2* __restrict__ part) {
+  using G = MTile<TM>;
+  using M = MStage<TM>;
   constexpr int TK = 16;
-  __shared__ float ar[2][TK][kLdm], ai[2][TK][kLdm], br[2][TK][kLdm], bi[2][TK][kLdm];
+  __shared__ float ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
   const long long nn = (long long)n * n, bins = 4 * nn;
   const int tid = threadIdx.x, lane = tid % 64;
-  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform: index math on the scalar unit
-  const int row0 = (wv / 2) * 32, col0 = (wv % 2) * 32;
-  const int dj0 = blockIdx.x * 64, nm = n - 1;                 // N is a power of two
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
+  const int row0 = (wv / G::WC) * 32, col0 = (wv % G::WC) * 32;
+  const int dj0 = blockIdx.x * G::TN, nm = n - 1;             // N is a power of two
   const int h = (int)blockIdx.y & 1, di = (int)blockIdx.y >> 1;  // h = 0: a >= d_i; h = 1: a < d_i
   const int a_lo = h ? 0 : di, a_hi = h ? di : n;
   const int b_lo = blockIdx.z * bchunk, b_hi = (b_lo + bchunk < n) ? b_lo + bchunk : n;
@@ -754,32 +796,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  // Element q of a thread in a step: a = a0 + wv + 4 q (one per wavefront); column dj = dj0 + lane, or pair lane.
-  float2 rb[4], ca[4], cb[4];
+  float2 rb[G::QB], ca[G::QA], cb[G::QA];
   auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] (indices mod N) and the tables of A
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = wv + 4 * q, jj = lane;
-      const int a = a0 + kk, dj = dj0 + jj;
-      const bool ok = a < a_hi;
-      rb[q] = load_or_first(w, ok && dj < n,
+    for (int q = 0; q < G::QB; ++q) {
+      const int a = a0 + M::b_row(wv, q), dj = dj0 + M::b_col(wv, lane);
+      rb[q] = load_or_first(w, a < a_hi && dj < n,
                             ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
-      const int ac = ok ? a : a_lo;  // A[kk][k] = u1[k][a] u2[k][a - di]
-      ca[q] = u1t[ac * kPairTile + jj];
-      cb[q] = u2t[((ac - di) & nm) * kPairTile + jj];
+    }
+#pragma unroll
+    for (int q = 0; q < G::QA; ++q) {  // A[kk][k] = u1[k][a] u2[k][a - di]
+      const int a = a0 + M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
+      const int ac = a < a_hi ? a : a_lo;
+      ca[q] = u1t[ac * kPairTile + k];
+      cb[q] = u2t[((ac - di) & nm) * kPairTile + k];
     }
   };
   auto stage = [&](int buf, int a0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = wv + 4 * q, jj = lane;
-      const bool ok = a0 + kk < a_hi;
-      const float2 a = keep_or_zero(ok, cmul(ca[q], cb[q]));
-      const float2 v = keep_or_zero(ok && dj0 + jj < n, rb[q]);
-      ar[buf][kk][jj] = a.x;
-      ai[buf][kk][jj] = a.y;
+    for (int q = 0; q < G::QB; ++q) {
+      const int kk = M::b_row(wv, q), jj = M::b_col(wv, lane);
+      const float2 v = keep_or_zero(a0 + kk < a_hi && dj0 + jj < n, rb[q]);
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < G::QA; ++q) {
+      const int kk = M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
+      const float2 a = keep_or_zero(a0 + kk < a_hi, cmul(ca[q], cb[q]));
+      ar[buf][kk][k] = a.x;
+      ai[buf][kk][k] = a.y;
     }
   };
   const bool any = a_lo < a_hi && b_lo < b_hi;
@@ -796,7 +842,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nb = last_a ? b + 1 : b, na = last_a ? a_lo : a0 + TK;
     const bool more = nb < b_hi;
     if (more) fetch(nb, na);
-    ctile_mfma16(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    ctile_mfma16<G::LDA, G::LDB>(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (last_a) {
       // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj]; at b = dj - 1 the lower bin d_j - N is complete.
 #pragma unroll
@@ -1091,6 +1137,34 @@ static int pair_bsplit(int n) {
   return sb;
 }
 
+// The matrix-core contractions of one group (complex64): tiles of 32 pairs x 128 columns when the
+// group has at most 32 pairs, else 64 x 64. kind 0: row sums; 1: Fresnel difference sums; 2: the
+// polychromatic (unfolded) difference sums. The tables tr are [4][N][kPairTile] (u1, u2, ci, cj).
+template <int TM>
+static hipError_t launch_mfma_tm(int kind, int n, const float2* w, const float2* u1, const float2* u2,
+                                 const float2* tr, long long chunk, int bchunk, int sb, float2* part,
+                                 hipStream_t st) {
+  constexpr int TN = MTile<TM>::TN;
+  const long long nn = (long long)n * n, tq = (long long)kPairTile * n;
+  const unsigned tiles_j = (unsigned)((n + TN - 1) / TN);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_pair_rows_mfma<TM>, dim3((unsigned)((nn + TN - 1) / TN), kPairSplitK), dim3(256), 0, st, w, n,
+                       tr + 2 * tq, tr + 3 * tq, chunk, part);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_pair_diffs_mfma<TM>, dim3(tiles_j, (unsigned)n, (unsigned)sb), dim3(256), 0, st, w, n, u1, u2,
+                       tr, tr + tq, bchunk, part);
+  else  // folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks)
+    hipLaunchKernelGGL(k_poly_diffs_mfma<TM>, dim3(tiles_j, (unsigned)(2 * n), (unsigned)sb), dim3(256), 0, st, w, n,
+                       u1, u2, tr, tr + tq, bchunk, part);
+  return hipGetLastError();
+}
+
+static hipError_t launch_mfma(int count, int kind, int n, const float2* w, const float2* u1, const float2* u2,
+                              const float2* tr, long long chunk, int bchunk, int sb, float2* part, hipStream_t st) {
+  return count <= 32 ? launch_mfma_tm<32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st)
+                     : launch_mfma_tm<64>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
+}
+
 template <class T> size_t pair_work_bytes(int n) {
   using R = typename real_of<T>::type;
   const size_t nn = (size_t)n * n, g = (size_t)kPairTile * nn;
@@ -1154,11 +1228,8 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   const int bchunk = (n + sb - 1) / sb;
   const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK), grid_d((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb);
   if constexpr (sizeof(T) == 8) {  // complex64: matrix cores
-    hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)(tr + 2 * tq),
-                       (const T*)(tr + 3 * tq), chunk, part_r);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
-                       (const T*)(tr + tq), bchunk, part_d);
+    if ((e = launch_mfma(count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
+    e = launch_mfma(count, 1, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st);
   } else {
     hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1270,22 +1341,19 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
       const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
-      const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK);
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_pair_rows_mfma, grid_r, dim3(256), 0, st, w, n, (const T*)(tr + 2 * tq),
-                           (const T*)(tr + 3 * tq), chunk, part_r);
-      else
-        hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
       const int bchunk = (n + sb - 1) / sb;
-      // Folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks).
-      const dim3 grid_d((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb);
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_poly_diffs_mfma, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, (const T*)tr,
-                           (const T*)(tr + tq), bchunk, part_d);
-      else
-        hipLaunchKernelGGL(k_poly_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if constexpr (sizeof(T) == 8) {  // complex64: matrix cores
+        if ((e = launch_mfma(pg.count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
+        if ((e = launch_mfma(pg.count, 2, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st)) != hipSuccess) return e;
+      } else {
+        hipLaunchKernelGGL(k_pair_rows<T>, dim3((unsigned)((nn + 63) / 64), kPairSplitK), dim3(256), 0, st, w, n,
+                           (const T*)ci, (const T*)cj, chunk, part_r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // Folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks).
+        hipLaunchKernelGGL(k_poly_diffs<T>, dim3((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb),
+                           dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
       hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
                          kPairSplitK, n, kPairTile, (const T*)u2, rr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
