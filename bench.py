@@ -263,6 +263,10 @@ def extras(wolf, wl, args):
     timg = time_op(lambda: wolf.image_through_lens(o, p, lam, 0.4, 0.2, 0.4, wolf.GEO_CIRCLE, 0.3 * n * pb, out=o))
     out["c64_imaging_ms"] = round(timg, 4)
     out["c64_imaging_achieved_GBps"] = round(2 * 32.0 * elems / (timg * 1e-3) / 1e9, 1)
+    # The full N^4 degree of coherence (Algorithm 5 at every P1): one read of W and one write of mu.
+    tmu = time_op(lambda: wolf.degree_of_coherence(w, -1, -1, 1e-12, out=o))
+    out["c64_mu_full_ms"] = round(tmu, 4)
+    out["c64_mu_full_GBps"] = round(16.0 * elems / (tmu * 1e-3) / 1e9, 1)
     # Copy ceiling: read + write of the same 2 GiB array.
     tcp = time_op(lambda: o.copy_(w))
     out["copy_ceiling_GBps"] = round(2 * w.numel() * 8 / (tcp * 1e-3) / 1e9, 1)
