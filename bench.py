@@ -351,6 +351,21 @@ def batch_and_fit(wolf, args):
     del pwork
     del w0, work
     torch.cuda.empty_cache()
+    # The same 64-pair Fresnel batch in complex128 (vector-FMA contractions).
+    w0 = wolf.build_source(wl.source, n, p, torch.complex128)
+    work = torch.empty(wolf.batch_work_bytes(n, torch.complex128), dtype=torch.uint8, device="cuda")
+    run = lambda: wolf.propagate_batch(w0, p, pairs["wavelength"], pairs["z"], pairs["weight"], ip=wl.probe[0],
+                                       jp=wl.probe[1], work=work)
+    run()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    run()
+    b.record()
+    torch.cuda.synchronize()
+    out["batch64_c128_ms"] = round(a.elapsed_time(b), 3)
+    del w0, work
+    torch.cuda.empty_cache()
 
     fw, tw = WI.fit_map64(), WI.fit_target64()
     n, p, lam, z = fw.n, fw.pitch_m, fw.wavelength_m, fw.z_m
