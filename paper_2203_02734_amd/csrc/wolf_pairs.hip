@@ -61,186 +61,37 @@ __global__ __launch_bounds__(256) void k_pair_tables(PairGroup g, int n, int pi,
                T{(R)wj.x, (R)wj.y});
 }
 
-// Row sums: part[s][k][p2] = sum_{p1 in chunk s} ci[k][a] cj[k][b] W[p1][p2]. A workgroup computes a
-// tile of 64 pairs x 64 columns p2, 4 x 4 per thread; p1 is staged through LDS 16 at a time: the A
-// operand is generated from the tables, the W rows are 64 contiguous elements (512 bytes in complex64).
-template <class T>
-__global__ __launch_bounds__(256) void k_pair_rows(const T* __restrict__ w, int n, const T* __restrict__ ci,
-                                                   const T* __restrict__ cj, long long chunk, T* __restrict__ part) {
-  using R = typename real_of<T>::type;
-  constexpr int TM = kPairTile, TN = 64, TK = 16;
-  __shared__ T As[TK][TM + 1];
-  __shared__ T Bs[TK][TN + 1];
-  const long long nn = (long long)n * n;
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const long long j0 = (long long)blockIdx.x * TN;
-  const long long s = blockIdx.y;
-  const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
-  const T zero{(R)0, (R)0};
-  T acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = zero;
-  for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
-    T rb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {  // W rows: kk = e / 64, jj = e % 64
-      const int e = tid + 256 * q;
-      const int kk = e / TN, jj = e % TN;
-      const long long p1 = k0 + kk, p2 = j0 + jj;
-      rb[q] = load_or_first(w, p1 < p_end && p2 < nn, p1 * nn + p2);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {  // A: As[kk][k] = ci[k][a] cj[k][b], p1 = k0 + kk = a n + b
-      const int e = tid + 256 * q;
-      const int k = e / TK, kk = e % TK;
-      const long long p1 = k0 + kk;
-      const bool ok = p1 < p_end;
-      const int pi = ok ? (int)p1 : 0;  // p1 < N^2 fits an int: 32-bit division
-      const int a = pi / n, b = pi - a * n;
-      As[kk][k] = keep_or_zero(ok, cmul(ci[k * n + a], cj[k * n + b]));
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / TN, jj = e % TN;
-      Bs[kk][jj] = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          acc[r][c].x += av[r].x * bv[c].x - av[r].y * bv[c].y;
-          acc[r][c].y += av[r].x * bv[c].y + av[r].y * bv[c].x;
-        }
-    }
-    __syncthreads();
-  }
-  T* out = part + s * kPairTile * nn;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const long long j = j0 + tx + 16 * c;
-      if (j < nn) out[(long long)(ty + 16 * r) * nn + j] = acc[r][c];
-    }
-}
-
-// Difference sums: part[sb][k][di n + dj] = sum_{b in chunk sb} B_k^{dj}[b] sum_a A_k^{di}[a]
-// W[a, b; a - di, b - dj]. A workgroup owns di, 64 values of dj and a chunk of b; for each b the
-// sum over a is a 64 x 64 x N GEMM (the W operand: for each a, 64 consecutive columns b - dj of one
-// row, read backwards, wrapping at N), then the B factors are applied and summed over b.
-template <class T>
-__global__ __launch_bounds__(256) void k_pair_diffs(const T* __restrict__ w, int n, const T* __restrict__ u1,
-                                                    const T* __restrict__ u2, int bchunk, T* __restrict__ part) {
-  using R = typename real_of<T>::type;
-  constexpr int TM = kPairTile, TN = 64, TK = 16;
-  __shared__ T As[TK][TM + 1];
-  __shared__ T Bs[TK][TN + 1];
-  const long long nn = (long long)n * n;
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const int dj0 = blockIdx.x * TN, di = blockIdx.y, nm = n - 1;  // N is a power of two
-  const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
-  const T zero{(R)0, (R)0};
-  T dacc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) dacc[r][c] = zero;
-  for (int b = b_begin; b < b_end; ++b) {
-    T g[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) g[r][c] = zero;
-    for (int a0 = 0; a0 < n; a0 += TK) {
-      T rb[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // Bs[kk][jj] = W[a, b; a - di, b - dj], a = a0 + kk, dj = dj0 + jj
-        const int e = tid + 256 * q;
-        const int kk = e / TN, jj = e % TN;
-        const int a = a0 + kk, dj = dj0 + jj;
-        const int a2 = (a - di) & nm, b2 = (b - dj) & nm;
-        rb[q] = load_or_first(w, a < n && dj < n, ((long long)a * n + b) * nn + (long long)a2 * n + b2);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // As[kk][k] = u1[k][a] u2[k][a - di]
-        const int e = tid + 256 * q;
-        const int k = e / TK, kk = e % TK;
-        const int a = a0 + kk;
-        const bool ok = a < n;
-        const int ac = ok ? a : 0;
-        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ((ac - di) & nm)]));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        const int kk = e / TN, jj = e % TN;
-        Bs[kk][jj] = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < TK; ++kk) {
-        T av[4], bv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            g[r][c].x += av[r].x * bv[c].x - av[r].y * bv[c].y;
-            g[r][c].y += av[r].x * bv[c].y + av[r].y * bv[c].x;
-          }
-      }
-      __syncthreads();
-    }
-    // B_k^{dj}[b] = u1[k][b] u2[k][b - dj]
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = ty + 16 * r;
-      const T ub = u1[k * n + b];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int dj = dj0 + tx + 16 * c;
-        const T f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
-        const T t = cmul(f, g[r][c]);
-        dacc[r][c].x += t.x;
-        dacc[r][c].y += t.y;
-      }
-    }
-  }
-  T* out = part + (long long)blockIdx.z * kPairTile * nn;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int dj = dj0 + tx + 16 * c;
-      if (dj < n) out[(long long)(ty + 16 * r) * nn + (long long)di * n + dj] = dacc[r][c];
-    }
-}
-
 // ---------------------------------------------------------------------------------------------
-// complex64: the two contractions on the matrix cores (v_mfma_f32_16x16x4f32, 2x the FP32 vector
-// rate without packed math). A workgroup's TM x TN complex tile (TM pairs: 64 x 64, or 32 x 128 for a
-// group of at most 32 pairs) is four 32 x 32 wavefront blocks of 2 x 2 MFMA tiles. A complex product
-// takes three real ones (the 3M form): T1 = Ar Br, T2 = Ai Bi and T3 = (Ar + Ai)(Br + Bi) are accumulated
-// apart, then re = T1 - T2 and im = T3 - T1 - T2. Operands are staged in LDS as separate re / im planes
-// [16][width + 16]: lane l of a 16 x 16 x 4 step reads A[k 4 + l / 16][row l % 16] and
-// B[k 4 + l / 16][col l % 16], and holds D[4 (l / 16) + i][l % 16]; with a row stride of 16 mod 64 floats
-// (or 48) the four k rows of a step fall on distinct banks.
+// The two contractions on the matrix cores: v_mfma_f32_16x16x4f32 for complex64 (2x the FP32 vector
+// rate without packed math), v_mfma_f64_16x16x4f64 for complex128. A workgroup's TM x TN complex tile (TM
+// pairs: 64 x 64, or 32 x 128 for a complex64 group of at most 32 pairs) is four 32 x 32 wavefront blocks
+// of 2 x 2 MFMA tiles. A complex product takes three real ones (the 3M form): T1 = Ar Br, T2 = Ai Bi and
+// T3 = (Ar + Ai)(Br + Bi) are accumulated apart, then re = T1 - T2 and im = T3 - T1 - T2. Operands are
+// staged in LDS as separate re / im planes [16][width + 16]: lane l of a 16 x 16 x 4 step reads
+// A[k 4 + l / 16][row l % 16] and B[k 4 + l / 16][col l % 16] (output layout: Mfma<T>::row); with a row
+// stride of 16 mod 64 words (or 48) the four k rows of a step fall on distinct banks.
 // ---------------------------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// The 16 x 16 x 4 matrix-core product of each precision (FP32 for complex64, FP64 for complex128), and
+// the row within its 16 x 16 tile of output i of a lane (the two layouts differ; both were checked with
+// a probe): column lane % 16 in both.
+template <class T> struct Mfma;
+template <> struct Mfma<float2> {
+  using V = v4f;
+  __device__ __forceinline__ static V mac(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane / 16) + i; }
+};
+template <> struct Mfma<double2> {
+  using V = v4d;
+  __device__ __forceinline__ static V mac(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int i) { return lane / 16 + 4 * i; }
+};
 
 template <int TM> struct MTile {
   static_assert(TM == 64 || TM == 32, "tile height");
@@ -250,35 +101,35 @@ template <int TM> struct MTile {
   static constexpr int QA = TM * 16 / 256, QB = TN * 16 / 256;  // staged elements per thread and step
 };
 
-struct CTile {
-  v4f t1[2][2], t2[2][2], t3[2][2];
-  __device__ __forceinline__ float re(int r, int q, int i) const { return t1[r][q][i] - t2[r][q][i]; }
-  __device__ __forceinline__ float im(int r, int q, int i) const {
-    return t3[r][q][i] - t1[r][q][i] - t2[r][q][i];
-  }
+template <class T> struct CTile {
+  using R = typename real_of<T>::type;
+  using V = typename Mfma<T>::V;
+  V t1[2][2], t2[2][2], t3[2][2];
+  __device__ __forceinline__ R re(int r, int q, int i) const { return t1[r][q][i] - t2[r][q][i]; }
+  __device__ __forceinline__ R im(int r, int q, int i) const { return t3[r][q][i] - t1[r][q][i] - t2[r][q][i]; }
 };
 
-__device__ __forceinline__ void ctile_zero(CTile& c) {
+template <class T> __device__ __forceinline__ void ctile_zero(CTile<T>& c) {
+  using V = typename Mfma<T>::V;
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      c.t1[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
-      c.t2[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
-      c.t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int q = 0; q < 2; ++q) c.t1[r][q] = c.t2[r][q] = c.t3[r][q] = V{0, 0, 0, 0};
 }
 
 // c += A B over the 16 staged values of the contraction index, for the wavefront block at (row0, col0).
 // Bit q of `cols` (wavefront-uniform) enables the 16 columns col0 + 16 q; a disabled block is left as is.
-template <int LDA, int LDB>
-__device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[LDA], const float (*ai)[LDA],
-                                             const float (*br)[LDB], const float (*bi)[LDB], int row0, int col0,
+template <class T, int LDA, int LDB>
+__device__ __forceinline__ void ctile_mfma16(CTile<T>& c, const typename real_of<T>::type (*ar)[LDA],
+                                             const typename real_of<T>::type (*ai)[LDA],
+                                             const typename real_of<T>::type (*br)[LDB],
+                                             const typename real_of<T>::type (*bi)[LDB], int row0, int col0,
                                              int lane, int cols = 3) {
+  using R = typename real_of<T>::type;
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
     const int kk = ks * 4 + lane / 16, l16 = lane % 16;
-    float xr[2], xi[2], xs[2], yr[2], yi[2], ys[2];
+    R xr[2], xi[2], xs[2], yr[2], yi[2], ys[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       xr[r] = ar[kk][row0 + 16 * r + l16];
@@ -296,9 +147,9 @@ __device__ __forceinline__ void ctile_mfma16(CTile& c, const float (*ar)[LDA], c
       if (!((cols >> q) & 1)) continue;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        c.t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[r], yr[q], c.t1[r][q], 0, 0, 0);
-        c.t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[r], yi[q], c.t2[r][q], 0, 0, 0);
-        c.t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], c.t3[r][q], 0, 0, 0);
+        c.t1[r][q] = Mfma<T>::mac(xr[r], yr[q], c.t1[r][q]);
+        c.t2[r][q] = Mfma<T>::mac(xi[r], yi[q], c.t2[r][q]);
+        c.t3[r][q] = Mfma<T>::mac(xs[r], ys[q], c.t3[r][q]);
       }
     }
   }
@@ -321,17 +172,20 @@ template <int TM> struct MStage {
   }
 };
 
-// k_pair_rows on the matrix cores (same partial sums and layout) for the first TM pairs. The operands of
-// step s + 1 are loaded from HBM while the matrix cores work on step s, and staged into the second LDS
-// buffer after it: one barrier per step.
-template <int TM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rows_mfma(
-    const float2* __restrict__ w, int n, const float2* __restrict__ cit, const float2* __restrict__ cjt, long long chunk,
-    float2* __restrict__ part) {
+// Row sums: part[s][k][p2] = sum_{p1 in chunk s} ci[k][a] cj[k][b] W[p1][p2] (p1 = a N + b), for the
+// first TM pairs k. A workgroup computes a tile of TM pairs x TN columns p2; p1 runs through the chunk 16
+// at a time: the A operand is generated from the tables, the W rows are TN contiguous elements. The
+// operands of step s + 1 are loaded from HBM while the matrix cores work on step s, and staged into the
+// second LDS buffer after it: one barrier per step.
+template <class T, int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 2))) void k_pair_rows_mfma(
+    const T* __restrict__ w, int n, const T* __restrict__ cit, const T* __restrict__ cjt, long long chunk,
+    T* __restrict__ part) {
+  using R = typename real_of<T>::type;
   using G = MTile<TM>;
   using M = MStage<TM>;
   constexpr int TK = 16, TN = G::TN;
-  __shared__ float ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
+  __shared__ R ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lane = tid % 64;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
@@ -340,7 +194,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const long long s = blockIdx.y;
   const long long p_begin = s * chunk, p_end = (p_begin + chunk < nn) ? p_begin + chunk : nn;
   const int lg = __builtin_ctz((unsigned)n);
-  float2 rb[G::QB], ca[G::QA], cb[G::QA];
+  T rb[G::QB], ca[G::QA], cb[G::QA];
   auto fetch = [&](long long k0) {
 #pragma unroll
     for (int q = 0; q < G::QB; ++q) {  // W[p1][p2], p1 = k0 + row, p2 = j0 + column
@@ -360,19 +214,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int q = 0; q < G::QB; ++q) {
       const int kk = M::b_row(wv, q), jj = M::b_col(wv, lane);
-      const float2 v = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
+      const T v = keep_or_zero(k0 + kk < p_end && j0 + jj < nn, rb[q]);
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
     }
 #pragma unroll
     for (int q = 0; q < G::QA; ++q) {
       const int kk = M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
-      const float2 a = keep_or_zero(k0 + kk < p_end, cmul(ca[q], cb[q]));
+      const T a = keep_or_zero(k0 + kk < p_end, cmul(ca[q], cb[q]));
       ar[buf][kk][k] = a.x;
       ai[buf][kk][k] = a.y;
     }
   };
-  CTile acc;
+  CTile<T> acc;
   ctile_zero(acc);
   fetch(p_begin);
   stage(0, p_begin);
@@ -381,49 +235,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (long long k0 = p_begin; k0 < p_end; k0 += TK) {
     const bool more = k0 + TK < p_end;
     if (more) fetch(k0 + TK);
-    ctile_mfma16<G::LDA, G::LDB>(acc, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    ctile_mfma16<T, G::LDA, G::LDB>(acc, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (more) stage(buf ^ 1, k0 + TK);
     __syncthreads();
     buf ^= 1;
   }
-  float2* out = part + s * kPairTile * nn;
+  T* out = part + s * kPairTile * nn;
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const long long k = row0 + 16 * r + Mfma<T>::row(lane, i);
         const long long j = j0 + col0 + 16 * q + lane % 16;
-        if (j < nn) out[k * nn + j] = float2{acc.re(r, q, i), acc.im(r, q, i)};
+        if (j < nn) out[k * nn + j] = T{acc.re(r, q, i), acc.im(r, q, i)};
       }
 }
 
-// k_pair_diffs on the matrix cores (same partial sums and layout) for the first TM pairs. The steps
-// (b, a0) run in one sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b the
-// wavefront block folds its G tile into D.
-template <int TM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_diffs_mfma(
-    const float2* __restrict__ w, int n, const float2* __restrict__ u1, const float2* __restrict__ u2,
-    const float2* __restrict__ u1t, const float2* __restrict__ u2t, int bchunk, float2* __restrict__ part) {
+// Difference sums: part[z][k][di N + dj] = sum_{b in chunk z} B_k^{dj}[b] sum_a A_k^{di}[a]
+// W[a, b; a - di, b - dj] (indices mod N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj], for the first TM
+// pairs k. A workgroup owns di, TN values of dj and a chunk of b; for each b the inner sum is a GEMM over
+// a (TM x TN x N) whose W operand is TN consecutive columns of one row, read backwards and wrapping. The
+// steps (b, a0) run in one sequence, double-buffered like k_pair_rows_mfma; after the last a0 of each b
+// the wavefront block folds its G tile into D.
+template <class T, int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 2))) void k_pair_diffs_mfma(
+    const T* __restrict__ w, int n, const T* __restrict__ u1, const T* __restrict__ u2,
+    const T* __restrict__ u1t, const T* __restrict__ u2t, int bchunk, T* __restrict__ part) {
+  using R = typename real_of<T>::type;
   using G = MTile<TM>;
   using M = MStage<TM>;
   constexpr int TK = 16;
-  __shared__ float ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
+  __shared__ R ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lane = tid % 64;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
   const int row0 = (wv / G::WC) * 32, col0 = (wv % G::WC) * 32;
   const int dj0 = blockIdx.x * G::TN, di = blockIdx.y, nm = n - 1;  // N is a power of two
   const int b_begin = blockIdx.z * bchunk, b_end = (b_begin + bchunk < n) ? b_begin + bchunk : n;
-  float dre[2][2][4], dim[2][2][4];
+  R dre[2][2][4], dim[2][2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  float2 rb[G::QB], ca[G::QA], cb[G::QA];
+      for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = (R)0;
+  T rb[G::QB], ca[G::QA], cb[G::QA];
   auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] and the tables of A = u1[a] u2[a - di]
 #pragma unroll
     for (int q = 0; q < G::QB; ++q) {
@@ -443,14 +301,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int q = 0; q < G::QB; ++q) {
       const int kk = M::b_row(wv, q), jj = M::b_col(wv, lane);
-      const float2 v = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
+      const T v = keep_or_zero(a0 + kk < n && dj0 + jj < n, rb[q]);
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
     }
 #pragma unroll
     for (int q = 0; q < G::QA; ++q) {
       const int kk = M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
-      const float2 a = keep_or_zero(a0 + kk < n, cmul(ca[q], cb[q]));
+      const T a = keep_or_zero(a0 + kk < n, cmul(ca[q], cb[q]));
       ar[buf][kk][k] = a.x;
       ai[buf][kk][k] = a.y;
     }
@@ -460,7 +318,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     stage(0, 0);
   }
   __syncthreads();
-  CTile g;
+  CTile<T> g;
   ctile_zero(g);
   int buf = 0;
   for (int b = b_begin, a0 = 0; b < b_end;) {
@@ -468,20 +326,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nb = last_a ? b + 1 : b, na = last_a ? 0 : a0 + TK;
     const bool more = nb < b_end;
     if (more) fetch(nb, na);
-    ctile_mfma16<G::LDA, G::LDB>(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    ctile_mfma16<T, G::LDA, G::LDB>(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (last_a) {
       // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj], on the outputs this lane holds
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k = row0 + 16 * r + 4 * (lane / 16) + i;
-          const float2 ub = u1[k * n + b];
+          const int k = row0 + 16 * r + Mfma<T>::row(lane, i);
+          const T ub = u1[k * n + b];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int dj = dj0 + col0 + 16 * q + lane % 16;
-            const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
-            const float gr = g.re(r, q, i), gi = g.im(r, q, i);
+            const T f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
+            const R gr = g.re(r, q, i), gi = g.im(r, q, i);
             dre[r][q][i] += f.x * gr - f.y * gi;
             dim[r][q][i] += f.x * gi + f.y * gr;
           }
@@ -494,16 +352,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     b = nb;
     a0 = na;
   }
-  float2* out = part + (long long)blockIdx.z * kPairTile * nn;
+  T* out = part + (long long)blockIdx.z * kPairTile * nn;
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const long long k = row0 + 16 * r + Mfma<T>::row(lane, i);
         const int dj = dj0 + col0 + 16 * q + lane % 16;
-        if (dj < n) out[k * nn + (long long)di * n + dj] = float2{dre[r][q][i], dim[r][q][i]};
+        if (dj < n) out[k * nn + (long long)di * n + dj] = T{dre[r][q][i], dim[r][q][i]};
       }
 }
 
@@ -652,134 +510,24 @@ __global__ __launch_bounds__(256) void k_poly_tables(PolyGroup g, int n, int pi,
                T{(R)wj.x, (R)wj.y});
 }
 
-// Difference sums without wrap: part[z][k][(di + N) 2N + dj + N] = sum_{b} B_k^{dj}[b] sum_a A_k^{di}[a]
-// W[a, b; a - di, b - dj] over a - di, b - dj in [0, N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj]. They are
-// taken in the folded order of k_pair_diffs: for a folded offset (di, dj) in [0, N)^2 the folded sum
-// splits exactly into the unfolded bins. On the first point a >= di belongs to bin di and a < di to di - N
-// (the workgroup's half h takes one of the two a ranges); on the second point b >= dj belongs to dj and
-// b < dj to dj - N. As b rises through the chunk a thread's column dj switches bin once: the thread
-// stores the lower bin when b passes dj - 1 and writes each of its two bins exactly once.
-template <class T>
-__global__ __launch_bounds__(256) void k_poly_diffs(const T* __restrict__ w, int n, const T* __restrict__ u1,
-                                                    const T* __restrict__ u2, int bchunk, T* __restrict__ part) {
-  using R = typename real_of<T>::type;
-  constexpr int TM = kPairTile, TN = 64, TK = 16;
-  __shared__ T As[TK][TM + 1];
-  __shared__ T Bs[TK][TN + 1];
-  const long long nn = (long long)n * n, bins = 4 * nn;
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16, nm = n - 1;  // N is a power of two
-  const int dj0 = (int)blockIdx.x * TN;
-  const int h = (int)blockIdx.y & 1, di = (int)blockIdx.y >> 1;  // h = 0: a >= di; h = 1: a < di
-  const int a_lo = h ? 0 : di, a_hi = h ? di : n;
-  const int b_lo = (int)blockIdx.z * bchunk, b_hi = b_lo + bchunk < n ? b_lo + bchunk : n;
-  T* out = part + (long long)blockIdx.z * kPairTile * bins + (long long)(h ? di : di + n) * (2 * n) + n;
-  const T zero{(R)0, (R)0};
-  T dacc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dacc[r][q] = zero;
-  const bool any = a_lo < a_hi;
-  for (int b = b_lo; any && b < b_hi; ++b) {
-    T g[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) g[r][q] = zero;
-    for (int a0 = a_lo; a0 < a_hi; a0 += TK) {
-      T rb[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // Bs[kk][jj] = W[a, b; a - di, b - dj] (indices mod N)
-        const int e = tid + 256 * q;
-        const int kk = e / TN, jj = e % TN;
-        const int a = a0 + kk, dj = dj0 + jj;
-        rb[q] = load_or_first(w, a < a_hi && dj < n,
-                              ((long long)a * n + b) * nn + (long long)((a - di) & nm) * n + ((b - dj) & nm));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // As[kk][k] = u1[k][a] u2[k][a - di]
-        const int e = tid + 256 * q;
-        const int k = e / TK, kk = e % TK;
-        const int a = a0 + kk;
-        const bool ok = a < a_hi;
-        const int ac = ok ? a : a_lo;
-        As[kk][k] = keep_or_zero(ok, cmul(u1[k * n + ac], u2[k * n + ((ac - di) & nm)]));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        const int kk = e / TN, jj = e % TN;
-        Bs[kk][jj] = keep_or_zero(a0 + kk < a_hi && dj0 + jj < n, rb[q]);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < TK; ++kk) {
-        T av[4], bv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bv[q] = Bs[kk][tx + 16 * q];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            g[r][q].x += av[r].x * bv[q].x - av[r].y * bv[q].y;
-            g[r][q].y += av[r].x * bv[q].y + av[r].y * bv[q].x;
-          }
-      }
-      __syncthreads();
-    }
-    // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj]; at b = dj - 1 the lower bin dj - N is complete.
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = ty + 16 * r;
-      const T ub = u1[k * n + b];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int dj = dj0 + tx + 16 * q;
-        const T t = cmul(cmul(ub, u2[k * n + ((b - dj) & nm)]), g[r][q]);
-        dacc[r][q].x += t.x;
-        dacc[r][q].y += t.y;
-        if (b == dj - 1 && dj < b_hi && dj < n) {
-          out[(long long)k * bins + dj - n] = dacc[r][q];
-          dacc[r][q] = zero;
-        }
-      }
-    }
-  }
-  // Each thread writes both of its bins once (see k_poly_diffs_mfma).
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long long k = ty + 16 * r;
-      const int dj = dj0 + tx + 16 * q;
-      if (dj >= n) continue;
-      if (!any || dj >= b_hi) {
-        out[k * bins + dj - n] = dacc[r][q];
-        out[k * bins + dj] = zero;
-      } else {
-        out[k * bins + dj] = dacc[r][q];
-        if (dj <= b_lo) out[k * bins + dj - n] = zero;
-      }
-    }
-}
-
-// k_poly_diffs on the matrix cores (complex64; same partial sums and layout). The unfolded sums are
-// taken in the folded order of k_pair_diffs_mfma, with no wasted rows: for a folded offset
+// Difference sums without wrap: part[z][k][(di + N) 2N + dj + N] = sum_b B_k^{dj}[b] sum_a A_k^{di}[a]
+// W[a, b; a - di, b - dj] over a - di, b - dj in [0, N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj]
+// (di, dj in [-N, N)). They are taken in the folded order of k_pair_diffs_mfma, with no wasted rows: for a
+// folded offset
 // (d_i, d_j) in [0, N)^2 the folded sum over a and b splits exactly into the unfolded bins. On the first
 // point, a >= d_i belongs to bin d_i and a < d_i to bin d_i - N (the workgroup's half h takes one of the
 // two a ranges); on the second point, b >= d_j belongs to bin d_j and b < d_j to bin d_j - N. As b rises
 // through the workgroup's chunk, a lane's column d_j switches bin once: the lane stores the lower bin's
 // sum when b passes d_j - 1 and writes each of its two bins exactly once. For the first TM pairs.
-template <int TM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_poly_diffs_mfma(
-    const float2* __restrict__ w, int n, const float2* __restrict__ u1, const float2* __restrict__ u2,
-    const float2* __restrict__ u1t, const float2* __restrict__ u2t, int bchunk, float2* __restrict__ part) {
+template <class T, int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 2))) void k_poly_diffs_mfma(
+    const T* __restrict__ w, int n, const T* __restrict__ u1, const T* __restrict__ u2,
+    const T* __restrict__ u1t, const T* __restrict__ u2t, int bchunk, T* __restrict__ part) {
+  using R = typename real_of<T>::type;
   using G = MTile<TM>;
   using M = MStage<TM>;
   constexpr int TK = 16;
-  __shared__ float ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
+  __shared__ R ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
   const long long nn = (long long)n * n, bins = 4 * nn;
   const int tid = threadIdx.x, lane = tid % 64;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
@@ -788,15 +536,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int h = (int)blockIdx.y & 1, di = (int)blockIdx.y >> 1;  // h = 0: a >= d_i; h = 1: a < d_i
   const int a_lo = h ? 0 : di, a_hi = h ? di : n;
   const int b_lo = blockIdx.z * bchunk, b_hi = (b_lo + bchunk < n) ? b_lo + bchunk : n;
-  float2* out = part + (long long)blockIdx.z * kPairTile * bins + (long long)(h ? di : di + n) * (2 * n) + n;
-  float dre[2][2][4], dim[2][2][4];
+  T* out = part + (long long)blockIdx.z * kPairTile * bins + (long long)(h ? di : di + n) * (2 * n) + n;
+  R dre[2][2][4], dim[2][2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = 0.f;
-  float2 rb[G::QB], ca[G::QA], cb[G::QA];
+      for (int i = 0; i < 4; ++i) dre[r][q][i] = dim[r][q][i] = (R)0;
+  T rb[G::QB], ca[G::QA], cb[G::QA];
   auto fetch = [&](int b, int a0) {  // W[a, b; a - di, b - dj] (indices mod N) and the tables of A
 #pragma unroll
     for (int q = 0; q < G::QB; ++q) {
@@ -816,14 +564,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int q = 0; q < G::QB; ++q) {
       const int kk = M::b_row(wv, q), jj = M::b_col(wv, lane);
-      const float2 v = keep_or_zero(a0 + kk < a_hi && dj0 + jj < n, rb[q]);
+      const T v = keep_or_zero(a0 + kk < a_hi && dj0 + jj < n, rb[q]);
       br[buf][kk][jj] = v.x;
       bi[buf][kk][jj] = v.y;
     }
 #pragma unroll
     for (int q = 0; q < G::QA; ++q) {
       const int kk = M::a_row(tid, wv, q), k = M::a_pair(tid, lane);
-      const float2 a = keep_or_zero(a0 + kk < a_hi, cmul(ca[q], cb[q]));
+      const T a = keep_or_zero(a0 + kk < a_hi, cmul(ca[q], cb[q]));
       ar[buf][kk][k] = a.x;
       ai[buf][kk][k] = a.y;
     }
@@ -834,7 +582,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     stage(0, a_lo);
   }
   __syncthreads();
-  CTile g;
+  CTile<T> g;
   ctile_zero(g);
   int buf = 0;
   for (int b = b_lo, a0 = a_lo; any && b < b_hi;) {
@@ -842,25 +590,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nb = last_a ? b + 1 : b, na = last_a ? a_lo : a0 + TK;
     const bool more = nb < b_hi;
     if (more) fetch(nb, na);
-    ctile_mfma16<G::LDA, G::LDB>(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    ctile_mfma16<T, G::LDA, G::LDB>(g, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
     if (last_a) {
       // D += B_k^{dj}[b] G, B = u1[k][b] u2[k][b - dj]; at b = dj - 1 the lower bin d_j - N is complete.
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k = row0 + 16 * r + 4 * (lane / 16) + i;
-          const float2 ub = u1[k * n + b];
+          const int k = row0 + 16 * r + Mfma<T>::row(lane, i);
+          const T ub = u1[k * n + b];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int dj = dj0 + col0 + 16 * q + lane % 16;
-            const float2 f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
-            const float gr = g.re(r, q, i), gi = g.im(r, q, i);
+            const T f = cmul(ub, u2[k * n + ((b - dj) & nm)]);
+            const R gr = g.re(r, q, i), gi = g.im(r, q, i);
             dre[r][q][i] += f.x * gr - f.y * gi;
             dim[r][q][i] += f.x * gi + f.y * gr;
             if (b == dj - 1 && dj < b_hi && dj < n) {
-              out[(long long)k * bins + dj - n] = float2{dre[r][q][i], dim[r][q][i]};
-              dre[r][q][i] = dim[r][q][i] = 0.f;
+              out[(long long)k * bins + dj - n] = T{dre[r][q][i], dim[r][q][i]};
+              dre[r][q][i] = dim[r][q][i] = (R)0;
             }
           }
         }
@@ -880,10 +628,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long k = row0 + 16 * r + 4 * (lane / 16) + i;
+        const long long k = row0 + 16 * r + Mfma<T>::row(lane, i);
         const int dj = dj0 + col0 + 16 * q + lane % 16;
         if (dj >= n) continue;
-        const float2 v{dre[r][q][i], dim[r][q][i]}, z{0.f, 0.f};
+        const T v{dre[r][q][i], dim[r][q][i]}, z{(R)0, (R)0};
         if (!any || dj >= b_hi) {  // every b of the chunk is below dj (or there is no term at all)
           out[k * bins + dj - n] = v;
           out[k * bins + dj] = z;
@@ -1064,8 +812,8 @@ __global__ __launch_bounds__(1024) void k_poly_mu(const double* __restrict__ s_a
 // pair). With one row the two contractions are matrix-vector products, bound by HBM, and both come
 // from one pass over the source. A workgroup takes a range of slabs p1 and a block of columns; each
 // thread keeps kOneCols columns i of both raw sums in registers:
-//   R[i] += ci[a] cj[b] W[p1; i]                                  (k_pair_rows with one row)
-//   D[i] += u1[a] u1[b] u2[a - d_i] u2[b - d_j] W[p1; p1 - d], d = i  (k_pair_diffs; indices mod N)
+//   R[i] += ci[a] cj[b] W[p1; i]                                  (the row sums with one row)
+//   D[i] += u1[a] u1[b] u2[a - d_i] u2[b - d_j] W[p1; p1 - d], d = i  (the difference sums; indices mod N)
 // The read of a slab for D finds it in the caches after the read for R.
 // ---------------------------------------------------------------------------------------------
 template <class T>
@@ -1137,32 +885,35 @@ static int pair_bsplit(int n) {
   return sb;
 }
 
-// The matrix-core contractions of one group (complex64): tiles of 32 pairs x 128 columns when the
-// group has at most 32 pairs, else 64 x 64. kind 0: row sums; 1: Fresnel difference sums; 2: the
-// polychromatic (unfolded) difference sums. The tables tr are [4][N][kPairTile] (u1, u2, ci, cj).
-template <int TM>
-static hipError_t launch_mfma_tm(int kind, int n, const float2* w, const float2* u1, const float2* u2,
-                                 const float2* tr, long long chunk, int bchunk, int sb, float2* part,
-                                 hipStream_t st) {
+// The matrix-core contractions of one group: tiles of 32 pairs x 128 columns when a complex64 group has
+// at most 32 pairs, else 64 x 64 (complex128 always; its FP64 operands fill the LDS twice as fast). kind 0:
+// row sums; 1: Fresnel difference sums; 2: the polychromatic (unfolded) difference sums. The tables tr are
+// [4][N][kPairTile] (u1, u2, ci, cj).
+template <class T, int TM>
+static hipError_t launch_mfma_tm(int kind, int n, const T* w, const T* u1, const T* u2, const T* tr, long long chunk,
+                                 int bchunk, int sb, T* part, hipStream_t st) {
   constexpr int TN = MTile<TM>::TN;
   const long long nn = (long long)n * n, tq = (long long)kPairTile * n;
   const unsigned tiles_j = (unsigned)((n + TN - 1) / TN);
   if (kind == 0)
-    hipLaunchKernelGGL(k_pair_rows_mfma<TM>, dim3((unsigned)((nn + TN - 1) / TN), kPairSplitK), dim3(256), 0, st, w, n,
-                       tr + 2 * tq, tr + 3 * tq, chunk, part);
+    hipLaunchKernelGGL((k_pair_rows_mfma<T, TM>), dim3((unsigned)((nn + TN - 1) / TN), kPairSplitK), dim3(256), 0, st,
+                       w, n, tr + 2 * tq, tr + 3 * tq, chunk, part);
   else if (kind == 1)
-    hipLaunchKernelGGL(k_pair_diffs_mfma<TM>, dim3(tiles_j, (unsigned)n, (unsigned)sb), dim3(256), 0, st, w, n, u1, u2,
-                       tr, tr + tq, bchunk, part);
-  else  // folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks)
-    hipLaunchKernelGGL(k_poly_diffs_mfma<TM>, dim3(tiles_j, (unsigned)(2 * n), (unsigned)sb), dim3(256), 0, st, w, n,
+    hipLaunchKernelGGL((k_pair_diffs_mfma<T, TM>), dim3(tiles_j, (unsigned)n, (unsigned)sb), dim3(256), 0, st, w, n,
                        u1, u2, tr, tr + tq, bchunk, part);
+  else  // folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks)
+    hipLaunchKernelGGL((k_poly_diffs_mfma<T, TM>), dim3(tiles_j, (unsigned)(2 * n), (unsigned)sb), dim3(256), 0, st,
+                       w, n, u1, u2, tr, tr + tq, bchunk, part);
   return hipGetLastError();
 }
 
-static hipError_t launch_mfma(int count, int kind, int n, const float2* w, const float2* u1, const float2* u2,
-                              const float2* tr, long long chunk, int bchunk, int sb, float2* part, hipStream_t st) {
-  return count <= 32 ? launch_mfma_tm<32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st)
-                     : launch_mfma_tm<64>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
+template <class T>
+static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u1, const T* u2, const T* tr,
+                              long long chunk, int bchunk, int sb, T* part, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    if (count <= 32) return launch_mfma_tm<T, 32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
+  }
+  return launch_mfma_tm<T, 64>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
 }
 
 template <class T> size_t pair_work_bytes(int n) {
@@ -1226,15 +977,8 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   }
   const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
   const int bchunk = (n + sb - 1) / sb;
-  const dim3 grid_r((unsigned)((nn + 63) / 64), kPairSplitK), grid_d((unsigned)pair_tiles_j(n), (unsigned)n, (unsigned)sb);
-  if constexpr (sizeof(T) == 8) {  // complex64: matrix cores
-    if ((e = launch_mfma(count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
-    e = launch_mfma(count, 1, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st);
-  } else {
-    hipLaunchKernelGGL(k_pair_rows<T>, grid_r, dim3(256), 0, st, w, n, (const T*)ci, (const T*)cj, chunk, part_r);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_diffs<T>, grid_d, dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
-  }
+  if ((e = launch_mfma<T>(count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
+  e = launch_mfma<T>(count, 1, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned sum_blocks = (unsigned)((g + 255) / 256);
   hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n, kPairTile,
@@ -1342,18 +1086,8 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
     } else {
       const long long chunk = (nn + kPairSplitK - 1) / kPairSplitK;
       const int bchunk = (n + sb - 1) / sb;
-      if constexpr (sizeof(T) == 8) {  // complex64: matrix cores
-        if ((e = launch_mfma(pg.count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
-        if ((e = launch_mfma(pg.count, 2, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st)) != hipSuccess) return e;
-      } else {
-        hipLaunchKernelGGL(k_pair_rows<T>, dim3((unsigned)((nn + 63) / 64), kPairSplitK), dim3(256), 0, st, w, n,
-                           (const T*)ci, (const T*)cj, chunk, part_r);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        // Folded offsets: (tiles of d_j in [0, N)) x (d_i in [0, N), two halves of the a range) x (b chunks).
-        hipLaunchKernelGGL(k_poly_diffs<T>, dim3((unsigned)pair_tiles_j(n), (unsigned)(2 * n), (unsigned)sb),
-                           dim3(256), 0, st, w, n, (const T*)u1, (const T*)u2, bchunk, part_d);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-      }
+      if ((e = launch_mfma<T>(pg.count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
+      if ((e = launch_mfma<T>(pg.count, 2, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
                          kPairSplitK, n, kPairTile, (const T*)u2, rr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
