@@ -10,6 +10,7 @@
 // points for each point: W_B = pitch^4 conj(H) W_A H^T, two complex GEMMs of size N^2.
 #include "wolf_device.hpp"
 #include "wolf_internal.hpp"
+#include "wolf_mfma.hpp"
 
 namespace wolf {
 
@@ -38,98 +39,78 @@ __global__ __launch_bounds__(256) void k_rs_kernel(T* __restrict__ h, int n, dou
 
 // C = alpha op(A) op(B), complex, square NN x NN, row-major. op(A) = A or conj(A) (CONJ_A).
 // B_TRANS: op(B)[k][j] = B[j][k]; else op(B)[k][j] = B[k][j].
-// Tiles of 64 x 64 outputs per workgroup of 256 threads; thread (tx, ty) owns rows ty + 16 r and
-// columns tx + 16 c (r, c < 4), so that the LDS reads of a wavefront are broadcasts (A) or
-// consecutive (B), and the stores are 16 consecutive elements. The k dimension is staged through
-// LDS 16 at a time. Out-of-range elements load as zero and are not stored (NN < 64).
-// complex128 tiles need about 200 registers: at most two waves per SIMD, rather than spills.
-template <class T> constexpr int cgemm_max_waves() { return sizeof(T) == 16 ? 2 : 8; }
-
+// On the matrix cores (FP32 for complex64, FP64 for complex128) in the 3M form: 64 x 64 outputs per
+// workgroup of four wavefronts (32 x 32 blocks), k staged through double-buffered LDS 16 at a time, the
+// HBM loads of step s + 1 issued before the products of step s. Out-of-range elements load as zero and
+// are not stored (NN < 64).
 template <class T, bool CONJ_A, bool B_TRANS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, cgemm_max_waves<T>()))) void k_cgemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
-                                               int nn, double alpha) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 2))) void k_cgemm(
+    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int nn, double alpha) {
   using R = typename real_of<T>::type;
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ T As[TK][TM + 1];
-  __shared__ T Bs[TK][TN + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
-  const long long i0 = (long long)blockIdx.y * TM, j0 = (long long)blockIdx.x * TN;
-  T acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = T{(R)0, (R)0};
-  const T zero{(R)0, (R)0};
-  for (long long k0 = 0; k0 < nn; k0 += TK) {
-    // All eight loads are issued before any is used (out-of-range lanes read element 0, then zero).
-    T ra[4], rb[4];
+  using G = MTile<64>;
+  constexpr int TK = 16;
+  __shared__ R ar[2][TK][G::LDA], ai[2][TK][G::LDA], br[2][TK][G::LDB], bi[2][TK][G::LDB];
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
+  const int row0 = (wv / G::WC) * 32, col0 = (wv % G::WC) * 32;
+  const long long i0 = (long long)blockIdx.y * 64, j0 = (long long)blockIdx.x * 64;
+  // Element q of thread tid in a step: rows of A (and of B when B_TRANS) as (row e / 16, k e % 16): 16
+  // consecutive k of one row; B otherwise as (k e / 64, column e % 64): 64 consecutive columns.
+  T ra[4], rb[4];
+  auto fetch = [&](long long k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
-      const int ii = e / TK, kk = e % TK;
-      const long long gi = i0 + ii, gk = k0 + kk;
+      const long long gi = i0 + e / TK, gk = k0 + e % TK;
       ra[q] = load_or_first(A, gi < nn && gk < nn, gi * nn + gk);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
       if constexpr (B_TRANS) {
-        const int jj = e / TK, kk = e % TK;
-        const long long gj = j0 + jj, gk = k0 + kk;
+        const long long gj = j0 + e / TK;
         rb[q] = load_or_first(B, gj < nn && gk < nn, gj * nn + gk);
       } else {
-        const int kk = e / TN, jj = e % TN;
-        const long long gj = j0 + jj, gk = k0 + kk;
-        rb[q] = load_or_first(B, gj < nn && gk < nn, gk * nn + gj);
+        const long long gj = j0 + e % 64, gkb = k0 + e / 64;
+        rb[q] = load_or_first(B, gj < nn && gkb < nn, gkb * nn + gj);
       }
     }
+  };
+  auto stage = [&](int buf, long long k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int ii = e / TK, kk = e % TK;
       T v = keep_or_zero(i0 + ii < nn && k0 + kk < nn, ra[q]);
       if constexpr (CONJ_A) v.y = -v.y;
-      As[kk][ii] = v;
+      ar[buf][kk][ii] = v.x;
+      ai[buf][kk][ii] = v.y;
+      const int jj = B_TRANS ? e / TK : e % 64, kb = B_TRANS ? e % TK : e / 64;
+      const T u = keep_or_zero(j0 + jj < nn && k0 + kb < nn, rb[q]);
+      br[buf][kb][jj] = u.x;
+      bi[buf][kb][jj] = u.y;
     }
+  };
+  CTile<T> acc;
+  ctile_zero(acc);
+  fetch(0);
+  stage(0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (long long k0 = 0; k0 < nn; k0 += TK) {
+    const bool more = k0 + TK < nn;
+    if (more) fetch(k0 + TK);
+    ctile_mfma16<T, G::LDA, G::LDB>(acc, ar[buf], ai[buf], br[buf], bi[buf], row0, col0, lane);
+    if (more) stage(buf ^ 1, k0 + TK);
+    __syncthreads();
+    buf ^= 1;
+  }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      if constexpr (B_TRANS) {
-        const int jj = e / TK, kk = e % TK;
-        Bs[kk][jj] = keep_or_zero(j0 + jj < nn && k0 + kk < nn, rb[q]);
-      } else {
-        const int kk = e / TN, jj = e % TN;
-        Bs[kk][jj] = keep_or_zero(j0 + jj < nn && k0 + kk < nn, rb[q]);
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long gi = i0 + row0 + 16 * r + Mfma<T>::row(lane, i), gj = j0 + col0 + 16 * q + lane % 16;
+        if (gi < nn && gj < nn)
+          C[gi * nn + gj] = T{(R)(alpha * acc.re(r, q, i)), (R)(alpha * acc.im(r, q, i))};
       }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          acc[r][c].x += a[r].x * b[c].x - a[r].y * b[c].y;
-          acc[r][c].y += a[r].x * b[c].y + a[r].y * b[c].x;
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const long long gi = i0 + ty + 16 * r;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const long long gj = j0 + tx + 16 * c;
-      if (gi < nn && gj < nn) C[gi * nn + gj] = T{(R)(alpha * acc[r][c].x), (R)(alpha * acc[r][c].y)};
-    }
-  }
 }
 
 template <class T>
