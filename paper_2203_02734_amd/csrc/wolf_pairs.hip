@@ -1,5 +1,5 @@
-// Observables of many (lambda, z) pairs from one read of the source: the sums that S and the row
-// W_B[P; .] need are contractions over the first point that every pair shares (eq. W_fresnel).
+// Observables of many (lambda, z) pairs without a propagated N^4 array: the sums that S and the row
+// W_B[P; .] need are contractions over the first point that the pairs of a group share (eq. W_fresnel).
 //
 // With the operator's checkerboarded tables u1 = pre1, u2 = pre2 (per axis; they carry the source
 // chirp of each pair and the (-1)^n centring), the raw sums of S and of the row are
@@ -11,7 +11,8 @@
 //   R = C W with C[k][p1] = ci_k[a] cj_k[b] (a complex GEMM, pairs x N^2 x N^2), and
 //   D[k][(di, dj)] = sum_b B_k^{dj}[b] sum_a A_k^{di}[a] W[a, b; a - di, b - dj] with A = u1[a] u2[a - di],
 //   B = u1[b] u2[b - dj]: for each di and b a GEMM over a (pairs x N x N).
-// The source is read twice in all, whatever the number of pairs; then two N x N DFTs per pair.
+// The source is read twice per group of up to 64 pairs (once for a group of one entry), then two N x N
+// DFTs per pair. The polychromatic sum on a common grid (below) uses the same contractions.
 #include "wolf_device.hpp"
 #include "wolf_internal.hpp"
 #include "wolf_mfma.hpp"
