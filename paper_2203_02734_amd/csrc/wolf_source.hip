@@ -67,11 +67,20 @@ __global__ __launch_bounds__(256) void k_build_source(T* __restrict__ w, int n, 
     }
     return;
   }
-  for (long long e = threadIdx.x; e < nn; e += blockDim.x) {
-    const int i2 = (int)(e / n), j2 = (int)(e - (e / n) * n);
+  // Element e = i2 N + j2 advances by the block size each step: (i2, j2) advance by (bs / N, bs % N) with
+  // a carry, so the loop needs no division.
+  const int bs = (int)blockDim.x, di = bs / n, dj = bs - di * n;
+  int i2 = (int)threadIdx.x / n, j2 = (int)threadIdx.x - i2 * n;
+  for (int e = (int)threadIdx.x; e < (int)nn; e += bs) {
     R m = inside(sp, i2 - n / 2, j2 - n / 2, n, i2, j2) ? am1 : (R)0;
     if (sp.model == 1) m *= sqrt((R)sp.imap[e]);
     slab[e] = cscale(cmul(fx[i2], fy[j2]), m);
+    i2 += di;
+    j2 += dj;
+    if (j2 >= n) {
+      j2 -= n;
+      ++i2;
+    }
   }
 }
 
