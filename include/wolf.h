@@ -285,8 +285,8 @@ WOLF_API int64_t wolf_polychromatic_work_bytes(int32_t n, int32_t dtype);
 
 /*
  * wolf_batch_work_bytes -- bytes of the `work` buffer that wolf_propagate_batch needs for (n, dtype):
- * the partial sums of one group of 64 pairs (16 + up to 32 N^2 x 64 complex chunks), three N^2 x 64
- * buffers and the tables (about 190 MB at N = 128 complex64); never an N^4 array. -1 if (n, dtype)
+ * the partial sums of one group of 64 pairs (16 + up to 48 N^2 x 64 complex chunks), three N^2 x 64
+ * buffers and the tables (about 265 MB at N = 128 complex64); never an N^4 array. -1 if (n, dtype)
  * is not supported.
  */
 WOLF_API int64_t wolf_batch_work_bytes(int32_t n, int32_t dtype);
