@@ -292,6 +292,12 @@ def extras(wolf, wl, args):
     out["tophat_lens64_c64_rel_l2_vs_c128"] = float(
         torch.linalg.vector_norm(r[torch.complex64].to(torch.complex128) - r[torch.complex128]) /
         torch.linalg.vector_norm(r[torch.complex128]))
+    # The same N = 64 workload's step (build with the lens phase + propagation), complex64.
+    w64 = torch.empty((t.n,) * 4, dtype=torch.complex64, device="cuda")
+    t64s = time_op(lambda: wolf.propagate_fresnel(wolf.build_source(t.source, t.n, t.pitch_m, out=w64), t.pitch_m,
+                                                  t.wavelength_m, t.z_m, out=w64))
+    out["tophat_lens64_c64_step_ms"] = round(t64s, 4)
+    out["tophat_lens64_c64_elems_per_s"] = t.n ** 4 / (t64s * 1e-3)
     return out
 
 
