@@ -7,14 +7,15 @@
 // index (k - N/2)(n - N/2) mod N_z is exact in integers, and the table of the N_z roots of unity is
 // built in FP64. There is no FFT here: each axis is a dense product of the N x N matrix (generated
 // from the table, never stored) with the N-point lines of the array, tiled like a GEMM (64 x 64
-// outputs per tile, 4 x 4 per thread, 16 inputs per LDS stage) on a persistent grid that builds
-// the tables once per workgroup. The four axes run as four passes that alternate between the
+// outputs per tile on the matrix cores in the 3M form, 16 inputs per LDS stage) on a persistent grid
+// that builds the tables once per workgroup. The four axes run as four passes that alternate between the
 // output and a work buffer.
 //   COLS: a strided axis (stride S); the lines of one batch o are S contiguous columns:
 //         out[o N S + k S + c] from in[o N S + n S + c], tiles of 64 k x 64 c.
 //   !COLS: the contiguous axis: out[r N + k] from in[r N + n], tiles of 64 r x 64 k.
 #include "wolf_device.hpp"
 #include "wolf_internal.hpp"
+#include "wolf_mfma.hpp"
 
 namespace wolf {
 
@@ -35,15 +36,17 @@ __device__ __forceinline__ int dense_index(int k, int n, int c, int nz) {
 }
 
 template <class T, bool COLS, int SIGN>
-__global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T* __restrict__ out, DenseAxis d,
-                                                    Chirp pre, Chirp post, double scale) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 2))) void k_dense_axis(
+    const T* __restrict__ in, T* __restrict__ out, DenseAxis d, Chirp pre, Chirp post, double scale) {
   using R = typename real_of<T>::type;
+  using G = MTile<64>;
   constexpr int TM = 64, TN = 64, TK = 16;
   __shared__ T tw[kDenseMaxNz];
   __shared__ T tpre[kDenseMaxN], tpost[kDenseMaxN];
-  __shared__ T As[TK][TM + 1];
-  __shared__ T Bs[TK][TN + 1];
-  const int tid = threadIdx.x;
+  __shared__ R ar[TK][G::LDA], ai[TK][G::LDA], br[TK][G::LDB], bi[TK][G::LDB];
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);  // wavefront-uniform
+  const int row0 = (wv / G::WC) * 32, col0 = (wv % G::WC) * 32;
   const int n = d.n, nz = d.nz, c0 = n / 2;
   for (int i = tid; i < nz; i += 256) tw[i] = twiddle_entry<T, SIGN>(i, nz);
   for (int i = tid; i < n; i += 256) {
@@ -51,7 +54,6 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
     tpost[i] = chirp_entry<T>(post, i, n);
   }
   __syncthreads();
-  const int tx = tid % 16, ty = tid / 16;
   const T zero{(R)0, (R)0};
   const long long ktiles = (n + TM - 1) / TM;
   const long long tiles = COLS ? d.outer * d.ctiles * ktiles : ((d.rows + TM - 1) / TM) * ktiles;
@@ -69,11 +71,8 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
       j0 = (t % ktiles) * TN;            // outputs k
     }
     const long long base = o * (long long)n * d.S;
-    T acc[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = zero;
+    CTile<T> acc;
+    ctile_zero(acc);
     for (int n0 = 0; n0 < n; n0 += TK) {
       T raw[4];  // this thread's four elements of the array tile, all loads issued first
 #pragma unroll
@@ -91,6 +90,8 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
           raw[q] = load_or_first(in, gi < d.rows && gn < n, gi * n + gn);
         }
       }
+      // A (TM x TK): the DFT matrix (COLS) or the pre-multiplied lines (!COLS); B (TK x TN): the
+      // pre-multiplied columns (COLS) or the DFT matrix (!COLS). Staged as re / im planes.
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = tid + 256 * q;
@@ -104,64 +105,55 @@ __global__ __launch_bounds__(256) void k_dense_axis(const T* __restrict__ in, T*
           const T x = cmul(raw[q], tpre[gn < n ? gn : 0]);
           v = keep_or_zero(gi < d.rows && gn < n, x);
         }
-        As[kk][ii] = v;
+        ar[kk][ii] = v.x;
+        ai[kk][ii] = v.y;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = tid + 256 * q;
         T v = zero;
+        int kk, jj;
         if constexpr (COLS) {
-          const int kk = e / TN, jj = e % TN;
+          kk = e / TN;
+          jj = e % TN;
           const long long gc = j0 + jj;
           const int gn = n0 + kk;
           const T x = cmul(raw[q], tpre[gn < n ? gn : 0]);
           v = keep_or_zero(gc < d.S && gn < n, x);
-          Bs[kk][jj] = v;
         } else {
-          const int jj = e / TK, kk = e % TK;
+          jj = e / TK;
+          kk = e % TK;
           const long long gk = j0 + jj;
           const int gn = n0 + kk;
           if (gk < n && gn < n) v = tw[dense_index((int)gk, gn, c0, nz)];
-          Bs[kk][jj] = v;
         }
+        br[kk][jj] = v.x;
+        bi[kk][jj] = v.y;
       }
       __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < TK; ++kk) {
-        T a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            acc[r][c].x += a[r].x * b[c].x - a[r].y * b[c].y;
-            acc[r][c].y += a[r].x * b[c].y + a[r].y * b[c].x;
-          }
-      }
+      ctile_mfma16<T, G::LDA, G::LDB>(acc, ar, ai, br, bi, row0, col0, lane);
       __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long gi = i0 + ty + 16 * r;
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const long long gj = j0 + tx + 16 * c;
-        if constexpr (COLS) {
-          if (gi < n && gj < d.S) {
-            const T v = cmul(acc[r][c], tpost[gi]);
-            out[base + gi * d.S + gj] = T{(R)(scale * v.x), (R)(scale * v.y)};
-          }
-        } else {
-          if (gi < d.rows && gj < n) {
-            const T v = cmul(acc[r][c], tpost[gj]);
-            out[gi * n + gj] = T{(R)(scale * v.x), (R)(scale * v.y)};
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const long long gi = i0 + row0 + 16 * r + Mfma<T>::row(lane, i), gj = j0 + col0 + 16 * q + lane % 16;
+          const T a{acc.re(r, q, i), acc.im(r, q, i)};
+          if constexpr (COLS) {
+            if (gi < n && gj < d.S) {
+              const T v = cmul(a, tpost[gi]);
+              out[base + gi * d.S + gj] = T{(R)(scale * v.x), (R)(scale * v.y)};
+            }
+          } else {
+            if (gi < d.rows && gj < n) {
+              const T v = cmul(a, tpost[gj]);
+              out[gi * n + gj] = T{(R)(scale * v.x), (R)(scale * v.y)};
+            }
           }
         }
-      }
-    }
   }
 }
 
