@@ -47,8 +47,10 @@ def fp32_bound(w, n, p, z, farfield, nz):
 
 # (N, N_z): zero-padded FFT passes for powers of two and for the mixed lengths 6, 10, 12, 20, 24, 36,
 # 48 (N_z = Q L2^2 with odd factors 3 and 5); dense passes for 14, 22, 40 (no such split in the list).
+# N_z = 8, 32 with 2N <= N_z take the folded first stage, with the padding offset s = 2, 10, 9, 8
+# (s mod L2 = 0, 2, 1, 0 at L2 = 2, 4).
 CASES = [(2, 2), (4, 8), (6, 6), (6, 10), (10, 16), (12, 12), (16, 40), (24, 64), (10, 20), (20, 24), (12, 36),
-         (24, 48), (6, 14), (10, 22)]
+         (24, 48), (6, 14), (10, 22), (12, 32), (14, 32), (16, 32), (18, 32)]
 
 
 @pytest.mark.parametrize("farfield", [False, True])
@@ -97,12 +99,15 @@ def test_source_builder_even_n(gpu_lib, model):
 @pytest.mark.parametrize("n,nz,dtype", [(200, 512, torch.complex64), (96, 192, torch.complex128),
                                         (100, 256, torch.complex128), (200, 200, torch.complex64),
                                         (100, 100, torch.complex128), (144, 144, torch.complex64),
-                                        (200, 210, torch.complex64)])
+                                        (200, 210, torch.complex64), (60, 128, torch.complex64),
+                                        (120, 512, torch.complex128), (256, 512, torch.complex64)])
 def test_padded_full_size_gsm(gpu_lib, n, nz, dtype):
     """The paper's example sizes: N = 200 padded to N_z = 512 and N = 200 unpadded (complex64, 1.6e9
     elements; power-of-two and 20 x 10 mixed-radix FFT passes), with N = 96 padded to 192, N = 100
     padded to 256, N = 100 unpadded (complex128), N = 144 unpadded (FFT passes) and N = 200 padded to
-    210 (dense passes), GSM source, against the separable oracle with the same padding."""
+    210 (dense passes), GSM source, against the separable oracle with the same padding; N = 60 padded
+    to 128, N = 120 padded to 512 (complex128) and N = 256 padded to 512 (the largest N, 2N = N_z) take
+    the folded first stage."""
     p, z, ss, sg = 20e-6, 0.5, 0.1e-3, 0.05e-3
     sp = SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=ss, sigma_g_m=sg, geometry=WI.GEO_NONE,
                          geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None, lens_focal_m=0.0,
