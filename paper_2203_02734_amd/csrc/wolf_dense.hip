@@ -275,7 +275,6 @@ template <class T, int NZ> constexpr int pad_groups() {
 template <class T, int NZ, int SIGN, bool CONTIG>
 __global__ __launch_bounds__((LineCfg<T, NZ>::kThreads)) void k_axis_pad(const T* src, T* dst, PadJob j) {
   using S = LineCfg<T, NZ>;
-  using R = typename real_of<T>::type;
   constexpr int N1 = S::L1, N2 = S::L2, Q = S::Q, C = S::C, NT = S::kThreads, G = pad_groups<T, NZ>();
   using L = PadLayout<T, NZ, CONTIG, G>;
   __shared__ T xch[L::kSize];

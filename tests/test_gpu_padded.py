@@ -47,10 +47,10 @@ def fp32_bound(w, n, p, z, farfield, nz):
 
 # (N, N_z): zero-padded FFT passes for powers of two and for the mixed lengths 6, 10, 12, 20, 24, 36,
 # 48 (N_z = Q L2^2 with odd factors 3 and 5); dense passes for 14, 22, 40 (no such split in the list).
-# N_z = 8, 32 with 2N <= N_z take the folded first stage, with the padding offset s = 2, 10, 9, 8
-# (s mod L2 = 0, 2, 1, 0 at L2 = 2, 4).
+# N_z = 8, 32, 128 with 2N <= N_z take the folded first stage, with the padding offset s = 3, 2, 10, 9, 8,
+# 61 (s mod L2 = 1, 0, 2, 1, 0, 5 at L2 = 2, 4, 8); (18, 32) is past the fold (2N > N_z).
 CASES = [(2, 2), (4, 8), (6, 6), (6, 10), (10, 16), (12, 12), (16, 40), (24, 64), (10, 20), (20, 24), (12, 36),
-         (24, 48), (6, 14), (10, 22), (12, 32), (14, 32), (16, 32), (18, 32)]
+         (24, 48), (6, 14), (10, 22), (2, 8), (12, 32), (14, 32), (16, 32), (18, 32), (6, 128)]
 
 
 @pytest.mark.parametrize("farfield", [False, True])
