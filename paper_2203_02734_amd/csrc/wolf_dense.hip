@@ -250,9 +250,9 @@ template <class T, int NZ> struct LineCfg {
 //           covers whole lines of memory; entry at c G N2 (N2 + 1) + k1l (N2 + 1) + n2.
 // The paddings (C entries per k1l, one per N2) keep the writes and the reads of a phase free of
 // bank conflicts beyond the two passes that 64 eight-byte accesses need.
-template <class T, int NZ, bool CONTIG, int G> struct PadLayout {
+template <class T, int NZ, bool CONTIG, int G, int CC = LineCfg<T, NZ>::C> struct PadLayout {
   static constexpr int N2 = LineCfg<T, NZ>::L2;
-  static constexpr int C = LineCfg<T, NZ>::C;
+  static constexpr int C = CC;
   static constexpr int kSize = CONTIG ? C * G * N2 * (N2 + 1) : G * N2 * (N2 * C + C);
   static __device__ __forceinline__ int at(int k1l, int n2, int c) {
     return CONTIG ? c * (G * N2 * (N2 + 1)) + k1l * (N2 + 1) + n2 : k1l * (N2 * C + C) + n2 * C + c;
@@ -348,19 +348,27 @@ __global__ __launch_bounds__((LineCfg<T, NZ>::kThreads)) void k_axis_pad(const T
 // exchange (second-stage thread t takes k1 = 2t + p). A thread holds L1/2 inputs instead of L1, and
 // its addresses are one per-lane start plus wave-uniform steps (input r at start + r L2 stride,
 // output k2 at start + k2 L1 stride), so no per-element offsets stay live across tiles. The register
-// budget is held to the workgroups per CU that the LDS allows (256 threads: one wave per SIMD each).
-template <class T, int NZ> constexpr int fold_waves() {
-  constexpr size_t w = kMaxLds / pad_lds_bytes<T, NZ, 1>();
-  return w < 1 ? 1 : (w > 8 ? 8 : (int)w);
-}
+// budget is held to the waves per SIMD that the LDS allows. A workgroup owns C lines of 128 bytes
+// across (16 in complex64, 8 in complex128, whose exchange then takes half the LDS).
+template <class T, int NZ> struct FoldCfg {
+  static constexpr int N2 = LineCfg<T, NZ>::L2;
+  static constexpr int C = (sizeof(T) == 16 ? 128 : 256) / N2;
+  static constexpr int kThreads = N2 * C;
+  static constexpr size_t kLds = (PadLayout<T, NZ, false, 1, C>::kSize + 2 * kDenseMaxN + NZ) * sizeof(T);
+  static constexpr int kWaves = [] {
+    const int w = (int)((kMaxLds / kLds) * (kThreads / 64) + 3) / 4;  // workgroups per CU over 4 SIMDs
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+  }();
+};
 
 template <class T, int NZ, int SIGN, bool CONTIG>
-__global__ __launch_bounds__((LineCfg<T, NZ>::kThreads)) __attribute__((amdgpu_waves_per_eu(fold_waves<T, NZ>())))
+__global__ __launch_bounds__((FoldCfg<T, NZ>::kThreads)) __attribute__((amdgpu_waves_per_eu(FoldCfg<T, NZ>::kWaves)))
 void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
   using S = LineCfg<T, NZ>;
-  constexpr int N1 = S::L1, N2 = S::L2, H = N1 / 2, C = S::C, NT = S::kThreads;
+  using F = FoldCfg<T, NZ>;
+  constexpr int N1 = S::L1, N2 = S::L2, H = N1 / 2, C = F::C, NT = F::kThreads;
   static_assert(is_pow2(NZ) && S::Q == 2 && H == N2, "folded split");
-  using L = PadLayout<T, NZ, CONTIG, 1>;
+  using L = PadLayout<T, NZ, CONTIG, 1, C>;
   __shared__ T xch[L::kSize];
   __shared__ T tpre[kDenseMaxN], tpost[kDenseMaxN], tw[NZ];
   const int n = j.n, sft = j.s;
@@ -423,17 +431,18 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
 }
 
 template <class T, int NZ, bool CONTIG>
+static hipError_t launch_fold_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
+  constexpr int NT = FoldCfg<T, NZ>::kThreads;
+  if (sign < 0)
+    hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, -1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
+  else
+    hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, +1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
+  return hipGetLastError();
+}
+
+template <class T, int NZ, bool CONTIG>
 static hipError_t launch_pad_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
   constexpr int NT = LineCfg<T, NZ>::kThreads;
-  if constexpr (is_pow2(NZ) && NZ >= 8 && LineCfg<T, NZ>::Q == 2) {
-    if (2 * j.n <= NZ) {  // then s = (N_z - N)/2 >= N_z/4 >= L2
-      if (sign < 0)
-        hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, -1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
-      else
-        hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, +1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
-      return hipGetLastError();
-    }
-  }
   if (sign < 0)
     hipLaunchKernelGGL((k_axis_pad<T, NZ, -1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
   else
@@ -443,6 +452,17 @@ static hipError_t launch_pad_nzc(const T* src, T* dst, const PadJob& j, int sign
 
 template <class T, int NZ>
 static hipError_t launch_pad_nz(const T* src, T* dst, PadJob j, int sign, hipStream_t st) {
+  if constexpr (is_pow2(NZ) && NZ >= 8 && LineCfg<T, NZ>::Q == 2) {
+    if (2 * j.n <= NZ) {  // then s = (N_z - N)/2 >= N_z/4 >= L2, as the folded kernel assumes
+      constexpr int C = FoldCfg<T, NZ>::C;
+      j.tiles_per_outer = (j.ncols + C - 1) / C;
+      j.tiles = j.outer * j.tiles_per_outer;
+      const long long grid = j.tiles < 4096 ? j.tiles : 4096;
+      if (grid < 1) return hipSuccess;
+      return j.axis_stride == 1 ? launch_fold_nzc<T, NZ, true>(src, dst, j, sign, (unsigned)grid, st)
+                                : launch_fold_nzc<T, NZ, false>(src, dst, j, sign, (unsigned)grid, st);
+    }
+  }
   constexpr int C = LineCfg<T, NZ>::C;
   j.tiles_per_outer = (j.ncols + C - 1) / C;
   j.tiles = j.outer * j.tiles_per_outer;
