@@ -98,6 +98,27 @@ WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double
                                        void* w_out, void* stream);
 
 /*
+ * wolf_propagate_source -- the source of wolf_build_source propagated over z_m in one call
+ * (Algorithm 1: build the source, then Algorithms 2-3; Sec. 2.1 eqs. W_fresnel, W_farfield).
+ *
+ * The result is wolf_build_source(src, ..., w_out) followed by wolf_propagate_fresnel (far_field = 0)
+ * or wolf_propagate_farfield (far_field = 1) in place on w_out, bit for bit. Where the propagation
+ * runs the half-buffer slab pass (the default plan at N = 128; N = 32 or 64 with that pass set by
+ * wolf_set_plan) and the source is decided by
+ * the coordinates alone (WOLF_MODEL_GSM or WOLF_MODEL_COHERENT with WOLF_GEO_NONE, CIRCLE, SQUARE
+ * or ANNULUS, with or without a lens), that pass forms each W0 entry where it would load it, so W0
+ * is never written to memory: one write and one read of the N^4 array less. Other sources and sizes
+ * build W0 in w_out first.
+ *   src, n, pitch_m   as wolf_build_source (N a power of two in [2, 256]).
+ *   wavelength_m, z_m, kind, out_pitch_m   as wolf_propagate_fresnel.
+ *   far_field         0 (Fresnel) or 1 (far field).
+ *   w_out             device, N^4 complex of `dtype`, written in full.
+ */
+WOLF_API wolf_status wolf_propagate_source(const wolf_source* src, int32_t n, double pitch_m, double wavelength_m,
+                                           double z_m, int32_t far_field, int32_t kind, int32_t dtype, void* w_out,
+                                           double* out_pitch_m, void* stream);
+
+/*
  * wolf_propagate_fresnel -- free-space Fresnel propagation of W over distance z
  * (Sec. 2.1 eq. W_fresnel; Sec. 3.4 Algorithms 2-3).
  *

@@ -32,7 +32,8 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_set_plan", "wolf_get_plan", "wolf_autotune", "wolf_diag_embed", "wolf_fit_gradient",
             "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
             "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes",
-            "wolf_propagate_padded", "wolf_propagate_polychromatic", "wolf_polychromatic_work_bytes"]
+            "wolf_propagate_padded", "wolf_propagate_polychromatic", "wolf_polychromatic_work_bytes",
+            "wolf_propagate_source"]
 
 
 class WolfError(RuntimeError):
@@ -63,6 +64,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     pd = ctypes.POINTER(ctypes.c_double)
     sig = {
         "wolf_build_source": [ctypes.POINTER(_Source), i32, f64, i32, vp, vp],
+        "wolf_propagate_source": [ctypes.POINTER(_Source), i32, f64, f64, f64, i32, i32, i32, vp, pd, vp],
         "wolf_propagate_fresnel": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_farfield": [vp, vp, i32, f64, f64, f64, i32, i32, pd, vp],
         "wolf_propagate_lens": [vp, vp, i32, f64, f64, f64, i32, f64, f64, i32, i32, pd, vp],
@@ -160,21 +162,48 @@ def build_source(spec, n: int, pitch: float, dtype: torch.dtype = torch.complex6
         out = torch.empty((n, n, n, n), dtype=dtype, device=dev)
     else:
         _csd(out, "out")
-    imap = getattr(spec, "intensity_map", None)
-    mask = getattr(spec, "mask", None)
-    imap_t = None if imap is None else torch.as_tensor(np.asarray(imap) if not isinstance(imap, torch.Tensor) else imap,
-                                                       dtype=torch.float32).to(out.device).contiguous()
-    mask_t = None if mask is None else torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask,
-                                                       dtype=torch.uint8).to(out.device).contiguous()
-    s = _Source(int(spec.model), int(spec.geometry), float(spec.amplitude), float(spec.sigma_s_m),
-                float(spec.sigma_g_m), float(spec.geo_r0_m), float(spec.geo_r1_m),
-                imap_t.data_ptr() if imap_t is not None else None, mask_t.data_ptr() if mask_t is not None else None,
-                float(spec.lens_focal_m), float(spec.wavelength_m))
+    s, _keep = _source_struct(spec, out.device)
     _check(lib.wolf_build_source(ctypes.byref(s), n, pitch, _code(out.dtype), _ptr(out), _stream()),
            "wolf_build_source")
     # The uploaded map/mask may be freed now: the caching allocator orders their reuse after this
     # kernel on the same stream.
     return out
+
+
+def _source_struct(spec, device):
+    """wolf_source for `spec`, with a host intensity map or mask copied to `device` (the tensors are
+    returned so that they outlive the call)."""
+    imap = getattr(spec, "intensity_map", None)
+    mask = getattr(spec, "mask", None)
+    imap_t = None if imap is None else torch.as_tensor(np.asarray(imap) if not isinstance(imap, torch.Tensor) else imap,
+                                                       dtype=torch.float32).to(device).contiguous()
+    mask_t = None if mask is None else torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask,
+                                                       dtype=torch.uint8).to(device).contiguous()
+    s = _Source(int(spec.model), int(spec.geometry), float(spec.amplitude), float(spec.sigma_s_m),
+                float(spec.sigma_g_m), float(spec.geo_r0_m), float(spec.geo_r1_m),
+                imap_t.data_ptr() if imap_t is not None else None, mask_t.data_ptr() if mask_t is not None else None,
+                float(spec.lens_focal_m), float(spec.wavelength_m))
+    return s, (imap_t, mask_t)
+
+
+def propagate_source(spec, n: int, pitch: float, wavelength: float, z: float, farfield: bool = False,
+                     kind: int = SECONDARY, dtype: torch.dtype = torch.complex64,
+                     out: Optional[torch.Tensor] = None, device=None) -> Tuple[torch.Tensor, float]:
+    """The source of `spec` (as build_source) propagated over z in the Fresnel or far-field form, in
+    one call: equal to build_source followed by the in-place propagation, without W0 in memory where
+    the slab pass forms it. Returns (W_B, dx)."""
+    lib = load()
+    dev = torch.device(device) if device is not None else (out.device if out is not None else torch.device("cuda"))
+    if out is None:
+        out = torch.empty((n, n, n, n), dtype=dtype, device=dev)
+    else:
+        _csd(out, "out")
+    s, _keep = _source_struct(spec, out.device)
+    dx = ctypes.c_double(0.0)
+    _check(lib.wolf_propagate_source(ctypes.byref(s), n, pitch, wavelength, z, int(bool(farfield)), kind,
+                                     _code(out.dtype), _ptr(out), ctypes.byref(dx), _stream()),
+           "wolf_propagate_source")
+    return out, dx.value
 
 
 def _propagate(fn_name: str, w: torch.Tensor, pitch: float, wavelength: float, z: float, kind: int,

@@ -347,6 +347,56 @@ wolf_status propagate_common(const void* w_in, void* w_out, int32_t n, double pi
   return run_operator<double2>(static_cast<const double2*>(w_in), static_cast<double2*>(w_out), n, dtype, op, st);
 }
 
+// Validates a source description and converts it to pixel units (shared by the builder and the
+// propagation of a source).
+wolf_status source_params(const wolf_source* src, int32_t n, double pitch_m, wolf::SourceParams* out, const char* who) {
+  if (src == nullptr) return fail(WOLF_EINVAL, "%s: null source", who);
+  if (!pos_finite(pitch_m)) return fail(WOLF_EINVAL, "%s: pitch must be finite and > 0", who);
+  if (src->model < 0 || src->model > 3) return fail(WOLF_EINVAL, "%s: bad model %d", who, src->model);
+  if (src->geometry < 0 || src->geometry > 4) return fail(WOLF_EINVAL, "%s: bad geometry", who);
+  if (!std::isfinite(src->amplitude) || src->amplitude < 0) return fail(WOLF_EINVAL, "amplitude must be >= 0");
+  const bool uses_s = src->model == WOLF_MODEL_GSM;
+  const bool uses_g = src->model == WOLF_MODEL_GSM || src->model == WOLF_MODEL_MAP;
+  if (uses_s && !(src->sigma_s_m > 0)) return fail(WOLF_EINVAL, "sigma_s_m must be > 0 (or +inf)");
+  if (uses_g && !(src->sigma_g_m > 0)) return fail(WOLF_EINVAL, "sigma_g_m must be > 0 (or +inf)");
+  wolf::SourceParams sp{};
+  sp.model = src->model;
+  sp.geometry = src->geometry;
+  sp.amplitude = src->amplitude;
+  sp.inv4s2_px = (uses_s && !std::isinf(src->sigma_s_m)) ? pitch_m * pitch_m / (4.0 * src->sigma_s_m * src->sigma_s_m) : 0.0;
+  sp.inv2g2_px = (uses_g && !std::isinf(src->sigma_g_m)) ? pitch_m * pitch_m / (2.0 * src->sigma_g_m * src->sigma_g_m) : 0.0;
+  sp.inv4s2 = 0.0;
+  auto thresh = [&](double r) {
+    const double rho = r / pitch_m;
+    return (long long)std::floor(rho * rho * (1.0 + 1e-9));
+  };
+  if (src->geometry == WOLF_GEO_CIRCLE || src->geometry == WOLF_GEO_SQUARE || src->geometry == WOLF_GEO_ANNULUS) {
+    if (!pos_finite(src->geo_r0_m)) return fail(WOLF_EINVAL, "geo_r0_m must be finite and > 0");
+    if (src->geo_r0_m / pitch_m > 1e6) return fail(WOLF_EINVAL, "geo_r0_m too large");
+    sp.t0 = thresh(src->geo_r0_m);
+  }
+  if (src->geometry == WOLF_GEO_ANNULUS) {
+    if (!(src->geo_r1_m >= 0 && src->geo_r1_m < src->geo_r0_m)) return fail(WOLF_EINVAL, "need 0 <= geo_r1_m < geo_r0_m");
+    sp.t1 = thresh(src->geo_r1_m);
+  }
+  wolf_status s;
+  if (src->model == WOLF_MODEL_MAP) {
+    if ((s = check_buf(src->intensity_map, (size_t)n * n * 4, "intensity_map")) != WOLF_OK) return s;
+    sp.imap = src->intensity_map;
+  }
+  if (src->geometry == WOLF_GEO_MASK) {
+    if ((s = check_buf(src->mask, (size_t)n * n, "mask")) != WOLF_OK) return s;
+    sp.mask = src->mask;
+  }
+  if (src->lens_focal_m != 0.0) {
+    if (!std::isfinite(src->lens_focal_m) || !pos_finite(src->wavelength_m))
+      return fail(WOLF_EINVAL, "lens needs a finite focal length and a wavelength > 0");
+    sp.lens_alpha = pitch_m * pitch_m / (src->wavelength_m * src->lens_focal_m);
+  }
+  *out = sp;
+  return WOLF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -491,56 +541,48 @@ WOLF_API wolf_status wolf_propagate_adjoint(const void* g_out, void* g_in, int32
 
 WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double pitch_m, int32_t dtype, void* w_out,
                                        void* stream) {
-  if (src == nullptr) return fail(WOLF_EINVAL, "wolf_build_source: null source");
   if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_build_source: N=%d (even, 2..256)", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_build_source: bad dtype");
-  if (!pos_finite(pitch_m)) return fail(WOLF_EINVAL, "wolf_build_source: pitch must be finite and > 0");
-  if (src->model < 0 || src->model > 3) return fail(WOLF_EINVAL, "wolf_build_source: bad model %d", src->model);
-  if (src->geometry < 0 || src->geometry > 4) return fail(WOLF_EINVAL, "wolf_build_source: bad geometry");
-  if (!std::isfinite(src->amplitude) || src->amplitude < 0) return fail(WOLF_EINVAL, "amplitude must be >= 0");
-  const bool uses_s = src->model == WOLF_MODEL_GSM;
-  const bool uses_g = src->model == WOLF_MODEL_GSM || src->model == WOLF_MODEL_MAP;
-  if (uses_s && !(src->sigma_s_m > 0)) return fail(WOLF_EINVAL, "sigma_s_m must be > 0 (or +inf)");
-  if (uses_g && !(src->sigma_g_m > 0)) return fail(WOLF_EINVAL, "sigma_g_m must be > 0 (or +inf)");
   wolf::SourceParams sp{};
-  sp.model = src->model;
-  sp.geometry = src->geometry;
-  sp.amplitude = src->amplitude;
-  sp.inv4s2_px = (uses_s && !std::isinf(src->sigma_s_m)) ? pitch_m * pitch_m / (4.0 * src->sigma_s_m * src->sigma_s_m) : 0.0;
-  sp.inv2g2_px = (uses_g && !std::isinf(src->sigma_g_m)) ? pitch_m * pitch_m / (2.0 * src->sigma_g_m * src->sigma_g_m) : 0.0;
-  sp.inv4s2 = 0.0;
-  auto thresh = [&](double r) {
-    const double rho = r / pitch_m;
-    return (long long)std::floor(rho * rho * (1.0 + 1e-9));
-  };
-  if (src->geometry == WOLF_GEO_CIRCLE || src->geometry == WOLF_GEO_SQUARE || src->geometry == WOLF_GEO_ANNULUS) {
-    if (!pos_finite(src->geo_r0_m)) return fail(WOLF_EINVAL, "geo_r0_m must be finite and > 0");
-    if (src->geo_r0_m / pitch_m > 1e6) return fail(WOLF_EINVAL, "geo_r0_m too large");
-    sp.t0 = thresh(src->geo_r0_m);
-  }
-  if (src->geometry == WOLF_GEO_ANNULUS) {
-    if (!(src->geo_r1_m >= 0 && src->geo_r1_m < src->geo_r0_m)) return fail(WOLF_EINVAL, "need 0 <= geo_r1_m < geo_r0_m");
-    sp.t1 = thresh(src->geo_r1_m);
-  }
   wolf_status s;
-  if (src->model == WOLF_MODEL_MAP) {
-    if ((s = check_buf(src->intensity_map, (size_t)n * n * 4, "intensity_map")) != WOLF_OK) return s;
-    sp.imap = src->intensity_map;
-  }
-  if (src->geometry == WOLF_GEO_MASK) {
-    if ((s = check_buf(src->mask, (size_t)n * n, "mask")) != WOLF_OK) return s;
-    sp.mask = src->mask;
-  }
-  if (src->lens_focal_m != 0.0) {
-    if (!std::isfinite(src->lens_focal_m) || !pos_finite(src->wavelength_m))
-      return fail(WOLF_EINVAL, "lens needs a finite focal length and a wavelength > 0");
-    sp.lens_alpha = pitch_m * pitch_m / (src->wavelength_m * src->lens_focal_m);
-  }
+  if ((s = source_params(src, n, pitch_m, &sp, "wolf_build_source")) != WOLF_OK) return s;
   if ((s = check_buf(w_out, n4(n) * elem_bytes(dtype), "w_out")) != WOLF_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = dtype == WOLF_C64 ? wolf::launch_build_source<float2>(n, sp, static_cast<float2*>(w_out), st)
                                    : wolf::launch_build_source<double2>(n, sp, static_cast<double2*>(w_out), st);
   return launched(e, "wolf_build_source");
+}
+
+WOLF_API wolf_status wolf_propagate_source(const wolf_source* src, int32_t n, double pitch_m, double wavelength_m,
+                                           double z_m, int32_t far_field, int32_t kind, int32_t dtype, void* w_out,
+                                           double* out_pitch_m, void* stream) {
+  const char* who = "wolf_propagate_source";
+  if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d is not a power of two in [2, 256]", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype %d", who, dtype);
+  if (far_field != 0 && far_field != 1) return fail(WOLF_EINVAL, "%s: far_field must be 0 or 1", who);
+  if (!pos_finite(pitch_m) || !pos_finite(wavelength_m) || !pos_finite(z_m))
+    return fail(WOLF_EINVAL, "%s: pitch, wavelength and z must be finite and > 0", who);
+  if (kind != WOLF_SECONDARY && kind != WOLF_PRIMARY) return fail(WOLF_EINVAL, "%s: bad kind %d", who, kind);
+  wolf::SourceParams sp{};
+  wolf_status s;
+  if ((s = source_params(src, n, pitch_m, &sp, who)) != WOLF_OK) return s;
+  if ((s = check_buf(w_out, n4(n) * elem_bytes(dtype), "w_out")) != WOLF_OK) return s;
+  const wolf::Plan plan = plan_for(n, dtype);
+  const bool gen = plan.fused_slab == 3 && !plan.coop &&
+                   (dtype == WOLF_C64 ? wolf::gen_slab_supported<float2>(n, sp) : wolf::gen_slab_supported<double2>(n, sp));
+  if (!gen) {  // build the array, then propagate it in place
+    if ((s = wolf_build_source(src, n, pitch_m, dtype, w_out, stream)) != WOLF_OK) return s;
+    return propagate_common(w_out, w_out, n, pitch_m, wavelength_m, z_m, far_field == 1, kind, dtype, false,
+                            out_pitch_m, stream, who);
+  }
+  const wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m, z_m, far_field == 1, kind, false);
+  if (out_pitch_m) *out_pitch_m = wavelength_m * z_m / ((double)n * pitch_m);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e =
+      dtype == WOLF_C64
+          ? wolf::launch_operator<float2>(n, nullptr, static_cast<float2*>(w_out), op, plan, nullptr, st, &sp)
+          : wolf::launch_operator<double2>(n, nullptr, static_cast<double2*>(w_out), op, plan, nullptr, st, &sp);
+  return launched(e, who);
 }
 
 WOLF_API wolf_status wolf_spectral_density(const void* w, int32_t n, int32_t dtype, void* s_out, void* stream) {

@@ -17,6 +17,7 @@
 // n2 and writes X[k1 + N1 k2]. With this ownership the outputs of the N2 threads are contiguous.
 #include "wolf_device.hpp"
 #include "wolf_internal.hpp"
+#include "wolf_source.hpp"
 
 namespace wolf {
 
@@ -353,9 +354,14 @@ template <class T, int N> constexpr int half_waves_per_simd() {
   return (2 * half_lds_bytes<T, N>() <= kMaxLds ? 2 : 1) * (waves < 1 ? 1 : waves);
 }
 
-template <class T, int N, int SIGN>
+// GEN > 0: the slab's input is the source W0 of `sp` (wolf_source.hpp), formed where it would be
+// loaded, so W0 is never stored; the values are the builder's, bit for bit. Sources decided by the
+// coordinates alone (GSM and coherent models, a lens): GEN = 1 without an aperture, GEN = 2 with a
+// circle, square or annulus. The column phase uses the first N H entries of the buffer; the two
+// source rows sit behind them until the row phase.
+template <class T, int N, int SIGN, int GEN>
 __global__ __launch_bounds__(Split<N>::N2 * N / 2) __attribute__((amdgpu_waves_per_eu(half_waves_per_simd<T, N>())))
-void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pupil pu) {
+void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pupil pu, SourceParams sp) {
   using S = Split<N>;
   using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
@@ -365,6 +371,9 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
   static_assert(H % N1 == 0 && SP >= N, "half slab layout");
   __shared__ T buf[H * SP];
   __shared__ T tpre[N], tpost[N], tw[N], sc[2];
+  static_assert(H * SP - N * H >= 2 * N, "source rows behind the column-phase buffer");
+  T* const gx = buf + N * H;  // GEN: the source rows fx(i1, .), fy(j1, .)
+  T* const gy = gx + N;
 
   const long long p1 = blockIdx.x;
   const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
@@ -372,6 +381,10 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
     tpre[i] = chirp_entry<T>(pre, i, N);
     tpost[i] = chirp_entry<T>(post, i, N);
     tw[i] = twiddle_entry<T, SIGN>(i, N);
+    if constexpr (GEN > 0) {
+      gx[i] = axis_factor<T>(sp, a1, i, N);
+      gy[i] = axis_factor<T>(sp, b1, i, N);
+    }
   }
   if (threadIdx.x < 2) sc[threadIdx.x] = chirp_entry<T>(slab_pre, threadIdx.x == 0 ? a1 : b1, N);
   const int tid = threadIdx.x;
@@ -388,8 +401,19 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
   for (int vt = 0; vt < 2; ++vt) {
     const int c = cl + H * vt;
     T v[N1];
+    if constexpr (GEN == 1) {
+      const R am1 = (R)sp.amplitude;  // A m(p1) with no aperture and no map
+      const T fy = gy[c];
 #pragma unroll
-    for (int a = 0; a < N1; ++a) v[a] = in[(N2 * a + t1) * N + c];
+      for (int a = 0; a < N1; ++a) v[a] = cscale(cmul(gx[N2 * a + t1], fy), am1);
+    } else if constexpr (GEN == 2) {
+      const R am1 = slab_scale<R>(sp, a1, b1, N);
+#pragma unroll
+      for (int a = 0; a < N1; ++a) v[a] = source_entry_coords<T>(sp, gx, gy, am1, N2 * a + t1, c, N);
+    } else {
+#pragma unroll
+      for (int a = 0; a < N1; ++a) v[a] = in[(N2 * a + t1) * N + c];
+    }
     if (pu.geo != 0) {
 #pragma unroll
       for (int a = 0; a < N1; ++a)
@@ -589,17 +613,25 @@ template <class T, int N> constexpr long long slab_resident_wgs() {
 
 template <class T, int N, int SIGN>
 static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chirp& pre, const Chirp& post,
-                                const Chirp& slab_pre, const Pupil& pu, int mode, hipStream_t st) {
+                                const Chirp& slab_pre, const Pupil& pu, int mode, const SourceParams* gen,
+                                hipStream_t st) {
   if (slabs > 0x7fffffffll) return hipErrorInvalidValue;
   if (mode == 3) {
     if constexpr (N >= 32 && N <= 128 && half_lds_bytes<T, N>() <= kMaxLds) {
-      hipLaunchKernelGGL((k_slab_half<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N / 2), 0, st, src,
-                         dst, pre, post, slab_pre, pu);
+      const dim3 grid((unsigned)slabs), block(Split<N>::N2 * N / 2);
+      if (gen && gen->geometry == 0)
+        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 1>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen);
+      else if (gen)
+        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 2>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen);
+      else
+        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 0>), grid, block, 0, st, src, dst, pre, post, slab_pre, pu,
+                           SourceParams{});
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
     }
   }
+  if (gen) return hipErrorInvalidValue;  // only the half-buffer pass generates its input
   if constexpr (slab_lds_bytes<T, N>() > kMaxLds) {
     return hipErrorInvalidValue;
   } else {
@@ -645,9 +677,12 @@ hipError_t launch_row_pass(int n, const T* src, T* dst, long long rows, int sign
 
 template <class T>
 hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slabs, int sign, const Chirp& pre,
-                            const Chirp& post, const Chirp& slab_pre, const Pupil& pu, int mode, hipStream_t st) {
-  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, pu, mode, st))) }
-  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, pu, mode, st)))
+                            const Chirp& post, const Chirp& slab_pre, const Pupil& pu, int mode, const SourceParams* gen,
+                            hipStream_t st) {
+  if (sign < 0) {
+    WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, pu, mode, gen, st)))
+  }
+  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, pu, mode, gen, st)))
 }
 
 template <class T>
@@ -686,6 +721,13 @@ template <class T> bool slab_pass_supported(int n) {
     default: return false;
   }
 }
+
+template <class T> bool gen_slab_supported(int n, const SourceParams& sp) {
+  if ((sp.model != 0 && sp.model != 2) || sp.geometry < 0 || sp.geometry > 3) return false;
+  return half_slab_supported<T>(n);
+}
+template bool gen_slab_supported<float2>(int, const SourceParams&);
+template bool gen_slab_supported<double2>(int, const SourceParams&);
 
 template <class T> bool half_slab_supported(int n) {
   switch (n) {
@@ -734,10 +776,11 @@ int axis_tile_cols(int n, int elem_bytes) {
 // ---------------------------------------------------------------------------------------------
 template <class T>
 hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, void* counters,
-                           hipStream_t st) {
+                           hipStream_t st, const SourceParams* gen) {
   const long long N = n, NN = N * N, NNN = NN * N;
   hipError_t e;
   const Chirp ident{0.0, 1.0, +1, 0};
+  if (gen && plan.fused_slab != 3) return hipErrorInvalidValue;
   // An input pupil is applied while the slab pass loads; the other schedules apply it first.
   if (op.pupil.geo != 0 && !plan.fused_slab) {
     e = launch_apply_pupil<T>(n, in, out, op.pupil, st);
@@ -746,7 +789,7 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   }
   // Second-point axes (i2, j2).
   if (plan.fused_slab) {
-    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, op.pupil, plan.fused_slab, st);
+    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, op.pupil, plan.fused_slab, gen, st);
     if (e != hipSuccess) return e;
   } else {
     const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk
@@ -859,9 +902,9 @@ template hipError_t launch_operator_diag<double2>(int, const double*, double2*, 
                                                   void*, hipStream_t);
 
 template hipError_t launch_operator<float2>(int, const float2*, float2*, const OperatorTables&, const Plan&, void*,
-                                            hipStream_t);
+                                            hipStream_t, const SourceParams*);
 template hipError_t launch_operator<double2>(int, const double2*, double2*, const OperatorTables&, const Plan&, void*,
-                                             hipStream_t);
+                                             hipStream_t, const SourceParams*);
 template bool slab_pass_supported<float2>(int);
 template bool slab_pass_supported<double2>(int);
 

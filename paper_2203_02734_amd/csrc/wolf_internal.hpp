@@ -56,10 +56,14 @@ struct AxisJob {
   Chirp pre, post;
 };
 
+struct SourceParams;
+
 // `counters`: per-stream device scratch of at least coop_counter_bytes(n) (used when plan.coop).
+// `gen` (half-buffer slab pass only, plan.fused_slab == 3): the input is the source described by
+// *gen, formed inside the slab pass; `in` is not read.
 template <class T>
 hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, void* counters,
-                           hipStream_t st);
+                           hipStream_t st, const SourceParams* gen = nullptr);
 // The operator applied to diag(g), g an N*N real array (no N^4 input is read).
 template <class T>
 hipError_t launch_operator_diag(int n, const typename real_of<T>::type* g, T* out, const OperatorTables& op,
@@ -141,6 +145,8 @@ struct SourceParams {
 
 template <class T>
 hipError_t launch_build_source(int n, const SourceParams& sp, T* w, hipStream_t st);
+// The half-buffer slab pass can form this source itself (launch_operator's `gen`) at this N.
+template <class T> bool gen_slab_supported(int n, const SourceParams& sp);
 
 template <class T>
 hipError_t launch_spectral_density(int n, const T* w, typename real_of<T>::type* s, hipStream_t st);
