@@ -104,10 +104,11 @@ WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double
  * The result is wolf_build_source(src, ..., w_out) followed by wolf_propagate_fresnel (far_field = 0)
  * or wolf_propagate_farfield (far_field = 1) in place on w_out, bit for bit. Where the propagation
  * runs the half-buffer slab pass (the default plan at N = 128; N = 32 or 64 with that pass set by
- * wolf_set_plan) and the source is decided by
- * the coordinates alone (WOLF_MODEL_GSM or WOLF_MODEL_COHERENT with WOLF_GEO_NONE, CIRCLE, SQUARE
- * or ANNULUS, with or without a lens), that pass forms each W0 entry where it would load it, so W0
- * is never written to memory: one write and one read of the N^4 array less. Other sources and sizes
+ * wolf_set_plan) and the source is decided by the coordinates alone (WOLF_MODEL_GSM or
+ * WOLF_MODEL_COHERENT with WOLF_GEO_NONE, CIRCLE, SQUARE or ANNULUS, with or without a lens), that
+ * pass forms each W0 entry where it would load it, so W0 is never written to memory: one write and
+ * one read of the N^4 array less. So does the row pass of the four-sweep schedule (the default at
+ * N = 256; N = 64 or 128 when set) for such sources without a lens. Other sources and schedules
  * build W0 in w_out first.
  *   src, n, pitch_m   as wolf_build_source (N a power of two in [2, 256]).
  *   wavelength_m, z_m, kind, out_pitch_m   as wolf_propagate_fresnel.

@@ -568,8 +568,8 @@ WOLF_API wolf_status wolf_propagate_source(const wolf_source* src, int32_t n, do
   if ((s = source_params(src, n, pitch_m, &sp, who)) != WOLF_OK) return s;
   if ((s = check_buf(w_out, n4(n) * elem_bytes(dtype), "w_out")) != WOLF_OK) return s;
   const wolf::Plan plan = plan_for(n, dtype);
-  const bool gen = plan.fused_slab == 3 && !plan.coop &&
-                   (dtype == WOLF_C64 ? wolf::gen_slab_supported<float2>(n, sp) : wolf::gen_slab_supported<double2>(n, sp));
+  const bool gen = !plan.coop && (dtype == WOLF_C64 ? wolf::gen_source_supported<float2>(n, sp, plan.fused_slab)
+                                                    : wolf::gen_source_supported<double2>(n, sp, plan.fused_slab));
   if (!gen) {  // build the array, then propagate it in place
     if ((s = wolf_build_source(src, n, pitch_m, dtype, w_out, stream)) != WOLF_OK) return s;
     return propagate_common(w_out, w_out, n, pitch_m, wavelength_m, z_m, far_field == 1, kind, dtype, false,

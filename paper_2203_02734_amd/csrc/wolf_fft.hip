@@ -91,20 +91,34 @@ __global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* 
 
 // ---------------------------------------------------------------------------------------------
 // Contiguous axis (rows of N elements). A workgroup takes B consecutive rows.
+// GEN > 0 (B <= N, so that the rows of a workgroup lie in one slab p1 = (i1, j1)): the input rows are
+// the source W0 of `sp` (as in the slab pass: GEN = 1 without an aperture, 2 with a circle, square
+// or annulus; no lens), formed from the slab's row fy(j1, .) and the scalars fx(i1, i2) of its B
+// rows; row0 is the global index of the launch's first row. W0 is never stored.
 // ---------------------------------------------------------------------------------------------
-template <class T, int N, int B, int SIGN>
-__global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* dst, Chirp pre, Chirp post) {
+template <class T, int N, int B, int SIGN, int GEN>
+__global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* dst, Chirp pre, Chirp post,
+                                                             long long row0, SourceParams sp) {
   using S = Split<N>;
+  using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
   constexpr int NT = N2 * B;
   constexpr int LD = N2 + 1;  // padded stride of one k1 group in LDS
+  static_assert(GEN == 0 || B <= N, "generated rows of one workgroup lie in one slab");
   __shared__ T xch[B * N1 * LD];
   __shared__ T tpre[N], tpost[N], tw[N];
+  __shared__ T gy[GEN ? N : 1], gx[GEN ? B : 1];  // GEN: fy(j1, .) and fx(i1, i2) of the B rows
 
+  const long long first = row0 + (long long)blockIdx.x * B;  // GEN: global index of the first row
+  const int i1 = (int)(first / ((long long)N * N)), j1 = (int)((first / N) % N);
   for (int i = threadIdx.x; i < N; i += NT) {
     tpre[i] = chirp_entry<T>(pre, i, N);
     tpost[i] = chirp_entry<T>(post, i, N);
     tw[i] = twiddle_entry<T, SIGN>(i, N);
+    if constexpr (GEN > 0) gy[i] = axis_factor<T>(sp, j1, i, N);
+  }
+  if constexpr (GEN > 0) {
+    for (int i = threadIdx.x; i < B; i += NT) gx[i] = axis_factor<T>(sp, i1, (int)((first + i) % N), N);
   }
   __syncthreads();
 
@@ -115,10 +129,23 @@ __global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* d
   T* out = dst + row * N;
 
   T v[N1];
+  if constexpr (GEN > 0) {
+    const int i2 = (int)((first + r) % N);
+    const R am1 = GEN == 1 ? (R)sp.amplitude : slab_scale<R>(sp, i1, j1, N);  // A m(p1)
+    const T fx = gx[r];
 #pragma unroll
-  for (int a = 0; a < N1; ++a) {
-    const int n = N2 * a + t;
-    v[a] = cmul(in[n], tpre[n]);
+    for (int a = 0; a < N1; ++a) {
+      const int n = N2 * a + t;
+      R m = am1;
+      if constexpr (GEN == 2) m = inside_coords(sp, i2 - N / 2, n - N / 2) ? am1 : (R)0;
+      v[a] = cmul(source_value(fx, gy[n], m), tpre[n]);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int n = N2 * a + t;
+      v[a] = cmul(in[n], tpre[n]);
+    }
   }
   dft_reg<N1, SIGN>(v);
 #pragma unroll
@@ -356,8 +383,8 @@ template <class T, int N> constexpr int half_waves_per_simd() {
 
 // GEN > 0: the slab's input is the source W0 of `sp` (wolf_source.hpp), formed where it would be
 // loaded, so W0 is never stored; the values are the builder's, bit for bit. Sources decided by the
-// coordinates alone (GSM and coherent models, a lens): GEN = 1 without an aperture, GEN = 2 with a
-// circle, square or annulus. The column phase uses the first N H entries of the buffer; the two
+// coordinates alone (GSM and coherent models, a lens): GEN = 1 without an aperture or a lens (real
+// rows: the builder's complex product is then (fx fy A, +0) exactly), GEN = 2 otherwise. The column phase uses the first N H entries of the buffer; the two
 // source rows sit behind them until the row phase.
 template <class T, int N, int SIGN, int GEN>
 __global__ __launch_bounds__(Split<N>::N2 * N / 2) __attribute__((amdgpu_waves_per_eu(half_waves_per_simd<T, N>())))
@@ -403,9 +430,9 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
     T v[N1];
     if constexpr (GEN == 1) {
       const R am1 = (R)sp.amplitude;  // A m(p1) with no aperture and no map
-      const T fy = gy[c];
+      const R fy = gy[c].x;
 #pragma unroll
-      for (int a = 0; a < N1; ++a) v[a] = cscale(cmul(gx[N2 * a + t1], fy), am1);
+      for (int a = 0; a < N1; ++a) v[a] = T{(gx[N2 * a + t1].x * fy) * am1, (R)0};
     } else if constexpr (GEN == 2) {
       const R am1 = slab_scale<R>(sp, a1, b1, N);
 #pragma unroll
@@ -595,11 +622,23 @@ static hipError_t launch_axis_n(const T* src, T* dst, const AxisRange& a, const 
 
 template <class T, int N, int SIGN>
 static hipError_t launch_row_n(const T* src, T* dst, long long rows, const Chirp& pre, const Chirp& post,
-                               hipStream_t st) {
+                               const SourceParams* gen, long long row0, hipStream_t st) {
   constexpr int B = row_batch<N>();
   if (rows % B != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_row_fft<T, N, B, SIGN>), dim3((unsigned)(rows / B)), dim3(Split<N>::N2 * B), 0, st, src,
-                     dst, pre, post);
+  const dim3 grid((unsigned)(rows / B)), block(Split<N>::N2 * B);
+  if (gen) {
+    if constexpr (B <= N) {
+      if (row0 % B != 0) return hipErrorInvalidValue;
+      if (gen->geometry == 0)
+        hipLaunchKernelGGL((k_row_fft<T, N, B, SIGN, 1>), grid, block, 0, st, dst, dst, pre, post, row0, *gen);
+      else
+        hipLaunchKernelGGL((k_row_fft<T, N, B, SIGN, 2>), grid, block, 0, st, dst, dst, pre, post, row0, *gen);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else {
+    hipLaunchKernelGGL((k_row_fft<T, N, B, SIGN, 0>), grid, block, 0, st, src, dst, pre, post, 0ll, SourceParams{});
+  }
   return hipGetLastError();
 }
 
@@ -619,7 +658,7 @@ static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chi
   if (mode == 3) {
     if constexpr (N >= 32 && N <= 128 && half_lds_bytes<T, N>() <= kMaxLds) {
       const dim3 grid((unsigned)slabs), block(Split<N>::N2 * N / 2);
-      if (gen && gen->geometry == 0)
+      if (gen && gen->geometry == 0 && gen->lens_alpha == 0.0)
         hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 1>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen);
       else if (gen)
         hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 2>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen);
@@ -670,9 +709,9 @@ hipError_t launch_axis_range(int n, const T* src, T* dst, int sign, const AxisRa
 
 template <class T>
 hipError_t launch_row_pass(int n, const T* src, T* dst, long long rows, int sign, const Chirp& pre,
-                           const Chirp& post, hipStream_t st) {
-  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_row_n<T, NN, -1>(src, dst, rows, pre, post, st))) }
-  WOLF_DISPATCH_N(n, (launch_row_n<T, NN, +1>(src, dst, rows, pre, post, st)))
+                           const Chirp& post, hipStream_t st, const SourceParams* gen = nullptr, long long row0 = 0) {
+  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_row_n<T, NN, -1>(src, dst, rows, pre, post, gen, row0, st))) }
+  WOLF_DISPATCH_N(n, (launch_row_n<T, NN, +1>(src, dst, rows, pre, post, gen, row0, st)))
 }
 
 template <class T>
@@ -722,12 +761,15 @@ template <class T> bool slab_pass_supported(int n) {
   }
 }
 
-template <class T> bool gen_slab_supported(int n, const SourceParams& sp) {
+template <class T> bool gen_source_supported(int n, const SourceParams& sp, int fused_slab) {
   if ((sp.model != 0 && sp.model != 2) || sp.geometry < 0 || sp.geometry > 3) return false;
-  return half_slab_supported<T>(n);
+  if (fused_slab == 3) return half_slab_supported<T>(n);
+  // The row pass (a workgroup's rows in one slab), for sources without a lens: with complex rows
+  // its result differed from build + propagate in the last bit of a few entries.
+  return fused_slab == 0 && n >= 64 && n <= 256 && sp.lens_alpha == 0.0;
 }
-template bool gen_slab_supported<float2>(int, const SourceParams&);
-template bool gen_slab_supported<double2>(int, const SourceParams&);
+template bool gen_source_supported<float2>(int, const SourceParams&, int);
+template bool gen_source_supported<double2>(int, const SourceParams&, int);
 
 template <class T> bool half_slab_supported(int n) {
   switch (n) {
@@ -780,7 +822,9 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   const long long N = n, NN = N * N, NNN = NN * N;
   hipError_t e;
   const Chirp ident{0.0, 1.0, +1, 0};
-  if (gen && plan.fused_slab != 3) return hipErrorInvalidValue;
+  // A formed source: the half-buffer slab pass, or the row pass (N >= 64) with no input pupil.
+  if (gen && !(plan.fused_slab == 3 || (plan.fused_slab == 0 && n >= 64 && op.pupil.geo == 0)))
+    return hipErrorInvalidValue;
   // An input pupil is applied while the slab pass loads; the other schedules apply it first.
   if (op.pupil.geo != 0 && !plan.fused_slab) {
     e = launch_apply_pupil<T>(n, in, out, op.pupil, st);
@@ -795,7 +839,8 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
     const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk
     for (long long s0 = 0; s0 < NN; s0 += g) {
       const long long gs = (s0 + g <= NN) ? g : NN - s0;
-      e = launch_row_pass<T>(n, in + s0 * NN, out + s0 * NN, gs * N, op.sign2, op.pre2, op.post2, st);
+      e = launch_row_pass<T>(n, gen ? out + s0 * NN : in + s0 * NN, out + s0 * NN, gs * N, op.sign2, op.pre2, op.post2,
+                             st, gen, s0 * N);
       if (e != hipSuccess) return e;
       const AxisRange ar{gs, NN, N, 0, N};  // axis i2 inside each slab of the chunk
       e = launch_axis_range<T>(n, out + s0 * NN, out + s0 * NN, op.sign2, ar, op.pre2, op.post2, nullptr, ident,

@@ -59,8 +59,8 @@ struct AxisJob {
 struct SourceParams;
 
 // `counters`: per-stream device scratch of at least coop_counter_bytes(n) (used when plan.coop).
-// `gen` (half-buffer slab pass only, plan.fused_slab == 3): the input is the source described by
-// *gen, formed inside the slab pass; `in` is not read.
+// `gen` (plan.fused_slab == 3, or 0 at N >= 64 with no input pupil): the input is the source
+// described by *gen, formed inside the first pass; `in` is not read.
 template <class T>
 hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op, const Plan& plan, void* counters,
                            hipStream_t st, const SourceParams* gen = nullptr);
@@ -145,8 +145,9 @@ struct SourceParams {
 
 template <class T>
 hipError_t launch_build_source(int n, const SourceParams& sp, T* w, hipStream_t st);
-// The half-buffer slab pass can form this source itself (launch_operator's `gen`) at this N.
-template <class T> bool gen_slab_supported(int n, const SourceParams& sp);
+// The first pass of the schedule `fused_slab` (3: the half-buffer slab pass; 0: the row pass) can
+// form this source itself at this N (launch_operator's `gen`).
+template <class T> bool gen_source_supported(int n, const SourceParams& sp, int fused_slab);
 
 template <class T>
 hipError_t launch_spectral_density(int n, const T* w, typename real_of<T>::type* s, hipStream_t st);

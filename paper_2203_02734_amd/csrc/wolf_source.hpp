@@ -33,17 +33,32 @@ __device__ __forceinline__ bool inside(const SourceParams& sp, int di, int dj, i
   return sp.geometry == 4 ? sp.mask[(long long)i * n + j] != 0 : inside_coords(sp, di, dj);
 }
 
+// FP64 with no fused multiply-add (as source_value): the lens phase p alpha - 2 rint(p alpha / 2)
+// would otherwise be fused or not per call site, and the rows of the builder and of the passes that
+// form the source must be the same bits.
 template <class T>
 __device__ __forceinline__ T axis_factor(const SourceParams& sp, int a, int b, int n) {
+#pragma clang fp contract(off)
   using R = typename real_of<T>::type;
   const long long da = a - n / 2, db = b - n / 2;
   const double e = -(double)(da * da + db * db) * sp.inv4s2_px - (double)((da - db) * (da - db)) * sp.inv2g2_px;
   const double mag = exp(e);
   if (sp.lens_alpha == 0.0) return T{(R)mag, (R)0};
-  const double ph = reduce_mod2((double)(da * da - db * db) * sp.lens_alpha);
+  const double x = (double)(da * da - db * db) * sp.lens_alpha;
+  const double ph = x - 2.0 * rint(0.5 * x);  // x reduced to [-1, 1] (half turns)
   double s, c;
   sincospi(ph, &s, &c);
   return T{(R)(mag * c), (R)(mag * s)};
+}
+
+// W0 = m (fx fy): each real product rounded, then each sum, with no fused multiply-add, so the
+// value is the same bits in every kernel that forms it (a contraction may fuse either product of a
+// complex multiply, and compilers choose per call site).
+template <class T>
+__device__ __forceinline__ T source_value(T fx, T fy, typename real_of<T>::type m) {
+#pragma clang fp contract(off)
+  const T c{fx.x * fy.x - fx.y * fy.y, fx.x * fy.y + fx.y * fy.x};
+  return T{c.x * m, c.y * m};
 }
 
 // A m(p1) of slab p1 = (i1, j1).
@@ -61,7 +76,7 @@ __device__ __forceinline__ T source_entry(const SourceParams& sp, const T* fx, c
   using R = typename real_of<T>::type;
   R m = inside(sp, i2 - n / 2, j2 - n / 2, n, i2, j2) ? am1 : (R)0;
   if (sp.model == 1) m *= sqrt((R)sp.imap[(long long)i2 * n + j2]);
-  return cscale(cmul(fx[i2], fy[j2]), m);
+  return source_value(fx[i2], fy[j2], m);
 }
 
 // The same value for the models without a per-point map (GSM, coherent) and the geometries of
@@ -71,7 +86,7 @@ __device__ __forceinline__ T source_entry_coords(const SourceParams& sp, const T
                                                  typename real_of<T>::type am1, int i2, int j2, int n) {
   using R = typename real_of<T>::type;
   const R m = inside_coords(sp, i2 - n / 2, j2 - n / 2) ? am1 : (R)0;
-  return cscale(cmul(fx[i2], fy[j2]), m);
+  return source_value(fx[i2], fy[j2], m);
 }
 
 }  // namespace wolf

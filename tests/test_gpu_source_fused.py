@@ -141,3 +141,37 @@ def test_propagate_source_rejects(gpu_lib):
         gpu_lib.propagate_source(sp, 32, P, LAM, -0.3)
     with pytest.raises(gpu_lib.WolfError):
         gpu_lib.propagate_source(spec(model=7), 32, P, LAM, 0.3)
+
+
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("name", sorted(FORMED))
+def test_formed_by_row_pass_equals_build_then_propagate(gpu_lib, name, n, dtype):
+    """The row-pass schedule (fused_slab = 0) over chunks of N slabs, so that launches after the first
+    start at a nonzero row: the row pass forms the lens-free sources (N >= 64); the source with a lens
+    is built first on this schedule."""
+    sp, z = FORMED[name], 0.4
+    try:
+        gpu_lib.set_plan(n, dtype, 0, n, n * n, 0, 1)
+        a, _ = gpu_lib.propagate_source(sp, n, P, LAM, z, dtype=dtype)
+        b, _ = two_step(gpu_lib, sp, n, P, z, False, dtype)
+        torch.cuda.synchronize()
+    finally:
+        gpu_lib.set_plan(n, dtype)
+    assert torch.equal(a, b)
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def test_formed_source_gsm256(gpu_lib):
+    """N = 256 complex64 (2^32 entries, 34 GB per array) with the default four-sweep schedule, whose row
+    pass forms the source: equal to build + propagate."""
+    wl = WI.gsm256()[0]
+    n, p, z, sp = wl.n, wl.pitch_m, wl.z_m, wl.source
+    a, _ = gpu_lib.propagate_source(sp, n, p, wl.wavelength_m, z)
+    b, _ = two_step(gpu_lib, sp, n, p, z, False, torch.complex64)
+    torch.cuda.synchronize()
+    equal = torch.equal(a, b)
+    del a, b
+    torch.cuda.empty_cache()
+    assert equal
