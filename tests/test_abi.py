@@ -119,6 +119,25 @@ def test_build_source_validation(lib):
         assert lib.wolf_build_source(ctypes.byref(s), 16, 1e-5, 0, None, None) == -1
 
 
+def test_propagate_source_validation(lib):
+    """wolf_propagate_source checks its size, physics, flags and source before any device work."""
+    import paper_2203_02734_amd as wolf
+    S = wolf._Source
+    good = S(0, 0, 1.0, 1e-4, 1e-4, 0, 0, None, None, 0, 0)
+    for n in (0, 1, 3, 12, 200, 512, -4):
+        assert lib.wolf_propagate_source(ctypes.byref(good), n, 1e-5, 5e-7, 0.1, 0, 0, 0, None, None, None) == -2
+    for p, lam, z in ((0.0, 5e-7, 0.1), (1e-5, -5e-7, 0.1), (1e-5, 5e-7, float("nan")), (1e-5, 5e-7, 0.0)):
+        assert lib.wolf_propagate_source(ctypes.byref(good), 16, p, lam, z, 0, 0, 0, None, None, None) == -1
+    assert lib.wolf_propagate_source(ctypes.byref(good), 16, 1e-5, 5e-7, 0.1, 2, 0, 0, None, None, None) == -1  # flag
+    assert lib.wolf_propagate_source(ctypes.byref(good), 16, 1e-5, 5e-7, 0.1, 0, 5, 0, None, None, None) == -1  # kind
+    assert lib.wolf_propagate_source(ctypes.byref(good), 16, 1e-5, 5e-7, 0.1, 0, 0, 7, None, None, None) == -1  # dtype
+    assert lib.wolf_propagate_source(None, 16, 1e-5, 5e-7, 0.1, 0, 0, 0, None, None, None) == -1
+    assert b"null" in lib.wolf_last_error_message()
+    bad = S(0, 3, 1.0, 1e-4, 1e-4, 1e-4, 2e-4, None, None, 0, 0)  # annulus r1 >= r0
+    assert lib.wolf_propagate_source(ctypes.byref(bad), 16, 1e-5, 5e-7, 0.1, 0, 0, 0, None, None, None) == -1
+    assert lib.wolf_propagate_source(ctypes.byref(good), 16, 1e-5, 5e-7, 0.1, 0, 0, 0, None, None, None) == -1  # w_out
+
+
 def test_host_pointer_is_rejected(lib):
     buf = (ctypes.c_float * (2 * 16 ** 4))()
     p = ctypes.cast(buf, ctypes.c_void_p)
