@@ -37,12 +37,13 @@ def parse():
     ap.add_argument("--plan", default="auto",
                     help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or 'fused,slab_chunk,col_chunk'")
     ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None,
-                    choices=["propagate", "batch", "padded"],
+                    choices=["propagate", "batch", "padded", "source"],
                     help="run one untimed invocation for a counter run and exit: 'propagate' (build, in-place "
                          "propagation, then a 2 GiB runtime copy of known size for calibration), 'batch' "
                          "(the 64-pair observables batch, then the 16-wavelength sum at z = 0.5 m on the FFT grid of "
-                         "500 nm) or 'padded' (N = 200 complex64 in place, padded to "
-                         "N_z = 512, then unpadded)")
+                         "500 nm), 'padded' (N = 200 complex64 in place, padded to "
+                         "N_z = 512, then unpadded) or 'source' (build + propagation, then the one-call source "
+                         "propagation, five times each)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="rocprofv3 FETCH/WRITE summary for the current kernels (optional)")
     return ap.parse_args()
@@ -118,6 +119,17 @@ def main():
         wolf.propagate_fresnel(w, p, lam, z, out=w)
         cal = torch.empty_like(w)
         cal.copy_(w)  # calibration: 2 GiB read + 2 GiB write by the runtime's copy kernel
+        torch.cuda.synchronize()
+        print("pmc sample done", flush=True)
+        return
+    if args.pmc_sample == "source":
+        # Build + in-place propagation five times, then the source and its propagation in one call
+        # (wolf_propagate_source) five times.
+        for _ in range(5):
+            wolf.build_source(wl.source, n, p, out=w)
+            wolf.propagate_fresnel(w, p, lam, z, out=w)
+        for _ in range(5):
+            wolf.propagate_source(wl.source, n, p, lam, z, out=w)
         torch.cuda.synchronize()
         print("pmc sample done", flush=True)
         return
