@@ -338,6 +338,18 @@ def propagate_adjoint(g: np.ndarray, n: int, pitch: float, lam: float, z: float,
     return s * out
 
 
+def propagate_adjoint_separable(gx: np.ndarray, gy: np.ndarray, n: int, pitch: float, lam: float, z: float,
+                                farfield: bool = False, kind: int = KIND_SECONDARY) -> Tuple[np.ndarray, np.ndarray]:
+    """The adjoint of `propagate_adjoint` for a separable G_B[m1, n1, m2, n2] = gx[m1, m2] gy[n1, n2]:
+    P^H(G_B) = ax[i1, i2] ay[j1, j2], with ax = C d^4 Kx^T gx conj(Kx) and ay = Ky^T gy conj(Ky).
+    This is the same sum with the x and y output coordinates summed separately (as propagate_separable).
+    """
+    kx = kernel_1d(n, pitch, lam, z, farfield, "x")
+    ky = kernel_1d(n, pitch, lam, z, farfield, "y")
+    s = coupling_constant(lam, z, kind) * pitch ** 4
+    return s * (kx.T @ gx @ np.conj(kx)), ky.T @ gy @ np.conj(ky)
+
+
 # ----------------------------------------------------------------------------------------------
 # Exact free-space kernel (eq. h_free; the check of eq. approx_L and of the Fresnel expansion; R8)
 # ----------------------------------------------------------------------------------------------

@@ -142,6 +142,24 @@ def _csd(w: torch.Tensor, name: str = "w") -> int:
     return w.shape[0]
 
 
+def _out(out: torch.Tensor, shape, dtype: torch.dtype, device, name: str = "out") -> torch.Tensor:
+    """Checks a caller's output tensor against the call: a contiguous tensor of exactly `shape` and
+    `dtype` on `device`. The library only checks that a buffer lies inside one device allocation, and
+    torch's caching allocator places many tensors in one allocation, so a wrong shape or dtype here
+    would let the kernels write into neighbouring tensors."""
+    if not (isinstance(out, torch.Tensor) and out.is_cuda):
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(out.shape)}")
+    if out.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {out.dtype}")
+    if not out.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and out.device != torch.device(device):
+        raise ValueError(f"{name} is on {out.device}, expected {device}")
+    return out
+
+
 def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr() if t is not None else None)
 
@@ -161,8 +179,9 @@ def build_source(spec, n: int, pitch: float, dtype: torch.dtype = torch.complex6
     if out is None:
         out = torch.empty((n, n, n, n), dtype=dtype, device=dev)
     else:
-        _csd(out, "out")
-    s, _keep = _source_struct(spec, out.device)
+        _code(out.dtype)
+        _out(out, (n, n, n, n), out.dtype, dev)
+    s, _keep = _source_struct(spec, out.device, n)
     _check(lib.wolf_build_source(ctypes.byref(s), n, pitch, _code(out.dtype), _ptr(out), _stream()),
            "wolf_build_source")
     # The uploaded map/mask may be freed now: the caching allocator orders their reuse after this
@@ -170,15 +189,18 @@ def build_source(spec, n: int, pitch: float, dtype: torch.dtype = torch.complex6
     return out
 
 
-def _source_struct(spec, device):
+def _source_struct(spec, device, n: int):
     """wolf_source for `spec`, with a host intensity map or mask copied to `device` (the tensors are
-    returned so that they outlive the call)."""
+    returned so that they outlive the call). A map or mask must be (n, n)."""
     imap = getattr(spec, "intensity_map", None)
     mask = getattr(spec, "mask", None)
     imap_t = None if imap is None else torch.as_tensor(np.asarray(imap) if not isinstance(imap, torch.Tensor) else imap,
                                                        dtype=torch.float32).to(device).contiguous()
     mask_t = None if mask is None else torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask,
                                                        dtype=torch.uint8).to(device).contiguous()
+    for t, name in ((imap_t, "intensity_map"), (mask_t, "mask")):
+        if t is not None and tuple(t.shape) != (n, n):
+            raise ValueError(f"{name} must have shape ({n}, {n}), got {tuple(t.shape)}")
     s = _Source(int(spec.model), int(spec.geometry), float(spec.amplitude), float(spec.sigma_s_m),
                 float(spec.sigma_g_m), float(spec.geo_r0_m), float(spec.geo_r1_m),
                 imap_t.data_ptr() if imap_t is not None else None, mask_t.data_ptr() if mask_t is not None else None,
@@ -197,8 +219,9 @@ def propagate_source(spec, n: int, pitch: float, wavelength: float, z: float, fa
     if out is None:
         out = torch.empty((n, n, n, n), dtype=dtype, device=dev)
     else:
-        _csd(out, "out")
-    s, _keep = _source_struct(spec, out.device)
+        _code(out.dtype)
+        _out(out, (n, n, n, n), out.dtype, dev)
+    s, _keep = _source_struct(spec, out.device, n)
     dx = ctypes.c_double(0.0)
     _check(lib.wolf_propagate_source(ctypes.byref(s), n, pitch, wavelength, z, int(bool(farfield)), kind,
                                      _code(out.dtype), _ptr(out), ctypes.byref(dx), _stream()),
@@ -213,9 +236,7 @@ def _propagate(fn_name: str, w: torch.Tensor, pitch: float, wavelength: float, z
     if out is None:
         out = torch.empty_like(w)
     else:
-        _csd(out, "out")
-        if out.dtype != w.dtype or out.shape != w.shape:
-            raise ValueError("out must match w in shape and dtype")
+        _out(out, w.shape, w.dtype, w.device)
     dx = ctypes.c_double(0.0)
     _check(getattr(lib, fn_name)(_ptr(w), _ptr(out), n, pitch, wavelength, z, kind, _code(w.dtype),
                                  ctypes.byref(dx), _stream()), fn_name)
@@ -248,9 +269,7 @@ def propagate_lens(w: torch.Tensor, pitch: float, wavelength: float, focal: floa
     if out is None:
         out = torch.empty_like(w)
     else:
-        _csd(out, "out")
-        if out.dtype != w.dtype or out.shape != w.shape:
-            raise ValueError("out must match w in shape and dtype")
+        _out(out, w.shape, w.dtype, w.device)
     dx = ctypes.c_double(0.0)
     _check(lib.wolf_propagate_lens(_ptr(w), _ptr(out), n, pitch, wavelength, focal, pupil_geometry, pupil_radius,
                                    z, kind, _code(w.dtype), ctypes.byref(dx), _stream()), "wolf_propagate_lens")
@@ -276,9 +295,7 @@ def propagate_direct(w: torch.Tensor, pitch: float, wavelength: float, z: float,
     if out is None:
         out = torch.empty_like(w)
     else:
-        _csd(out, "out")
-        if out.dtype != w.dtype or out.shape != w.shape:
-            raise ValueError("out must match w in shape and dtype")
+        _out(out, w.shape, w.dtype, w.device)
     nbytes = int(lib.wolf_direct_work_bytes(n, _code(w.dtype)))
     if nbytes < 0:
         raise WolfError(EUNSUPPORTED, "wolf_direct_work_bytes", f"N={n} unsupported")
@@ -313,9 +330,7 @@ def propagate_padded(w: torch.Tensor, pitch: float, wavelength: float, z: float,
     if out is None:
         out = torch.empty_like(w)
     else:
-        _csd(out, "out")
-        if out.dtype != w.dtype or out.shape != w.shape:
-            raise ValueError("out must match w in shape and dtype")
+        _out(out, w.shape, w.dtype, w.device)
     if work is None:
         work = torch.empty_like(w)
     dx = ctypes.c_double(0.0)
@@ -333,7 +348,7 @@ def propagate_adjoint(g: torch.Tensor, pitch: float, wavelength: float, z: float
     if out is None:
         out = torch.empty_like(g)
     else:
-        _csd(out, "out")
+        _out(out, g.shape, g.dtype, g.device)
     _check(lib.wolf_propagate_adjoint(_ptr(g), _ptr(out), n, pitch, wavelength, z, int(bool(farfield)), kind,
                                       _code(g.dtype), _stream()), "wolf_propagate_adjoint")
     return out
@@ -350,7 +365,7 @@ def propagate_adjoint_diag(g: torch.Tensor, pitch: float, wavelength: float, z: 
     if out is None:
         out = torch.empty((n, n, n, n), dtype=dtype, device=g.device)
     else:
-        _csd(out, "out")
+        _out(out, (n, n, n, n), dtype, g.device)
     _check(lib.wolf_propagate_adjoint_diag(_ptr(g), _ptr(out), n, pitch, wavelength, z, int(bool(farfield)), kind,
                                            _code(dtype), _stream()), "wolf_propagate_adjoint_diag")
     return out
@@ -362,6 +377,8 @@ def spectral_density(w: torch.Tensor, out: Optional[torch.Tensor] = None) -> tor
     n = _csd(w)
     if out is None:
         out = torch.empty((n, n), dtype=_real(w.dtype), device=w.device)
+    else:
+        _out(out, (n, n), _real(w.dtype), w.device)
     _check(lib.wolf_spectral_density(_ptr(w), n, _code(w.dtype), _ptr(out), _stream()), "wolf_spectral_density")
     return out
 
@@ -371,9 +388,11 @@ def degree_of_coherence(w: torch.Tensor, ip: int = -1, jp: int = -1, floor_rel: 
     """mu(P1, .) for P1 = (ip, jp) (Algorithm 5), or the full N^4 mu when ip = jp = -1."""
     lib = load()
     n = _csd(w)
+    shape = (n, n, n, n) if (ip == -1 and jp == -1) else (n, n)
     if out is None:
-        shape = (n, n, n, n) if (ip == -1 and jp == -1) else (n, n)
         out = torch.empty(shape, dtype=w.dtype, device=w.device)
+    else:
+        _out(out, shape, w.dtype, w.device)
     _check(lib.wolf_degree_of_coherence(_ptr(w), n, _code(w.dtype), ip, jp, floor_rel, _ptr(out), _stream()),
            "wolf_degree_of_coherence")
     return out

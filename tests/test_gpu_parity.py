@@ -216,6 +216,75 @@ def test_adjoint_dot_product_gpu(gpu_lib):
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("farfield", [False, True])
+@pytest.mark.parametrize("dtype", DT)
+def test_adjoint_full_size_n128(gpu_lib, farfield, dtype):
+    """The adjoint at N = 128 (the size the step's adjoint runs at: the half-buffer slab pass with the
+    inverse DFT and the first-point passes with the direct DFT), all 2^28 entries, on a separable
+    random input G_B = gx (x) gy against the oracle's separable adjoint."""
+    n, p, z = 128, 20e-6, 0.5
+    r = WI.rng(93)
+    gx = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    gy = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    ax, ay = O.propagate_adjoint_separable(gx, gy, n, p, LAM, z, farfield)
+    gxt = torch.from_numpy(gx).to(dtype).cuda()
+    gyt = torch.from_numpy(gy).to(dtype).cuda()
+    g = (gxt[:, None, :, None] * gyt[None, :, None, :]).contiguous()
+    got = gpu_lib.propagate_adjoint(g, p, LAM, z, farfield, out=g)       # in place, as the step runs it
+    assert _separable_rel(got, ax, ay) < TOL[dtype]
+    del g, got
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("n", [32, 64])
+def test_autotune_keeps_a_valid_plan(gpu_lib, n, dtype):
+    """wolf_autotune times the candidate schedules and keeps the fastest: get_plan returns that plan,
+    set_plan accepts it again, and the propagation under it matches the oracle."""
+    p, z = 20e-6, 0.1
+    try:
+        plan, best = gpu_lib.autotune(n, dtype, reps=1)
+        assert best > 0 and math.isfinite(best)
+        assert gpu_lib.get_plan(n, dtype) == plan
+        assert plan["fused_slab"] in (0, 1, 2, 3)
+        gpu_lib.set_plan(n, dtype, plan["fused_slab"], plan["slab_chunk"], plan["col_chunk"], plan["coop_wgs"],
+                         plan["coop_lookahead"])
+        assert gpu_lib.get_plan(n, dtype) == plan
+        if n == 32:
+            w = WI.random_complex((n, n, n, n), seed=52)
+            ref, _ = O.propagate(w, n, p, LAM, z)
+            got, _ = gpu_lib.propagate_fresnel(dev(w, dtype), p, LAM, z)
+            assert rel(host(got), ref) < TOL[dtype]
+        else:
+            sp = spec(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3)
+            bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x"),
+                                           O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y"), n, p, LAM, z)
+            w = gpu_lib.build_source(sp, n, p, dtype)
+            gpu_lib.propagate_fresnel(w, p, LAM, z, out=w)
+            assert _separable_rel(w, bx, by) < TOL[dtype]
+    finally:
+        gpu_lib.set_plan(n, dtype)
+
+
+@pytest.mark.parametrize("dtype", DT)
+def test_nan_input_propagates_without_error(gpu_lib, dtype):
+    """A NaN in the input spreads through the transforms (no crash, no error status), S and mu are
+    computed, and the next call on clean data is correct (no sticky error)."""
+    n, p, z = 16, 20e-6, 0.1
+    w = WI.random_complex((n, n, n, n), seed=53)
+    bad = w.copy()
+    bad[3, 4, 5, 6] = np.nan
+    out, _ = gpu_lib.propagate_fresnel(dev(bad, dtype), p, LAM, z)
+    o = host(out)
+    assert np.isnan(o).all()                     # every output entry depends on every input entry
+    host(gpu_lib.spectral_density(out))
+    mu = host(gpu_lib.degree_of_coherence(out, 8, 8))
+    assert not np.isinf(mu).any()
+    ref, _ = O.propagate(w, n, p, LAM, z)
+    got, _ = gpu_lib.propagate_fresnel(dev(w, dtype), p, LAM, z)
+    assert rel(host(got), ref) < TOL[dtype]
+
+
 # ---------------------------------------------------------------------------------------------
 # Full-size workloads (N = 128 headline; N = 256), every entry against the separable oracle.
 # The GSM source is separable, so the oracle's output is bx[m1, m2] by[n1, n2]. The test forms
@@ -412,3 +481,42 @@ def test_overlapping_buffers_rejected(gpu_lib):
         assert b"too small" in lib.wolf_last_error_message()
     finally:
         hip.hipFree(ptr)
+
+
+def test_binding_rejects_mismatched_outputs(gpu_lib):
+    """Every binding checks a caller's `out` against the call (shape, dtype, device) and the map and
+    mask against N before anything is launched: a mis-sized tensor inside a larger caching-allocator
+    segment would otherwise be written past its end."""
+    n, p = 16, 20e-6
+    sp = spec(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3)
+    w = gpu_lib.build_source(sp, n, p, torch.complex64)
+    small = torch.empty((8, 8, 8, 8), dtype=torch.complex64, device="cuda")
+    wrong = torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda")
+    with pytest.raises(ValueError):
+        gpu_lib.build_source(sp, n, p, out=small)
+    with pytest.raises(ValueError):
+        gpu_lib.propagate_source(sp, n, p, LAM, 0.1, out=small)
+    with pytest.raises(ValueError):
+        gpu_lib.propagate_fresnel(w, p, LAM, 0.1, out=wrong)
+    with pytest.raises(ValueError):
+        gpu_lib.propagate_adjoint(w, p, LAM, 0.1, out=small)
+    with pytest.raises(ValueError):
+        gpu_lib.propagate_adjoint(w, p, LAM, 0.1, out=wrong)
+    g = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        gpu_lib.propagate_adjoint_diag(g, p, LAM, 0.1, out=small)
+    with pytest.raises(ValueError):
+        gpu_lib.spectral_density(w, out=torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        gpu_lib.spectral_density(w, out=torch.empty((8, 8), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        gpu_lib.degree_of_coherence(w, 1, 1, out=torch.empty((n, n, n, n), dtype=torch.complex64, device="cuda"))
+    with pytest.raises(ValueError):
+        gpu_lib.degree_of_coherence(w, -1, -1, out=torch.empty((n, n), dtype=torch.complex64, device="cuda"))
+    with pytest.raises(ValueError):
+        gpu_lib.build_source(spec(model=WI.MODEL_MAP, sigma_g_m=0.05e-3, intensity_map=np.ones((8, 8))), n, p)
+    with pytest.raises(ValueError):
+        gpu_lib.build_source(spec(geometry=WI.GEO_MASK, mask=np.ones((n, n + 1))), n, p)
+    # The correct tensors still work.
+    s = gpu_lib.spectral_density(w, out=torch.empty((n, n), dtype=torch.float32, device="cuda"))
+    assert torch.isfinite(s).all()

@@ -595,3 +595,133 @@ def test_polychromatic_sum_of_closed_forms():
     mur = row / np.sqrt(sr[ip, jp] * sr)
     mur[sr <= 1e-6 * sr.max()] = 0
     assert rel(mu, mur) < 1e-8
+
+
+# ---------------------------------------------------------------------------------------------
+# The full 4D degree of coherence (Algorithm 5 at every P1, eq. defMu, floor reading R6) against
+# closed forms, where the floor masks a large part of the grid on both points.
+# Catches: a mask applied to one point only, a missing mask, S taken from the wrong point, or a
+# missing square root.
+# ---------------------------------------------------------------------------------------------
+def _mu_full_one_sided(w, floor_rel=1e-12):
+    """A planted mistake (for the pin tests below only): the floor applied to the second point only."""
+    s = np.real(np.einsum("ijij->ij", w))
+    ok = s > floor_rel * s.max()
+    root = np.sqrt(np.where(s > 0, s, 1.0))
+    mu = w / (root[:, :, None, None] * root[None, None, :, :])
+    return np.where(ok[None, None, :, :], mu, 0.0)
+
+
+def _mu_full_unmasked(w, floor_rel=1e-12):
+    """A planted mistake: no floor at all (S below tau divides W anyway)."""
+    s = np.real(np.einsum("ijij->ij", w))
+    root = np.sqrt(np.where(s > 0, s, 1.0))
+    return w / (root[:, :, None, None] * root[None, None, :, :])
+
+
+def _gsm_source_mu_error(mu_fn):
+    """GSM source plane: S = A exp(-xi^2 / (2 sS^2)) and mu = exp(-|xi1 - xi2|^2 / (2 sg^2)) (reading R3).
+    sS = 20 um at a 20 um pitch puts most of the 16 x 16 grid below the floor 1e-12 max S."""
+    n, p, a, ss, sg, floor = 16, 20e-6, 2.5, 20e-6, 50e-6, 1e-12
+    w = O.build_source(spec(amplitude=a, sigma_s_m=ss, sigma_g_m=sg), n, p)
+    xs, ys = O.grid_x(n, p), O.grid_y(n, p)
+    r2 = xs[:, None] ** 2 + ys[None, :] ** 2
+    s_cf = a * np.exp(-r2 / (2 * ss ** 2))
+    tau = floor * a                                  # max S = A, at the grid centre
+    assert np.abs(s_cf / tau - 1).min() > 1e-3       # no point sits on the floor
+    ok = s_cf > tau
+    assert 0.2 < ok.mean() < 0.8                     # the mask matters on both sides
+    d2 = (xs[:, None, None, None] - xs[None, None, :, None]) ** 2 + \
+         (ys[None, :, None, None] - ys[None, None, None, :]) ** 2
+    ref = np.where(ok[:, :, None, None] & ok[None, None, :, :], np.exp(-d2 / (2 * sg ** 2)), 0.0)
+    return np.abs(mu_fn(w, floor) - ref).max()
+
+
+def _coherent_circle_mu_error(mu_fn):
+    """Coherent top-hat (mu = 1 on the source, Sec. 5.1): mu = Y(p1) Y(p2) exactly, whatever the floor."""
+    n, p = 16, 20e-6
+    w = O.build_source(spec(model=O.MODEL_COHERENT, amplitude=0.7, geometry=O.GEO_CIRCLE, geo_r0_m=5 * p), n, p)
+    y = O.geometry_mask(n, p, O.GEO_CIRCLE, 5 * p)
+    ref = y[:, :, None, None] * y[None, None, :, :]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        got = mu_fn(w, 1e-12)
+    return np.nan_to_num(np.abs(got - ref), nan=np.inf).max()
+
+
+def _propagated_gsm_mu_error(mu_fn):
+    """Propagated GSM (Mandel-Wolf beam): mu(x1, x2) = exp(-|x2 - x1|^2 / (2 sg^2 D^2))
+    exp(i k (|x2|^2 - |x1|^2) / (2 Rz)), masked where S = A D^-2 exp(-|x|^2 / (2 sS^2 D^2)) is below
+    1e-3 of its maximum on either point. Window and source as in the 4D closed-form pin (truncation
+    below 1e-9); with the floor at 1e-3 the oracle's error in W is at most ~1e-9 / 1e-3 in mu."""
+    n, p, ss, sg, z, floor = 64, 20e-6, 0.08e-3, 0.12e-3, 0.3, 1e-3
+    w = O.build_source(spec(sigma_s_m=ss, sigma_g_m=sg), n, p)
+    wb, dx = O.propagate(w, n, p, LAM, z)
+    X, Y = O.grid_x(n, dx), O.grid_y(n, dx)
+    cx = CF.gsm_axis_closed_form(X[:, None], X[None, :], ss, sg, LAM, z, False)
+    cy = CF.gsm_axis_closed_form(Y[:, None], Y[None, :], ss, sg, LAM, z, False)
+    sx, sy = np.real(np.diag(cx)), np.real(np.diag(cy))
+    s_cf = sx[:, None] * sy[None, :]
+    tau = floor * s_cf.max()
+    assert np.abs(s_cf / tau - 1).min() > 1e-4
+    ok = s_cf > tau
+    assert 0.005 < ok.mean() < 0.5
+    mux = cx / np.sqrt(sx[:, None] * sx[None, :])
+    muy = cy / np.sqrt(sy[:, None] * sy[None, :])
+    ref = np.where(ok[:, :, None, None] & ok[None, None, :, :], mux[:, None, :, None] * muy[None, :, None, :], 0.0)
+    return np.abs(mu_fn(wb, floor) - ref).max()
+
+
+@pytest.mark.parametrize("case,tol", [(_gsm_source_mu_error, 1e-14), (_coherent_circle_mu_error, 1e-14),
+                                      (_propagated_gsm_mu_error, 1e-5)])
+def test_mu_full_closed_forms(case, tol):
+    assert case(O.degree_of_coherence_full) < tol
+
+
+@pytest.mark.parametrize("planted", [_mu_full_one_sided, _mu_full_unmasked])
+def test_mu_full_pins_reject_planted_masks(planted):
+    """The planted one-sided and missing masks fail the GSM pins (so the pins do constrain the mask)."""
+    assert _gsm_source_mu_error(planted) > 1e-3
+    assert _propagated_gsm_mu_error(planted) > 1e-3
+
+
+def test_mu_slice_matches_full_closed_form():
+    """The slice mu(P1, .) (Algorithm 5) is row P1 of the full mu; both masked on both points."""
+    n, p, ss, sg, z, floor = 64, 20e-6, 0.08e-3, 0.12e-3, 0.3, 1e-3
+    w = O.build_source(spec(sigma_s_m=ss, sigma_g_m=sg), n, p)
+    wb, _ = O.propagate(w, n, p, LAM, z)
+    full = O.degree_of_coherence_full(wb, floor)
+    for ip, jp in [(32, 32), (30, 35), (0, 0), (5, 60)]:
+        sl = O.degree_of_coherence(wb, ip, jp, floor)
+        assert np.array_equal(sl != 0, full[ip, jp] != 0)
+        assert np.abs(sl - full[ip, jp]).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------------------------
+# The separable adjoint (used for the full-size adjoint parity at N = 128): the dot-product test
+# against the separable forward operator at N = 128, and equality with the 4D adjoint at N = 8.
+# Catches: a transposed or unconjugated axis factor, the scale on the wrong factor.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("farfield", [False, True])
+def test_adjoint_separable_dot_product_n128(farfield):
+    n, p, z = 128, 20e-6, 0.5
+    r = WI.rng(91)
+    w = [r.standard_normal((n, n)) + 1j * r.standard_normal((n, n)) for _ in range(2)]
+    g = [r.standard_normal((n, n)) + 1j * r.standard_normal((n, n)) for _ in range(2)]
+    bx, by = O.propagate_separable(w[0], w[1], n, p, LAM, z, farfield)
+    ax, ay = O.propagate_adjoint_separable(g[0], g[1], n, p, LAM, z, farfield)
+    # <a (x) b, c (x) d> = <a, c> <b, d> for the 4D tensors of the separable factors.
+    lhs = np.vdot(bx, g[0]) * np.vdot(by, g[1])
+    rhs = np.vdot(w[0], ax) * np.vdot(w[1], ay)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("farfield", [False, True])
+def test_adjoint_separable_equals_4d(farfield):
+    n, p, z = 8, 20e-6, 0.05
+    r = WI.rng(92)
+    gx = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    gy = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    ax, ay = O.propagate_adjoint_separable(gx, gy, n, p, LAM, z, farfield)
+    g4 = gx[:, None, :, None] * gy[None, :, None, :]
+    ref = O.propagate_adjoint(g4, n, p, LAM, z, farfield)
+    assert rel(ax[:, None, :, None] * ay[None, :, None, :], ref) < 1e-13
