@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
+def log(msg: str) -> None:
+    """Progress on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -33,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the c128 / far-field / adjoint / copy detail")
-    ap.add_argument("--big", action="store_true", help="also time the N=256 complex64 workload (34 GB)")
+    ap.add_argument("--no-big", action="store_true", help="skip the N=256 complex64 workload (34 GB)")
     ap.add_argument("--plan", default="auto",
                     help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or 'fused,slab_chunk,col_chunk'")
     ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None,
@@ -81,7 +86,11 @@ def timed_steps(fn, steps, warmup, marks):
     for step in ev:
         for (a, ea), (b, eb) in zip(step[:-1], step[1:]):
             seg.setdefault(b, []).append(ea.elapsed_time(eb))
-    return total, wall, {k: sum(v) / len(v) for k, v in seg.items()}
+        seg.setdefault("step", []).append(step[0][1].elapsed_time(step[-1][1]))
+    mean = {k: sum(v) / len(v) for k, v in seg.items()}
+    median = {k: sorted(v)[len(v) // 2] if len(v) % 2 else 0.5 * (sorted(v)[len(v) // 2 - 1] + sorted(v)[len(v) // 2])
+              for k, v in seg.items()}
+    return total, wall, mean, median
 
 
 def main():
@@ -165,7 +174,8 @@ def main():
         wolf.degree_of_coherence(w, ip, jp)
         record("observables")
 
-    total_ms, wall_ms, seg = timed_steps(step, args.steps, args.warmup, None)
+    log("timed steps")
+    total_ms, wall_ms, seg, seg_median = timed_steps(step, args.steps, args.warmup, None)
     ms_per_step = total_ms / args.steps
     prop_ms = seg["propagate"]
     bytes_prop = 32.0 * elems            # algorithmic: 2 sweeps x (read + write) x 8 B
@@ -182,15 +192,30 @@ def main():
 
     detail = {"plan_c64": plan, "build_ms": round(seg["build"], 4), "propagate_ms": round(prop_ms, 4),
               "observables_ms": round(seg["observables"], 4),
+              "median_ms_per_step": round(seg_median["step"], 4),
+              "median_propagate_ms": round(seg_median["propagate"], 4),
               "propagate_elems_per_s": elems / (prop_ms * 1e-3),
               "wall_ms_timed_region": round(wall_ms, 3)}
+    # The complex64 result of the last timed step, kept on the host for its error against the FP64 oracle.
+    torch.cuda.synchronize()
+    w_last = w.cpu()
+    log("full mu, ceilings")
+    detail.update(mu_full(wolf, w, ip, jp))
+    detail.update(ceilings(wolf, w))       # overwrites w (the write-only pass fills it with zeros)
+    del w
+    torch.cuda.empty_cache()
 
     if not args.no_extras:
+        log("extras")
         detail.update(extras(wolf, wl, args))
+        log("batch and fit")
         detail.update(batch_and_fit(wolf, args))
+        log("direct check")
         detail.update(direct_check(wolf))
+        log("padded")
         detail.update(padded_check(wolf))
-    if args.big:
+    if not args.no_big:
+        log("N = 256")
         detail.update(big(wolf, args))
 
     result = {
@@ -216,8 +241,99 @@ def main():
         "detail": detail,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(wl)
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"], wb_ref = cpu_baseline(wl)
+        detail["c64_rel_l2_vs_fp64_oracle"] = rel_l2_slabs(w_last, wb_ref)
+        detail["c64_rel_l2_vs_fp64_oracle_source"] = "the oracle's W_B of the cpu_baseline step (full 4D, FP64)"
+        del wb_ref
+        log("cpu baseline N = 64")
+        detail["cpu_baseline_n64"] = cpu_baseline_n64()
+    else:
+        detail["c64_rel_l2_vs_fp64_oracle"] = rel_l2_separable(w_last, wl)
+        detail["c64_rel_l2_vs_fp64_oracle_source"] = "the oracle's separable FP64 form of W_B (GSM source)"
     print(json.dumps(result), flush=True)
+
+
+def _time(fn, reps):
+    """Mean ms of `reps` calls of fn on the current stream (HIP events), after two warm-up calls."""
+    import torch
+
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def ceilings(wolf, w):
+    """Measured memory ceilings on the same 2 GiB array (hand-written streaming kernels, see
+    wolf_memory_ceiling): in-place read + write (the pattern of every in-place pass), write only, read
+    only. The propagation passes are compared with the first."""
+    nbytes = w.numel() * w.element_size()
+    out = {}
+    for mode, tag, moved in ((0, "rmw", 2), (1, "write", 1), (2, "read", 1)):
+        t = _time(lambda: wolf.memory_ceiling(w, mode), 10)
+        out[f"ceiling_{tag}_GBps"] = round(moved * nbytes / (t * 1e-3) / 1e9, 1)
+    return out
+
+
+def mu_full(wolf, w, ip, jp):
+    """The full N^4 degree of coherence (Algorithm 5 at every P1) of the propagated W_B of the step.
+    It writes every mu entry (8 B) and reads W only where both S exceed the floor, so the bytes it moves
+    are 8 + 8 f B/element, f the fraction of (p1, p2) pairs above the floor."""
+    import torch
+
+    n = w.shape[0]
+    elems = float(n) ** 4
+    o = torch.empty_like(w)
+    floor = 1e-12
+    t = _time(lambda: wolf.degree_of_coherence(w, -1, -1, floor, out=o), 5)
+    s = wolf.spectral_density(w).double()
+    f = float((s > floor * s.max()).double().mean()) ** 2
+    moved = (8.0 + 8.0 * f) * elems
+    del o
+    return {"c64_mu_full_ms": round(t, 4), "c64_mu_full_pairs_read_fraction": round(f, 4),
+            "c64_mu_full_moved_GBps": round(moved / (t * 1e-3) / 1e9, 1),
+            "c64_mu_full_note": "propagated W_B of the step, floor 1e-12; bytes = 8 B write + 8 B read per pair above the floor"}
+
+
+def rel_l2_slabs(w_dev_host, wb_ref):
+    """Relative L2 distance of the complex64 result from the FP64 oracle, over all N^4 entries, one slab
+    row at a time."""
+    import numpy as np
+
+    num = den = 0.0
+    for i in range(wb_ref.shape[0]):
+        a = w_dev_host[i].numpy().astype(np.complex128)
+        b = wb_ref[i]
+        num += float(np.sum(np.abs(a - b) ** 2))
+        den += float(np.sum(np.abs(b) ** 2))
+    return math.sqrt(num / den)
+
+
+def rel_l2_separable(w_dev_host, wl):
+    """The same distance against the oracle's separable FP64 form of W_B (GSM source)."""
+    import numpy as np
+
+    import oracle as O
+
+    n, p, lam, z = wl.n, wl.pitch_m, wl.wavelength_m, wl.z_m
+    sp = wl.source
+    bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x"),
+                                   O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y"), n, p, lam, z)
+    num = den = 0.0
+    for i in range(n):
+        a = w_dev_host[i].numpy().astype(np.complex128)
+        b = bx[i][None, :, None] * by[:, None, :]
+        num += float(np.sum(np.abs(a - b) ** 2))
+        den += float(np.sum(np.abs(b) ** 2))
+    return math.sqrt(num / den)
 
 
 def kernels_sha() -> str:
@@ -275,13 +391,6 @@ def extras(wolf, wl, args):
     timg = time_op(lambda: wolf.image_through_lens(o, p, lam, 0.4, 0.2, 0.4, wolf.GEO_CIRCLE, 0.3 * n * pb, out=o))
     out["c64_imaging_ms"] = round(timg, 4)
     out["c64_imaging_achieved_GBps"] = round(2 * 32.0 * elems / (timg * 1e-3) / 1e9, 1)
-    # The full N^4 degree of coherence (Algorithm 5 at every P1): one read of W and one write of mu.
-    tmu = time_op(lambda: wolf.degree_of_coherence(w, -1, -1, 1e-12, out=o))
-    out["c64_mu_full_ms"] = round(tmu, 4)
-    out["c64_mu_full_GBps"] = round(16.0 * elems / (tmu * 1e-3) / 1e9, 1)
-    # Copy ceiling: read + write of the same 2 GiB array.
-    tcp = time_op(lambda: o.copy_(w))
-    out["copy_ceiling_GBps"] = round(2 * w.numel() * 8 / (tcp * 1e-3) / 1e9, 1)
     del w, o
     torch.cuda.empty_cache()
     w = wolf.build_source(wl.source, n, p, torch.complex128)
@@ -552,8 +661,12 @@ def big(wolf, args):
     t = a.elapsed_time(b) / reps
     del w
     torch.cuda.empty_cache()
+    ach = 32.0 * n ** 4 / (t * 1e-3) / 1e9
     return {"n256_plan": plan, "n256_c64_fresnel_ms": round(t, 3), "n256_elems_per_s": n ** 4 / (t * 1e-3),
-            "n256_achieved_GBps": round(32.0 * n ** 4 / (t * 1e-3) / 1e9, 1)}
+            "n256_roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4),
+                              "kernel": "wolf_propagate_fresnel at N = 256 GSM complex64 in place, 32 B/element "
+                                        "algorithmic (2^32 elements)"}}
 
 
 def cpu_baseline(wl):
@@ -574,8 +687,23 @@ def cpu_baseline(wl):
     O.spectral_density(wb)
     O.degree_of_coherence(wb, *wl.probe)
     t = time.perf_counter() - t0
-    return {"value": n ** 4 / t, "unit": "elems/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full step of the same workload (N={n}, build + FP64 propagate + S + mu), {t:.1f} s"}
+    return ({"value": n ** 4 / t, "unit": "elems/s", "cores": cores, "kind": "oracle",
+             "sample": f"one full step of the same workload (N={n}, build + FP64 propagate + S + mu), {t:.1f} s"}, wb)
+
+
+def cpu_baseline_n64():
+    """The oracle's FP64 Fresnel propagation alone at N = 64 (the GSM source of the headline workload on
+    a 64-point grid), on the host cores."""
+    import oracle as O
+    import wolf_inputs as WI
+
+    wl = WI.gsm128()
+    n, p, lam, z = 64, wl.pitch_m, wl.wavelength_m, wl.z_m
+    w = O.build_source(wl.source, n, p)
+    t0 = time.perf_counter()
+    O.propagate(w, n, p, lam, z)
+    t = time.perf_counter() - t0
+    return {"value": n ** 4 / t, "unit": "elems/s", "sample": f"one FP64 Fresnel propagation at N=64, {t:.2f} s"}
 
 
 if __name__ == "__main__":

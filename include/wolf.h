@@ -390,6 +390,17 @@ WOLF_API wolf_status wolf_coop_error_flag(void* stream, int32_t* flag);
 WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t reps, double* best_ms,
                                    void* stream);
 
+/*
+ * wolf_memory_ceiling -- a measurement aid, not an operation of the paper: one streaming pass over
+ * `bytes` of `buf`, to compare the propagation passes with what HBM delivers in practice.
+ *   mode 0: in place, every byte read and written back (the access pattern of an in-place pass);
+ *   mode 1: every byte written (the builder's pattern);
+ *   mode 2: every byte read (the observables-only passes).
+ *   buf     device memory owned by the caller; mode 0 leaves its contents unchanged, mode 1 writes zeros.
+ *   bytes   a positive multiple of 16384. WOLF_EINVAL otherwise.
+ */
+WOLF_API wolf_status wolf_memory_ceiling(void* buf, int64_t bytes, int32_t mode, void* stream);
+
 /* Output pitch dx = lambda z / (N pitch) of eq. (spatial_resolution). Pure host arithmetic. */
 WOLF_API double wolf_output_pitch(int32_t n, double pitch_m, double wavelength_m, double z_m);
 

@@ -33,7 +33,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
             "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes",
             "wolf_propagate_padded", "wolf_propagate_polychromatic", "wolf_polychromatic_work_bytes",
-            "wolf_propagate_source"]
+            "wolf_propagate_source", "wolf_memory_ceiling"]
 
 
 class WolfError(RuntimeError):
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_autotune": [i32, i32, vp, i32, pd, vp],
         "wolf_diag_embed": [vp, i32, i32, vp, vp],
         "wolf_fit_gradient": [vp, vp, i32, f64, f64, i32, vp, vp, vp, vp],
+        "wolf_memory_ceiling": [vp, ctypes.c_int64, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -501,6 +502,15 @@ def autotune(n: int, dtype: torch.dtype = torch.complex64, reps: int = 3, work: 
     best = ctypes.c_double(0.0)
     _check(load().wolf_autotune(n, _code(dtype), _ptr(work), reps, ctypes.byref(best), _stream()), "wolf_autotune")
     return get_plan(n, dtype), best.value
+
+
+def memory_ceiling(buf: torch.Tensor, mode: int = 0) -> None:
+    """One streaming pass over the bytes of `buf` (0: read and write in place, 1: write zeros, 2: read):
+    a measurement aid for the memory ceilings (see include/wolf.h)."""
+    if not (buf.is_cuda and buf.is_contiguous()):
+        raise ValueError("buf must be a contiguous CUDA tensor")
+    _check(load().wolf_memory_ceiling(_ptr(buf), buf.numel() * buf.element_size(), mode, _stream()),
+           "wolf_memory_ceiling")
 
 
 def diag_embed(g: torch.Tensor, dtype: torch.dtype) -> torch.Tensor:

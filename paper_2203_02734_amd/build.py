@@ -14,7 +14,8 @@ BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libwolf.so")
 SOURCES = ["wolf_fft.hip", "wolf_source.hip", "wolf_observables.hip", "wolf_fit.hip", "wolf_coop.hip", "wolf_direct.hip",
-           "wolf_dense.hip", "wolf_pairs.hip", "wolf_api.cpp"]
+           "wolf_dense.hip", "wolf_pairs.hip", "wolf_measure.hip",
+           "wolf_api.cpp"]
 ARCH = "gfx950"
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -895,6 +895,15 @@ WOLF_API wolf_status wolf_coop_error_flag(void* stream, int32_t* flag) {
   return WOLF_OK;
 }
 
+WOLF_API wolf_status wolf_memory_ceiling(void* buf, int64_t bytes, int32_t mode, void* stream) {
+  const char* who = "wolf_memory_ceiling";
+  if (mode < 0 || mode > 2) return fail(WOLF_EINVAL, "%s: mode must be 0, 1 or 2", who);
+  if (bytes <= 0 || bytes % (256 * 64) != 0) return fail(WOLF_EINVAL, "%s: bytes must be a positive multiple of 16384", who);
+  wolf_status s;
+  if ((s = check_buf(buf, (size_t)bytes, "buf")) != WOLF_OK) return s;
+  return launched(wolf::launch_ceiling(buf, bytes, mode, static_cast<hipStream_t>(stream)), who);
+}
+
 WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t reps, double* best_ms,
                                    void* stream) {
   if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_autotune: N=%d unsupported", n);

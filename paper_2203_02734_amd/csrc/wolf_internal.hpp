@@ -169,4 +169,8 @@ hipError_t launch_fit_gradient(int n, const T* ga, const float* imap, double inv
 int fit_slabs_per_group(int n);
 size_t fit_work_bytes(int n, int real_bytes);
 
+// Memory ceilings (wolf_measure.hip): mode 0 in-place read-modify-write, 1 write only, 2 read only,
+// over `bytes` (a multiple of 16 KB) of `buf`.
+hipError_t launch_ceiling(void* buf, long long bytes, int mode, hipStream_t st);
+
 }  // namespace wolf
