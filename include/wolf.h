@@ -360,23 +360,24 @@ WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double waveleng
  *   col_chunk   columns m2 per chunk of the j1 + i1 pass pair (0 = all). A power-of-two divisor
  *               of N^2 and a multiple of the axis tile. Chunks of tens of MB let the second pass of
  *               a pair read the first pass's output from the Infinity Cache instead of HBM.
- *   coop_wgs    > 0: the first-point axes run as one cooperative pass (one HBM sweep) on a persistent
- *               grid of coop_wgs workgroups (a multiple of 8). Each 128 B-wide column tile is
- *               transformed along j1 and then i1 by the workgroups of one XCD, through that XCD's L2.
- *               Needs 32 <= N <= 128. 0: two passes, chunked by col_chunk. The library disables the
- *               cooperative pass: coop_wgs > 0 returns WOLF_EUNSUPPORTED.
- *   coop_lookahead  tiles whose phase A may run ahead of phase B on an XCD (1..8).
+ *   coop_cols   > 0: the first-point axes (j1, i1) run as one cooperative pass (one HBM sweep instead
+ *               of two). The N^2 columns are cut into tiles of coop_cols columns (64, 128 or 256 bytes
+ *               of each row: 8, 16 or 32 columns in complex64, 4, 8 or 16 in complex128), and each tile
+ *               is transformed along j1 and then along i1 by the workgroups of one XCD, through that
+ *               XCD's L2. Needs N = 32, 64 or 128 and a tile of at most 2 MB. 0: two passes over
+ *               column chunks (col_chunk).
+ *   coop_lookahead  tiles whose j1 phase may run ahead of their i1 phase on an XCD (1..8).
  * wolf_set_plan with fused_slab = slab_chunk = col_chunk = -1 restores the built-in default.
  * A plan that is not valid for (n, dtype) returns WOLF_EINVAL. Plans are per process.
  */
 WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab, int64_t slab_chunk,
-                                   int64_t col_chunk, int32_t coop_wgs, int32_t coop_lookahead);
+                                   int64_t col_chunk, int32_t coop_cols, int32_t coop_lookahead);
 WOLF_API wolf_status wolf_get_plan(int32_t n, int32_t dtype, int32_t* fused_slab, int64_t* slab_chunk,
-                                   int64_t* col_chunk, int32_t* coop_wgs, int32_t* coop_lookahead);
+                                   int64_t* col_chunk, int32_t* coop_cols, int32_t* coop_lookahead);
 
 /*
- * wolf_coop_error_flag -- 1 if a cooperative pass on `stream` gave up waiting for a tile (its
- * bounded wait ran out; the result of that call is then wrong), else 0. Synchronises the stream.
+ * wolf_coop_error_flag -- 1 if the last cooperative pass on `stream` gave up waiting for a tile (a
+ * wait is bounded to 20 ms; the result of that call is then wrong), else 0. Synchronises the stream.
  * The flag is cleared at the start of every cooperative pass.
  */
 WOLF_API wolf_status wolf_coop_error_flag(void* stream, int32_t* flag);

@@ -472,10 +472,10 @@ def batch_work_bytes(n: int, dtype: torch.dtype) -> int:
 
 
 def set_plan(n: int, dtype: torch.dtype, fused_slab: int = -1, slab_chunk: int = -1, col_chunk: int = -1,
-             coop_wgs: int = 0, coop_lookahead: int = 1) -> None:
+             coop_cols: int = 0, coop_lookahead: int = 1) -> None:
     """Fix the pass schedule for (n, dtype); fused_slab = slab_chunk = col_chunk = -1 restores the
     default (see include/wolf.h)."""
-    _check(load().wolf_set_plan(n, _code(dtype), fused_slab, slab_chunk, col_chunk, coop_wgs, coop_lookahead),
+    _check(load().wolf_set_plan(n, _code(dtype), fused_slab, slab_chunk, col_chunk, coop_cols, coop_lookahead),
            "wolf_set_plan")
 
 
@@ -483,7 +483,7 @@ def get_plan(n: int, dtype: torch.dtype):
     f, s, c, w, la = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
     _check(load().wolf_get_plan(n, _code(dtype), ctypes.byref(f), ctypes.byref(s), ctypes.byref(c), ctypes.byref(w),
                                 ctypes.byref(la)), "wolf_get_plan")
-    return {"fused_slab": f.value, "slab_chunk": s.value, "col_chunk": c.value, "coop_wgs": w.value,
+    return {"fused_slab": f.value, "slab_chunk": s.value, "col_chunk": c.value, "coop_cols": w.value,
             "coop_lookahead": la.value}
 
 

@@ -104,6 +104,13 @@ wolf_status stream_scratch(void* stream, void** out) {
     *out = it->second;
     return WOLF_OK;
   }
+  // The library allocates only outside graph capture: a stream's first call that needs the scratch
+  // must not be captured.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(WOLF_EINVAL,
+                "the first call on a stream that needs the library's scratch (mu, the cooperative pass) must run "
+                "outside graph capture; call it once before capturing");
   void* p = nullptr;
   static_assert(kScratchBytes >= (16 + 256 * 256) * sizeof(unsigned), "coop counters fit");
   if (hipMalloc(&p, kScratchBytes) != hipSuccess) {
@@ -216,7 +223,6 @@ struct BatchGraph {
 std::mutex g_batch_mu;
 std::vector<BatchGraph> g_batch_graphs;  // recorded batch graphs (most recent last, at most 8)
 
-constexpr bool kCoopEnabled = false;
 
 std::mutex g_plan_mu;
 std::map<std::pair<int, int>, wolf::Plan> g_plans;  // (n, dtype) -> plan chosen by wolf_set_plan / autotune
@@ -237,13 +243,8 @@ bool plan_valid(int32_t n, int32_t dtype, const wolf::Plan& p) {
   // The row pass over a chunk of slabs needs whole workgroups of rows.
   if (!p.fused_slab && p.slab_chunk > 0 && (p.slab_chunk * n) % wolf::row_pass_rows(n) != 0) return false;
   if (p.coop != 0 && p.coop != 1) return false;
-  // The cooperative first-point pass is disabled: its cross-workgroup wait did not complete on
-  // gfx950 (the tile counters were not seen by the waiting workgroups). It stays unreachable until
-  // the cause is established.
-  if (p.coop && !kCoopEnabled) return false;
   if (p.coop) {
-    if (!(dtype == WOLF_C64 ? wolf::coop_supported<float2>(n) : wolf::coop_supported<double2>(n))) return false;
-    if (p.coop_wgs < 8 || p.coop_wgs > 65536 || p.coop_wgs % 8 != 0) return false;
+    if (!wolf::coop_supported(n, (int)elem_bytes(dtype), p.coop_cols)) return false;
     if (p.coop_lookahead < 1 || p.coop_lookahead > 8) return false;
   }
   return true;
@@ -267,7 +268,7 @@ wolf::Plan default_plan(int32_t n, int32_t dtype) {
   while (slabs > 1 && slabs * nn * eb > target && ((slabs >> 1) * n) % wolf::row_pass_rows(n) == 0) slabs >>= 1;
   p.slab_chunk = slabs;
   p.coop = 0;  // opt in through wolf_set_plan / wolf_autotune
-  p.coop_wgs = 1024;
+  p.coop_cols = 0;
   p.coop_lookahead = 1;
   if (n == 128) {
     // Measured on MI355X (in-place propagation, N = 128): the half-buffer slab pass is the fastest in
@@ -568,20 +569,22 @@ WOLF_API wolf_status wolf_propagate_source(const wolf_source* src, int32_t n, do
   if ((s = source_params(src, n, pitch_m, &sp, who)) != WOLF_OK) return s;
   if ((s = check_buf(w_out, n4(n) * elem_bytes(dtype), "w_out")) != WOLF_OK) return s;
   const wolf::Plan plan = plan_for(n, dtype);
-  const bool gen = !plan.coop && (dtype == WOLF_C64 ? wolf::gen_source_supported<float2>(n, sp, plan.fused_slab)
-                                                    : wolf::gen_source_supported<double2>(n, sp, plan.fused_slab));
+  const bool gen = dtype == WOLF_C64 ? wolf::gen_source_supported<float2>(n, sp, plan.fused_slab)
+                                     : wolf::gen_source_supported<double2>(n, sp, plan.fused_slab);
   if (!gen) {  // build the array, then propagate it in place
     if ((s = wolf_build_source(src, n, pitch_m, dtype, w_out, stream)) != WOLF_OK) return s;
     return propagate_common(w_out, w_out, n, pitch_m, wavelength_m, z_m, far_field == 1, kind, dtype, false,
                             out_pitch_m, stream, who);
   }
   const wolf::OperatorTables op = make_op(n, pitch_m, wavelength_m, z_m, far_field == 1, kind, false);
+  void* scratch = nullptr;
+  if (plan.coop && (s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
   if (out_pitch_m) *out_pitch_m = wavelength_m * z_m / ((double)n * pitch_m);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const hipError_t e =
       dtype == WOLF_C64
-          ? wolf::launch_operator<float2>(n, nullptr, static_cast<float2*>(w_out), op, plan, nullptr, st, &sp)
-          : wolf::launch_operator<double2>(n, nullptr, static_cast<double2*>(w_out), op, plan, nullptr, st, &sp);
+          ? wolf::launch_operator<float2>(n, nullptr, static_cast<float2*>(w_out), op, plan, scratch, st, &sp)
+          : wolf::launch_operator<double2>(n, nullptr, static_cast<double2*>(w_out), op, plan, scratch, st, &sp);
   return launched(e, who);
 }
 
@@ -849,7 +852,7 @@ WOLF_API wolf_status wolf_fit_gradient(const void* ga, const float* imap, int32_
 }
 
 WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab, int64_t slab_chunk,
-                                   int64_t col_chunk, int32_t coop_wgs, int32_t coop_lookahead) {
+                                   int64_t col_chunk, int32_t coop_cols, int32_t coop_lookahead) {
   if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_set_plan: N=%d unsupported", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_set_plan: bad dtype");
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -858,26 +861,24 @@ WOLF_API wolf_status wolf_set_plan(int32_t n, int32_t dtype, int32_t fused_slab,
     return WOLF_OK;
   }
   if (fused_slab < 0 || fused_slab > 3) return fail(WOLF_EINVAL, "wolf_set_plan: fused_slab must be 0..3");
-  const wolf::Plan p{fused_slab, (long long)slab_chunk, (long long)col_chunk, coop_wgs > 0 ? 1 : 0,
-                     coop_wgs > 0 ? coop_wgs : 0, coop_wgs > 0 ? coop_lookahead : 1};
-  if (p.coop && !kCoopEnabled)
-    return fail(WOLF_EUNSUPPORTED, "wolf_set_plan: the cooperative first-point pass is disabled in this build");
+  const wolf::Plan p{fused_slab, (long long)slab_chunk, (long long)col_chunk, coop_cols > 0 ? 1 : 0,
+                     coop_cols > 0 ? coop_cols : 0, coop_cols > 0 ? coop_lookahead : 1};
   if (!plan_valid(n, dtype, p)) return fail(WOLF_EINVAL, "wolf_set_plan: plan not valid for N=%d", n);
   g_plans[{n, dtype}] = p;
   return WOLF_OK;
 }
 
 WOLF_API wolf_status wolf_get_plan(int32_t n, int32_t dtype, int32_t* fused_slab, int64_t* slab_chunk,
-                                   int64_t* col_chunk, int32_t* coop_wgs, int32_t* coop_lookahead) {
+                                   int64_t* col_chunk, int32_t* coop_cols, int32_t* coop_lookahead) {
   if (!supported_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_get_plan: N=%d unsupported", n);
   if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_get_plan: bad dtype");
-  if (!fused_slab || !slab_chunk || !col_chunk || !coop_wgs || !coop_lookahead)
+  if (!fused_slab || !slab_chunk || !col_chunk || !coop_cols || !coop_lookahead)
     return fail(WOLF_EINVAL, "wolf_get_plan: null output");
   const wolf::Plan p = plan_for(n, dtype);
   *fused_slab = p.fused_slab;
   *slab_chunk = p.slab_chunk;
   *col_chunk = p.col_chunk;
-  *coop_wgs = p.coop ? p.coop_wgs : 0;
+  *coop_cols = p.coop ? p.coop_cols : 0;
   *coop_lookahead = p.coop_lookahead;
   return WOLF_OK;
 }
@@ -917,10 +918,11 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
   std::vector<wolf::Plan> cands;
   const wolf::Plan def = default_plan(n, dtype);
   for (int fused = 3; fused >= 0; --fused) {
-    for (int wgs : {512, 1024, 2048}) {
+    const int c0 = 64 / (int)elem_bytes(dtype);
+    for (int cols : {c0, 2 * c0, 4 * c0}) {
       for (int la : {1, 2}) {
-        wolf::Plan p{fused, def.slab_chunk, nn, 1, wgs, la};
-        if (kCoopEnabled && plan_valid(n, dtype, p)) cands.push_back(p);
+        wolf::Plan p{fused, def.slab_chunk, nn, 1, cols, la};
+        if (plan_valid(n, dtype, p)) cands.push_back(p);
       }
     }
     for (long long cols = nn; cols >= c; cols >>= 1) {

@@ -849,7 +849,7 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
     }
   }
   const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
-  if (plan.coop) return launch_first_point_coop<T>(n, out, op, pre1, plan.coop_wgs, plan.coop_lookahead, counters, st);
+  if (plan.coop) return launch_first_point_coop<T>(n, out, op, pre1, plan.coop_cols, plan.coop_lookahead, counters, st);
   // First-point axes (j1, i1) over column chunks of the N^2 columns m2. The i1 pass of chunk k - 1
   // shares a launch with the j1 pass of chunk k: they touch disjoint columns.
   const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
@@ -920,7 +920,7 @@ hipError_t launch_operator_diag(int n, const typename real_of<T>::type* g, T* ou
                        op.post2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (plan.coop) return launch_first_point_coop<T>(n, out, op, ident, plan.coop_wgs, plan.coop_lookahead, counters, st);
+  if (plan.coop) return launch_first_point_coop<T>(n, out, op, ident, plan.coop_cols, plan.coop_lookahead, counters, st);
   const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
   Chirp post_last = op.post1;
   post_last.scale = op.scale;

@@ -28,7 +28,7 @@ struct Plan {
   long long slab_chunk;
   long long col_chunk;
   int coop;        // 1: first-point axes in one cooperative pass (wolf_coop.hip); col_chunk unused
-  int coop_wgs;    // persistent grid of the cooperative pass (a multiple of 8)
+  int coop_cols;   // columns of a cooperative tile (64, 128 or 256 bytes of each row)
   int coop_lookahead;
 };
 
@@ -98,9 +98,9 @@ template <class T>
 hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, const double* beta, const double* gamma,
                        const double* coef, int pi, int pj, double floor_rel, void* work,
                        typename real_of<T>::type* s_out, T* mu_out, hipStream_t st);
-template <class T> bool coop_supported(int n);
+bool coop_supported(int n, int elem_bytes, int cols);
 template <class T>
-hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int wgs,
+hipError_t launch_first_point_coop(int n, T* data, const OperatorTables& op, const Chirp& pre1, int cols,
                                    int lookahead, void* counters, hipStream_t st);
 size_t coop_counter_bytes(int n);
 template <class T> bool slab_pass_supported(int n);

@@ -117,3 +117,49 @@ def test_mu_gsm128(gpu_lib, dtype):
     assert bad == 0 and err < tol, (err, bad)
     del mu
     torch.cuda.empty_cache()
+
+
+def test_mu_scratch_is_not_allocated_under_capture(gpu_lib):
+    """The library allocates its per-stream scratch only outside graph capture: the first mu call on a
+    stream that is being captured fails with WOLF_EINVAL and records nothing; after one call outside
+    capture the same call can be captured, and the replayed graph gives the eager result each time."""
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    n, p = 16, 20e-6
+    sp = WI.gsm_small()[0].source
+    w = gpu_lib.build_source(sp, n, p, torch.complex64)
+    mu = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    hs = ctypes.c_void_p(s.cuda_stream)
+    graph = ctypes.c_void_p()
+    with torch.cuda.stream(s):
+        assert hip.hipStreamBeginCapture(hs, 2) == 0                      # relaxed mode
+        try:
+            with pytest.raises(gpu_lib.WolfError) as err:
+                gpu_lib.degree_of_coherence(w, 8, 8, out=mu)
+            assert err.value.status == gpu_lib.EINVAL
+        finally:
+            assert hip.hipStreamEndCapture(hs, ctypes.byref(graph)) == 0
+            hip.hipGraphDestroy(graph)
+        eager = gpu_lib.degree_of_coherence(w, 8, 8).clone()               # allocates the scratch
+        s.synchronize()
+        assert hip.hipStreamBeginCapture(hs, 2) == 0
+        try:
+            gpu_lib.degree_of_coherence(w, 8, 8, out=mu)
+        finally:
+            assert hip.hipStreamEndCapture(hs, ctypes.byref(graph)) == 0
+        exe = ctypes.c_void_p()
+        assert hip.hipGraphInstantiate(ctypes.byref(exe), graph, None, None, ctypes.c_size_t(0)) == 0
+        try:
+            for _ in range(3):
+                mu.zero_()
+                assert hip.hipGraphLaunch(exe, hs) == 0
+                s.synchronize()
+                assert torch.equal(mu, eager)
+                gpu_lib.degree_of_coherence(w, 4, 4)                       # eager work between replays
+                s.synchronize()
+        finally:
+            hip.hipGraphExecDestroy(exe)
+            hip.hipGraphDestroy(graph)

@@ -247,7 +247,7 @@ def test_autotune_keeps_a_valid_plan(gpu_lib, n, dtype):
         assert best > 0 and math.isfinite(best)
         assert gpu_lib.get_plan(n, dtype) == plan
         assert plan["fused_slab"] in (0, 1, 2, 3)
-        gpu_lib.set_plan(n, dtype, plan["fused_slab"], plan["slab_chunk"], plan["col_chunk"], plan["coop_wgs"],
+        gpu_lib.set_plan(n, dtype, plan["fused_slab"], plan["slab_chunk"], plan["col_chunk"], plan["coop_cols"],
                          plan["coop_lookahead"])
         assert gpu_lib.get_plan(n, dtype) == plan
         if n == 32:
@@ -405,19 +405,24 @@ def test_complex128_n128_uses_the_half_buffer_slab_pass(gpu_lib):
     assert gpu_lib.get_plan(128, torch.complex128)["fused_slab"] == 3
 
 
-COOP_SKIP = ("the cooperative first-point pass is disabled: its cross-workgroup wait did not complete "
-             "on gfx950; the library rejects coop plans until the cause is established")
+COOP_COLS = {torch.complex64: (8, 16, 32), torch.complex128: (4, 8, 16)}
 
 
-@pytest.mark.skip(reason=COOP_SKIP)
 @pytest.mark.parametrize("dtype", DT)
 def test_cooperative_schedules_agree(gpu_lib, dtype):
+    """The cooperative first-point pass (one sweep for j1 and i1, tiles through the L2 of one XCD) at
+    N = 32 on a random input, for every tile width and several lookaheads, after the whole-slab and the
+    row passes, against the oracle; no bounded wait runs out."""
     n, p, z = 32, 20e-6, 0.05
     w = WI.random_complex((n, n, n, n), seed=51)
     ref, _ = O.propagate(w, n, p, LAM, z)
+    c = COOP_COLS[dtype]
     try:
-        for plan in [(1, 0, 0, 8, 1), (1, 0, 0, 64, 2), (1, 0, 0, 1024, 8), (0, 0, 0, 256, 1)]:
+        for plan in [(1, 0, 0, c[0], 1), (1, 0, 0, c[1], 2), (1, 0, 0, c[2], 8), (0, 0, 0, c[1], 1),
+                     (3, 0, 0, c[0], 1)]:
+            print("coop plan", dtype, plan, flush=True)
             gpu_lib.set_plan(n, dtype, *plan)
+            assert gpu_lib.get_plan(n, dtype)["coop_cols"] == plan[3]
             got, _ = gpu_lib.propagate_fresnel(dev(w, dtype), p, LAM, z)
             assert gpu_lib.coop_error_flag() == 0, plan
             assert rel(host(got), ref) < TOL[dtype], plan
@@ -425,28 +430,57 @@ def test_cooperative_schedules_agree(gpu_lib, dtype):
         gpu_lib.set_plan(n, dtype)
 
 
-@pytest.mark.skip(reason=COOP_SKIP)
 @pytest.mark.parametrize("dtype", DT)
 @pytest.mark.parametrize("n", [64, 128])
 def test_cooperative_pass_full_size(gpu_lib, dtype, n):
-    """The cooperative first-point pass against the two-pass schedule (bitwise: same arithmetic in
-    the same order) and against the oracle, on GSM sources."""
+    """The cooperative first-point pass against the two-pass schedule and against the oracle, on GSM
+    sources at full size (every tile width that fits the 2 MB tile limit), in place."""
     wl = WI.gsm128()
     p, z = wl.pitch_m, wl.z_m
     sp = wl.source
-    w = gpu_lib.build_source(sp, n, p, dtype)
-    try:
-        gpu_lib.set_plan(n, dtype, 1 if gpu_lib.get_plan(n, dtype)["fused_slab"] else 0, 0, 0, 1024, 1)
-        a, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
-        assert gpu_lib.coop_error_flag() == 0
-        gpu_lib.set_plan(n, dtype, 1 if gpu_lib.get_plan(n, dtype)["fused_slab"] else 0, 0, 0, 0, 1)
-        b, _ = gpu_lib.propagate_fresnel(w, p, LAM, z)
-        assert torch.equal(a, b)
-    finally:
-        gpu_lib.set_plan(n, dtype)
     bx, by = O.propagate_separable(O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "x"),
                                    O.gsm_axis_factor(n, p, sp.sigma_s_m, sp.sigma_g_m, "y"), n, p, LAM, z)
-    assert _separable_rel(a, bx, by) < TOL[dtype]
+    base = gpu_lib.get_plan(n, dtype)
+    try:
+        b = gpu_lib.build_source(sp, n, p, dtype)
+        gpu_lib.propagate_fresnel(b, p, LAM, z, out=b)                 # the default (two-pass) schedule
+        for cols in COOP_COLS[dtype]:
+            if n * n * cols * (8 if dtype == torch.complex64 else 16) > (2 << 20):
+                continue
+            print("coop full size", n, dtype, cols, flush=True)
+            gpu_lib.set_plan(n, dtype, base["fused_slab"], base["slab_chunk"], 0, cols, 1)
+            a = gpu_lib.build_source(sp, n, p, dtype)
+            gpu_lib.propagate_fresnel(a, p, LAM, z, out=a)
+            assert gpu_lib.coop_error_flag() == 0
+            d = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+            assert d <= (1e-6 if dtype == torch.complex64 else 1e-14), (cols, d)
+            assert _separable_rel(a, bx, by) < TOL[dtype]
+            del a
+            torch.cuda.empty_cache()
+    finally:
+        gpu_lib.set_plan(n, dtype)
+
+
+@pytest.mark.parametrize("dtype", DT)
+def test_cooperative_pass_adjoint_and_source(gpu_lib, dtype):
+    """The cooperative pass in the adjoint (inverse DFT signs swapped) and in the one-call source
+    propagation (the slab pass forms the source), N = 64, against the oracle and the two-pass form."""
+    n, p, z = 64, 20e-6, 0.3
+    g = WI.random_complex((n, n, n, n), seed=54)
+    ref = O.propagate_adjoint(g, n, p, LAM, z)
+    sp = spec(sigma_s_m=0.1e-3, sigma_g_m=0.05e-3)
+    two, _ = gpu_lib.propagate_source(sp, n, p, LAM, z, dtype=dtype)
+    try:
+        gpu_lib.set_plan(n, dtype, 3, 0, 0, COOP_COLS[dtype][1], 1)
+        got = gpu_lib.propagate_adjoint(dev(g, dtype), p, LAM, z)
+        assert gpu_lib.coop_error_flag() == 0
+        assert rel(host(got), ref) < TOL[dtype]
+        one, _ = gpu_lib.propagate_source(sp, n, p, LAM, z, dtype=dtype)
+        assert gpu_lib.coop_error_flag() == 0
+        d = float(torch.linalg.vector_norm(one - two) / torch.linalg.vector_norm(two))
+        assert d <= (1e-6 if dtype == torch.complex64 else 1e-14), d
+    finally:
+        gpu_lib.set_plan(n, dtype)
 
 
 def test_invalid_plan_rejected(gpu_lib):
@@ -457,7 +491,7 @@ def test_invalid_plan_rejected(gpu_lib):
     with pytest.raises(gpu_lib.WolfError):
         gpu_lib.set_plan(32, torch.complex64, 0, 1, 0)        # one slab is less than a row-pass workgroup
     with pytest.raises(gpu_lib.WolfError):
-        gpu_lib.set_plan(64, torch.complex64, 1, 0, 0, 1024, 1)    # cooperative pass disabled in this build
+        gpu_lib.set_plan(64, torch.complex64, 1, 0, 0, 12, 1)      # cooperative tile of 12 columns
 
 
 def test_overlapping_buffers_rejected(gpu_lib):
