@@ -256,6 +256,20 @@ WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t 
                                               double s_floor_rel, void* mu_out, void* stream);
 
 /*
+ * wolf_degree_of_coherence_noalloc -- wolf_degree_of_coherence (same arguments, same kernels, the same
+ * result bit for bit) for callers that cannot allocate device memory: code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc. It allocates nothing: its scratch
+ * (the maximum of S and the N^2 values of S) is a static device array of 256 + 256*256*8 bytes
+ * (enough for any N <= 256 in either dtype), one copy per GPU, looked up on the first call on each
+ * device and held until the process ends. Sizes beyond that array return WOLF_EINVAL.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from different threads without ordering) race and give wrong results. Order them
+ * (one stream, or synchronise).
+ */
+WOLF_API wolf_status wolf_degree_of_coherence_noalloc(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp,
+                                                      double s_floor_rel, void* mu_out, void* stream);
+
+/*
  * wolf_propagate_batch -- many (lambda, z) pairs of one source (polychromatic light; the paper's
  * Sec. 6 names it as future work). For pair k, weight[k] * w_src is propagated to distance z[k]
  * at wavelength lambda[k] (Sec. 2.1, eqs. W_fresnel / W_farfield), and S_k (Algorithm 4) and

@@ -33,7 +33,7 @@ EXPORTED = ["wolf_build_source", "wolf_propagate_fresnel", "wolf_propagate_farfi
             "wolf_fit_work_bytes", "wolf_coop_error_flag", "wolf_propagate_adjoint_diag", "wolf_batch_work_bytes",
             "wolf_propagate_lens", "wolf_propagate_direct", "wolf_direct_work_bytes",
             "wolf_propagate_padded", "wolf_propagate_polychromatic", "wolf_polychromatic_work_bytes",
-            "wolf_propagate_source", "wolf_memory_ceiling"]
+            "wolf_propagate_source", "wolf_memory_ceiling", "wolf_degree_of_coherence_noalloc"]
 
 
 class WolfError(RuntimeError):
@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "wolf_propagate_adjoint_diag": [vp, vp, i32, f64, f64, f64, i32, i32, i32, vp],
         "wolf_spectral_density": [vp, i32, i32, vp, vp],
         "wolf_degree_of_coherence": [vp, i32, i32, i32, i32, f64, vp, vp],
+        "wolf_degree_of_coherence_noalloc": [vp, i32, i32, i32, i32, f64, vp, vp],
         "wolf_propagate_batch": [vp, i32, f64, i32, pd, pd, pd, i32, i32, i32, i32, i32, f64, vp, vp, vp, vp],
         "wolf_propagate_polychromatic": [vp, i32, f64, i32, pd, pd, pd, f64, i32, i32, i32, i32, i32, f64, vp, vp, vp,
                                          vp],

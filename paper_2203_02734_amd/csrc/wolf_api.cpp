@@ -398,6 +398,38 @@ wolf_status source_params(const wolf_source* src, int32_t n, double pitch_m, wol
   return WOLF_OK;
 }
 
+// Arguments of the degree of coherence (both entry points): validated, and the buffers checked.
+wolf_status coherence_args(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp, double s_floor_rel,
+                           void* mu_out, const char* who) {
+  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "%s: N=%d (even, 2..256)", who, n);
+  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "%s: bad dtype", who);
+  const bool full = ip == -1 && jp == -1;
+  if (!full && (ip < 0 || ip >= n || jp < 0 || jp >= n))
+    return fail(WOLF_EINVAL, "%s: (ip, jp) must be in [0, N) or both -1", who);
+  if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "%s: s_floor_rel must be >= 0", who);
+  const size_t eb = elem_bytes(dtype);
+  wolf_status s;
+  if ((s = check_buf(w, n4(n) * eb, "w")) != WOLF_OK) return s;
+  const size_t out_bytes = full ? n4(n) * eb : (size_t)n * n * eb;
+  if ((s = check_buf(mu_out, out_bytes, "mu_out")) != WOLF_OK) return s;
+  if (intervals_overlap(w, n4(n) * eb, mu_out, out_bytes))
+    return fail(WOLF_EINVAL, "%s: mu_out overlaps w (mu is never computed in place)", who);
+  return WOLF_OK;
+}
+
+wolf_status coherence_launch(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp, double s_floor_rel,
+                             void* mu_out, void* scratch, void* stream, const char* who) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool full = ip == -1 && jp == -1;
+  const int i = full ? -1 : ip, j = full ? -1 : jp;
+  hipError_t e = dtype == WOLF_C64
+                     ? wolf::launch_coherence<float2>(n, static_cast<const float2*>(w), i, j, s_floor_rel,
+                                                      static_cast<float2*>(mu_out), scratch, st)
+                     : wolf::launch_coherence<double2>(n, static_cast<const double2*>(w), i, j, s_floor_rel,
+                                                       static_cast<double2*>(mu_out), scratch, st);
+  return launched(e, who);
+}
+
 }  // namespace
 
 extern "C" {
@@ -603,29 +635,28 @@ WOLF_API wolf_status wolf_spectral_density(const void* w, int32_t n, int32_t dty
 
 WOLF_API wolf_status wolf_degree_of_coherence(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp,
                                               double s_floor_rel, void* mu_out, void* stream) {
-  if (!even_n(n)) return fail(WOLF_EUNSUPPORTED, "wolf_degree_of_coherence: N=%d (even, 2..256)", n);
-  if (dtype != WOLF_C64 && dtype != WOLF_C128) return fail(WOLF_EINVAL, "wolf_degree_of_coherence: bad dtype");
-  const bool full = ip == -1 && jp == -1;
-  if (!full && (ip < 0 || ip >= n || jp < 0 || jp >= n))
-    return fail(WOLF_EINVAL, "wolf_degree_of_coherence: (ip, jp) must be in [0, N) or both -1");
-  if (!std::isfinite(s_floor_rel) || s_floor_rel < 0) return fail(WOLF_EINVAL, "s_floor_rel must be >= 0");
-  const size_t eb = elem_bytes(dtype);
+  const char* who = "wolf_degree_of_coherence";
   wolf_status s;
-  if ((s = check_buf(w, n4(n) * eb, "w")) != WOLF_OK) return s;
-  const size_t out_bytes = full ? n4(n) * eb : (size_t)n * n * eb;
-  if ((s = check_buf(mu_out, out_bytes, "mu_out")) != WOLF_OK) return s;
-  if (intervals_overlap(w, n4(n) * eb, mu_out, out_bytes))
-    return fail(WOLF_EINVAL, "wolf_degree_of_coherence: mu_out overlaps w (mu is never computed in place)");
+  if ((s = coherence_args(w, n, dtype, ip, jp, s_floor_rel, mu_out, who)) != WOLF_OK) return s;
   void* scratch = nullptr;
   if ((s = stream_scratch(stream, &scratch)) != WOLF_OK) return s;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int i = full ? -1 : ip, j = full ? -1 : jp;
-  hipError_t e = dtype == WOLF_C64
-                     ? wolf::launch_coherence<float2>(n, static_cast<const float2*>(w), i, j, s_floor_rel,
-                                                      static_cast<float2*>(mu_out), scratch, st)
-                     : wolf::launch_coherence<double2>(n, static_cast<const double2*>(w), i, j, s_floor_rel,
-                                                       static_cast<double2*>(mu_out), scratch, st);
-  return launched(e, "wolf_degree_of_coherence");
+  return coherence_launch(w, n, dtype, ip, jp, s_floor_rel, mu_out, scratch, stream, who);
+}
+
+WOLF_API wolf_status wolf_degree_of_coherence_noalloc(const void* w, int32_t n, int32_t dtype, int32_t ip, int32_t jp,
+                                                      double s_floor_rel, void* mu_out, void* stream) {
+  const char* who = "wolf_degree_of_coherence_noalloc";
+  wolf_status s;
+  if ((s = coherence_args(w, n, dtype, ip, jp, s_floor_rel, mu_out, who)) != WOLF_OK) return s;
+  void* scratch = nullptr;
+  size_t cap = 0;
+  const hipError_t e = wolf::mu_static_scratch(&scratch, &cap);
+  if (e != hipSuccess) return fail(WOLF_EDEVICE, "%s: cannot find the static scratch: %s", who, hipGetErrorString(e));
+  const size_t need = 256 + (size_t)n * n * real_bytes(dtype);
+  if (need > cap)
+    return fail(WOLF_EINVAL, "%s: N=%d needs %zu bytes of scratch, more than the %zu of the static scratch", who, n,
+                need, cap);
+  return coherence_launch(w, n, dtype, ip, jp, s_floor_rel, mu_out, scratch, stream, who);
 }
 
 WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double wavelength_m, double z_m, int32_t dtype,

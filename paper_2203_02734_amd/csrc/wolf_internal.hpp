@@ -157,6 +157,10 @@ template <class T>
 hipError_t launch_coherence(int n, const T* w, int ip, int jp, double floor_rel, T* mu, void* scratch,
                             hipStream_t st);
 
+// Device address and size of the static scratch of the allocation-free mu entry point on the current
+// device (looked up once per device; allocates nothing).
+hipError_t mu_static_scratch(void** out, size_t* bytes);
+
 template <class T>
 hipError_t launch_chirp_table(int n, const Chirp& ch, T* out, hipStream_t st);
 

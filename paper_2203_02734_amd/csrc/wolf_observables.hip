@@ -5,9 +5,37 @@
 // (slice) or the whole array (full mu), and S.
 // The floor tau = floor_rel * max S masks points with no light (mu = 0 there). max S is an
 // order-independent reduction, done with an atomic max on order-preserving integer keys.
+#include <map>
+#include <mutex>
+
 #include "wolf_internal.hpp"
 
 namespace wolf {
+
+// Scratch of the allocation-free degree-of-coherence entry point: the order key of max S (at
+// offset 0) and the N^2 values of S (at offset 256), up to N = 256 in FP64. One copy per GPU, held
+// until the process ends, shared by every call on that GPU.
+constexpr size_t kMuStaticBytes = 256 + (size_t)256 * 256 * 8;
+static __device__ __align__(256) unsigned char scratch[kMuStaticBytes];
+
+hipError_t mu_static_scratch(void** out, size_t* bytes) {
+  static std::mutex mu;
+  static std::map<int, void*> ptrs;  // device -> address of that device's copy of `scratch`
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it == ptrs.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the device address; `scratch` itself is a host stand-in
+    if (e != hipSuccess) return e;
+    it = ptrs.emplace(dev, p).first;
+  }
+  *out = it->second;
+  *bytes = kMuStaticBytes;
+  return hipSuccess;
+}
 
 template <class T>
 __global__ __launch_bounds__(256) void k_sdiag(const T* __restrict__ w, int n, typename real_of<T>::type* __restrict__ s) {

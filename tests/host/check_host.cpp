@@ -174,6 +174,10 @@ static void propagation(int n, int dtype) {
   ok_call(wolf_spectral_density(a, n, dtype, s, S0), "S");
   ok_call(wolf_degree_of_coherence(a, n, dtype, n / 2, n / 2, 1e-12, mu, S0), "mu slice");
   ok_call(wolf_degree_of_coherence(a, n, dtype, -1, -1, 1e-12, b, S0), "mu full");
+  ok_call(wolf_degree_of_coherence_noalloc(a, n, dtype, n / 2, n / 2, 1e-12, mu, S0), "mu slice, no allocation");
+  ok_call(wolf_degree_of_coherence_noalloc(a, n, dtype, -1, -1, 1e-12, b, S0), "mu full, no allocation");
+  bad_call(wolf_degree_of_coherence_noalloc(a, n, dtype, -1, 0, 1e-12, mu, S0), WOLF_EINVAL, "noalloc mu half -1");
+  bad_call(wolf_degree_of_coherence_noalloc(a, n, dtype, -1, -1, 1e-12, a, S0), WOLF_EINVAL, "noalloc mu in place");
   bad_call(wolf_degree_of_coherence(a, n, dtype, n, 0, 1e-12, mu, S0), WOLF_EINVAL, "mu P1 out of range");
   bad_call(wolf_degree_of_coherence(a, n, dtype, -1, 0, 1e-12, mu, S0), WOLF_EINVAL, "mu half -1");
   bad_call(wolf_degree_of_coherence(a, n, dtype, 0, 0, -1.0, mu, S0), WOLF_EINVAL, "negative floor");

@@ -20,15 +20,31 @@ struct Alloc {
 };
 // Held through pointers that are never freed, so that the allocations stay reachable from a global
 // until the process ends (no static destructor runs before the leak check).
+// The library's module constructors register device variables before this file's globals would be
+// initialised, so every table is built on first use.
 std::mutex g_mu;
-std::vector<Alloc>& g_allocs = *new std::vector<Alloc>;
-std::vector<stub::Launch>& g_launches = *new std::vector<stub::Launch>;
-std::set<uintptr_t>& g_capturing = *new std::set<uintptr_t>;  // streams between BeginCapture and EndCapture
+std::vector<Alloc>& allocs() {
+  static std::vector<Alloc>& v = *new std::vector<Alloc>;
+  return v;
+}
+std::vector<stub::Launch>& launches_log() {
+  static std::vector<stub::Launch>& v = *new std::vector<stub::Launch>;
+  return v;
+}
+std::set<uintptr_t>& capturing() {  // streams between BeginCapture and EndCapture
+  static std::set<uintptr_t>& v = *new std::set<uintptr_t>;
+  return v;
+}
 thread_local std::vector<stub::Launch> t_config;
 int g_handles = 0;
 
+std::vector<std::pair<const void*, void*>>& g_vars() {
+  static std::vector<std::pair<const void*, void*>>& v = *new std::vector<std::pair<const void*, void*>>;
+  return v;
+}
+
 const Alloc* find(const void* q) {
-  for (const auto& a : g_allocs)
+  for (const auto& a : allocs())
     if ((const char*)q >= a.p && (const char*)q < a.p + a.n) return &a;
   return nullptr;
 }
@@ -39,16 +55,16 @@ namespace stub {
 void* device_alloc(size_t bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   char* p = static_cast<char*>(std::calloc(bytes ? bytes : 1, 1));
-  g_allocs.push_back(Alloc{p, bytes});
+  allocs().push_back(Alloc{p, bytes});
   return p;
 }
 std::vector<Launch> launches() {
   std::lock_guard<std::mutex> lk(g_mu);
-  return g_launches;
+  return launches_log();
 }
 void clear_launches() {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_launches.clear();
+  launches_log().clear();
 }
 }  // namespace stub
 
@@ -123,18 +139,18 @@ hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_capturing.insert((uintptr_t)s);
+  capturing().insert((uintptr_t)s);
   return hipSuccess;
 }
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_capturing.erase((uintptr_t)s);
+  capturing().erase((uintptr_t)s);
   *g = static_cast<hipGraph_t>(handle());
   return hipSuccess;
 }
 hipError_t hipStreamIsCapturing(hipStream_t s, hipStreamCaptureStatus* st) {
   std::lock_guard<std::mutex> lk(g_mu);
-  *st = g_capturing.count((uintptr_t)s) ? hipStreamCaptureStatusActive : hipStreamCaptureStatusNone;
+  *st = capturing().count((uintptr_t)s) ? hipStreamCaptureStatusActive : hipStreamCaptureStatusNone;
   return hipSuccess;
 }
 hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t, hipGraphNode_t*, char*, size_t) {
@@ -162,7 +178,7 @@ hipError_t __hipPopCallConfiguration(dim3* grid, dim3* block, size_t* shm, hipSt
 }
 hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3 block, void**, size_t shm, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_launches.push_back(stub::Launch{f, grid.x, grid.y, grid.z, block.x, block.y, block.z, shm, (uintptr_t)s});
+  launches_log().push_back(stub::Launch{f, grid.x, grid.y, grid.z, block.x, block.y, block.z, shm, (uintptr_t)s});
   return hipSuccess;
 }
 void** __hipRegisterFatBinary(const void*) {
@@ -171,5 +187,23 @@ void** __hipRegisterFatBinary(const void*) {
 }
 void __hipRegisterFunction(void**, const void*, char*, const char*, unsigned int, uint3*, uint3*, dim3*, dim3*, int*) {}
 void __hipUnregisterFatBinary(void**) {}
+
+// Device variables: the host stand-in of each registered variable maps to a "device" allocation of
+// its size, which hipGetSymbolAddress returns (as the runtime returns the device copy's address).
+void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  char* p = static_cast<char*>(std::calloc(size ? size : 1, 1));
+  allocs().push_back(Alloc{p, size});
+  g_vars().push_back(std::make_pair(static_cast<const void*>(var), static_cast<void*>(p)));
+}
+hipError_t hipGetSymbolAddress(void** dev, const void* symbol) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (const auto& v : g_vars())
+    if (v.first == symbol) {
+      *dev = v.second;
+      return hipSuccess;
+    }
+  return hipErrorInvalidSymbol;
+}
 
 }  // extern "C"
