@@ -271,7 +271,7 @@ WOLF_API wolf_status wolf_degree_of_coherence_noalloc(const void* w, int32_t n, 
 
 /*
  * wolf_propagate_batch -- many (lambda, z) pairs of one source (polychromatic light; the paper's
- * Sec. 6 names it as future work). For pair k, weight[k] * w_src is propagated to distance z[k]
+ * Sec. 7 names it as future work). For pair k, weight[k] * w_src is propagated to distance z[k]
  * at wavelength lambda[k] (Sec. 2.1, eqs. W_fresnel / W_farfield), and S_k (Algorithm 4) and
  * mu_k(P1, .) (Algorithm 5) are written to s_out[k] and mu_out[k]. No propagated N^4 array is
  * returned.
@@ -296,7 +296,7 @@ WOLF_API wolf_status wolf_propagate_batch(const void* w_src, int32_t n, double p
 
 /*
  * wolf_propagate_polychromatic -- polychromatic light from one source on a common output grid
- * (the paper's Sec. 6 names polychromatic light as future work). The CSD at each frequency
+ * (the paper's Sec. 7 names polychromatic light as future work). The CSD at each frequency
  * propagates on its own (eq. W_general at wavelength_m[k] and distance z_m[k], Fresnel or far
  * field); on the output grid x = out_pitch_m (i - N/2), y = out_pitch_m (N/2 - j), which need not be
  * any pair's FFT grid, the weighted CSDs add: W = sum_k weight[k] W_k. s_out receives S of the sum
@@ -410,8 +410,10 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
  * `bytes` of `buf`, to compare the propagation passes with what HBM delivers in practice.
  *   mode 0: in place, every byte read and written back (the access pattern of an in-place pass);
  *   mode 1: every byte written (the builder's pattern);
- *   mode 2: every byte read (the observables-only passes).
- *   buf     device memory owned by the caller; mode 0 leaves its contents unchanged, mode 1 writes zeros.
+ *   mode 2: every byte read (the observables-only passes);
+ *   modes 3, 4, 5: the same three with the nontemporal hint on every load and store.
+ *   buf     device memory owned by the caller; modes 0, 2, 3, 5 leave its contents unchanged, 1 and 4
+ *           write zeros.
  *   bytes   a positive multiple of 16384. WOLF_EINVAL otherwise.
  */
 WOLF_API wolf_status wolf_memory_ceiling(void* buf, int64_t bytes, int32_t mode, void* stream);

@@ -506,8 +506,9 @@ def autotune(n: int, dtype: torch.dtype = torch.complex64, reps: int = 3, work: 
 
 
 def memory_ceiling(buf: torch.Tensor, mode: int = 0) -> None:
-    """One streaming pass over the bytes of `buf` (0: read and write in place, 1: write zeros, 2: read):
-    a measurement aid for the memory ceilings (see include/wolf.h)."""
+    """One streaming pass over the bytes of `buf` (0: read and write in place, 1: write zeros, 2: read;
+    3, 4, 5: the same with nontemporal loads and stores): a measurement aid for the memory ceilings
+    (see include/wolf.h)."""
     if not (buf.is_cuda and buf.is_contiguous()):
         raise ValueError("buf must be a contiguous CUDA tensor")
     _check(load().wolf_memory_ceiling(_ptr(buf), buf.numel() * buf.element_size(), mode, _stream()),

@@ -929,7 +929,7 @@ WOLF_API wolf_status wolf_coop_error_flag(void* stream, int32_t* flag) {
 
 WOLF_API wolf_status wolf_memory_ceiling(void* buf, int64_t bytes, int32_t mode, void* stream) {
   const char* who = "wolf_memory_ceiling";
-  if (mode < 0 || mode > 2) return fail(WOLF_EINVAL, "%s: mode must be 0, 1 or 2", who);
+  if (mode < 0 || mode > 5) return fail(WOLF_EINVAL, "%s: mode must be 0..5", who);
   if (bytes <= 0 || bytes % (256 * 64) != 0) return fail(WOLF_EINVAL, "%s: bytes must be a positive multiple of 16384", who);
   wolf_status s;
   if ((s = check_buf(buf, (size_t)bytes, "buf")) != WOLF_OK) return s;

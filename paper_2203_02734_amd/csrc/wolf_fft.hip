@@ -822,8 +822,8 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   const long long N = n, NN = N * N, NNN = NN * N;
   hipError_t e;
   const Chirp ident{0.0, 1.0, +1, 0};
-  // A formed source: the half-buffer slab pass, or the row pass (N >= 64) with no input pupil.
-  if (gen && !(plan.fused_slab == 3 || (plan.fused_slab == 0 && n >= 64 && op.pupil.geo == 0)))
+  // A formed source: the half-buffer slab pass or the row pass (N >= 64), with no input pupil.
+  if (gen && (op.pupil.geo != 0 || !(plan.fused_slab == 3 || (plan.fused_slab == 0 && n >= 64))))
     return hipErrorInvalidValue;
   // An input pupil is applied while the slab pass loads; the other schedules apply it first.
   if (op.pupil.geo != 0 && !plan.fused_slab) {

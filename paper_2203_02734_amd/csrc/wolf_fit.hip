@@ -8,8 +8,9 @@
 //   dL/dI(p) = [R(p) + K(p)] / (2 a(p)),  R(p) = sum_q Re(conj(G_A[p; q])) a(q) mu_g(p, q)
 //                                          K(p) = sum_q Re(conj(G_A[q; p])) a(q) mu_g(q, p)
 //   dL/dsg   = sum_{p, q} Re(conj(G_A[p; q]) W_A[p; q]) |xi_p - xi_q|^2 / sg^3
-// The row sums R come from one workgroup per slab. The column sums K are accumulated by workgroups
-// that each own a group of slabs, then reduced over the groups.
+// Workgroups own a group of slabs and a part of the N^2 columns (at most 4096 of them: one part below
+// N = 128, four at N = 128). Each gives a partial row sum R per slab and part, a partial column sum K
+// per column and group, and a partial of dL/dsg; the finishing kernel adds the parts in a fixed order.
 #include "wolf_device.hpp"
 #include "wolf_internal.hpp"
 
@@ -25,71 +26,75 @@ __global__ __launch_bounds__(256) void k_diag_embed(const typename real_of<T>::t
   for (long long e = threadIdx.x; e < nn; e += blockDim.x) slab[e] = T{e == p1 ? g[p1] : (R)0, (R)0};
 }
 
-// Per-group partials: rows[p1] (one per slab), colpart[group][q], sgpart[group]. A thread owns the
-// columns q = k 256 + tid; it issues the loads of 16 columns before it uses any. The row sum of a slab
-// is reduced by a butterfly within each wavefront and then over the four wavefronts in order.
+// Partials of one (group of slabs, part of the columns): rows[part][p] (a slab's row sum over the
+// part's columns), colpart[group][q] (q in the part), sgpart[group][part]. A thread owns the columns
+// q = part * COLS_PER_THREAD * 256 + k 256 + tid, k < COLS_PER_THREAD (at most 16, so that the column
+// sums stay in registers), issues their loads before it uses any, and computes a(q) of its columns once.
+// N divides 256 (both powers of two, N <= 128 here), so q has the fixed second index qj = tid mod N.
+// The row sum of a slab is reduced by a butterfly within each wavefront and then over the four
+// wavefronts in order.
 template <class T, int COLS_PER_THREAD>
 __global__ __launch_bounds__(256) void k_fit_partials(const T* __restrict__ ga, const float* __restrict__ imap, int n,
-                                                      double inv2g2_px, int slabs_per_group,
+                                                      double inv2g2_px, int slabs_per_group, int parts,
                                                       typename real_of<T>::type* __restrict__ rows,
                                                       typename real_of<T>::type* __restrict__ colpart,
                                                       double* __restrict__ sgpart) {
   using R = typename real_of<T>::type;
-  constexpr int CH = COLS_PER_THREAD < 16 ? COLS_PER_THREAD : 16;
+  constexpr int CPT = COLS_PER_THREAD;
   __shared__ R red[2][4];  // wavefront sums of the row, double-buffered by slab parity
   __shared__ double redd[256];
   __shared__ R gx[256];  // exp(-d^2 pitch^2 / (2 sg^2)) for d = 0..N-1; mu_g = gx[|di|] gx[|dj|]
-  const long long nn = (long long)n * n;
+  const int nn = n * n;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  for (int d = tid; d < n; d += blockDim.x) gx[d] = (R)exp(-(double)d * (double)d * inv2g2_px);
-  __syncthreads();
-  R colacc[COLS_PER_THREAD];
+  for (int d = tid; d < n; d += 256) gx[d] = (R)exp(-(double)d * (double)d * inv2g2_px);
+  const long long group = blockIdx.x / parts;
+  const int part = (int)(blockIdx.x - group * parts);
+  const int q0 = part * CPT * 256;
+  const int qj = tid % n, qi0 = (q0 + tid) / n, qstep = 256 / n;
+  R aqs[CPT];  // a(q) = sqrt(I(q)) of this thread's columns, the same for every slab
 #pragma unroll
-  for (int k = 0; k < COLS_PER_THREAD; ++k) colacc[k] = (R)0;
+  for (int k = 0; k < CPT; ++k) {
+    const int q = q0 + k * 256 + tid;
+    aqs[k] = q < nn ? sqrt((R)imap[q]) : (R)0;
+  }
+  __syncthreads();
+  R colacc[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) colacc[k] = (R)0;
   double sgacc = 0.0;
-  const long long group = blockIdx.x;
   for (int s = 0; s < slabs_per_group; ++s) {
     const long long p = group * slabs_per_group + s;
     const int pi = (int)(p / n), pj = (int)(p % n);
     const R ap = sqrt((R)imap[p]);
-    const T* row = ga + p * nn;
+    const T* row = ga + p * nn + q0;
+    const int dj = pj - qj;
+    const R muj = gx[dj < 0 ? -dj : dj];
+    T gv[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) gv[k] = load_or_first(row, q0 + k * 256 + tid < nn, k * 256 + tid);
     R racc = (R)0;
 #pragma unroll
-    for (int k0 = 0; k0 < COLS_PER_THREAD; k0 += CH) {
-      T gv[CH];
-      float im[CH];
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const long long q = (long long)(k0 + k) * 256 + tid;
-        gv[k] = load_or_first(row, q < nn, q);
-        im[k] = load_or_first(imap, q < nn, q);
-      }
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const long long q = (long long)(k0 + k) * 256 + tid;
-        const bool ok = q < nn;
-        const int qi = (int)(q / n), qj = (int)(q % n);
-        const int di = pi - qi, dj = pj - qj;
-        const double d2 = (double)(di * di + dj * dj);
-        const int ai = di < 0 ? -di : di, aj = dj < 0 ? -dj : dj;
-        const R mu = gx[ok ? ai : 0] * gx[ok ? aj : 0];
-        const R aq = sqrt((R)im[k]);
-        const R gre = ok ? gv[k].x : (R)0;
-        const R w = gre * aq * mu;                   // Re(conj(G) a(q) mu), a and mu real
-        racc += w;
-        colacc[k0 + k] += gre * ap * mu;             // contribution to K(q)
-        sgacc += (double)(w * ap) * d2;              // Re(conj(G) W_A) |d|^2 in pixel units
-      }
+    for (int k = 0; k < CPT; ++k) {
+      const bool ok = q0 + k * 256 + tid < nn;
+      const int di = pi - (qi0 + k * qstep);
+      const int ai = di < 0 ? -di : di;
+      const double d2 = (double)(di * di + dj * dj);
+      const R mu = gx[ok ? ai : 0] * muj;
+      const R gre = ok ? gv[k].x : (R)0;
+      const R w = gre * aqs[k] * mu;               // Re(conj(G) a(q) mu), a and mu real
+      racc += w;
+      colacc[k] += gre * ap * mu;                  // contribution to K(q)
+      sgacc += (double)(w * ap) * d2;              // Re(conj(G) W_A) |d|^2 in pixel units
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off);
     if (lane == 0) red[s & 1][wave] = racc;
     __syncthreads();
-    if (tid == 0) rows[p] = ((red[s & 1][0] + red[s & 1][1]) + red[s & 1][2]) + red[s & 1][3];
+    if (tid == 0) rows[(long long)part * nn + p] = ((red[s & 1][0] + red[s & 1][1]) + red[s & 1][2]) + red[s & 1][3];
   }
 #pragma unroll
-  for (int k = 0; k < COLS_PER_THREAD; ++k) {
-    const long long q = (long long)k * 256 + tid;
+  for (int k = 0; k < CPT; ++k) {
+    const int q = q0 + k * 256 + tid;
     if (q < nn) colpart[group * nn + q] = colacc[k];
   }
   redd[tid] = sgacc;
@@ -98,14 +103,15 @@ __global__ __launch_bounds__(256) void k_fit_partials(const T* __restrict__ ga, 
     if (tid < h) redd[tid] += redd[tid + h];
     __syncthreads();
   }
-  if (tid == 0) sgpart[group] = redd[0];
+  if (tid == 0) sgpart[blockIdx.x] = redd[0];
 }
 
-// dL/dI from the row sums and the column partials, and dL/dsg from the group partials. A workgroup
+// dL/dI from the row sums (added over the column parts) and the column partials, and dL/dsg from the
+// group partials. A workgroup
 // owns 32 columns; its eight slices of 32 threads each add every eighth group in order, and the slices
 // are combined in order. Workgroup 0 also adds the sg partials: 256 strided sums, then a fixed tree.
 template <class T>
-__global__ __launch_bounds__(256) void k_fit_finish(const float* __restrict__ imap, int n, int groups,
+__global__ __launch_bounds__(256) void k_fit_finish(const float* __restrict__ imap, int n, int groups, int parts,
                                                     const typename real_of<T>::type* __restrict__ rows,
                                                     const typename real_of<T>::type* __restrict__ colpart,
                                                     const double* __restrict__ sgpart, double sg_scale,
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(256) void k_fit_finish(const float* __restrict__ im
   part[sl][cx] = k;
   if (blockIdx.x == 0) {
     double t = 0.0;
-    for (int g = threadIdx.x; g < groups; g += 256) t += sgpart[g];
+    for (int g = threadIdx.x; g < groups * parts; g += 256) t += sgpart[g];
     sred[threadIdx.x] = t;
   }
   __syncthreads();
@@ -132,8 +138,10 @@ __global__ __launch_bounds__(256) void k_fit_finish(const float* __restrict__ im
     R kk = part[0][cx];
 #pragma unroll
     for (int j = 1; j < 8; ++j) kk += part[j][cx];
+    R rsum = rows[q];
+    for (int j = 1; j < parts; ++j) rsum += rows[(long long)j * nn + q];
     const R a = sqrt((R)imap[q]);
-    d_imap[q] = (float)((rows[q] + kk) / ((R)2 * a));
+    d_imap[q] = (float)((rsum + kk) / ((R)2 * a));
   }
   if (blockIdx.x == 0) {
     for (int h = 128; h > 0; h >>= 1) {
@@ -150,6 +158,12 @@ hipError_t launch_diag_embed(int n, const typename real_of<T>::type* g, T* out, 
   return hipGetLastError();
 }
 
+// Columns per part: 256 threads x at most 16 columns each.
+static int fit_parts(int n) {
+  const long long nn = (long long)n * n;
+  return nn > 4096 ? (int)(nn / 4096) : 1;
+}
+
 template <class T>
 hipError_t launch_fit_gradient(int n, const T* ga, const float* imap, double inv2g2_px, double sg_scale, void* work,
                                float* d_imap, double* d_sigma, hipStream_t st) {
@@ -157,20 +171,21 @@ hipError_t launch_fit_gradient(int n, const T* ga, const float* imap, double inv
   const long long nn = (long long)n * n;
   const int slabs_per_group = fit_slabs_per_group(n);
   const int groups = (int)(nn / slabs_per_group);
+  const int parts = fit_parts(n);
   R* rows = reinterpret_cast<R*>(work);
-  R* colpart = rows + nn;
-  double* sgpart = reinterpret_cast<double*>(colpart + (long long)groups * nn + 1) ;
+  R* colpart = rows + parts * nn;
+  double* sgpart = reinterpret_cast<double*>(colpart + (long long)groups * nn + 1);
   sgpart = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(sgpart) + 7) & ~(uintptr_t)7);
-  switch ((nn + 255) / 256) {
-    case 1: hipLaunchKernelGGL((k_fit_partials<T, 1>), dim3(groups), dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, rows, colpart, sgpart); break;
-    case 4: hipLaunchKernelGGL((k_fit_partials<T, 4>), dim3(groups), dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, rows, colpart, sgpart); break;
-    case 16: hipLaunchKernelGGL((k_fit_partials<T, 16>), dim3(groups), dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, rows, colpart, sgpart); break;
-    case 64: hipLaunchKernelGGL((k_fit_partials<T, 64>), dim3(groups), dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, rows, colpart, sgpart); break;
+  const dim3 grid((unsigned)(groups * parts));
+  switch (nn / parts > 256 ? (nn / parts + 255) / 256 : 1) {
+    case 1: hipLaunchKernelGGL((k_fit_partials<T, 1>), grid, dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, parts, rows, colpart, sgpart); break;
+    case 4: hipLaunchKernelGGL((k_fit_partials<T, 4>), grid, dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, parts, rows, colpart, sgpart); break;
+    case 16: hipLaunchKernelGGL((k_fit_partials<T, 16>), grid, dim3(256), 0, st, ga, imap, n, inv2g2_px, slabs_per_group, parts, rows, colpart, sgpart); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fit_finish<T>, dim3((unsigned)((nn + 31) / 32)), dim3(256), 0, st, imap, n, groups,
+  hipLaunchKernelGGL(k_fit_finish<T>, dim3((unsigned)((nn + 31) / 32)), dim3(256), 0, st, imap, n, groups, parts,
                      (const R*)rows, (const R*)colpart, (const double*)sgpart, sg_scale, d_imap, d_sigma);
   return hipGetLastError();
 }
@@ -185,7 +200,8 @@ int fit_slabs_per_group(int n) {
 size_t fit_work_bytes(int n, int real_bytes) {
   const long long nn = (long long)n * n;
   const long long groups = nn / fit_slabs_per_group(n);
-  return (size_t)(nn + groups * nn + 1) * real_bytes + 8 + (size_t)groups * 8;
+  const long long parts = fit_parts(n);
+  return (size_t)(parts * nn + groups * nn + 1) * real_bytes + 8 + (size_t)(groups * parts) * 8;
 }
 
 template hipError_t launch_diag_embed<float2>(int, const float*, float2*, hipStream_t);

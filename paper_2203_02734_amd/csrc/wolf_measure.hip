@@ -3,53 +3,71 @@
 //   mode 0: in place, read and write every byte (x <- s x, s = 1 at run time): the access pattern of
 //           an in-place pass (16 B per complex64 element per sweep);
 //   mode 1: write only (the source builder's pattern);
-//   mode 2: read only (the pattern of the observables-only passes).
-// Each thread moves 64 contiguous bytes as four 16-byte vectors, all loads issued before the first
-// store, and consecutive threads take consecutive 64-byte blocks, so that every wavefront covers
-// 4 KB of contiguous memory.
+//   mode 2: read only (the pattern of the observables-only passes);
+//   modes 3, 4, 5: the same with the nontemporal hint on every load and store.
+// A workgroup moves 16 KB: each of its four 16-byte vector loads (or stores) per thread covers 4 KB
+// of contiguous memory across the 256 threads, all loads issued before the first store.
 #include "wolf_internal.hpp"
 
 namespace wolf {
 
-__global__ __launch_bounds__(256) void k_ceiling_rmw(float4* __restrict__ p, long long nvec, float s) {
-  const long long base = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (base + 4 > nvec) return;
-  float4 v[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = p[base + k];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) p[base + k] = make_float4(v[k].x * s, v[k].y * s, v[k].z * s, v[k].w * s);
+constexpr int kCeilVec = 4;  // 16-byte vectors per thread
+typedef float ceil_v4f __attribute__((ext_vector_type(4)));
+
+// NT: the loads and stores carry the nontemporal hint (the data is touched once).
+template <bool NT> __device__ __forceinline__ ceil_v4f ld(const ceil_v4f* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT> __device__ __forceinline__ void st(ceil_v4f* p, ceil_v4f v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
-__global__ __launch_bounds__(256) void k_ceiling_fill(float4* __restrict__ p, long long nvec, float s) {
-  const long long base = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (base + 4 > nvec) return;
+template <bool NT>
+__global__ __launch_bounds__(256) void k_ceiling_rmw(ceil_v4f* __restrict__ p, float s) {
+  ceil_v4f* q = p + (long long)blockIdx.x * (256 * kCeilVec) + threadIdx.x;
+  ceil_v4f v[kCeilVec];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[base + k] = make_float4(s, s, s, s);
+  for (int k = 0; k < kCeilVec; ++k) v[k] = ld<NT>(&q[k * 256]);
+#pragma unroll
+  for (int k = 0; k < kCeilVec; ++k) st<NT>(&q[k * 256], v[k] * s);
 }
 
-__global__ __launch_bounds__(256) void k_ceiling_read(float4* __restrict__ p, long long nvec, float s) {
-  const long long base = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (base + 4 > nvec) return;
-  float4 v[4];
+template <bool NT>
+__global__ __launch_bounds__(256) void k_ceiling_fill(ceil_v4f* __restrict__ p, float s) {
+  ceil_v4f* q = p + (long long)blockIdx.x * (256 * kCeilVec) + threadIdx.x;
+  const ceil_v4f v = {s, s, s, s};
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = p[base + k];
+  for (int k = 0; k < kCeilVec; ++k) st<NT>(&q[k * 256], v);
+}
+
+// `never` is a value the data cannot sum to (the caller passes -1e38): the store keeps the loads.
+template <bool NT>
+__global__ __launch_bounds__(256) void k_ceiling_read(ceil_v4f* __restrict__ p, float never) {
+  ceil_v4f* q = p + (long long)blockIdx.x * (256 * kCeilVec) + threadIdx.x;
+  ceil_v4f v[kCeilVec];
+#pragma unroll
+  for (int k = 0; k < kCeilVec; ++k) v[k] = ld<NT>(&q[k * 256]);
   float acc = 0.f;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) acc += v[k].x + v[k].y + v[k].z + v[k].w;
-  // s is never NaN, so this store never happens; it keeps the loads.
-  if (acc == s && s != s) p[base] = make_float4(acc, acc, acc, acc);
+  for (int k = 0; k < kCeilVec; ++k) acc += (v[k].x + v[k].y) + (v[k].z + v[k].w);
+  if (acc == never) q[0] = ceil_v4f{acc, acc, acc, acc};
 }
 
 hipError_t launch_ceiling(void* buf, long long bytes, int mode, hipStream_t st) {
-  const long long nvec = bytes / 16;
-  const long long blocks = nvec / (256 * 4);
-  if (blocks <= 0 || blocks > 0x7fffffffll || bytes % (256 * 64) != 0) return hipErrorInvalidValue;
-  float4* p = static_cast<float4*>(buf);
+  const long long per_block = 256ll * kCeilVec * 16;  // 16 KB
+  const long long blocks = bytes / per_block;
+  if (blocks <= 0 || blocks > 0x7fffffffll || bytes % per_block != 0) return hipErrorInvalidValue;
+  ceil_v4f* p = static_cast<ceil_v4f*>(buf);
+  const dim3 g((unsigned)blocks), b(256);
   switch (mode) {
-    case 0: hipLaunchKernelGGL(k_ceiling_rmw, dim3((unsigned)blocks), dim3(256), 0, st, p, nvec, 1.0f); break;
-    case 1: hipLaunchKernelGGL(k_ceiling_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, nvec, 0.0f); break;
-    case 2: hipLaunchKernelGGL(k_ceiling_read, dim3((unsigned)blocks), dim3(256), 0, st, p, nvec, 1.0f); break;
+    case 0: hipLaunchKernelGGL(k_ceiling_rmw<false>, g, b, 0, st, p, 1.0f); break;
+    case 1: hipLaunchKernelGGL(k_ceiling_fill<false>, g, b, 0, st, p, 0.0f); break;
+    case 2: hipLaunchKernelGGL(k_ceiling_read<false>, g, b, 0, st, p, -1e38f); break;
+    case 3: hipLaunchKernelGGL(k_ceiling_rmw<true>, g, b, 0, st, p, 1.0f); break;
+    case 4: hipLaunchKernelGGL(k_ceiling_fill<true>, g, b, 0, st, p, 0.0f); break;
+    case 5: hipLaunchKernelGGL(k_ceiling_read<true>, g, b, 0, st, p, -1e38f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -18,13 +18,16 @@
 namespace wolf {
 
 // Y at centred pixel offsets (di, dj) for the geometries decided by the coordinates (none, circle,
-// square, annulus).
+// square, annulus). |di|, |dj| <= 128, so the squares and their sum (<= 32768) are exact in 32-bit
+// integers, and a threshold above 2^30 decides like one of 2^30.
+__device__ __forceinline__ int clamp_thr(long long t) { return t > (1ll << 30) ? (1 << 30) : (int)t; }
 __device__ __forceinline__ bool inside_coords(const SourceParams& sp, int di, int dj) {
-  const long long a = (long long)di * di, b = (long long)dj * dj;
+  const int a = di * di, b = dj * dj;
+  const int t0 = clamp_thr(sp.t0);
   switch (sp.geometry) {
-    case 1: return a + b <= sp.t0;
-    case 2: return a <= sp.t0 && b <= sp.t0;
-    case 3: return a + b <= sp.t0 && a + b > sp.t1;
+    case 1: return a + b <= t0;
+    case 2: return a <= t0 && b <= t0;
+    case 3: return a + b <= t0 && a + b > clamp_thr(sp.t1);
     default: return true;
   }
 }

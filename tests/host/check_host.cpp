@@ -253,10 +253,10 @@ static void propagation(int n, int dtype) {
   }
   // Memory ceilings.
   void* big = stub::device_alloc(64 * 1024);
-  for (int mode = 0; mode < 3; ++mode) ok_call(wolf_memory_ceiling(big, 64 * 1024, mode, S0), "memory ceiling");
+  for (int mode = 0; mode < 6; ++mode) ok_call(wolf_memory_ceiling(big, 64 * 1024, mode, S0), "memory ceiling");
   bad_call(wolf_memory_ceiling(big, 1000, 0, S0), WOLF_EINVAL, "ceiling size not a multiple of 16 KB");
   bad_call(wolf_memory_ceiling(big, 128 * 1024, 0, S0), WOLF_EINVAL, "ceiling beyond the allocation");
-  bad_call(wolf_memory_ceiling(big, 64 * 1024, 3, S0), WOLF_EINVAL, "ceiling mode 3");
+  bad_call(wolf_memory_ceiling(big, 64 * 1024, 6, S0), WOLF_EINVAL, "ceiling mode 6");
 }
 
 static void plans() {
