@@ -108,8 +108,8 @@ WOLF_API wolf_status wolf_build_source(const wolf_source* src, int32_t n, double
  * WOLF_MODEL_COHERENT with WOLF_GEO_NONE, CIRCLE, SQUARE or ANNULUS, with or without a lens), that
  * pass forms each W0 entry where it would load it, so W0 is never written to memory: one write and
  * one read of the N^4 array less. So does the row pass of the four-sweep schedule (the default at
- * N = 256; N = 64 or 128 when set) for such sources without a lens. Other sources and schedules
- * build W0 in w_out first.
+ * N = 256; N = 64 or 128 when set) for the same sources. Other sources and schedules build W0 in
+ * w_out first.
  *   src, n, pitch_m   as wolf_build_source (N a power of two in [2, 256]).
  *   wavelength_m, z_m, kind, out_pitch_m   as wolf_propagate_fresnel.
  *   far_field         0 (Fresnel) or 1 (far field).

@@ -37,6 +37,13 @@ template <class T> __device__ __forceinline__ T cmul(T a, T b) {
   return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 template <class T> __device__ __forceinline__ T cconj(T a) { return T{a.x, -a.y}; }
+// a b with each real product rounded before its sum (no fused multiply-add). A pass that either loads
+// its input or forms it (the source) applies its first factor with this, so that both forms give the
+// same bits: a contraction may fuse either product of a sum, and the compiler chooses per call site.
+template <class T> __device__ __forceinline__ T cmul_exact(T a, T b) {
+#pragma clang fp contract(off)
+  return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
 template <class T, class R> __device__ __forceinline__ T cscale(T a, R s) { return T{a.x * s, a.y * s}; }
 
 // Multiply by SIGN * i (SIGN = -1: forward DFT kernel e^{-2 pi i/4}; +1: inverse).

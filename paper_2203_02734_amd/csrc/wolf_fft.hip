@@ -92,8 +92,8 @@ __global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* 
 // ---------------------------------------------------------------------------------------------
 // Contiguous axis (rows of N elements). A workgroup takes B consecutive rows.
 // GEN > 0 (B <= N, so that the rows of a workgroup lie in one slab p1 = (i1, j1)): the input rows are
-// the source W0 of `sp` (as in the slab pass: GEN = 1 without an aperture, 2 with a circle, square
-// or annulus; no lens), formed from the slab's row fy(j1, .) and the scalars fx(i1, i2) of its B
+// the source W0 of `sp` (as in the slab pass: GEN = 1 without an aperture or a lens, 2 with a circle,
+// square, annulus or lens), formed from the slab's row fy(j1, .) and the scalars fx(i1, i2) of its B
 // rows; row0 is the global index of the launch's first row. W0 is never stored.
 // ---------------------------------------------------------------------------------------------
 template <class T, int N, int B, int SIGN, int GEN>
@@ -138,13 +138,13 @@ __global__ __launch_bounds__(Split<N>::N2 * B) void k_row_fft(const T* src, T* d
       const int n = N2 * a + t;
       R m = am1;
       if constexpr (GEN == 2) m = inside_coords(sp, i2 - N / 2, n - N / 2) ? am1 : (R)0;
-      v[a] = cmul(source_value(fx, gy[n], m), tpre[n]);
+      v[a] = cmul_exact(source_value(fx, gy[n], m), tpre[n]);
     }
   } else {
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
       const int n = N2 * a + t;
-      v[a] = cmul(in[n], tpre[n]);
+      v[a] = cmul_exact(in[n], tpre[n]);
     }
   }
   dft_reg<N1, SIGN>(v);
@@ -448,7 +448,7 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
     }
     const T cst = cmul(tpre[c], scal);
 #pragma unroll
-    for (int a = 0; a < N1; ++a) v[a] = cmul(v[a], tpre[N2 * a + t1]);
+    for (int a = 0; a < N1; ++a) v[a] = cmul_exact(v[a], tpre[N2 * a + t1]);
     dft_reg<N1, SIGN>(v);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t1) * H + cl] = cmul(v[k1], tw[(t1 * k1) & (N - 1)]);
@@ -764,9 +764,7 @@ template <class T> bool slab_pass_supported(int n) {
 template <class T> bool gen_source_supported(int n, const SourceParams& sp, int fused_slab) {
   if ((sp.model != 0 && sp.model != 2) || sp.geometry < 0 || sp.geometry > 3) return false;
   if (fused_slab == 3) return half_slab_supported<T>(n);
-  // The row pass (a workgroup's rows in one slab), for sources without a lens: with complex rows
-  // its result differed from build + propagate in the last bit of a few entries.
-  return fused_slab == 0 && n >= 64 && n <= 256 && sp.lens_alpha == 0.0;
+  return fused_slab == 0 && n >= 64 && n <= 256;  // the row pass: a workgroup's rows lie in one slab
 }
 template bool gen_source_supported<float2>(int, const SourceParams&, int);
 template bool gen_source_supported<double2>(int, const SourceParams&, int);

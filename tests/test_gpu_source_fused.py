@@ -148,8 +148,8 @@ def test_propagate_source_rejects(gpu_lib):
 @pytest.mark.parametrize("name", sorted(FORMED))
 def test_formed_by_row_pass_equals_build_then_propagate(gpu_lib, name, n, dtype):
     """The row-pass schedule (fused_slab = 0) over chunks of N slabs, so that launches after the first
-    start at a nonzero row: the row pass forms the lens-free sources (N >= 64); the source with a lens
-    is built first on this schedule."""
+    start at a nonzero row: the row pass forms every source decided by the coordinates, with or without
+    a lens (N >= 64), and the result equals build + propagate bit for bit."""
     sp, z = FORMED[name], 0.4
     try:
         gpu_lib.set_plan(n, dtype, 0, n, n * n, 0, 1)
