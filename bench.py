@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the c128 / far-field / adjoint / copy detail")
     ap.add_argument("--no-big", action="store_true", help="skip the N=256 complex64 workload (34 GB)")
     ap.add_argument("--plan", default="auto",
-                    help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or 'fused,slab_chunk,col_chunk'")
+                    help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or "
+                         "'fused,slab_chunk,col_chunk[,coop_cols,coop_lookahead]'")
     ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None,
                     choices=["propagate", "batch", "padded", "source"],
                     help="run one untimed invocation for a counter run and exit: 'propagate' (build, in-place "
@@ -118,8 +119,8 @@ def main():
     if args.plan == "auto":
         plan, _ = wolf.autotune(n, torch.complex64, reps=3, work=wb)
     elif args.plan != "default":
-        f, sc, cc = (int(x) for x in args.plan.split(","))
-        wolf.set_plan(n, torch.complex64, f, sc, cc)
+        vals = [int(x) for x in args.plan.split(",")]
+        wolf.set_plan(n, torch.complex64, *vals)   # fused, slab_chunk, col_chunk[, coop_cols, coop_lookahead]
     plan = wolf.get_plan(n, torch.complex64)
     del wb
     torch.cuda.empty_cache()
