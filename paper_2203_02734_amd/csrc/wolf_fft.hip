@@ -325,7 +325,7 @@ __device__ __forceinline__ void slab_transform_loaded(T* v, T* buf, const T* tpr
 
 template <class T, int N, int SIGN>
 __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T* dst, Chirp pre, Chirp post,
-                                                               Chirp slab_pre, Pupil pu) {
+                                                               Chirp slab_pre, Pupil pu, long long slab0) {
   using S = Split<N>;
   using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2(const T* src, T*
   __shared__ T buf[N * SP];
   __shared__ T tpre[N], tpost[N], tw[N], sc[2];
 
-  const long long p1 = blockIdx.x;
+  const long long p1 = slab0 + blockIdx.x;
   const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
   for (int i = threadIdx.x; i < N; i += NT) {
     tpre[i] = chirp_entry<T>(pre, i, N);
@@ -388,7 +388,8 @@ template <class T, int N> constexpr int half_waves_per_simd() {
 // source rows sit behind them until the row phase.
 template <class T, int N, int SIGN, int GEN>
 __global__ __launch_bounds__(Split<N>::N2 * N / 2) __attribute__((amdgpu_waves_per_eu(half_waves_per_simd<T, N>())))
-void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pupil pu, SourceParams sp) {
+void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pupil pu, SourceParams sp,
+                 long long slab0) {
   using S = Split<N>;
   using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
@@ -402,7 +403,7 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
   T* const gx = buf + N * H;  // GEN: the source rows fx(i1, .), fy(j1, .)
   T* const gy = gx + N;
 
-  const long long p1 = blockIdx.x;
+  const long long p1 = slab0 + blockIdx.x;
   const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
   for (int i = threadIdx.x; i < N; i += NT) {
     tpre[i] = chirp_entry<T>(pre, i, N);
@@ -522,8 +523,8 @@ void k_slab_half(const T* src, T* dst, Chirp pre, Chirp post, Chirp slab_pre, Pu
 // tables. The raw values of its next slab are loaded into registers while it transforms the
 // current one, so the loads of one slab overlap the arithmetic of the previous one.
 template <class T, int N, int SIGN>
-__global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T* dst, long long slabs, Chirp pre,
-                                                                Chirp post, Chirp slab_pre, Pupil pu) {
+__global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T* dst, long long slab0, long long slab_end,
+                                                                Chirp pre, Chirp post, Chirp slab_pre, Pupil pu) {
   using S = Split<N>;
   using R = typename real_of<T>::type;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
@@ -539,16 +540,16 @@ __global__ __launch_bounds__(Split<N>::N2 * N) void k_slab_fft2p(const T* src, T
   }
   __syncthreads();
   const long long nn = (long long)N * N;
-  long long p1 = blockIdx.x;
-  if (p1 >= slabs) return;
+  long long p1 = slab0 + blockIdx.x;
+  if (p1 >= slab_end) return;
   T cur[N1];
   slab_load<T, N>(src + p1 * nn, cur, (int)threadIdx.x);
-  for (; p1 < slabs; p1 += gridDim.x) {
+  for (; p1 < slab_end; p1 += gridDim.x) {
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));  // recompute thread-derived addresses per slab
     const long long pn = p1 + gridDim.x;
     T nxt[N1];
-    if (pn < slabs) slab_load<T, N>(src + pn * nn, nxt, tid);
+    if (pn < slab_end) slab_load<T, N>(src + pn * nn, nxt, tid);
     T u[N1];
     const int a1 = (int)(p1 / N), b1 = (int)(p1 % N);
     slab_mask<T, N>(pu, cur, tid);
@@ -651,20 +652,22 @@ template <class T, int N> constexpr long long slab_resident_wgs() {
 }
 
 template <class T, int N, int SIGN>
-static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chirp& pre, const Chirp& post,
-                                const Chirp& slab_pre, const Pupil& pu, int mode, const SourceParams* gen,
-                                hipStream_t st) {
-  if (slabs > 0x7fffffffll) return hipErrorInvalidValue;
+static hipError_t launch_slab_n(const T* src, T* dst, long long slab0, long long slabs, const Chirp& pre,
+                                const Chirp& post, const Chirp& slab_pre, const Pupil& pu, int mode,
+                                const SourceParams* gen, hipStream_t st) {
+  if (slabs <= 0 || slabs > 0x7fffffffll || slab0 < 0 || slab0 + slabs > (long long)N * N) return hipErrorInvalidValue;
   if (mode == 3) {
     if constexpr (N >= 32 && N <= 128 && half_lds_bytes<T, N>() <= kMaxLds) {
       const dim3 grid((unsigned)slabs), block(Split<N>::N2 * N / 2);
       if (gen && gen->geometry == 0 && gen->lens_alpha == 0.0)
-        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 1>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen);
+        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 1>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen,
+                           slab0);
       else if (gen)
-        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 2>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen);
+        hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 2>), grid, block, 0, st, dst, dst, pre, post, slab_pre, pu, *gen,
+                           slab0);
       else
         hipLaunchKernelGGL((k_slab_half<T, N, SIGN, 0>), grid, block, 0, st, src, dst, pre, post, slab_pre, pu,
-                           SourceParams{});
+                           SourceParams{}, slab0);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -677,10 +680,10 @@ static hipError_t launch_slab_n(const T* src, T* dst, long long slabs, const Chi
     if (mode == 2) {
       const long long g = slabs < slab_resident_wgs<T, N>() ? slabs : slab_resident_wgs<T, N>();
       hipLaunchKernelGGL((k_slab_fft2p<T, N, SIGN>), dim3((unsigned)g), dim3(Split<N>::N2 * N), 0, st, src, dst,
-                         slabs, pre, post, slab_pre, pu);
+                         slab0, slab0 + slabs, pre, post, slab_pre, pu);
     } else {
       hipLaunchKernelGGL((k_slab_fft2<T, N, SIGN>), dim3((unsigned)slabs), dim3(Split<N>::N2 * N), 0, st, src, dst,
-                         pre, post, slab_pre, pu);
+                         pre, post, slab_pre, pu, slab0);
     }
     return hipGetLastError();
   }
@@ -715,13 +718,13 @@ hipError_t launch_row_pass(int n, const T* src, T* dst, long long rows, int sign
 }
 
 template <class T>
-hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slabs, int sign, const Chirp& pre,
+hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slab0, long long slabs, int sign, const Chirp& pre,
                             const Chirp& post, const Chirp& slab_pre, const Pupil& pu, int mode, const SourceParams* gen,
                             hipStream_t st) {
   if (sign < 0) {
-    WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slabs, pre, post, slab_pre, pu, mode, gen, st)))
+    WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, -1>(src, dst, slab0, slabs, pre, post, slab_pre, pu, mode, gen, st)))
   }
-  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slabs, pre, post, slab_pre, pu, mode, gen, st)))
+  WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slab0, slabs, pre, post, slab_pre, pu, mode, gen, st)))
 }
 
 template <class T>
@@ -829,9 +832,36 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
     if (e != hipSuccess) return e;
     in = out;
   }
+  const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
+  Chirp post_last = op.post1;
+  post_last.scale = op.scale;
+  // Grouped schedule: the slab pass over a group of whole i1 planes (slab_chunk slabs), then at once
+  // the j1 pass of those planes, while they are still in the 256 MB memory-side cache; the i1 pass
+  // follows over column chunks. HBM then sees two sweeps of the array and the cache the third.
+  if (plan.fused_slab && !plan.coop && plan.slab_chunk > 0 && plan.slab_chunk < NN) {
+    const long long g = plan.slab_chunk;
+    if (g % N != 0) return hipErrorInvalidValue;
+    for (long long s0 = 0; s0 < NN; s0 += g) {
+      e = launch_slab_pass<T>(n, in, out, s0, g, op.sign2, op.pre2, op.post2, op.pre1, op.pupil, plan.fused_slab, gen,
+                              st);
+      if (e != hipSuccess) return e;
+      const AxisRange aj{g / N, NNN, NN, 0, NN};  // j1 of the group's planes: outer i1, stride N^2
+      e = launch_axis_range<T>(n, out + s0 * NN, out + s0 * NN, op.sign1, aj, pre1, op.post1, nullptr, ident, ident,
+                               st);
+      if (e != hipSuccess) return e;
+    }
+    const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
+    for (long long ci = 0; ci < NN; ci += m) {
+      const AxisRange ai{N, NN, NNN, ci, (ci + m <= NN) ? m : NN - ci};  // i1: outer j1, stride N^3
+      e = launch_axis_range<T>(n, out, out, op.sign1, ai, pre1, post_last, nullptr, ident, ident, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   // Second-point axes (i2, j2).
   if (plan.fused_slab) {
-    e = launch_slab_pass<T>(n, in, out, NN, op.sign2, op.pre2, op.post2, op.pre1, op.pupil, plan.fused_slab, gen, st);
+    e = launch_slab_pass<T>(n, in, out, 0, NN, op.sign2, op.pre2, op.post2, op.pre1, op.pupil, plan.fused_slab, gen,
+                            st);
     if (e != hipSuccess) return e;
   } else {
     const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk
@@ -846,13 +876,10 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
       if (e != hipSuccess) return e;
     }
   }
-  const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
   if (plan.coop) return launch_first_point_coop<T>(n, out, op, pre1, plan.coop_cols, plan.coop_lookahead, counters, st);
   // First-point axes (j1, i1) over column chunks of the N^2 columns m2. The i1 pass of chunk k - 1
   // shares a launch with the j1 pass of chunk k: they touch disjoint columns.
   const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
-  Chirp post_last = op.post1;
-  post_last.scale = op.scale;
   const long long chunks = (NN + m - 1) / m;
   for (long long k = 0; k <= chunks; ++k) {
     const bool has_j = k < chunks, has_i = k > 0;

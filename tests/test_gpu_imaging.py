@@ -58,7 +58,8 @@ def test_lens_all_schedules_agree(gpu_lib, dtype):
     ref, _ = O.propagate_lens(w, n, p, LAM, f, z, O.GEO_CIRCLE, r)
     nn = n * n
     try:
-        for plan in [(1, 0, 0, 0, 1), (2, 0, 0, 0, 1), (0, 0, 0, 0, 1), (0, nn // 4, 64, 0, 1)]:
+        for plan in [(1, 0, 0, 0, 1), (2, 0, 0, 0, 1), (0, 0, 0, 0, 1), (0, nn // 4, 64, 0, 1), (3, 4 * n, 0, 0, 1),
+                     (1, 8 * n, 0, 0, 1)]:
             gpu_lib.set_plan(n, dtype, *plan)
             got, _ = gpu_lib.propagate_lens(dev(w, dtype), p, LAM, f, z, O.GEO_CIRCLE, r)
             assert rel(host(got), ref) < TOL[dtype], plan

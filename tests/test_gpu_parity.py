@@ -337,7 +337,9 @@ def test_all_schedules_agree(gpu_lib, dtype):
     nn = n * n
     c = 256 // 4 if 256 // 4 < n else n       # axis tile at N = 32 (N2 = 4)
     plans = [(1, 0, 0, 0, 1), (1, 0, c, 0, 1), (1, 0, nn // 2, 0, 1), (0, 0, 0, 0, 1), (0, nn // 4, c, 0, 1),
-             (0, 2, nn // 8, 0, 1), (2, 0, 0, 0, 1), (2, 0, c, 0, 1), (3, 0, 0, 0, 1), (3, 0, c, 0, 1)]
+             (0, 2, nn // 8, 0, 1), (2, 0, 0, 0, 1), (2, 0, c, 0, 1), (3, 0, 0, 0, 1), (3, 0, c, 0, 1),
+             # grouped: slab pass + j1 pass over groups of i1 planes, then the i1 pass
+             (3, 4 * n, 0, 0, 1), (1, 8 * n, c, 0, 1), (2, 2 * n, nn // 2, 0, 1), (3, n, nn // 4, 0, 1)]
     try:
         for plan in plans:
             gpu_lib.set_plan(n, dtype, *plan)
@@ -397,6 +399,32 @@ def test_half_buffer_slab_pass_matches_per_slab(gpu_lib, n, dtype):
     torch.cuda.synchronize()
     d = float(torch.linalg.vector_norm(outs[1] - outs[0]) / torch.linalg.vector_norm(outs[0]))
     assert d <= (1e-6 if dtype == torch.complex64 else 1e-14), d
+
+
+@pytest.mark.parametrize("dtype", DT)
+def test_grouped_schedule_full_size(gpu_lib, dtype):
+    """N = 128 GSM at full size: the slab pass and the j1 pass over groups of 16 and of 4 i1 planes
+    (the complex64 default is 16) give the same bits as the slab pass over all slabs followed by the
+    paired j1/i1 column chunks, with a random input (no symmetry to hide a misplaced group)."""
+    n, p, z = 128, 20e-6, 0.5
+    w0 = dev(WI.random_complex((n, n, n, n), seed=91, dtype=np.complex64 if dtype == torch.complex64
+                               else np.complex128), dtype)
+    outs = []
+    try:
+        for plan in ((3, 0, 1024, 0, 1), (3, 16 * n, n * n, 0, 1), (3, 4 * n, 4096, 0, 1)):
+            gpu_lib.set_plan(n, dtype, *plan)
+            print("plan", dtype, plan, flush=True)
+            x = w0.clone()
+            gpu_lib.propagate_fresnel(x, p, LAM, z, out=x)
+            outs.append(x.cpu())
+            del x
+            torch.cuda.empty_cache()
+    finally:
+        gpu_lib.set_plan(n, dtype)
+    del w0
+    torch.cuda.empty_cache()
+    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[2])
 
 
 def test_complex128_n128_uses_the_half_buffer_slab_pass(gpu_lib):
