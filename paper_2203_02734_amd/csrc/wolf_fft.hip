@@ -727,6 +727,25 @@ hipError_t launch_slab_pass(int n, const T* src, T* dst, long long slab0, long l
   WOLF_DISPATCH_N(n, (launch_slab_n<T, NN, +1>(src, dst, slab0, slabs, pre, post, slab_pre, pu, mode, gen, st)))
 }
 
+// Plain 2D DFTs of `count` N x N arrays in place (no chirps, no centring):
+//   X[m1][m2] = sum_{i, p} e^{SIGN 2 pi i (m1 i + m2 p) / N} x[i][p],
+// a row pass over p, then an axis pass over i (stride N). count N must be whole row-pass workgroups.
+bool dft2_batch_ok(int n, long long count) {
+  return n >= 2 && n <= 256 && (n & (n - 1)) == 0 && count > 0 && (count * n) % row_pass_rows(n) == 0;
+}
+
+template <class T>
+hipError_t launch_dft2_batch(int n, T* data, long long count, int sign, hipStream_t st) {
+  if (!dft2_batch_ok(n, count)) return hipErrorInvalidValue;
+  const Chirp ident{0.0, 1.0, +1, 0};
+  hipError_t e = launch_row_pass<T>(n, data, data, count * n, sign, ident, ident, st);
+  if (e != hipSuccess) return e;
+  const AxisRange ar{count, (long long)n * n, n, 0, n};
+  return launch_axis_range<T>(n, data, data, sign, ar, ident, ident, nullptr, ident, ident, st);
+}
+template hipError_t launch_dft2_batch<float2>(int, float2*, long long, int, hipStream_t);
+template hipError_t launch_dft2_batch<double2>(int, double2*, long long, int, hipStream_t);
+
 template <class T>
 __global__ __launch_bounds__(256) void k_apply_pupil(const T* in, T* out, int n, Pupil pu) {
   using R = typename real_of<T>::type;

@@ -110,6 +110,12 @@ template <class T> bool half_slab_supported(int n);  // plan fused_slab = 3
 // out[p1; p2] = P(p1) P(p2) in[p1; p2] (in == out allowed).
 template <class T>
 hipError_t launch_apply_pupil(int n, const T* in, T* out, const Pupil& pu, hipStream_t st);
+
+// In-place plain 2D DFTs (sign of the exponent `sign`) of `count` N x N arrays: a row pass and an axis
+// pass of the operator's FFT kernels. dft2_batch_ok: count N is a whole number of row-pass workgroups.
+bool dft2_batch_ok(int n, long long count);
+template <class T>
+hipError_t launch_dft2_batch(int n, T* data, long long count, int sign, hipStream_t st);
 int axis_tile_cols(int n, int elem_bytes);  // columns of an axis-pass tile
 int row_pass_rows(int n);  // rows per workgroup of the row pass
 

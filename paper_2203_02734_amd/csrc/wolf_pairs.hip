@@ -161,6 +161,146 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
 }
 
+// Row sums of a complex64 group of more than 32 pairs at N = 64 or 128, with the W stream kept deep in
+// flight: part[s][k][p2] = sum_{a} ci[k][a] G_a[k][p2], G_a[k][p2] = sum_b cj[k][b] W[a N + b][p2], over the
+// whole rows a of chunk s. The tables cj and ci of the group sit in LDS for the whole launch (2 x N x 64
+// complex, one workgroup per CU), so the only memory loads of the loop are the W operand: a wavefront
+// owns all 64 pairs and 32 columns p2 and keeps eight steps of 16 rows of W in registers (one wavefront
+// per SIMD, up to 512 registers). Each step is 96 MFMAs into G (4 x 2 tiles of 16 x 16 in the 3M form,
+// A = cj from LDS); after the N / 16 steps of a row a, G is folded into the output sums with ci[k][a] and
+// cleared. Every load is unconditional (the ring's last loads re-read the chunk's last step) and the
+// scheduling barriers keep each step's loads ahead of the matrix-core block they precede, so that the
+// waits leave the seven later steps in flight.
+struct RingStep {
+  float2 v[4][2];  // W[k0 + 4 ks + l / 16][j0 + 16 q + l % 16]
+};
+
+template <int N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pair_rows_ring(
+    const float2* __restrict__ w, const float2* __restrict__ cit, const float2* __restrict__ cjt, long long chunk,
+    int items, float2* __restrict__ part) {
+  constexpr long long NN = (long long)N * N;
+  constexpr int SPA = N / 16;  // steps per row a
+  constexpr int RING = 8;
+  constexpr int TILES = (int)(NN / 128);  // 128-column tiles per chunk
+  static_assert(SPA <= RING && RING % SPA == 0, "ring of whole rows");
+  __shared__ float2 cjs[N * kPairTile], cis[N * kPairTile];
+  const int tid = threadIdx.x, lane = tid % 64, l16 = lane % 16, kq = lane / 16;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+  // cj[b][k] at b 64 + (k ^ 16 (b & 1)): the four rows of an MFMA step fall on alternate bank halves.
+  for (int e = tid; e < N * kPairTile; e += 256) {
+    const int b = e / kPairTile, k = e % kPairTile;
+    cjs[b * kPairTile + (k ^ ((b & 1) << 4))] = cjt[e];
+    cis[e] = cit[e];
+  }
+  __syncthreads();
+  // Items (column tile, chunk) item = blockIdx.x + i gridDim.x, i < mine, run back to back as one
+  // sequence of steps t = i steps + step, so the ring stays full across items.
+  const int steps = (int)(chunk / 16);
+  const int mine = (items - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int total = mine * steps;
+  auto item_of = [&](int i) { return (int)blockIdx.x + i * (int)gridDim.x; };
+  auto load = [&](RingStep& r, int t) {
+    const int tc = t < total ? t : total - 1;
+    const int it = item_of(tc / steps), step = tc % steps;
+    const long long j0 = (long long)(it % TILES) * 128 + 32 * wv;
+    const long long p1 = (long long)(it / TILES) * chunk + 16 * step + kq;
+    const float2* q0 = w + p1 * NN + j0 + l16;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) r.v[ks][q] = q0[(long long)ks * 4 * NN + 16 * q];
+  };
+  v4f t1[4][2], t2[4][2], t3[4][2];
+  float2 f[4][2][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f[r][q][i] = float2{0.f, 0.f};
+    }
+  // A operand of one step (cj rows b0 .. b0 + 15 of this lane's pairs), read from LDS one step ahead.
+  auto read_a = [&](float2 (&av)[4][4], int b0) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int b = b0 + 4 * ks + kq;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[ks][r] = cjs[b * kPairTile + ((16 * r + l16) ^ ((b & 1) << 4))];
+    }
+  };
+  auto step_mfma = [&](const float2 (&av)[4][4], const RingStep& bw) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      float xs[4], ys[2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ys[q] = bw.v[ks][q].x + bw.v[ks][q].y;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].x, bw.v[ks][q].x, t1[r][q], 0, 0, 0);
+          t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].y, bw.v[ks][q].y, t2[r][q], 0, 0, 0);
+          t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], t3[r][q], 0, 0, 0);
+        }
+    }
+  };
+  RingStep ring[RING];
+#pragma unroll
+  for (int u = 0; u < RING - 1; ++u) {
+    load(ring[u], u);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  float2 avs[2][4][4];
+  read_a(avs[0], 0);
+  for (int t0 = 0; t0 < total; t0 += RING) {  // steps is a multiple of RING: t0 is a multiple of SPA
+#pragma unroll
+    for (int u = 0; u < RING; ++u) {
+      load(ring[(u + RING - 1) % RING], t0 + u + RING - 1);
+      read_a(avs[(u + 1) % 2], ((u + 1) % SPA) * 16);  // the next step's operand
+      __builtin_amdgcn_sched_barrier(0);
+      step_mfma(avs[u % 2], ring[u]);
+      if ((u + 1) % SPA == 0) {  // the last step of row a: fold G into the sums with ci[k][a]
+        const int t = t0 + u, it = item_of(t / steps);
+        const int a = (int)(((long long)(it / TILES) * chunk + 16 * (t % steps)) / N);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float2 c = cis[a * kPairTile + 16 * r + Mfma<float2>::row(lane, i)];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const float gr = t1[r][q][i] - t2[r][q][i], gi = t3[r][q][i] - t1[r][q][i] - t2[r][q][i];
+              f[r][q][i].x += c.x * gr - c.y * gi;
+              f[r][q][i].y += c.x * gi + c.y * gr;
+            }
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+        if ((t + 1) % steps == 0) {  // the item's last step: store its sums and start the next item
+          float2* out = part + (long long)(it / TILES) * kPairTile * NN;
+          const long long j0 = (long long)(it % TILES) * 128 + 32 * wv;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                out[(16 * r + Mfma<float2>::row(lane, i)) * NN + j0 + 16 * q + l16] = f[r][q][i];
+                f[r][q][i] = float2{0.f, 0.f};
+              }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 // Difference sums: part[z][k][di N + dj] = sum_{b in chunk z} B_k^{dj}[b] sum_a A_k^{di}[a]
 // W[a, b; a - di, b - dj] (indices mod N), A = u1[a] u2[a - di], B = u1[b] u2[b - dj], for the first TM
 // pairs k. A workgroup owns di, TN values of dj and a chunk of b; for each b the inner sum is a GEMM over
@@ -271,6 +411,141 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const int dj = dj0 + col0 + 16 * q + lane % 16;
         if (dj < n) out[k * nn + (long long)di * n + dj] = T{dre[r][q][i], dim[r][q][i]};
       }
+}
+
+// Difference sums of a complex64 group of more than 32 pairs at N = 64 or 128, with the W stream kept deep
+// in flight (the ring of k_pair_rows_ring): part[z][k][di N + dj] = sum_{b in chunk z} B_k^{dj}[b] G_b[k][dj],
+// G_b[k][dj] = sum_a A^{di}[a][k] W[a, b; a - di, b - dj], A^{di}[a][k] = u1[k][a] u2[k][a - di],
+// B_k^{dj}[b] = u1[k][b] u2[k][b - dj] (indices mod N). A workgroup owns one di and 256 / N chunks of b
+// (z = blockIdx.x % (256 / N)), all 64 pairs and all N values of dj (a wavefront: 32 of them). A^{di}
+// (formed once) and u2 sit in LDS; u1[k][b] is loaded at the start of each b. Each step is 16 values of a
+// (96 MFMAs into G); after the N / 16 steps of one b, G is folded into the sums. Only N = 128 fills the
+// four wavefronts' 128 columns; at N = 64 wavefronts 2 and 3 hold no columns and stay idle.
+template <int N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pair_diffs_ring(
+    const float2* __restrict__ w, const float2* __restrict__ u1t, const float2* __restrict__ u2t,
+    float2* __restrict__ part) {
+  constexpr long long NN = (long long)N * N;
+  constexpr int SPB = N / 16;  // steps per b
+  constexpr int RING = 8, BSPLIT = 256 / N, BCH = N / BSPLIT;
+  constexpr int NM = N - 1;
+  static_assert(SPB <= RING && RING % SPB == 0, "ring of whole b");
+  __shared__ float2 as_[N * kPairTile], u2s[N * kPairTile];
+  const int tid = threadIdx.x, lane = tid % 64, l16 = lane % 16, kq = lane / 16;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int di = (int)blockIdx.x / BSPLIT, z = (int)blockIdx.x % BSPLIT;
+  const int b_lo = z * BCH;
+  // A^{di}[a][k] at a 64 + (k ^ 16 (a & 1)); u2[m][k] at m 64 + (k ^ 2 (m & 15)) (the fold's 16 lanes of one
+  // k read 16 consecutive m).
+  for (int e = tid; e < N * kPairTile; e += 256) {
+    const int m = e / kPairTile, k = e % kPairTile;
+    as_[m * kPairTile + (k ^ ((m & 1) << 4))] = cmul(u1t[e], u2t[((m - di) & NM) * kPairTile + k]);
+    u2s[m * kPairTile + (k ^ ((m & 15) << 1))] = u2t[e];
+  }
+  __syncthreads();
+  if (wv * 32 >= N) return;  // no columns for this wavefront (N = 64); no barrier follows
+  const int dj0 = 32 * wv;
+  constexpr int total = BCH * SPB;
+  auto load = [&](RingStep& r, int t) {
+    const int tc = t < total ? t : total - 1;
+    const int b = b_lo + tc / SPB, a0 = (tc % SPB) * 16;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int a = a0 + 4 * ks + kq;
+      const float2* row = w + ((long long)a * N + b) * NN + (long long)((a - di) & NM) * N;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) r.v[ks][q] = row[(b - dj0 - 16 * q - l16) & NM];
+    }
+  };
+  v4f t1[4][2], t2[4][2], t3[4][2];
+  float2 f[4][2][4], u1v[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f[r][q][i] = float2{0.f, 0.f};
+    }
+  auto read_a = [&](float2 (&av)[4][4], int a0) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int a = a0 + 4 * ks + kq;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[ks][r] = as_[a * kPairTile + ((16 * r + l16) ^ ((a & 1) << 4))];
+    }
+  };
+  auto step_mfma = [&](const float2 (&av)[4][4], const RingStep& bw) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      float xs[4], ys[2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ys[q] = bw.v[ks][q].x + bw.v[ks][q].y;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].x, bw.v[ks][q].x, t1[r][q], 0, 0, 0);
+          t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].y, bw.v[ks][q].y, t2[r][q], 0, 0, 0);
+          t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], t3[r][q], 0, 0, 0);
+        }
+    }
+  };
+  RingStep ring[RING];
+#pragma unroll
+  for (int u = 0; u < RING - 1; ++u) {
+    load(ring[u], u);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  float2 avs[2][4][4];
+  read_a(avs[0], 0);
+  for (int t0 = 0; t0 < total; t0 += RING) {  // t0 is a multiple of SPB
+#pragma unroll
+    for (int u = 0; u < RING; ++u) {
+      const int b = b_lo + (t0 + u) / SPB;
+      load(ring[(u + RING - 1) % RING], t0 + u + RING - 1);
+      if (u % SPB == 0) {  // u1[k][b] of this b, behind the ring's load (it is needed at the fold)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) u1v[r][i] = u1t[b * kPairTile + 16 * r + Mfma<float2>::row(lane, i)];
+      }
+      read_a(avs[(u + 1) % 2], ((u + 1) % SPB) * 16);  // the next step's operand
+      __builtin_amdgcn_sched_barrier(0);
+      step_mfma(avs[u % 2], ring[u]);
+      if ((u + 1) % SPB == 0) {  // the last step of b: D += u1[k][b] u2[k][b - dj] G
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * r + Mfma<float2>::row(lane, i);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int m = (b - dj0 - 16 * q - l16) & NM;
+              const float2 c = cmul(u1v[r][i], u2s[m * kPairTile + (k ^ ((m & 15) << 1))]);
+              const float gr = t1[r][q][i] - t2[r][q][i], gi = t3[r][q][i] - t1[r][q][i] - t2[r][q][i];
+              f[r][q][i].x += c.x * gr - c.y * gi;
+              f[r][q][i].y += c.x * gi + c.y * gr;
+            }
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  float2* out = part + (long long)z * kPairTile * NN;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        out[(16 * r + Mfma<float2>::row(lane, i)) * NN + (long long)di * N + dj0 + 16 * q + l16] = f[r][q][i];
 }
 
 // out[k][i] = f(k, i) sum_s part[s][k][i] (k < kcount), summed in FP64 in the order of s;
@@ -817,11 +1092,33 @@ static hipError_t launch_mfma_tm(int kind, int n, const T* w, const T* u1, const
   return hipGetLastError();
 }
 
+// The ring form of the Fresnel difference sums (complex64, more than 32 pairs, N = 128) writes 256 / N
+// chunks of b.
+static bool diffs_ring_ok(int n, int count) { return n == 128 && count > 32; }
+
 template <class T>
 static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u1, const T* u2, const T* tr,
                               long long chunk, int bchunk, int sb, T* part, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {
     if (count <= 32) return launch_mfma_tm<T, 32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
+    const long long nn = (long long)n * n, tq = (long long)kPairTile * n;
+    if (kind == 1 && diffs_ring_ok(n, count)) {
+      hipLaunchKernelGGL(k_pair_diffs_ring<128>, dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
+      return hipGetLastError();
+    }
+    if (kind == 0 && (n == 64 || n == 128) && chunk * kPairSplitK == nn) {  // whole rows a per chunk
+      // One workgroup per CU (the tables take 2 x N x 64 complex of LDS), each running an equal share of
+      // the (column tile, chunk) items.
+      const int items = (int)(nn / 128) * kPairSplitK;
+      const int grid = items < 256 ? items : 256;
+      if (n == 64)
+        hipLaunchKernelGGL(k_pair_rows_ring<64>, dim3(grid), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq, chunk,
+                           items, part);
+      else
+        hipLaunchKernelGGL(k_pair_rows_ring<128>, dim3(grid), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq, chunk,
+                           items, part);
+      return hipGetLastError();
+    }
   }
   return launch_mfma_tm<T, 64>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
 }
@@ -894,16 +1191,22 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n, kPairTile,
                      (const T*)u2, buf_r);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_d, sb, n, kPairTile,
-                     (const T*)nullptr,
-                     buf_d);
+  const int sd = (sizeof(T) == 8 && diffs_ring_ok(n, count)) ? 256 / n : sb;  // chunks of b written
+  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_d, sd, n, kPairTile,
+                     (const T*)nullptr, buf_d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned rows = (unsigned)(count * n);  // the group's pairs only
-  // s0 = Re F D F^T with the + sign; b0 = F* (u2 R) F*^T.
-  hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_d, n, buf_t);
-  hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_d);
-  hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_r, n, buf_t);
-  hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_r);
+  // s0 = Re F D F^T with the + sign; b0 = F* (u2 R) F*^T: FFT passes in place where the group's rows fill
+  // whole row-pass workgroups, else the direct DFT kernel (transposed twice).
+  if (dft2_batch_ok(n, count)) {
+    if ((e = launch_dft2_batch<T>(n, buf_d, count, +1, st)) != hipSuccess) return e;
+    if ((e = launch_dft2_batch<T>(n, buf_r, count, -1, st)) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_d, n, buf_t);
+    hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_d);
+    hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_r, n, buf_t);
+    hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_r);
+  }
   hipLaunchKernelGGL(k_pair_s0<T>, dim3((unsigned)count), dim3(256), 0, st, (const T*)buf_d, n, s0, key);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int k = 0; k < count; ++k) out[k] = ObsSums<T>{s0 + k * nn, buf_r + k * nn, key + k};

@@ -97,6 +97,28 @@ def test_batch_two_groups_vs_oracle(gpu_lib, farfield, dtype):
         assert rel(mu[k], O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor), k
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_batch_n32_full_and_ragged_groups_vs_oracle(gpu_lib, dtype):
+    """70 pairs at N = 32 on a random Hermitian source: a full group of 64 pairs (in complex64 the row
+    sums of more than 32 pairs take the kernel that loads both operands into registers from a formed
+    A table) and a group of 6, every pair against the oracle."""
+    n, p = 32, 20e-6
+    w = WI.random_hermitian_psd(n, seed=93)
+    g = WI.rng(94)
+    lam = g.uniform(450e-9, 750e-9, 70)
+    zs = g.uniform(0.05, 2.0, 70)
+    ws = g.uniform(0.1, 1.5, 70)
+    ip, jp = 20, 9
+    floor = 1e-4 if dtype == torch.complex64 else 1e-8
+    s, mu = gpu_lib.propagate_batch(torch.from_numpy(w).to(dtype).cuda(), p, lam, zs, ws, ip=ip, jp=jp,
+                                    floor_rel=floor)
+    s, mu = host(s), host(mu)
+    for k in range(70):
+        wb, _ = O.propagate(ws[k] * w, n, p, lam[k], zs[k])
+        assert rel(s[k], O.spectral_density(wb)) < TOL[dtype], k
+        assert rel(mu[k], O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor), k
+
+
 @pytest.mark.parametrize("n", [64, 256])
 def test_batch_gsm_separable_large(gpu_lib, n):
     """complex64 GSM at N = 64 and at the largest N (256: a 34 GB source, 65536-row contractions), three
@@ -161,6 +183,37 @@ def test_batch_n128_complex128_full_propagation(gpu_lib, farfield):
         mur[sr <= floor * sr.max()] = 0
         assert rel(s[k], sr) < 1e-12
         assert rel(mu[k], mur) < 1e-12 / math.sqrt(floor)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_batch_n128_non_separable_matches_operator(gpu_lib, dtype):
+    """N = 128 at full size on a source that is not separable (the GSM source plus a seeded random
+    array at 5 % of its peak): the 64-pair batch (in complex64 the register-ring contractions over all
+    offsets) against the propagation operator, whose full-size parity with the oracle is tested, followed
+    by S and mu, for six of the pairs."""
+    wl = WI.gsm128()
+    n, p = wl.n, wl.pitch_m
+    pairs = WI.polychromatic_pairs()
+    ip, jp = wl.probe
+    npd = np.complex64 if dtype == torch.complex64 else np.complex128
+    w0 = gpu_lib.build_source(wl.source, n, p, dtype)
+    w0 += 0.05 * float(w0.abs().max()) * torch.from_numpy(WI.random_complex((n, n, n, n), seed=95, dtype=npd)).cuda()
+    floor = 1e-3 if dtype == torch.complex64 else 1e-8
+    s, mu = gpu_lib.propagate_batch(w0, p, pairs["wavelength"], pairs["z"], pairs["weight"], ip=ip, jp=jp,
+                                    floor_rel=floor)
+    s, mu = host(s), host(mu)
+    tol = 2e-5 if dtype == torch.complex64 else 1e-12
+    for k in (0, 5, 21, 34, 50, 63):
+        wb, _ = gpu_lib.propagate_fresnel(w0 * float(pairs["weight"][k]), p, float(pairs["wavelength"][k]),
+                                          float(pairs["z"][k]))
+        sr = host(gpu_lib.spectral_density(wb))
+        mur = host(gpu_lib.degree_of_coherence(wb, ip, jp, floor))
+        del wb
+        torch.cuda.empty_cache()
+        assert rel(s[k], sr) < tol, k
+        assert rel(mu[k], mur) < tol / math.sqrt(floor), k
+    del w0
+    torch.cuda.empty_cache()
 
 
 def test_batch_full_size_polychromatic(gpu_lib):
