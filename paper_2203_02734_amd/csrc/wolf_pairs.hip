@@ -623,16 +623,24 @@ __global__ __launch_bounds__(256) void k_pair_emit(const typename real_of<T>::ty
                    s_out + k * nn, mu_out + k * nn);
 }
 
-// s0[k][m] = Re z[k][m] and key[k] = order key of max_m s0[k][m] (one workgroup per pair; fixed order).
+// s0[k][m] = Re z[k][m] and key[k] = order key of max_m s0[k][m]: blockIdx.y is the pair, blockIdx.x one of
+// gridDim.x ranges of m; the ranges' maxima meet in an atomic max on the order keys (order-independent),
+// which k_pair_clear_keys has zeroed.
+__global__ void k_pair_clear_keys(unsigned long long* key, int count) {
+  if ((int)threadIdx.x < count) key[threadIdx.x] = 0ull;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_pair_s0(const T* __restrict__ z, int n, typename real_of<T>::type* s0,
                                                  unsigned long long* key) {
   using R = typename real_of<T>::type;
   __shared__ double red[256];
   const long long nn = (long long)n * n;
-  const long long k = blockIdx.x;
+  const long long k = blockIdx.y;
+  const long long len = (nn + gridDim.x - 1) / gridDim.x, m0 = blockIdx.x * len;
+  const long long m1 = m0 + len < nn ? m0 + len : nn;
   double mx = -INFINITY;
-  for (long long m = threadIdx.x; m < nn; m += blockDim.x) {
+  for (long long m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
     const R v = z[k * nn + m].x;
     s0[k * nn + m] = v;
     mx = fmax(mx, (double)v);
@@ -643,7 +651,13 @@ __global__ __launch_bounds__(256) void k_pair_s0(const T* __restrict__ z, int n,
     if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) key[k] = order_key(red[0]);
+  if (threadIdx.x == 0 && m0 < m1) atomicMax(&key[k], order_key(red[0]));
+}
+
+// Ranges of m per pair in k_pair_s0: about 4096 elements each.
+static unsigned s0_ranges(int n) {
+  const long long nn = (long long)n * n;
+  return (unsigned)((nn + 4095) / 4096);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1092,6 +1106,13 @@ static hipError_t launch_mfma_tm(int kind, int n, const T* w, const T* u1, const
   return hipGetLastError();
 }
 
+// The ring form of the row sums (complex64, more than 32 pairs, N = 64 or 128): the number of chunks of
+// p1 it writes (256 workgroups over the N^2 / 128 column tiles), or 0 where it does not apply.
+static int rows_ring_parts(int n, int count) {
+  if (count <= 32 || (n != 64 && n != 128)) return 0;
+  return 256 / (n * n / 128);
+}
+
 // The ring form of the Fresnel difference sums (complex64, more than 32 pairs, N = 128) writes 256 / N
 // chunks of b.
 static bool diffs_ring_ok(int n, int count) { return n == 128 && count > 32; }
@@ -1106,17 +1127,17 @@ static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u
       hipLaunchKernelGGL(k_pair_diffs_ring<128>, dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
       return hipGetLastError();
     }
-    if (kind == 0 && (n == 64 || n == 128) && chunk * kPairSplitK == nn) {  // whole rows a per chunk
-      // One workgroup per CU (the tables take 2 x N x 64 complex of LDS), each running an equal share of
-      // the (column tile, chunk) items.
-      const int items = (int)(nn / 128) * kPairSplitK;
-      const int grid = items < 256 ? items : 256;
+    if (kind == 0 && rows_ring_parts(n, count) > 0) {
+      // One workgroup per CU (the tables take 2 x N x 64 complex of LDS): 256 items of one 128-column tile
+      // and one of rows_ring_parts chunks of p1, so the chunk sums are few partials.
+      const int parts = rows_ring_parts(n, count);
+      const long long ring_chunk = nn / parts;
       if (n == 64)
-        hipLaunchKernelGGL(k_pair_rows_ring<64>, dim3(grid), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq, chunk,
-                           items, part);
+        hipLaunchKernelGGL(k_pair_rows_ring<64>, dim3(256), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq,
+                           ring_chunk, 256, part);
       else
-        hipLaunchKernelGGL(k_pair_rows_ring<128>, dim3(grid), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq, chunk,
-                           items, part);
+        hipLaunchKernelGGL(k_pair_rows_ring<128>, dim3(256), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq,
+                           ring_chunk, 256, part);
       return hipGetLastError();
     }
   }
@@ -1177,7 +1198,8 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
     hipLaunchKernelGGL((k_pair_dft<T, +1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_t, n, buf_d);
     hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_r, n, buf_t);
     hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3((unsigned)n), dim3(256), 0, st, (const T*)buf_t, n, buf_r);
-    hipLaunchKernelGGL(k_pair_s0<T>, dim3(1), dim3(256), 0, st, (const T*)buf_d, n, s0, key);
+    hipLaunchKernelGGL(k_pair_clear_keys, dim3(1), dim3(64), 0, st, key, 1);
+    hipLaunchKernelGGL(k_pair_s0<T>, dim3(s0_ranges(n), 1), dim3(256), 0, st, (const T*)buf_d, n, s0, key);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     out[0] = ObsSums<T>{s0, buf_r, key};
     return hipSuccess;
@@ -1188,7 +1210,8 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
   e = launch_mfma<T>(count, 1, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned sum_blocks = (unsigned)((g + 255) / 256);
-  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, kPairSplitK, n, kPairTile,
+  const int sr = (sizeof(T) == 8 && rows_ring_parts(n, count) > 0) ? rows_ring_parts(n, count) : kPairSplitK;
+  hipLaunchKernelGGL(k_pair_sum<T>, dim3(sum_blocks), dim3(256), 0, st, (const T*)part_r, sr, n, kPairTile,
                      (const T*)u2, buf_r);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int sd = (sizeof(T) == 8 && diffs_ring_ok(n, count)) ? 256 / n : sb;  // chunks of b written
@@ -1207,7 +1230,9 @@ hipError_t launch_pair_sums(int n, const T* w, const double* a_src, int count, i
     hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_r, n, buf_t);
     hipLaunchKernelGGL((k_pair_dft<T, -1>), dim3(rows), dim3(256), 0, st, (const T*)buf_t, n, buf_r);
   }
-  hipLaunchKernelGGL(k_pair_s0<T>, dim3((unsigned)count), dim3(256), 0, st, (const T*)buf_d, n, s0, key);
+  hipLaunchKernelGGL(k_pair_clear_keys, dim3(1), dim3(64), 0, st, key, count);
+  hipLaunchKernelGGL(k_pair_s0<T>, dim3(s0_ranges(n), (unsigned)count), dim3(256), 0, st, (const T*)buf_d, n, s0,
+                     key);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int k = 0; k < count; ++k) out[k] = ObsSums<T>{s0 + k * nn, buf_r + k * nn, key + k};
   return hipSuccess;
@@ -1301,8 +1326,10 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       const int bchunk = (n + sb - 1) / sb;
       if ((e = launch_mfma<T>(pg.count, 0, n, w, u1, u2, tr, chunk, bchunk, sb, part_r, st)) != hipSuccess) return e;
       if ((e = launch_mfma<T>(pg.count, 2, n, w, u1, u2, tr, chunk, bchunk, sb, part_d, st)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r,
-                         kPairSplitK, n, kPairTile, (const T*)u2, rr);
+      const int rp = sizeof(T) == 8 ? rows_ring_parts(n, pg.count) : 0;
+      const int sr = rp > 0 ? rp : kPairSplitK;
+      hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r, sr, n,
+                         kPairTile, (const T*)u2, rr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d, sb,
                          2 * n, kPairTile, (const T*)nullptr, dfull);
