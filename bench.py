@@ -39,8 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the c128 / far-field / adjoint / copy detail")
     ap.add_argument("--no-big", action="store_true", help="skip the N=256 complex64 workload (34 GB)")
-    ap.add_argument("--plan", default="auto",
-                    help="pass schedule for N=128 complex64: 'auto' (autotune), 'default', or "
+    ap.add_argument("--plan", default="default",
+                    help="pass schedule for N=128 complex64: 'default' (the library's built-in plan), 'auto' "
+                         "(autotune), or "
                          "'fused,slab_chunk,col_chunk[,coop_cols,coop_lookahead]'")
     ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None,
                     choices=["propagate", "batch", "padded", "source"],
@@ -52,6 +53,10 @@ def parse():
                          "propagation, five times each)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="rocprofv3 FETCH/WRITE summary for the current kernels (optional)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="no GPU: from the counter_collection.csv files of two rocprofv3 runs of "
+                         "'--pmc-sample propagate' (FETCH_SIZE, then WRITE_SIZE) with the same --plan, write the "
+                         "calibrated HBM bytes of one propagation to --traffic and exit")
     return ap.parse_args()
 
 
@@ -96,6 +101,9 @@ def timed_steps(fn, steps, warmup, marks):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.plan, args.traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: measures one GPU only; run it with --gpus 1 "
               "(multi-GPU sharding of the CSD propagation is described, not built).", file=sys.stderr)
@@ -115,7 +123,7 @@ def main():
 
     w = torch.empty((n, n, n, n), dtype=torch.complex64, device="cuda")
     wb = torch.empty_like(w)
-    # Pass schedule: the library's autotuner (untimed, part of the set-up), or a given one.
+    # Pass schedule: the library's built-in plan, its autotuner (untimed, part of the set-up), or a given one.
     if args.plan == "auto":
         plan, _ = wolf.autotune(n, torch.complex64, reps=3, work=wb)
     elif args.plan != "default":
@@ -186,7 +194,8 @@ def main():
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
-            if tr.get("kernels_sha") == kernels_sha() and tr.get("workload") == "gsm128_fresnel_c64":
+            if (tr.get("kernels_sha") == kernels_sha() and tr.get("workload") == "gsm128_fresnel_c64"
+                    and tr.get("plan") == plan):
                 traffic = tr.get("propagate_bytes_per_launch")
         except Exception:
             traffic = None
@@ -339,6 +348,42 @@ def rel_l2_separable(w_dev_host, wl):
         num += float(np.sum(np.abs(a - b) ** 2))
         den += float(np.sum(np.abs(b) ** 2))
     return math.sqrt(num / den)
+
+
+def plan_dict(text: str) -> dict:
+    """The plan of '--plan f,s,c[,coop_cols,lookahead]' in the form get_plan returns."""
+    v = [int(x) for x in text.split(",")] + [0, 1][len(text.split(",")) - 3:]
+    return {"fused_slab": v[0], "slab_chunk": v[1], "col_chunk": v[2], "coop_cols": v[3], "coop_lookahead": v[4]}
+
+
+def write_traffic(fetch_csv: str, write_csv: str, plan_text: str, out_path: str) -> None:
+    """Calibrated HBM bytes of the one propagation of '--pmc-sample propagate': the FETCH_SIZE and WRITE_SIZE
+    values (KiB per dispatch) of the operator's dispatches (after the source build, before the copy), each
+    scaled by what the same counter reads for the runtime's 2 GiB copy (2 GiB read and 2 GiB written)."""
+    import csv
+
+    def read(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+
+    out = {}
+    for tag, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        seq = read(path, counter)
+        i0 = max(i for i, (k, _) in enumerate(seq) if "k_build_source" in k)
+        i1 = min(i for i, (k, _) in enumerate(seq) if "copyBuffer" in k and i > i0)
+        factor = float(2 << 30) / (seq[i1][1] * 1024.0)
+        out[tag] = sum(v for _, v in seq[i0 + 1:i1]) * 1024.0 * factor
+        out[tag + "_factor"] = round(factor, 4)
+        out[tag + "_dispatches"] = i1 - i0 - 1
+    rec = {"workload": "gsm128_fresnel_c64", "plan": plan_dict(plan_text), "kernels_sha": kernels_sha(),
+           "propagate_bytes_per_launch": int(out["fetch"] + out["write"]), "fetch_bytes": int(out["fetch"]),
+           "write_bytes": int(out["write"]), "fetch_factor": out["fetch_factor"],
+           "write_factor": out["write_factor"], "dispatches": out["fetch_dispatches"]}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
 
 
 def kernels_sha() -> str:
