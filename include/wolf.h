@@ -372,12 +372,12 @@ WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double waveleng
  *                  complex64, and it fits complex128 at N = 128). 0: a row pass and an i2 pass instead.
  *   slab_chunk  fused_slab = 0: slabs per chunk of the row + i2 pass pair (0 = all), a power-of-two
  *               divisor of N^2. fused_slab > 0: 0 or N^2 runs the slab pass over all slabs at once; a
- *               smaller power-of-two multiple of N runs it over groups of that many slabs (whole i1
- *               planes), each followed at once by the j1 pass of its planes while they are still in the
- *               256 MB Infinity Cache; the i1 pass then runs over chunks of col_chunk columns. Ignored
- *               by the cooperative pass.
- *   col_chunk   columns m2 per chunk of the j1 + i1 pass pair, or of the i1 pass of the grouped
- *               schedule (0 = all). A power-of-two divisor
+ *               smaller power-of-two multiple of N makes in-place calls (and wolf_propagate_source) run it
+ *               over groups of that many slabs (whole i1 planes), each followed at once by the j1 pass of
+ *               its planes while they are still in the 256 MB Infinity Cache, and then the i1 pass over
+ *               all columns in one launch; out-of-place calls keep the paired passes over col_chunk
+ *               chunks. Ignored by the cooperative pass.
+ *   col_chunk   columns m2 per chunk of the j1 + i1 pass pair (0 = all). A power-of-two divisor
  *               of N^2 and a multiple of the axis tile. Chunks of tens of MB let the second pass of
  *               a pair read the first pass's output from the Infinity Cache instead of HBM.
  *   coop_cols   > 0: the first-point axes (j1, i1) run as one cooperative pass (one HBM sweep instead

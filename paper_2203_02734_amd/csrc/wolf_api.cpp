@@ -286,10 +286,10 @@ wolf::Plan default_plan(int32_t n, int32_t dtype) {
     p.fused_slab = 3;
     p.col_chunk = dtype == WOLF_C64 ? 1024 : nn;
     if (dtype == WOLF_C64) {
-      // Grouped schedule: the slab pass and the j1 pass over groups of 16 i1 planes (256 MB), then the
-      // i1 pass in one launch: 2.31 ms against 2.40 ms (groups of 4 planes: 2.80 ms, launch-bound).
+      // In place, the grouped schedule: the slab pass and the j1 pass over groups of 16 i1 planes (256 MB),
+      // then the i1 pass in one launch: 2.31-2.37 ms against 2.39-2.40 ms for the paired chunks (groups of
+      // 4 planes: 2.80 ms, launch-bound). Out of place the paired 1024-column chunks: 2.43 ms against 2.50.
       p.slab_chunk = 16 * (long long)n;
-      p.col_chunk = nn;
     }
   }
   if (n == 256) {
@@ -300,6 +300,10 @@ wolf::Plan default_plan(int32_t n, int32_t dtype) {
   }
   return p;
 }
+
+// Column chunk of the paired j1/i1 passes that the grouped candidates of the autotuner carry (their
+// out-of-place schedule): the built-in one for (n, dtype).
+long long c_best_paired(int32_t n, int32_t dtype) { return default_plan(n, dtype).col_chunk; }
 
 wolf::Plan plan_for(int32_t n, int32_t dtype) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -976,8 +980,8 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
       if (cols < nn && cols * nn * (long long)elem_bytes(dtype) < (4ll << 20)) break;
       wolf::Plan p{fused, fused ? 0 : row_chunk_slabs(n, dtype), cols, 0, 0, 1};
       if (plan_valid(n, dtype, p)) cands.push_back(p);
-      if (fused && cols == nn) {
-        // The grouped schedule: slab pass and j1 pass over groups of 4 and 16 i1 planes.
+      if (fused && cols == c_best_paired(n, dtype)) {
+        // The grouped schedule (in place): slab pass and j1 pass over groups of 4 and 16 i1 planes.
         for (long long planes : {4ll, 16ll}) {
           wolf::Plan q{fused, planes * n, cols, 0, 0, 1};
           if (planes * n < nn && plan_valid(n, dtype, q)) cands.push_back(q);

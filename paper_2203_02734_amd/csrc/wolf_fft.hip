@@ -854,10 +854,11 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
   const Chirp pre1 = plan.fused_slab ? ident : op.pre1;
   Chirp post_last = op.post1;
   post_last.scale = op.scale;
-  // Grouped schedule: the slab pass over a group of whole i1 planes (slab_chunk slabs), then at once
-  // the j1 pass of those planes, while they are still in the 256 MB memory-side cache; the i1 pass
-  // follows over column chunks. HBM then sees two sweeps of the array and the cache the third.
-  if (plan.fused_slab && !plan.coop && plan.slab_chunk > 0 && plan.slab_chunk < NN) {
+  // Grouped schedule (in place, or a formed source): the slab pass over a group of whole i1 planes
+  // (slab_chunk slabs), then at once the j1 pass of those planes, while they are still in the 256 MB
+  // memory-side cache; the i1 pass follows in one launch. Out of place the paired column chunks below
+  // measured faster, so an out-of-place call with a grouped plan takes them.
+  if (plan.fused_slab && !plan.coop && plan.slab_chunk > 0 && plan.slab_chunk < NN && (in == out || gen)) {
     const long long g = plan.slab_chunk;
     if (g % N != 0) return hipErrorInvalidValue;
     for (long long s0 = 0; s0 < NN; s0 += g) {
@@ -869,13 +870,8 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
                                st);
       if (e != hipSuccess) return e;
     }
-    const long long m = plan.col_chunk > 0 ? plan.col_chunk : NN;
-    for (long long ci = 0; ci < NN; ci += m) {
-      const AxisRange ai{N, NN, NNN, ci, (ci + m <= NN) ? m : NN - ci};  // i1: outer j1, stride N^3
-      e = launch_axis_range<T>(n, out, out, op.sign1, ai, pre1, post_last, nullptr, ident, ident, st);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const AxisRange ai{N, NN, NNN, 0, NN};  // i1 over all columns: outer j1, stride N^3
+    return launch_axis_range<T>(n, out, out, op.sign1, ai, pre1, post_last, nullptr, ident, ident, st);
   }
   // Second-point axes (i2, j2).
   if (plan.fused_slab) {

@@ -347,6 +347,12 @@ def test_all_schedules_agree(gpu_lib, dtype):
             assert rel(host(got), ref) < TOL[dtype], plan
             adj = gpu_lib.propagate_adjoint(dev(w, dtype), p, LAM, z)
             assert rel(host(adj), adj_ref) < TOL[dtype], plan
+            x = dev(w, dtype)  # in place: the grouped plans take their grouped schedule only here
+            gpu_lib.propagate_fresnel(x, p, LAM, z, out=x)
+            assert torch.equal(x, got), plan
+            x = dev(w, dtype)
+            gpu_lib.propagate_adjoint(x, p, LAM, z, out=x)
+            assert torch.equal(x, adj), plan
             assert gpu_lib.coop_error_flag() == 0, plan
     finally:
         gpu_lib.set_plan(n, dtype)
