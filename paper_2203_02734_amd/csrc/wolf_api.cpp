@@ -967,18 +967,20 @@ WOLF_API wolf_status wolf_autotune(int32_t n, int32_t dtype, void* work, int32_t
   const int c = wolf::axis_tile_cols(n, (int)elem_bytes(dtype));
   std::vector<wolf::Plan> cands;
   const wolf::Plan def = default_plan(n, dtype);
+  // Row-pass chunks of the fused_slab = 0 candidates: the built-in one where the built-in plan is a row pass.
+  const long long rows_chunk = def.fused_slab == 0 ? def.slab_chunk : row_chunk_slabs(n, dtype);
   for (int fused = 3; fused >= 0; --fused) {
     const int c0 = 64 / (int)elem_bytes(dtype);
     for (int cols : {c0, 2 * c0, 4 * c0}) {
       for (int la : {1, 2}) {
-        wolf::Plan p{fused, fused ? 0 : row_chunk_slabs(n, dtype), nn, 1, cols, la};
+        wolf::Plan p{fused, fused ? 0 : rows_chunk, nn, 1, cols, la};
         if (plan_valid(n, dtype, p)) cands.push_back(p);
       }
     }
     for (long long cols = nn; cols >= c; cols >>= 1) {
       // Chunks below 4 MB only add launches.
       if (cols < nn && cols * nn * (long long)elem_bytes(dtype) < (4ll << 20)) break;
-      wolf::Plan p{fused, fused ? 0 : row_chunk_slabs(n, dtype), cols, 0, 0, 1};
+      wolf::Plan p{fused, fused ? 0 : rows_chunk, cols, 0, 0, 1};
       if (plan_valid(n, dtype, p)) cands.push_back(p);
       if (fused && cols == c_best_paired(n, dtype)) {
         // The grouped schedule (in place): slab pass and j1 pass over groups of 4 and 16 i1 planes.
