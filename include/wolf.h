@@ -371,7 +371,8 @@ WOLF_API wolf_status wolf_chirp_table(int32_t n, double pitch_m, double waveleng
  *                  through a buffer of N/2 rows (32 <= N <= 128; two resident workgroups per CU in
  *                  complex64, and it fits complex128 at N = 128). 0: a row pass and an i2 pass instead.
  *   slab_chunk  fused_slab = 0: slabs per chunk of the row + i2 pass pair (0 = all), a power-of-two
- *               divisor of N^2. fused_slab > 0: 0 or N^2 runs the slab pass over all slabs at once; a
+ *               divisor of N^2; in place, chunks of whole i1 planes also take their j1 pass at once, and
+ *               the i1 pass then runs over all columns in one launch. fused_slab > 0: 0 or N^2 runs the slab pass over all slabs at once; a
  *               smaller power-of-two multiple of N makes in-place calls (and wolf_propagate_source) run it
  *               over groups of that many slabs (whole i1 planes), each followed at once by the j1 pass of
  *               its planes while they are still in the 256 MB Infinity Cache, and then the i1 pass over

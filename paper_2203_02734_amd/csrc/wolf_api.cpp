@@ -293,9 +293,10 @@ wolf::Plan default_plan(int32_t n, int32_t dtype) {
     }
   }
   if (n == 256) {
-    // Measured at N = 256 complex64 (row and i2 passes over chunks of slabs, then j1 and i1): 256-slab
-    // chunks and unchunked first-point passes, 51 ms, against 58 ms with 64 MB chunks of both.
-    p.slab_chunk = 256;
+    // Measured at N = 256 complex64, in place: row, i2 and j1 passes over chunks of 512 slabs (two i1 planes,
+    // 256 MB, in the memory-side cache), then the i1 pass: 45.8 ms, against 49.1 ms (512) and 50.8 ms (256)
+    // with the j1 pass after all chunks, 54.8 ms with 1024-slab chunks, and 58 ms with 64 MB chunks of both.
+    p.slab_chunk = 512;
     p.col_chunk = nn;
   }
   return p;

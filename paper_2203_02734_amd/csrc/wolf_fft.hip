@@ -880,6 +880,9 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
     if (e != hipSuccess) return e;
   } else {
     const long long g = plan.slab_chunk > 0 ? plan.slab_chunk : NN;  // slabs per chunk
+    // In place, chunks of whole i1 planes also take their j1 pass at once (as the grouped slab-pass
+    // schedule), while the chunk is still in the memory-side cache; the i1 pass then runs alone.
+    const bool grouped_j1 = !plan.coop && (in == out || gen) && g < NN && g % N == 0;
     for (long long s0 = 0; s0 < NN; s0 += g) {
       const long long gs = (s0 + g <= NN) ? g : NN - s0;
       e = launch_row_pass<T>(n, gen ? out + s0 * NN : in + s0 * NN, out + s0 * NN, gs * N, op.sign2, op.pre2, op.post2,
@@ -889,6 +892,16 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
       e = launch_axis_range<T>(n, out + s0 * NN, out + s0 * NN, op.sign2, ar, op.pre2, op.post2, nullptr, ident,
                                ident, st);
       if (e != hipSuccess) return e;
+      if (grouped_j1) {
+        const AxisRange aj{gs / N, NNN, NN, 0, NN};  // j1 of the chunk's planes: outer i1, stride N^2
+        e = launch_axis_range<T>(n, out + s0 * NN, out + s0 * NN, op.sign1, aj, op.pre1, op.post1, nullptr, ident,
+                                 ident, st);
+        if (e != hipSuccess) return e;
+      }
+    }
+    if (grouped_j1) {
+      const AxisRange ai{N, NN, NNN, 0, NN};  // i1 over all columns: outer j1, stride N^3
+      return launch_axis_range<T>(n, out, out, op.sign1, ai, op.pre1, post_last, nullptr, ident, ident, st);
     }
   }
   if (plan.coop) return launch_first_point_coop<T>(n, out, op, pre1, plan.coop_cols, plan.coop_lookahead, counters, st);

@@ -22,7 +22,8 @@ struct OperatorTables {
 // Schedule of the passes. fused_slab: one slab pass for (i2, j2); with 0 < slab_chunk < N^2 (whole
 // i1 planes), an in-place call runs it over groups of slab_chunk slabs, each followed at once by the
 // j1 pass of its planes, and the i1 pass follows in one launch. Otherwise a row pass and an i2 pass
-// run over chunks of `slab_chunk` slabs. Without groups (and out of place), the j1 and i1 passes run
+// run over chunks of `slab_chunk` slabs (in place, chunks of whole planes take their j1 pass at once
+// too). Without groups (and out of place), the j1 and i1 passes run
 // over chunks of `col_chunk` columns m2 (0 = all), the i1 pass of one chunk beside the j1 pass of the next.
 struct Plan {
   int fused_slab;  // 0: row pass + i2 axis pass; 1: one slab per workgroup; 2: persistent slab pass;
