@@ -25,7 +25,10 @@ namespace wolf {
 // Strided axis: element (o, n, c) at o * outer_stride + n * axis_stride + inner_offset + c.
 // A workgroup takes one outer index and C consecutive columns c (coalesced runs of C elements).
 // ---------------------------------------------------------------------------------------------
-template <class T, int N, int C, int SIGN>
+// NTL: the loads carry the nontemporal hint (data read once from HBM: the grouped schedule's final i1
+// pass, and every axis pass in complex128; measured faster there, slower where the input comes from the
+// memory-side cache).
+template <class T, int N, int C, int SIGN, bool NTL = false>
 __global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* dst, AxisJob ja, AxisJob jb) {
   using S = Split<N>;
   constexpr int N1 = S::N1, N2 = S::N2, Q = S::Q;
@@ -64,7 +67,14 @@ __global__ __launch_bounds__(Split<N>::N2 * C) void k_axis_fft(const T* src, T* 
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
     const int n = N2 * a + t;
-    v[a] = cmul(src[base + (long long)n * as], tpre[n]);
+    if constexpr (NTL) {
+      typedef typename real_of<T>::type R;
+      typedef R r2 __attribute__((ext_vector_type(2)));
+      const r2 x = __builtin_nontemporal_load(reinterpret_cast<const r2*>(src + base + (long long)n * as));
+      v[a] = cmul(T{x.x, x.y}, tpre[n]);
+    } else {
+      v[a] = cmul(src[base + (long long)n * as], tpre[n]);
+    }
   }
   dft_reg<N1, SIGN>(v);
 #pragma unroll
@@ -619,15 +629,20 @@ static bool make_job(const AxisRange& ar, const Chirp& pre, const Chirp& post, A
 
 template <class T, int N, int SIGN>
 static hipError_t launch_axis_n(const T* src, T* dst, const AxisRange& a, const Chirp& pre_a, const Chirp& post_a,
-                                const AxisRange* b, const Chirp& pre_b, const Chirp& post_b, hipStream_t st) {
+                                const AxisRange* b, const Chirp& pre_b, const Chirp& post_b, bool nt_loads,
+                                hipStream_t st) {
   constexpr int C = axis_cols<T, N>();
   AxisJob ja{}, jb{};
   if (!make_job<T, N>(a, pre_a, post_a, &ja)) return hipErrorInvalidValue;
   if (b != nullptr && !make_job<T, N>(*b, pre_b, post_b, &jb)) return hipErrorInvalidValue;
   const long long blocks = ja.blocks + jb.blocks;
   if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_axis_fft<T, N, C, SIGN>), dim3((unsigned)blocks), dim3(Split<N>::N2 * C), 0, st, src, dst,
-                     ja, jb);
+  if (nt_loads)
+    hipLaunchKernelGGL((k_axis_fft<T, N, C, SIGN, true>), dim3((unsigned)blocks), dim3(Split<N>::N2 * C), 0, st, src,
+                       dst, ja, jb);
+  else
+    hipLaunchKernelGGL((k_axis_fft<T, N, C, SIGN>), dim3((unsigned)blocks), dim3(Split<N>::N2 * C), 0, st, src, dst,
+                       ja, jb);
   return hipGetLastError();
 }
 
@@ -718,9 +733,11 @@ static hipError_t launch_slab_n(const T* src, T* dst, long long slab0, long long
 template <class T>
 hipError_t launch_axis_range(int n, const T* src, T* dst, int sign, const AxisRange& a, const Chirp& pre_a,
                              const Chirp& post_a, const AxisRange* b, const Chirp& pre_b, const Chirp& post_b,
-                             hipStream_t st) {
-  if (sign < 0) { WOLF_DISPATCH_N(n, (launch_axis_n<T, NN, -1>(src, dst, a, pre_a, post_a, b, pre_b, post_b, st))) }
-  WOLF_DISPATCH_N(n, (launch_axis_n<T, NN, +1>(src, dst, a, pre_a, post_a, b, pre_b, post_b, st)))
+                             hipStream_t st, bool nt_loads = sizeof(T) == 16) {
+  if (sign < 0) {
+    WOLF_DISPATCH_N(n, (launch_axis_n<T, NN, -1>(src, dst, a, pre_a, post_a, b, pre_b, post_b, nt_loads, st)))
+  }
+  WOLF_DISPATCH_N(n, (launch_axis_n<T, NN, +1>(src, dst, a, pre_a, post_a, b, pre_b, post_b, nt_loads, st)))
 }
 
 template <class T>
@@ -887,7 +904,7 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
       if (e != hipSuccess) return e;
     }
     const AxisRange ai{N, NN, NNN, 0, NN};  // i1 over all columns: outer j1, stride N^3
-    return launch_axis_range<T>(n, out, out, op.sign1, ai, pre1, post_last, nullptr, ident, ident, st);
+    return launch_axis_range<T>(n, out, out, op.sign1, ai, pre1, post_last, nullptr, ident, ident, st, true);
   }
   // Second-point axes (i2, j2).
   if (plan.fused_slab) {
@@ -917,7 +934,7 @@ hipError_t launch_operator(int n, const T* in, T* out, const OperatorTables& op,
     }
     if (grouped_j1) {
       const AxisRange ai{N, NN, NNN, 0, NN};  // i1 over all columns: outer j1, stride N^3
-      return launch_axis_range<T>(n, out, out, op.sign1, ai, op.pre1, post_last, nullptr, ident, ident, st);
+      return launch_axis_range<T>(n, out, out, op.sign1, ai, op.pre1, post_last, nullptr, ident, ident, st, true);
     }
   }
   if (plan.coop) return launch_first_point_coop<T>(n, out, op, pre1, plan.coop_cols, plan.coop_lookahead, counters, st);
