@@ -361,7 +361,13 @@ template <class T, int NZ> struct FoldCfg {
   }();
 };
 
-template <class T, int NZ, int SIGN, bool CONTIG>
+// KW > 0 instantiates a band of N for the centred crop s = (N_z - N)/2: 4 L2 KW <= N < 4 L2 (KW + 1).
+// Input row r (data indices m0 + L2 r, m0 in [0, L2) over the lanes) is then in the data on every lane
+// for r < 4 KW and on none for r >= 4 KW + 4. Output k2 = L2/2 + d of phase p has data index
+// 2 t + p + N/2 + 2 L2 d (t in [0, L2)): in the data on every lane for d in [-KW, KW), on none for
+// d < -KW - 1 or d > KW. Those rows skip their per-lane range tests or are dropped at compile time
+// (with the arithmetic that only feeds them). KW = 0 tests every row.
+template <class T, int NZ, int SIGN, bool CONTIG, int KW>
 __global__ __launch_bounds__((FoldCfg<T, NZ>::kThreads)) __attribute__((amdgpu_waves_per_eu(FoldCfg<T, NZ>::kWaves)))
 void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
   using S = LineCfg<T, NZ>;
@@ -384,22 +390,39 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
   const int m0 = N2 * a0 + t - sft;        // data index of input r = 0, in [0, L2)
   const int tk = t + N2 * a0;              // first-stage twiddle factor t + L2 a0
   const long long as = j.axis_stride, in_step = (long long)N2 * as, out_step = (long long)N1 * as;
+  constexpr int RA = 4 * KW, RZ = KW > 0 ? 4 * KW + 4 : H;  // rows below RA: all lanes; from RZ: none
+  static_assert(KW >= 0 && RA <= H && (KW == 0 || KW < N2 / 2), "bands of N within N_z / 2");
   for (long long tile = blockIdx.x; tile < j.tiles; tile += gridDim.x) {
     const long long o = tile / j.tiles_per_outer;
-    const long long col = (tile - o * j.tiles_per_outer) * C + c;
+    const long long col0 = (tile - o * j.tiles_per_outer) * C;
+    const long long col = col0 + c;
     const bool valid = col < j.ncols;
-    const long long base = o * j.outer_stride + col * j.col_stride;
+    // With RA > 0, lanes of columns past the end of a ragged tile work on the tile's first column (in
+    // bounds; their results are not stored), so the unconditional rows need no column test.
+    const long long base = o * j.outer_stride + (RA > 0 && !valid ? col0 : col) * j.col_stride;
+    const bool lane_ok = RA > 0 || valid;
     T z[H];
     {
       long long at = base + (long long)m0 * as;
 #pragma unroll
-      for (int r = 0; r < H; ++r, at += in_step) z[r] = load_or_first(src, valid && m0 + N2 * r < n, at);
+      for (int r = 0; r < H; ++r, at += in_step) {
+        if (r < RA)
+          z[r] = src[at];
+        else if (r < RZ)
+          z[r] = load_or_first(src, lane_ok && m0 + N2 * r < n, at);
+      }
     }
 #pragma unroll
     for (int r = 0; r < H; ++r) {
       const int m = m0 + N2 * r;
-      const bool ok = valid && m < n;
-      z[r] = keep_or_zero(ok, cmul(z[r], tpre[ok ? m : 0]));
+      if (r < RA) {
+        z[r] = cmul(z[r], tpre[m]);
+      } else if (r >= RZ) {
+        z[r] = T{(typename real_of<T>::type)0, (typename real_of<T>::type)0};
+      } else {
+        const bool ok = lane_ok && m < n;
+        z[r] = keep_or_zero(ok, cmul(z[r], tpre[ok ? m : 0]));
+      }
     }
     // Every load of the tile has been consumed here, so the stores below may overwrite src.
 #pragma unroll
@@ -423,21 +446,43 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
       long long at = base + (long long)mk * as;
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2, at += out_step) {
-        const int m = mk + N1 * k2;
-        if (valid && m >= 0 && m < n) dst[at] = cmul(u[k2], tpost[m]);
+        const int m = mk + N1 * k2, d = k2 - N2 / 2;
+        if (KW > 0 && d >= -KW && d < KW) {
+          if (valid) dst[at] = cmul(u[k2], tpost[m]);
+        } else if (KW == 0 || (d >= -KW - 1 && d <= KW)) {
+          if (valid && m >= 0 && m < n) dst[at] = cmul(u[k2], tpost[m]);
+        }
       }
     }
   }
 }
 
-template <class T, int NZ, bool CONTIG>
-static hipError_t launch_fold_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
+template <class T, int NZ, bool CONTIG, int KW>
+static hipError_t launch_fold_nzcb(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
   constexpr int NT = FoldCfg<T, NZ>::kThreads;
   if (sign < 0)
-    hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, -1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
+    hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, -1, CONTIG, KW>), dim3(grid), dim3(NT), 0, st, src, dst, j);
   else
-    hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, +1, CONTIG>), dim3(grid), dim3(NT), 0, st, src, dst, j);
+    hipLaunchKernelGGL((k_axis_pad_fold<T, NZ, +1, CONTIG, KW>), dim3(grid), dim3(NT), 0, st, src, dst, j);
   return hipGetLastError();
+}
+
+// At N_z = 512 (L2 = 16) a centred crop with 128 <= N <= 256 takes the instantiated band of N
+// (KW = N / 64: 2, 3 or 4); other cases test every row.
+template <class T, int NZ, bool CONTIG>
+static hipError_t launch_fold_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
+  if constexpr (NZ == 512) {
+    constexpr int N2 = LineCfg<T, NZ>::L2;
+    if (2 * j.s == NZ - j.n) {
+      switch (j.n / (4 * N2)) {
+        case 2: return launch_fold_nzcb<T, NZ, CONTIG, 2>(src, dst, j, sign, grid, st);
+        case 3: return launch_fold_nzcb<T, NZ, CONTIG, 3>(src, dst, j, sign, grid, st);
+        case 4: return launch_fold_nzcb<T, NZ, CONTIG, 4>(src, dst, j, sign, grid, st);
+        default: break;
+      }
+    }
+  }
+  return launch_fold_nzcb<T, NZ, CONTIG, 0>(src, dst, j, sign, grid, st);
 }
 
 template <class T, int NZ, bool CONTIG>
