@@ -355,9 +355,11 @@ template <class T, int NZ> struct FoldCfg {
   static constexpr int C = (sizeof(T) == 16 ? 128 : 256) / N2;
   static constexpr int kThreads = N2 * C;
   static constexpr size_t kLds = (PadLayout<T, NZ, false, 1, C>::kSize + 2 * kDenseMaxN + NZ) * sizeof(T);
+  // Waves per SIMD: what the LDS allows, at most 5 (the 8 + 8 register DFTs of N_z = 128 need about 90
+  // VGPRs; at the 80 of six waves they spill).
   static constexpr int kWaves = [] {
     const int w = (int)((kMaxLds / kLds) * (kThreads / 64) + 3) / 4;  // workgroups per CU over 4 SIMDs
-    return w < 1 ? 1 : (w > 8 ? 8 : w);
+    return w < 1 ? 1 : (w > 5 ? 5 : w);
   }();
 };
 
