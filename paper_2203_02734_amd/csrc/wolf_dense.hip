@@ -469,14 +469,15 @@ static hipError_t launch_fold_nzcb(const T* src, T* dst, const PadJob& j, int si
   return hipGetLastError();
 }
 
-// At N_z = 512 (L2 = 16) a centred crop with 128 <= N <= 256 takes the instantiated band of N
-// (KW = N / 64: 2, 3 or 4); other cases test every row.
+// At N_z = 512 (L2 = 16) a centred crop with 64 <= N <= 256 takes the instantiated band of N
+// (KW = N / 64: 1, 2, 3 or 4); other cases test every row.
 template <class T, int NZ, bool CONTIG>
 static hipError_t launch_fold_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
   if constexpr (NZ == 512) {
     constexpr int N2 = LineCfg<T, NZ>::L2;
     if (2 * j.s == NZ - j.n) {
       switch (j.n / (4 * N2)) {
+        case 1: return launch_fold_nzcb<T, NZ, CONTIG, 1>(src, dst, j, sign, grid, st);
         case 2: return launch_fold_nzcb<T, NZ, CONTIG, 2>(src, dst, j, sign, grid, st);
         case 3: return launch_fold_nzcb<T, NZ, CONTIG, 3>(src, dst, j, sign, grid, st);
         case 4: return launch_fold_nzcb<T, NZ, CONTIG, 4>(src, dst, j, sign, grid, st);

@@ -101,16 +101,18 @@ def test_source_builder_even_n(gpu_lib, model):
                                         (100, 100, torch.complex128), (144, 144, torch.complex64),
                                         (200, 210, torch.complex64), (60, 128, torch.complex64),
                                         (120, 512, torch.complex128), (256, 512, torch.complex64),
-                                        (136, 512, torch.complex64), (196, 512, torch.complex128)])
+                                        (136, 512, torch.complex64), (196, 512, torch.complex128),
+                                        (100, 512, torch.complex64)])
 def test_padded_full_size_gsm(gpu_lib, n, nz, dtype):
     """The paper's example sizes: N = 200 padded to N_z = 512 and N = 200 unpadded (complex64, 1.6e9
     elements; power-of-two and 20 x 10 mixed-radix FFT passes), with N = 96 padded to 192, N = 100
     padded to 256, N = 100 unpadded (complex128), N = 144 unpadded (FFT passes) and N = 200 padded to
     210 (dense passes), GSM source, against the separable oracle with the same padding; N = 60 padded
     to 128, N = 120 padded to 512 (complex128) and N = 256 padded to 512 (the largest N, 2N = N_z) take
-    the folded first stage. At N_z = 512 the bands of N in [128, 256] take compile-time row ranges:
-    N = 136 (complex64, band 128-191, ragged 16-line tiles), 200 (band 192-255) and 256, and N = 196
-    (complex128, band 192-255, ragged 8-line tiles)."""
+    the folded first stage. At N_z = 512 the bands of N in [64, 256] take compile-time row ranges:
+    N = 100 (complex64, band 64-127, ragged 16-line tiles), 136 (band 128-191, ragged), 200 (band
+    192-255) and 256, and N = 120 and 196 (complex128, bands 64-127 and 192-255, 196 with ragged 8-line
+    tiles)."""
     p, z, ss, sg = 20e-6, 0.5, 0.1e-3, 0.05e-3
     sp = SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=ss, sigma_g_m=sg, geometry=WI.GEO_NONE,
                          geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None, lens_focal_m=0.0,
