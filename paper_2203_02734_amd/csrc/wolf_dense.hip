@@ -469,20 +469,31 @@ static hipError_t launch_fold_nzcb(const T* src, T* dst, const PadJob& j, int si
   return hipGetLastError();
 }
 
-// At N_z = 512 (L2 = 16) a centred crop with 64 <= N <= 256 takes the instantiated band of N
-// (KW = N / 64: 1, 2, 3 or 4); other cases test every row.
+// A centred crop with N >= 4 L2 takes the instantiated band of N, KW = N / (4 L2): at N_z = 512 (L2 = 16)
+// KW = 1 .. 4 (N = 64 .. 256), at N_z = 128 (L2 = 8) KW = 1, 2 (N = 32 .. 64); other cases test every row.
+template <class T, int NZ, bool CONTIG, int KW>
+static hipError_t launch_fold_band(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st,
+                                   bool& done) {
+  constexpr int N2 = LineCfg<T, NZ>::L2;
+  if constexpr (4 * KW <= N2) {
+    if (j.n / (4 * N2) == KW) {
+      done = true;
+      return launch_fold_nzcb<T, NZ, CONTIG, KW>(src, dst, j, sign, grid, st);
+    }
+  }
+  return hipSuccess;
+}
+
 template <class T, int NZ, bool CONTIG>
 static hipError_t launch_fold_nzc(const T* src, T* dst, const PadJob& j, int sign, unsigned grid, hipStream_t st) {
-  if constexpr (NZ == 512) {
-    constexpr int N2 = LineCfg<T, NZ>::L2;
+  if constexpr (NZ == 128 || NZ == 512) {
     if (2 * j.s == NZ - j.n) {
-      switch (j.n / (4 * N2)) {
-        case 1: return launch_fold_nzcb<T, NZ, CONTIG, 1>(src, dst, j, sign, grid, st);
-        case 2: return launch_fold_nzcb<T, NZ, CONTIG, 2>(src, dst, j, sign, grid, st);
-        case 3: return launch_fold_nzcb<T, NZ, CONTIG, 3>(src, dst, j, sign, grid, st);
-        case 4: return launch_fold_nzcb<T, NZ, CONTIG, 4>(src, dst, j, sign, grid, st);
-        default: break;
-      }
+      bool done = false;
+      hipError_t e = launch_fold_band<T, NZ, CONTIG, 1>(src, dst, j, sign, grid, st, done);
+      if (!done) e = launch_fold_band<T, NZ, CONTIG, 2>(src, dst, j, sign, grid, st, done);
+      if (!done) e = launch_fold_band<T, NZ, CONTIG, 3>(src, dst, j, sign, grid, st, done);
+      if (!done) e = launch_fold_band<T, NZ, CONTIG, 4>(src, dst, j, sign, grid, st, done);
+      if (done) return e;
     }
   }
   return launch_fold_nzcb<T, NZ, CONTIG, 0>(src, dst, j, sign, grid, st);

@@ -1,7 +1,7 @@
-"""Host check of the compile-time row ranges of the folded zero-padded FFT pass at N_z = 512.
+"""Host check of the compile-time row ranges of the folded zero-padded FFT pass at N_z = 512 and 128.
 
 A padded axis (Sec. 3.3) embeds N data points at offset s = (N_z - N)/2 of an N_z-point transform,
-N_z = 2 L2^2 (L2 = 16, L1 = 32). Thread t of a line holds the first-stage inputs at data indices
+N_z = 2 L2^2 (L2 = 16 or 8, L1 = 2 L2). Thread t of a line holds the first-stage inputs at data indices
 m0 + L2 r (r < L1/2) with m0 = L2 ceil((s - t)/L2) + t - s, and writes the outputs k1 = 2t + p,
 k2 of phase p at data index 2t + p - s + L1 k2. For a band 4 L2 KW <= N < 4 L2 (KW + 1) the kernel
 treats input rows r < 4 KW and outputs k2 = L2/2 + d, d in [-KW, KW), as in the data on every lane,
@@ -10,11 +10,14 @@ test enumerates every even N of the instantiated bands and every lane and checks
 """
 from __future__ import annotations
 
-L2, L1, NZ = 16, 32, 512
-H = L1 // 2
+import pytest
+
+# (L2, instantiated bands KW)
+SPLITS = [(16, (1, 2, 3, 4)), (8, (1, 2))]
 
 
-def _lanes(n):
+def _lanes(n, L2):
+    NZ = 2 * L2 * L2
     s = (NZ - n) // 2
     for t in range(L2):
         a0 = (s - t + L2 - 1) // L2
@@ -23,14 +26,18 @@ def _lanes(n):
         yield t, s, m0
 
 
-def test_band_rows_and_outputs():
+@pytest.mark.parametrize("L2,bands", SPLITS)
+def test_band_rows_and_outputs(L2, bands):
+    L1, NZ = 2 * L2, 2 * L2 * L2
+    H = L1 // 2
     checked = 0
     for n in range(2, NZ // 2 + 1, 2):
         kw = n // (4 * L2)
-        if kw not in (1, 2, 3, 4):
+        if kw not in bands:
             continue
         ra, rz = 4 * kw, 4 * kw + 4
-        for t, s, m0 in _lanes(n):
+        assert ra <= H
+        for t, s, m0 in _lanes(n, L2):
             for r in range(H):
                 inside = m0 + L2 * r < n
                 if r < ra:
@@ -47,14 +54,18 @@ def test_band_rows_and_outputs():
                     if not (-kw - 1 <= d <= kw):
                         assert not inside, (n, t, p, k2)
                     checked += 1
-    assert checked == 97 * L2 * 2 * L2  # N = 64, 66, ..., 256
+    assert checked == (NZ // 2 - 4 * L2) // 2 * L2 * 2 * L2 + L2 * 2 * L2  # every even N from 4 L2 to N_z / 2
 
 
-def test_every_data_point_is_read_and_written_once():
+@pytest.mark.parametrize("L2,sizes", [(16, (64, 100, 126, 128, 136, 190, 192, 200, 254, 256)),
+                                      (8, (32, 48, 60, 62, 64))])
+def test_every_data_point_is_read_and_written_once(L2, sizes):
     """Over the lanes and rows of one line, the inputs cover [0, N) once and the outputs cover [0, N) once."""
-    for n in (64, 100, 126, 128, 136, 190, 192, 200, 254, 256):
+    L1 = 2 * L2
+    H = L1 // 2
+    for n in sizes:
         reads, writes = [], []
-        for t, s, m0 in _lanes(n):
+        for t, s, m0 in _lanes(n, L2):
             reads += [m0 + L2 * r for r in range(H) if m0 + L2 * r < n]
             writes += [2 * t + p - s + L1 * k2 for p in range(2) for k2 in range(L2)
                        if 0 <= 2 * t + p - s + L1 * k2 < n]
