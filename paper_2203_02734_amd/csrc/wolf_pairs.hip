@@ -161,21 +161,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
 }
 
-// Row sums of a complex64 group of more than 32 pairs at N = 64 or 128, with the W stream kept deep in
-// flight: part[s][k][p2] = sum_{a} ci[k][a] G_a[k][p2], G_a[k][p2] = sum_b cj[k][b] W[a N + b][p2], over the
-// whole rows a of chunk s. The tables cj and ci of the group sit in LDS for the whole launch (2 x N x 64
-// complex, one workgroup per CU), so the only memory loads of the loop are the W operand: a wavefront
-// owns all 64 pairs and 32 columns p2 and keeps eight steps of 16 rows of W in registers (one wavefront
-// per SIMD, up to 512 registers). Each step is 96 MFMAs into G (4 x 2 tiles of 16 x 16 in the 3M form,
-// A = cj from LDS); after the N / 16 steps of a row a, G is folded into the output sums with ci[k][a] and
-// cleared. Every load is unconditional (the ring's last loads re-read the chunk's last step) and the
+// Row sums of a complex64 group at N = 64 or 128, with the W stream kept deep in flight:
+// part[s][k][p2] = sum_{a} ci[k][a] G_a[k][p2], G_a[k][p2] = sum_b cj[k][b] W[a N + b][p2], over the
+// whole rows a of chunk s, for the first 16 R pairs k (R = 4: groups of more than 32 pairs; 2: 17-32; 1: up
+// to 16; the rows of the other pairs are not written). The tables cj and ci of the group sit in LDS for the
+// whole launch (2 x N x 64 complex, one workgroup per CU), so the only memory loads of the loop are the W
+// operand: a wavefront owns the 16 R pairs and 32 columns p2 and keeps eight steps of 16 rows of W in
+// registers (one wavefront per SIMD, up to 512 registers). Each step is 24 R MFMAs into G (R x 2 tiles of
+// 16 x 16 in the 3M form, A = cj from LDS); after the N / 16 steps of a row a, G is folded into the output
+// sums with ci[k][a] and cleared. Every load is unconditional (the ring's last loads re-read the chunk's last step) and the
 // scheduling barriers keep each step's loads ahead of the matrix-core block they precede, so that the
 // waits leave the seven later steps in flight.
 struct RingStep {
   float2 v[4][2];  // W[k0 + 4 ks + l / 16][j0 + 16 q + l % 16]
 };
 
-template <int N>
+template <int N, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pair_rows_ring(
     const float2* __restrict__ w, const float2* __restrict__ cit, const float2* __restrict__ cjt, long long chunk,
     int items, float2* __restrict__ part) {
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   constexpr int RING = 8;
   constexpr int TILES = (int)(NN / 128);  // 128-column tiles per chunk
   static_assert(SPA <= RING && RING % SPA == 0, "ring of whole rows");
+  static_assert(R >= 1 && 16 * R <= kPairTile, "tiles of 16 pairs");
   __shared__ float2 cjs[N * kPairTile], cis[N * kPairTile];
   const int tid = threadIdx.x, lane = tid % 64, l16 = lane % 16, kq = lane / 16;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -211,10 +213,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
       for (int q = 0; q < 2; ++q) r.v[ks][q] = q0[(long long)ks * 4 * NN + 16 * q];
   };
-  v4f t1[4][2], t2[4][2], t3[4][2];
-  float2 f[4][2][4];
+  v4f t1[R][2], t2[R][2], t3[R][2];
+  float2 f[R][2][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -222,26 +224,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       for (int i = 0; i < 4; ++i) f[r][q][i] = float2{0.f, 0.f};
     }
   // A operand of one step (cj rows b0 .. b0 + 15 of this lane's pairs), read from LDS one step ahead.
-  auto read_a = [&](float2 (&av)[4][4], int b0) {
+  auto read_a = [&](float2 (&av)[4][R], int b0) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int b = b0 + 4 * ks + kq;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[ks][r] = cjs[b * kPairTile + ((16 * r + l16) ^ ((b & 1) << 4))];
+      for (int r = 0; r < R; ++r) av[ks][r] = cjs[b * kPairTile + ((16 * r + l16) ^ ((b & 1) << 4))];
     }
   };
-  auto step_mfma = [&](const float2 (&av)[4][4], const RingStep& bw) {
+  auto step_mfma = [&](const float2 (&av)[4][R], const RingStep& bw) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      float xs[4], ys[2];
+      float xs[R], ys[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
+      for (int r = 0; r < R; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
 #pragma unroll
       for (int q = 0; q < 2; ++q) ys[q] = bw.v[ks][q].x + bw.v[ks][q].y;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
           t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].x, bw.v[ks][q].x, t1[r][q], 0, 0, 0);
           t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].y, bw.v[ks][q].y, t2[r][q], 0, 0, 0);
           t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], t3[r][q], 0, 0, 0);
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     load(ring[u], u);
     __builtin_amdgcn_sched_barrier(0);
   }
-  float2 avs[2][4][4];
+  float2 avs[2][4][R];
   read_a(avs[0], 0);
   for (int t0 = 0; t0 < total; t0 += RING) {  // steps is a multiple of RING: t0 is a multiple of SPA
 #pragma unroll
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         const int t = t0 + u, it = item_of(t / steps);
         const int a = (int)(((long long)(it / TILES) * chunk + 16 * (t % steps)) / N);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const float2 c = cis[a * kPairTile + 16 * r + Mfma<float2>::row(lane, i)];
@@ -279,14 +281,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             }
           }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int q = 0; q < 2; ++q) t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
         if ((t + 1) % steps == 0) {  // the item's last step: store its sums and start the next item
           float2* out = part + (long long)(it / TILES) * kPairTile * NN;
           const long long j0 = (long long)(it % TILES) * 128 + 32 * wv;
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
+          for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -417,11 +419,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // in flight (the ring of k_pair_rows_ring): part[z][k][di N + dj] = sum_{b in chunk z} B_k^{dj}[b] G_b[k][dj],
 // G_b[k][dj] = sum_a A^{di}[a][k] W[a, b; a - di, b - dj], A^{di}[a][k] = u1[k][a] u2[k][a - di],
 // B_k^{dj}[b] = u1[k][b] u2[k][b - dj] (indices mod N). A workgroup owns one di and 256 / N chunks of b
-// (z = blockIdx.x % (256 / N)), all 64 pairs and all N values of dj (a wavefront: 32 of them). A^{di}
+// (z = blockIdx.x % (256 / N)), the first 16 R pairs (R = 4, 2, 1 for groups of more than 32, 17-32 and
+// up to 16 pairs; the other pairs' sums are not written) and all N values of dj (a wavefront: 32 of them). A^{di}
 // (formed once) and u2 sit in LDS; u1[k][b] is loaded at the start of each b. Each step is 16 values of a
-// (96 MFMAs into G); after the N / 16 steps of one b, G is folded into the sums. Only N = 128 fills the
+// (24 R MFMAs into G); after the N / 16 steps of one b, G is folded into the sums. Only N = 128 fills the
 // four wavefronts' 128 columns; at N = 64 wavefronts 2 and 3 hold no columns and stay idle.
-template <int N>
+template <int N, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pair_diffs_ring(
     const float2* __restrict__ w, const float2* __restrict__ u1t, const float2* __restrict__ u2t,
     float2* __restrict__ part) {
@@ -430,6 +433,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   constexpr int RING = 8, BSPLIT = 256 / N, BCH = N / BSPLIT;
   constexpr int NM = N - 1;
   static_assert(SPB <= RING && RING % SPB == 0, "ring of whole b");
+  static_assert(R >= 1 && 16 * R <= kPairTile, "tiles of 16 pairs");
   __shared__ float2 as_[N * kPairTile], u2s[N * kPairTile];
   const int tid = threadIdx.x, lane = tid % 64, l16 = lane % 16, kq = lane / 16;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -457,36 +461,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       for (int q = 0; q < 2; ++q) r.v[ks][q] = row[(b - dj0 - 16 * q - l16) & NM];
     }
   };
-  v4f t1[4][2], t2[4][2], t3[4][2];
-  float2 f[4][2][4], u1v[4][4];
+  v4f t1[R][2], t2[R][2], t3[R][2];
+  float2 f[R][2][4], u1v[R][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 4; ++i) f[r][q][i] = float2{0.f, 0.f};
     }
-  auto read_a = [&](float2 (&av)[4][4], int a0) {
+  auto read_a = [&](float2 (&av)[4][R], int a0) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int a = a0 + 4 * ks + kq;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[ks][r] = as_[a * kPairTile + ((16 * r + l16) ^ ((a & 1) << 4))];
+      for (int r = 0; r < R; ++r) av[ks][r] = as_[a * kPairTile + ((16 * r + l16) ^ ((a & 1) << 4))];
     }
   };
-  auto step_mfma = [&](const float2 (&av)[4][4], const RingStep& bw) {
+  auto step_mfma = [&](const float2 (&av)[4][R], const RingStep& bw) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      float xs[4], ys[2];
+      float xs[R], ys[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
+      for (int r = 0; r < R; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
 #pragma unroll
       for (int q = 0; q < 2; ++q) ys[q] = bw.v[ks][q].x + bw.v[ks][q].y;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
           t1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].x, bw.v[ks][q].x, t1[r][q], 0, 0, 0);
           t2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].y, bw.v[ks][q].y, t2[r][q], 0, 0, 0);
           t3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], t3[r][q], 0, 0, 0);
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     load(ring[u], u);
     __builtin_amdgcn_sched_barrier(0);
   }
-  float2 avs[2][4][4];
+  float2 avs[2][4][R];
   read_a(avs[0], 0);
   for (int t0 = 0; t0 < total; t0 += RING) {  // t0 is a multiple of SPB
 #pragma unroll
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       load(ring[(u + RING - 1) % RING], t0 + u + RING - 1);
       if (u % SPB == 0) {  // u1[k][b] of this b, behind the ring's load (it is needed at the fold)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int i = 0; i < 4; ++i) u1v[r][i] = u1t[b * kPairTile + 16 * r + Mfma<float2>::row(lane, i)];
       }
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       step_mfma(avs[u % 2], ring[u]);
       if ((u + 1) % SPB == 0) {  // the last step of b: D += u1[k][b] u2[k][b - dj] G
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int k = 16 * r + Mfma<float2>::row(lane, i);
@@ -531,7 +535,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             }
           }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int q = 0; q < 2; ++q) t1[r][q] = t2[r][q] = t3[r][q] = v4f{0.f, 0.f, 0.f, 0.f};
       }
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   float2* out = part + (long long)z * kPairTile * NN;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -1106,40 +1110,43 @@ static hipError_t launch_mfma_tm(int kind, int n, const T* w, const T* u1, const
   return hipGetLastError();
 }
 
-// The ring form of the row sums (complex64, more than 32 pairs, N = 64 or 128): the number of chunks of
-// p1 it writes (256 workgroups over the N^2 / 128 column tiles), or 0 where it does not apply.
+// The ring form of the row sums (complex64, N = 64 or 128, any count): the number of chunks of p1 it writes
+// (256 workgroups over the N^2 / 128 column tiles), or 0 where it does not apply.
 static int rows_ring_parts(int n, int count) {
-  if (count <= 32 || (n != 64 && n != 128)) return 0;
+  if (count < 1 || (n != 64 && n != 128)) return 0;
   return 256 / (n * n / 128);
 }
 
-// The ring form of the Fresnel difference sums (complex64, more than 32 pairs, N = 128) writes 256 / N
-// chunks of b.
-static bool diffs_ring_ok(int n, int count) { return n == 128 && count > 32; }
+// The ring form of the Fresnel difference sums (complex64, N = 128, any count) writes 256 / N chunks of b.
+static bool diffs_ring_ok(int n, int count) { return n == 128 && count >= 1; }
 
 template <class T>
 static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u1, const T* u2, const T* tr,
                               long long chunk, int bchunk, int sb, T* part, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {
-    if (count <= 32) return launch_mfma_tm<T, 32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
     const long long nn = (long long)n * n, tq = (long long)kPairTile * n;
-    if (kind == 1 && diffs_ring_ok(n, count)) {
-      hipLaunchKernelGGL(k_pair_diffs_ring<128>, dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
-      return hipGetLastError();
-    }
     if (kind == 0 && rows_ring_parts(n, count) > 0) {
       // One workgroup per CU (the tables take 2 x N x 64 complex of LDS): 256 items of one 128-column tile
       // and one of rows_ring_parts chunks of p1, so the chunk sums are few partials.
       const int parts = rows_ring_parts(n, count);
       const long long ring_chunk = nn / parts;
-      if (n == 64)
-        hipLaunchKernelGGL(k_pair_rows_ring<64>, dim3(256), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq,
-                           ring_chunk, 256, part);
-      else
-        hipLaunchKernelGGL(k_pair_rows_ring<128>, dim3(256), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq,
-                           ring_chunk, 256, part);
+      using RowsRing = void (*)(const float2*, const float2*, const float2*, long long, int, float2*);
+      const RowsRing rows = n == 64 ? (count > 32 ? k_pair_rows_ring<64, 4>
+                                                  : count > 16 ? k_pair_rows_ring<64, 2> : k_pair_rows_ring<64, 1>)
+                                    : (count > 32 ? k_pair_rows_ring<128, 4>
+                                                  : count > 16 ? k_pair_rows_ring<128, 2> : k_pair_rows_ring<128, 1>);
+      hipLaunchKernelGGL(rows, dim3(256), dim3(256), 0, st, w, tr + 2 * tq, tr + 3 * tq, ring_chunk, 256, part);
       return hipGetLastError();
     }
+    if (kind == 1 && diffs_ring_ok(n, count)) {
+      using DiffsRing = void (*)(const float2*, const float2*, const float2*, float2*);
+      const DiffsRing diffs = count > 32   ? k_pair_diffs_ring<128, 4>
+                              : count > 16 ? k_pair_diffs_ring<128, 2>
+                                           : k_pair_diffs_ring<128, 1>;
+      hipLaunchKernelGGL(diffs, dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
+      return hipGetLastError();
+    }
+    if (count <= 32) return launch_mfma_tm<T, 32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
   }
   return launch_mfma_tm<T, 64>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
 }
