@@ -552,6 +552,199 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         out[(16 * r + Mfma<float2>::row(lane, i)) * NN + (long long)di * N + dj0 + 16 * q + l16] = f[r][q][i];
 }
 
+// The polychromatic difference sums without wrap (the bins of k_poly_diffs_mfma) on the register ring of
+// k_pair_diffs_ring, for a complex64 group of at most 16 pairs at N = 128 (one tile of 16 pairs, R = 1; with
+// two tiles the two bins' sums exceed the registers of one wavefront per SIMD and spill). A
+// workgroup owns one folded d_i, 256 / N chunks of b (z = blockIdx.x % (256 / N)) and every a: a step of 16
+// values of a adds into the G of bin d_i (a >= d_i) or of bin d_i - N (a < d_i); the one step that holds d_i
+// runs twice, with the A rows of the other bin zeroed. After the N / 16 steps of one b both G are folded into
+// their sums. On the second point a lane's column d_j switches bin once as b rises, so the lane stores its
+// lower bin's sums when b passes d_j - 1 and writes each of its four bins (two of d_i, two of d_j) exactly once
+// per chunk of b, zeros where the chunk holds no term.
+template <int N, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_poly_diffs_ring(
+    const float2* __restrict__ w, const float2* __restrict__ u1t, const float2* __restrict__ u2t,
+    float2* __restrict__ part) {
+  constexpr long long NN = (long long)N * N, BINS = 4 * NN;
+  constexpr int SPB = N / 16;  // steps per b
+  constexpr int RING = 8, BSPLIT = 256 / N, BCH = N / BSPLIT;
+  constexpr int NM = N - 1;
+  static_assert(SPB <= RING && RING % SPB == 0, "ring of whole b");
+  static_assert(R == 1, "groups of at most 16 pairs");
+  __shared__ float2 as_[N * kPairTile], u2s[N * kPairTile];
+  const int tid = threadIdx.x, lane = tid % 64, l16 = lane % 16, kq = lane / 16;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int di = (int)blockIdx.x / BSPLIT, z = (int)blockIdx.x % BSPLIT;
+  const int b_lo = z * BCH, b_hi = b_lo + BCH;
+  // A^{di}[a][k] at a 64 + (k ^ 16 (a & 1)); u2[m][k] at m 64 + (k ^ 2 (m & 15)), as in k_pair_diffs_ring.
+  for (int e = tid; e < N * kPairTile; e += 256) {
+    const int m = e / kPairTile, k = e % kPairTile;
+    as_[m * kPairTile + (k ^ ((m & 1) << 4))] = cmul(u1t[e], u2t[((m - di) & NM) * kPairTile + k]);
+    u2s[m * kPairTile + (k ^ ((m & 15) << 1))] = u2t[e];
+  }
+  __syncthreads();
+  if (wv * 32 >= N) return;  // no columns for this wavefront; no barrier follows
+  const int dj0 = 32 * wv;
+  constexpr int total = BCH * SPB;
+  auto load = [&](RingStep& r, int t) {
+    const int tc = t < total ? t : total - 1;
+    const int b = b_lo + tc / SPB, a0 = (tc % SPB) * 16;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int a = a0 + 4 * ks + kq;
+      const float2* row = w + ((long long)a * N + b) * NN + (long long)((a - di) & NM) * N;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) r.v[ks][q] = row[(b - dj0 - 16 * q - l16) & NM];
+    }
+  };
+  // [h]: h = 0 the bin d_i (a >= d_i), h = 1 the bin d_i - N (a < d_i).
+  v4f t1[2][R][2], t2[2][R][2], t3[2][R][2];
+  float2 f[2][R][2][4], u1v[R][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        t1[h][r][q] = t2[h][r][q] = t3[h][r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[h][r][q][i] = float2{0.f, 0.f};
+      }
+  auto read_a = [&](float2 (&av)[4][R], int a0) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int a = a0 + 4 * ks + kq;
+#pragma unroll
+      for (int r = 0; r < R; ++r) av[ks][r] = as_[a * kPairTile + ((16 * r + l16) ^ ((a & 1) << 4))];
+    }
+  };
+  auto step_mfma = [&](const float2 (&av)[4][R], const RingStep& bw, v4f (&s1)[R][2], v4f (&s2)[R][2],
+                       v4f (&s3)[R][2]) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      float xs[R], ys[2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) xs[r] = av[ks][r].x + av[ks][r].y;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ys[q] = bw.v[ks][q].x + bw.v[ks][q].y;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          s1[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].x, bw.v[ks][q].x, s1[r][q], 0, 0, 0);
+          s2[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][r].y, bw.v[ks][q].y, s2[r][q], 0, 0, 0);
+          s3[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[r], ys[q], s3[r][q], 0, 0, 0);
+        }
+    }
+  };
+  // The lane's four bins of pair k: d_i bin h (row di + N, or di), d_j bin dj (upper) or dj - N (lower).
+  float2* const out = part + (long long)z * kPairTile * BINS;
+  auto bin_at = [&](int k, int h, int dj_bin) {
+    return (long long)k * BINS + (long long)(h == 0 ? di + N : di) * (2 * N) + dj_bin + N;
+  };
+  RingStep ring[RING];
+#pragma unroll
+  for (int u = 0; u < RING - 1; ++u) {
+    load(ring[u], u);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  float2 avs[2][4][R];
+  read_a(avs[0], 0);
+  for (int t0 = 0; t0 < total; t0 += RING) {  // t0 is a multiple of SPB
+#pragma unroll
+    for (int u = 0; u < RING; ++u) {
+      const int b = b_lo + (t0 + u) / SPB, a0 = (u % SPB) * 16;
+      load(ring[(u + RING - 1) % RING], t0 + u + RING - 1);
+      if (u % SPB == 0) {  // u1[k][b] of this b, behind the ring's load (it is needed at the fold)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) u1v[r][i] = u1t[b * kPairTile + 16 * r + Mfma<float2>::row(lane, i)];
+      }
+      read_a(avs[(u + 1) % 2], ((u + 1) % SPB) * 16);  // the next step's operand
+      __builtin_amdgcn_sched_barrier(0);
+      if (a0 >= di) {  // workgroup-uniform: every a of the step is in the bin d_i
+        step_mfma(avs[u % 2], ring[u], t1[0], t2[0], t3[0]);
+      } else if (a0 + 16 <= di) {  // every a is in the bin d_i - N
+        step_mfma(avs[u % 2], ring[u], t1[1], t2[1], t3[1]);
+      } else {  // the step holds d_i: each bin with the other bin's rows of A zeroed
+        float2 am[4][R];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const bool upper = a0 + 4 * ks + kq >= di;
+#pragma unroll
+          for (int r = 0; r < R; ++r) am[ks][r] = upper ? avs[u % 2][ks][r] : float2{0.f, 0.f};
+        }
+        step_mfma(am, ring[u], t1[0], t2[0], t3[0]);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const bool upper = a0 + 4 * ks + kq >= di;
+#pragma unroll
+          for (int r = 0; r < R; ++r) am[ks][r] = upper ? float2{0.f, 0.f} : avs[u % 2][ks][r];
+        }
+        step_mfma(am, ring[u], t1[1], t2[1], t3[1]);
+      }
+      if ((u + 1) % SPB == 0) {  // the last step of b: D_h += u1[k][b] u2[k][b - dj] G_h, then the d_j switch
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * r + Mfma<float2>::row(lane, i);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int dj = dj0 + 16 * q + l16;
+              const int m = (b - dj) & NM;
+              const float2 c = cmul(u1v[r][i], u2s[m * kPairTile + (k ^ ((m & 15) << 1))]);
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const float gr = t1[h][r][q][i] - t2[h][r][q][i];
+                const float gi = t3[h][r][q][i] - t1[h][r][q][i] - t2[h][r][q][i];
+                f[h][r][q][i].x += c.x * gr - c.y * gi;
+                f[h][r][q][i].y += c.x * gi + c.y * gr;
+              }
+              if (b == dj - 1 && dj < b_hi) {  // every b below d_j is summed: the lower d_j bin is complete
+                // (at dj = b_hi the sums stay held: the chunk ends there and stores them in the lower bin)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                  out[bin_at(k, h, dj - N)] = f[h][r][q][i];
+                  f[h][r][q][i] = float2{0.f, 0.f};
+                }
+              }
+            }
+          }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) t1[h][r][q] = t2[h][r][q] = t3[h][r][q] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // The sums still held belong to the d_j bin of the chunk's last b; the other d_j bin was stored at the
+  // switch, or has no term in this chunk (zero).
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * r + Mfma<float2>::row(lane, i);
+        const int dj = dj0 + 16 * q + l16;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (dj >= b_hi) {  // every b of the chunk is below d_j
+            out[bin_at(k, h, dj - N)] = f[h][r][q][i];
+            out[bin_at(k, h, dj)] = float2{0.f, 0.f};
+          } else {
+            out[bin_at(k, h, dj)] = f[h][r][q][i];
+            if (dj <= b_lo) out[bin_at(k, h, dj - N)] = float2{0.f, 0.f};  // no b of the chunk is below d_j
+          }
+        }
+      }
+}
+
 // out[k][i] = f(k, i) sum_s part[s][k][i] (k < kcount), summed in FP64 in the order of s;
 // f = u2[k][i / n] u2[k][i % n] when u2 is given (the row sums), else 1.
 template <class T>
@@ -1120,6 +1313,10 @@ static int rows_ring_parts(int n, int count) {
 // The ring form of the Fresnel difference sums (complex64, N = 128, any count) writes 256 / N chunks of b.
 static bool diffs_ring_ok(int n, int count) { return n == 128 && count >= 1; }
 
+// The ring form of the polychromatic difference sums (complex64, N = 128, at most 16 pairs) writes 256 / N
+// chunks of b.
+static bool poly_diffs_ring_ok(int n, int count) { return n == 128 && count >= 1 && count <= 16; }
+
 template <class T>
 static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u1, const T* u2, const T* tr,
                               long long chunk, int bchunk, int sb, T* part, hipStream_t st) {
@@ -1144,6 +1341,10 @@ static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u
                               : count > 16 ? k_pair_diffs_ring<128, 2>
                                            : k_pair_diffs_ring<128, 1>;
       hipLaunchKernelGGL(diffs, dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
+      return hipGetLastError();
+    }
+    if (kind == 2 && poly_diffs_ring_ok(n, count)) {
+      hipLaunchKernelGGL((k_poly_diffs_ring<128, 1>), dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
       return hipGetLastError();
     }
     if (count <= 32) return launch_mfma_tm<T, 32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);
@@ -1338,8 +1539,9 @@ hipError_t launch_poly(int n, const T* w, int n_pairs, const double* alpha, cons
       hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, st, (const T*)part_r, sr, n,
                          kPairTile, (const T*)u2, rr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d, sb,
-                         2 * n, kPairTile, (const T*)nullptr, dfull);
+      const int sdp = (sizeof(T) == 8 && poly_diffs_ring_ok(n, pg.count)) ? 256 / n : sb;  // chunks of b written
+      hipLaunchKernelGGL(k_pair_sum<T>, dim3((unsigned)((4 * g + 255) / 256)), dim3(256), 0, st, (const T*)part_d,
+                         sdp, 2 * n, kPairTile, (const T*)nullptr, dfull);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // S: the + transform of D over [-N, N)^2 (offset N); the row: the - transform of T R (offset N/2). Only

@@ -128,6 +128,35 @@ def test_polychromatic_full_size_gsm(gpu_lib):
     assert rel(mu, mur) < 1e-5 / math.sqrt(floor)
 
 
+def test_polychromatic_small_group_paths_agree(gpu_lib):
+    """N = 128 complex64 on a source that is not separable (the GSM source plus a seeded random array at
+    5 % of its peak), 12 wavelengths at four distances on a common grid of no pair's pitch: the group of 12
+    pairs (its difference sums on the register ring, at most 16 pairs) against the same pairs followed by
+    21 pairs of zero weight (a group of 33: the LDS-staged difference sums that the small-N oracle tests
+    cover). The sums are the same up to FP32 summation order."""
+    wl = WI.gsm128()
+    n, p = wl.n, wl.pitch_m
+    pairs = WI.polychromatic_pairs()
+    lam, zs, ws = pairs["wavelength"][:12], pairs["z"][:12], pairs["weight"][:12]
+    g = WI.rng(97)
+    lam_pad = np.concatenate([lam, g.uniform(500e-9, 700e-9, 21)])
+    zs_pad = np.concatenate([zs, g.uniform(0.1, 1.0, 21)])
+    ws_pad = np.concatenate([ws, np.zeros(21)])
+    dx = 0.87 * O.output_pitch(n, p, 600e-9, 0.5)
+    ip, jp = wl.probe
+    floor = 1e-3
+    w0 = gpu_lib.build_source(wl.source, n, p, torch.complex64)
+    w0 += 0.05 * float(w0.abs().max()) * torch.from_numpy(
+        WI.random_complex((n, n, n, n), seed=98, dtype=np.complex64)).cuda()
+    s1, mu1 = gpu_lib.propagate_polychromatic(w0, p, lam, zs, ws, dx, ip=ip, jp=jp, floor_rel=floor)
+    s2, mu2 = gpu_lib.propagate_polychromatic(w0, p, lam_pad, zs_pad, ws_pad, dx, ip=ip, jp=jp, floor_rel=floor)
+    s1, mu1, s2, mu2 = host(s1), host(mu1), host(s2), host(mu2)
+    del w0
+    torch.cuda.empty_cache()
+    assert rel(s1, s2) < 1e-5
+    assert rel(mu1, mu2) < 1e-5 / math.sqrt(floor)
+
+
 def test_polychromatic_rejects(gpu_lib):
     w = torch.zeros((8, 8, 8, 8), dtype=torch.complex64, device="cuda")
     with pytest.raises(gpu_lib.WolfError):
