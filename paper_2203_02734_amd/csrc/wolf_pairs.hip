@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
 }
 
-// Difference sums of a complex64 group of more than 32 pairs at N = 64 or 128, with the W stream kept deep
+// Difference sums of a complex64 group at N = 128, with the W stream kept deep
 // in flight (the ring of k_pair_rows_ring): part[z][k][di N + dj] = sum_{b in chunk z} B_k^{dj}[b] G_b[k][dj],
 // G_b[k][dj] = sum_a A^{di}[a][k] W[a, b; a - di, b - dj], A^{di}[a][k] = u1[k][a] u2[k][a - di],
 // B_k^{dj}[b] = u1[k][b] u2[k][b - dj] (indices mod N). A workgroup owns one di and 256 / N chunks of b
