@@ -103,7 +103,8 @@ def test_source_builder_even_n(gpu_lib, model):
                                         (120, 512, torch.complex128), (256, 512, torch.complex64),
                                         (136, 512, torch.complex64), (196, 512, torch.complex128),
                                         (100, 512, torch.complex64), (32, 128, torch.complex64),
-                                        (64, 128, torch.complex128)])
+                                        (64, 128, torch.complex128), (160, 512, torch.complex128),
+                                        (40, 128, torch.complex128)])
 def test_padded_full_size_gsm(gpu_lib, n, nz, dtype):
     """The paper's example sizes: N = 200 padded to N_z = 512 and N = 200 unpadded (complex64, 1.6e9
     elements; power-of-two and 20 x 10 mixed-radix FFT passes), with N = 96 padded to 192, N = 100
@@ -113,8 +114,8 @@ def test_padded_full_size_gsm(gpu_lib, n, nz, dtype):
     the folded first stage. At N_z = 512 the bands of N in [64, 256] take compile-time row ranges:
     N = 100 (complex64, band 64-127, ragged 16-line tiles), 136 (band 128-191, ragged), 200 (band
     192-255) and 256, and N = 120 and 196 (complex128, bands 64-127 and 192-255, 196 with ragged 8-line
-    tiles); at N_z = 128 the bands 32-63 (N = 32 and 60, complex64, 60 with ragged 32-line tiles) and 64
-    (complex128)."""
+    tiles), and N = 160 (complex128, band 128-191); at N_z = 128 the bands 32-63 (N = 32 and 60 in complex64,
+    60 with ragged 32-line tiles; N = 40 in complex128) and 64 (complex128)."""
     p, z, ss, sg = 20e-6, 0.5, 0.1e-3, 0.05e-3
     sp = SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=ss, sigma_g_m=sg, geometry=WI.GEO_NONE,
                          geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None, lens_focal_m=0.0,
