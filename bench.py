@@ -469,12 +469,10 @@ def extras(wolf, wl, args):
                                                   t.wavelength_m, t.z_m, out=w64))
     out["tophat_lens64_c64_step_ms"] = round(t64s, 4)
     out["tophat_lens64_c64_elems_per_s"] = t.n ** 4 / (t64s * 1e-3)
-    # The same steps through wolf_propagate_source: the half-buffer slab pass forms the source where it
-    # would load W0 (bit-identical result), so W0 is never written and read back. It is the default
-    # schedule at N = 128 and is set here for N = 64.
-    wolf.set_plan(t.n, torch.complex64, 3, 0, t.n * t.n, 0, 1)
+    # The same steps through wolf_propagate_source: the half-buffer slab pass (the built-in schedule at
+    # N = 64 and 128) forms the source where it would load W0 (bit-identical result), so W0 is never
+    # written and read back.
     t64f = time_op(lambda: wolf.propagate_source(t.source, t.n, t.pitch_m, t.wavelength_m, t.z_m, out=w64))
-    wolf.set_plan(t.n, torch.complex64)
     out["tophat_lens64_c64_source_step_ms"] = round(t64f, 4)
     del w64
     w = torch.empty((n,) * 4, dtype=torch.complex64, device="cuda")
