@@ -1036,6 +1036,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
 }
 
+// Block of the one-pass sums: (column tile, slab range). The hardware deals consecutive workgroups to the
+// 8 XCDs in turn, so the linear index is remapped to put every column tile of one slab range on one XCD:
+// the slab's rows that a tile gathers for D were read for R by another tile of the same range, and are
+// then found in that XCD's L2 (with the x-fastest order each XCD held one column tile of every range, and
+// the gathered rows came from the other XCDs' reads). Identity where the ranges are not a multiple of 8.
+struct OneBlock {
+  int x, y;
+};
+__device__ __forceinline__ OneBlock one_block() {
+  const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+  if (gy % 8 != 0) return OneBlock{(int)blockIdx.x, (int)blockIdx.y};
+  const int l = (int)blockIdx.x + gx * (int)blockIdx.y;
+  return OneBlock{(l / 8) % gx, l % 8 + 8 * (l / (8 * gx))};
+}
+
 // The polychromatic sums of a group of one pair in one pass over the source, as k_one_sums: R as there,
 // and the unfolded difference sums D[d], d in [-N, N)^2. The element W[p1; p1 - d] of a thread's folded
 // column d = (d_i, d_j) belongs to the unfolded bin (a >= d_i ? d_i : d_i - N, b >= d_j ? d_j : d_j - N);
@@ -1052,9 +1067,10 @@ __global__ __launch_bounds__(kOneThreads) void k_one_poly_sums(const T* __restri
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kOneThreads) su2[i] = u2[i];
   __syncthreads();
-  const int c0 = (int)blockIdx.x * kOneThreads * kOneCols + tid;
+  const OneBlock ob = one_block();
+  const int c0 = ob.x * kOneThreads * kOneCols + tid;
   const int di0 = c0 >> lg, dj0 = c0 & nm, step = kOneThreads >> lg;
-  const int p_lo = (int)blockIdx.y * slabs, p_hi = p_lo + slabs < nn ? p_lo + slabs : nn;
+  const int p_lo = ob.y * slabs, p_hi = p_lo + slabs < nn ? p_lo + slabs : nn;
   const T zero{(R)0, (R)0};
   T r[kOneCols], d[4][kOneCols];  // d[2 (a < d_i) + (b < d_j)][j]
 #pragma unroll
@@ -1091,8 +1107,8 @@ __global__ __launch_bounds__(kOneThreads) void k_one_poly_sums(const T* __restri
       }
     }
   }
-  T* orr = part_r + (long long)blockIdx.y * nn;
-  T* odd = part_d + (long long)blockIdx.y * 4 * nn;
+  T* orr = part_r + (long long)ob.y * nn;
+  T* odd = part_d + (long long)ob.y * 4 * nn;
 #pragma unroll
   for (int j = 0; j < kOneCols; ++j) {
     const int i = c0 + kOneThreads * j;
@@ -1221,10 +1237,11 @@ __global__ __launch_bounds__(kOneThreads) void k_one_sums(const T* __restrict__ 
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kOneThreads) su2[i] = u2[i];
   __syncthreads();
-  const int c0 = (int)blockIdx.x * kOneThreads * kOneCols + tid;
+  const OneBlock ob = one_block();
+  const int c0 = ob.x * kOneThreads * kOneCols + tid;
   // Column i = c0 + kOneThreads j is d = (di0 + step j, dj0): kOneThreads is a multiple of N.
   const int di0 = c0 >> lg, dj0 = c0 & nm, step = kOneThreads >> lg;
-  const int p_lo = (int)blockIdx.y * slabs, p_hi = p_lo + slabs < nn ? p_lo + slabs : nn;
+  const int p_lo = ob.y * slabs, p_hi = p_lo + slabs < nn ? p_lo + slabs : nn;
   const T zero{(R)0, (R)0};
   T r[kOneCols], d[kOneCols];
 #pragma unroll
@@ -1256,8 +1273,8 @@ __global__ __launch_bounds__(kOneThreads) void k_one_sums(const T* __restrict__ 
       d[j].y += t.y;
     }
   }
-  T* orr = part_r + (long long)blockIdx.y * nn;
-  T* odd = part_d + (long long)blockIdx.y * nn;
+  T* orr = part_r + (long long)ob.y * nn;
+  T* odd = part_d + (long long)ob.y * nn;
 #pragma unroll
   for (int j = 0; j < kOneCols; ++j) {
     const int i = c0 + kOneThreads * j;
