@@ -1,4 +1,5 @@
-"""Host check of the compile-time row ranges of the folded zero-padded FFT pass at N_z = 512 and 128.
+"""Host checks of index maps: the compile-time row ranges of the folded zero-padded FFT pass at N_z = 512
+and 128, and the workgroup order of the one-pass sums.
 
 A padded axis (Sec. 3.3) embeds N data points at offset s = (N_z - N)/2 of an N_z-point transform,
 N_z = 2 L2^2 (L2 = 16 or 8, L1 = 2 L2). Thread t of a line holds the first-stage inputs at data indices
@@ -71,3 +72,18 @@ def test_every_data_point_is_read_and_written_once(L2, sizes):
                        if 0 <= 2 * t + p - s + L1 * k2 < n]
         assert sorted(reads) == list(range(n))
         assert sorted(writes) == list(range(n))
+
+
+@pytest.mark.parametrize("gx", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("gy", [8, 16, 64, 256])
+def test_one_pass_block_order(gx, gy):
+    """The one-pass sums of a group of one entry remap the linear workgroup index l (dealt to XCD l mod 8)
+    to (column tile, slab range) = ((l / 8) mod gx, l mod 8 + 8 (l / (8 gx))): a bijection onto the grid in
+    which every column tile of a slab range has the same l mod 8."""
+    seen = set()
+    for l in range(gx * gy):
+        x, y = (l // 8) % gx, l % 8 + 8 * (l // (8 * gx))
+        assert 0 <= x < gx and 0 <= y < gy
+        assert y % 8 == l % 8
+        seen.add((x, y))
+    assert len(seen) == gx * gy
