@@ -553,24 +553,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 // The polychromatic difference sums without wrap (the bins of k_poly_diffs_mfma) on the register ring of
-// k_pair_diffs_ring, for a complex64 group of at most 16 pairs at N = 128 (one tile of 16 pairs, R = 1; with
-// two tiles the two bins' sums exceed the registers of one wavefront per SIMD and spill). A
+// k_pair_diffs_ring, for the pairs k0 .. k0 + 16 R - 1 of a complex64 group at N = 128: one tile of 16 pairs
+// with eight steps of the source in flight (R = 1, RING = 8), or two tiles with four steps (R = 2, RING = 4:
+// with eight, the two bins' sums of two tiles exceed the registers of one wavefront per SIMD and spill). A
 // workgroup owns one folded d_i, 256 / N chunks of b (z = blockIdx.x % (256 / N)) and every a: a step of 16
 // values of a adds into the G of bin d_i (a >= d_i) or of bin d_i - N (a < d_i); the one step that holds d_i
 // runs twice, with the A rows of the other bin zeroed. After the N / 16 steps of one b both G are folded into
 // their sums. On the second point a lane's column d_j switches bin once as b rises, so the lane stores its
 // lower bin's sums when b passes d_j - 1 and writes each of its four bins (two of d_i, two of d_j) exactly once
 // per chunk of b, zeros where the chunk holds no term.
-template <int N, int R>
+template <int N, int R, int RING>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_poly_diffs_ring(
-    const float2* __restrict__ w, const float2* __restrict__ u1t, const float2* __restrict__ u2t,
+    const float2* __restrict__ w, const float2* __restrict__ u1t, const float2* __restrict__ u2t, int k0,
     float2* __restrict__ part) {
   constexpr long long NN = (long long)N * N, BINS = 4 * NN;
   constexpr int SPB = N / 16;  // steps per b
-  constexpr int RING = 8, BSPLIT = 256 / N, BCH = N / BSPLIT;
+  constexpr int BSPLIT = 256 / N, BCH = N / BSPLIT;
   constexpr int NM = N - 1;
-  static_assert(SPB <= RING && RING % SPB == 0, "ring of whole b");
-  static_assert(R == 1, "groups of at most 16 pairs");
+  static_assert((SPB <= RING && RING % SPB == 0) || (RING < SPB && SPB % RING == 0), "ring and steps per b nest");
+  static_assert((R == 1 && RING == 8) || (R == 2 && RING == 4), "the register budgets measured");
   __shared__ float2 as_[N * kPairTile], u2s[N * kPairTile];
   const int tid = threadIdx.x, lane = tid % 64, l16 = lane % 16, kq = lane / 16;
   const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int ks = 0; ks < 4; ++ks) {
       const int a = a0 + 4 * ks + kq;
 #pragma unroll
-      for (int r = 0; r < R; ++r) av[ks][r] = as_[a * kPairTile + ((16 * r + l16) ^ ((a & 1) << 4))];
+      for (int r = 0; r < R; ++r) av[ks][r] = as_[a * kPairTile + ((k0 + 16 * r + l16) ^ ((a & 1) << 4))];
     }
   };
   auto step_mfma = [&](const float2 (&av)[4][R], const RingStep& bw, v4f (&s1)[R][2], v4f (&s2)[R][2],
@@ -640,7 +641,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   // The lane's four bins of pair k: d_i bin h (row di + N, or di), d_j bin dj (upper) or dj - N (lower).
   float2* const out = part + (long long)z * kPairTile * BINS;
   auto bin_at = [&](int k, int h, int dj_bin) {
-    return (long long)k * BINS + (long long)(h == 0 ? di + N : di) * (2 * N) + dj_bin + N;
+    return (long long)(k0 + k) * BINS + (long long)(h == 0 ? di + N : di) * (2 * N) + dj_bin + N;
   };
   RingStep ring[RING];
 #pragma unroll
@@ -650,18 +651,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   float2 avs[2][4][R];
   read_a(avs[0], 0);
-  for (int t0 = 0; t0 < total; t0 += RING) {  // t0 is a multiple of SPB
+  for (int t0 = 0; t0 < total; t0 += RING) {
 #pragma unroll
     for (int u = 0; u < RING; ++u) {
-      const int b = b_lo + (t0 + u) / SPB, a0 = (u % SPB) * 16;
+      // Step of this b: known at compile time when the ring holds whole b (t0 a multiple of SPB), else
+      // wavefront-uniform.
+      const int sb = RING % SPB == 0 ? u % SPB : (t0 + u) % SPB;
+      const int b = b_lo + (t0 + u) / SPB, a0 = sb * 16;
       load(ring[(u + RING - 1) % RING], t0 + u + RING - 1);
-      if (u % SPB == 0) {  // u1[k][b] of this b, behind the ring's load (it is needed at the fold)
+      if (sb == 0) {  // u1[k][b] of this b, behind the ring's load (it is needed at the fold)
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) u1v[r][i] = u1t[b * kPairTile + 16 * r + Mfma<float2>::row(lane, i)];
+          for (int i = 0; i < 4; ++i) u1v[r][i] = u1t[b * kPairTile + k0 + 16 * r + Mfma<float2>::row(lane, i)];
       }
-      read_a(avs[(u + 1) % 2], ((u + 1) % SPB) * 16);  // the next step's operand
+      read_a(avs[(u + 1) % 2], ((sb + 1) % SPB) * 16);  // the next step's operand
       __builtin_amdgcn_sched_barrier(0);
       if (a0 >= di) {  // workgroup-uniform: every a of the step is in the bin d_i
         step_mfma(avs[u % 2], ring[u], t1[0], t2[0], t3[0]);
@@ -684,7 +688,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
         step_mfma(am, ring[u], t1[1], t2[1], t3[1]);
       }
-      if ((u + 1) % SPB == 0) {  // the last step of b: D_h += u1[k][b] u2[k][b - dj] G_h, then the d_j switch
+      if (sb == SPB - 1) {  // the last step of b: D_h += u1[k][b] u2[k][b - dj] G_h, then the d_j switch
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -694,7 +698,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             for (int q = 0; q < 2; ++q) {
               const int dj = dj0 + 16 * q + l16;
               const int m = (b - dj) & NM;
-              const float2 c = cmul(u1v[r][i], u2s[m * kPairTile + (k ^ ((m & 15) << 1))]);
+              const float2 c = cmul(u1v[r][i], u2s[m * kPairTile + ((k0 + k) ^ ((m & 15) << 1))]);
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 const float gr = t1[h][r][q][i] - t2[h][r][q][i];
@@ -1330,9 +1334,9 @@ static int rows_ring_parts(int n, int count) {
 // The ring form of the Fresnel difference sums (complex64, N = 128, any count) writes 256 / N chunks of b.
 static bool diffs_ring_ok(int n, int count) { return n == 128 && count >= 1; }
 
-// The ring form of the polychromatic difference sums (complex64, N = 128, at most 16 pairs) writes 256 / N
-// chunks of b.
-static bool poly_diffs_ring_ok(int n, int count) { return n == 128 && count >= 1 && count <= 16; }
+// The ring form of the polychromatic difference sums (complex64, N = 128, any count) writes 256 / N chunks
+// of b.
+static bool poly_diffs_ring_ok(int n, int count) { return n == 128 && count >= 1; }
 
 template <class T>
 static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u1, const T* u2, const T* tr,
@@ -1361,7 +1365,12 @@ static hipError_t launch_mfma(int count, int kind, int n, const T* w, const T* u
       return hipGetLastError();
     }
     if (kind == 2 && poly_diffs_ring_ok(n, count)) {
-      hipLaunchKernelGGL((k_poly_diffs_ring<128, 1>), dim3(256), dim3(256), 0, st, w, tr, tr + tq, part);
+      if (count <= 16) {
+        hipLaunchKernelGGL((k_poly_diffs_ring<128, 1, 8>), dim3(256), dim3(256), 0, st, w, tr, tr + tq, 0, part);
+      } else {  // tiles of 32 pairs, one launch each
+        for (int k0 = 0; k0 < count; k0 += 32)
+          hipLaunchKernelGGL((k_poly_diffs_ring<128, 2, 4>), dim3(256), dim3(256), 0, st, w, tr, tr + tq, k0, part);
+      }
       return hipGetLastError();
     }
     if (count <= 32) return launch_mfma_tm<T, 32>(kind, n, w, u1, u2, tr, chunk, bchunk, sb, part, st);

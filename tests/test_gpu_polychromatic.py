@@ -157,6 +157,34 @@ def test_polychromatic_small_group_paths_agree(gpu_lib):
     assert rel(mu1, mu2) < 1e-5 / math.sqrt(floor)
 
 
+@pytest.mark.parametrize("count", [24, 64])
+def test_polychromatic_on_shared_fft_grid_equals_batch_sum(gpu_lib, count):
+    """N = 128 complex64 on a source that is not separable (the GSM source plus a seeded random array at
+    5 % of its peak), with pairs of one product lambda z, so that every pair's FFT grid is the common grid:
+    the polychromatic S equals the sum over pairs of the batch's S (groups of 24 pairs: the difference sums
+    on the register ring over two tiles of 16 pairs; 64: two launches of it). The batch takes the folded
+    Fresnel difference sums, so this pins the unfolded bins of the ring on a non-separable source."""
+    wl = WI.gsm128()
+    n, p = wl.n, wl.pitch_m
+    g = WI.rng(99)
+    lam = np.sort(g.uniform(500e-9, 700e-9, count))
+    lz = 600e-9 * 0.5
+    zs = lz / lam
+    ws = g.uniform(0.2, 1.0, count)
+    dx = O.output_pitch(n, p, 600e-9, 0.5)
+    ip, jp = wl.probe
+    w0 = gpu_lib.build_source(wl.source, n, p, torch.complex64)
+    w0 += 0.05 * float(w0.abs().max()) * torch.from_numpy(
+        WI.random_complex((n, n, n, n), seed=100, dtype=np.complex64)).cuda()
+    s_poly, _ = gpu_lib.propagate_polychromatic(w0, p, lam, zs, ws, dx, ip=ip, jp=jp)
+    s_batch, _ = gpu_lib.propagate_batch(w0, p, lam, zs, ws, ip=ip, jp=jp)
+    s_poly = host(s_poly).astype(np.float64)
+    s_sum = host(s_batch).astype(np.float64).sum(axis=0)
+    del w0
+    torch.cuda.empty_cache()
+    assert rel(s_poly, s_sum) < 1e-5
+
+
 def test_polychromatic_rejects(gpu_lib):
     w = torch.zeros((8, 8, 8, 8), dtype=torch.complex64, device="cuda")
     with pytest.raises(gpu_lib.WolfError):
