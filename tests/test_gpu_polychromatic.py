@@ -131,9 +131,9 @@ def test_polychromatic_full_size_gsm(gpu_lib):
 def test_polychromatic_small_group_paths_agree(gpu_lib):
     """N = 128 complex64 on a source that is not separable (the GSM source plus a seeded random array at
     5 % of its peak), 12 wavelengths at four distances on a common grid of no pair's pitch: the group of 12
-    pairs (its difference sums on the register ring, at most 16 pairs) against the same pairs followed by
-    21 pairs of zero weight (a group of 33: the LDS-staged difference sums that the small-N oracle tests
-    cover). The sums are the same up to FP32 summation order."""
+    pairs (its difference sums on the register ring over one tile of 16 pairs) against the same pairs
+    followed by 21 pairs of zero weight (a group of 33: two launches of the ring over two tiles each, the
+    second at a pair offset of 32). The sums are the same up to FP32 summation order."""
     wl = WI.gsm128()
     n, p = wl.n, wl.pitch_m
     pairs = WI.polychromatic_pairs()
