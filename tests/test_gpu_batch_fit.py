@@ -119,18 +119,20 @@ def test_batch_n32_full_and_ragged_groups_vs_oracle(gpu_lib, dtype):
         assert rel(mu[k], O.degree_of_coherence(wb, ip, jp, floor)) < TOL[dtype] / math.sqrt(floor), k
 
 
-@pytest.mark.parametrize("n", [64, 256])
-def test_batch_gsm_separable_large(gpu_lib, n):
-    """complex64 GSM at N = 64 and at the largest N (256: a 34 GB source, 65536-row contractions), three
-    pairs against the separable oracle: S and the mu row."""
+@pytest.mark.parametrize("n,count", [(64, 3), (64, 20), (64, 40), (256, 3)])
+def test_batch_gsm_separable_large(gpu_lib, n, count):
+    """complex64 GSM at N = 64 (3, 20 and 40 pairs: the row sums on the register ring over one, two and
+    four tiles of 16 pairs) and at the largest N (256: a 34 GB source, 65536-row contractions), against
+    the separable oracle: S and the mu row of three of the pairs."""
     if n == 256:
         wl = WI.gsm256()[0]
         p, sp = wl.pitch_m, wl.source
     else:
         p, sp = 20e-6, WI.SourceSpec(model=WI.MODEL_GSM, sigma_s_m=0.1e-3, sigma_g_m=0.05e-3)
-    lam = np.array([500e-9, 632.8e-9, 700e-9])
-    zs = np.array([0.3, 1.0, 0.6])
-    ws = np.array([1.0, 0.4, 0.8])
+    g = WI.rng(101)
+    lam = np.concatenate([[500e-9, 632.8e-9, 700e-9], g.uniform(500e-9, 700e-9, count - 3)])
+    zs = np.concatenate([[0.3, 1.0, 0.6], g.uniform(0.2, 1.0, count - 3)])
+    ws = np.concatenate([[1.0, 0.4, 0.8], g.uniform(0.2, 1.0, count - 3)])
     ip, jp, floor = n // 2, n // 2 - 3, 1e-4
     w0 = gpu_lib.build_source(sp, n, p, torch.complex64)
     s, mu = gpu_lib.propagate_batch(w0, p, lam, zs, ws, ip=ip, jp=jp, floor_rel=floor)
