@@ -44,19 +44,24 @@ def parse():
                          "(autotune), or "
                          "'fused,slab_chunk,col_chunk[,coop_cols,coop_lookahead]'")
     ap.add_argument("--pmc-sample", nargs="?", const="propagate", default=None,
-                    choices=["propagate", "batch", "padded", "source"],
+                    choices=["propagate", "batch", "padded", "source", "n256"],
                     help="run one untimed invocation for a counter run and exit: 'propagate' (build, in-place "
                          "propagation, then a 2 GiB runtime copy of known size for calibration), 'batch' "
                          "(the 64-pair observables batch, then the 16-wavelength sum at z = 0.5 m on the FFT grid of "
                          "500 nm), 'padded' (N = 200 complex64 in place, padded to "
                          "N_z = 512, then unpadded) or 'source' (build + propagation, then the one-call source "
-                         "propagation, five times each)")
+                         "propagation, five times each) or 'n256' (the N = 256 GSM complex64 build and one in-place "
+                         "propagation under the plan the autotuner picks for it, 0,512,64, then a 2 GiB runtime copy "
+                         "for calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="rocprofv3 FETCH/WRITE summary for the current kernels (optional)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="no GPU: from the counter_collection.csv files of two rocprofv3 runs of "
                          "'--pmc-sample propagate' (FETCH_SIZE, then WRITE_SIZE) with the same --plan, write the "
                          "calibrated HBM bytes of one propagation to --traffic and exit")
+    ap.add_argument("--traffic-workload", default="gsm128_fresnel_c64", choices=["gsm128_fresnel_c64", "gsm256_fresnel_c64"],
+                    help="workload name recorded by --write-traffic ('gsm256_fresnel_c64' for '--pmc-sample n256', "
+                         "with --plan 0,512,64 and --traffic profiles/traffic_gsm256.json)")
     return ap.parse_args()
 
 
@@ -102,7 +107,7 @@ def timed_steps(fn, steps, warmup, marks):
 def main():
     args = parse()
     if args.write_traffic:
-        write_traffic(args.write_traffic[0], args.write_traffic[1], args.plan, args.traffic)
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.plan, args.traffic, args.traffic_workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: measures one GPU only; run it with --gpus 1 "
@@ -157,6 +162,19 @@ def main():
         n2, p2, z2, w2 = padded_source(wolf)
         for nz in (512, 200):
             wolf.propagate_padded(w2, p2, wolf_lam(), z2, nz, out=w2)
+        torch.cuda.synchronize()
+        print("pmc sample done", flush=True)
+        return
+    if args.pmc_sample == "n256":
+        del w
+        torch.cuda.empty_cache()
+        wl2 = WI.gsm256()[0]
+        n2, p2 = wl2.n, wl2.pitch_m
+        wolf.set_plan(n2, torch.complex64, *N256_PLAN)
+        w2 = wolf.build_source(wl2.source, n2, p2, torch.complex64)
+        wolf.propagate_fresnel(w2, p2, wl2.wavelength_m, wl2.z_m, out=w2)
+        cal = torch.empty(1 << 28, dtype=torch.complex64, device="cuda")
+        cal.copy_(w2.view(-1)[: 1 << 28])  # calibration: 2 GiB read + 2 GiB write by the runtime's copy kernel
         torch.cuda.synchronize()
         print("pmc sample done", flush=True)
         return
@@ -356,8 +374,9 @@ def plan_dict(text: str) -> dict:
     return {"fused_slab": v[0], "slab_chunk": v[1], "col_chunk": v[2], "coop_cols": v[3], "coop_lookahead": v[4]}
 
 
-def write_traffic(fetch_csv: str, write_csv: str, plan_text: str, out_path: str) -> None:
-    """Calibrated HBM bytes of the one propagation of '--pmc-sample propagate': the FETCH_SIZE and WRITE_SIZE
+def write_traffic(fetch_csv: str, write_csv: str, plan_text: str, out_path: str,
+                  workload: str = "gsm128_fresnel_c64") -> None:
+    """Calibrated HBM bytes of the one propagation of '--pmc-sample propagate' (or 'n256'): the FETCH_SIZE and WRITE_SIZE
     values (KiB per dispatch) of the operator's dispatches (after the source build, before the copy), each
     scaled by what the same counter reads for the runtime's 2 GiB copy (2 GiB read and 2 GiB written)."""
     import csv
@@ -376,7 +395,7 @@ def write_traffic(fetch_csv: str, write_csv: str, plan_text: str, out_path: str)
         out[tag] = sum(v for _, v in seq[i0 + 1:i1]) * 1024.0 * factor
         out[tag + "_factor"] = round(factor, 4)
         out[tag + "_dispatches"] = i1 - i0 - 1
-    rec = {"workload": "gsm128_fresnel_c64", "plan": plan_dict(plan_text), "kernels_sha": kernels_sha(),
+    rec = {"workload": workload, "plan": plan_dict(plan_text), "kernels_sha": kernels_sha(),
            "propagate_bytes_per_launch": int(out["fetch"] + out["write"]), "fetch_bytes": int(out["fetch"]),
            "write_bytes": int(out["write"]), "fetch_factor": out["fetch_factor"],
            "write_factor": out["write_factor"], "dispatches": out["fetch_dispatches"]}
@@ -687,6 +706,11 @@ def wolf_lam():
     return WI.LAMBDA_HENE
 
 
+# The plan the autotuner picks for the N = 256 complex64 workload (row pass, i2 and j1 passes over chunks of 512
+# slabs, 64-column first-point chunks); the counter sample runs under it.
+N256_PLAN = (0, 512, 64)
+
+
 def big(wolf, args):
     import torch
 
@@ -712,9 +736,19 @@ def big(wolf, args):
     del w
     torch.cuda.empty_cache()
     ach = 32.0 * n ** 4 / (t * 1e-3) / 1e9
+    traffic = None
+    path = os.path.join(ROOT, "profiles", "traffic_gsm256.json")
+    if os.path.exists(path):
+        try:
+            tr = json.load(open(path))
+            if (tr.get("kernels_sha") == kernels_sha() and tr.get("workload") == "gsm256_fresnel_c64"
+                    and tr.get("plan") == plan):
+                traffic = tr.get("propagate_bytes_per_launch")
+        except Exception:
+            traffic = None
     return {"n256_plan": plan, "n256_c64_fresnel_ms": round(t, 3), "n256_elems_per_s": n ** 4 / (t * 1e-3),
             "n256_roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(ach / HBM_PEAK_GBS, 4),
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                               "kernel": "wolf_propagate_fresnel at N = 256 GSM complex64 in place, 32 B/element "
                                         "algorithmic (2^32 elements)"}}
 

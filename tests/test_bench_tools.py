@@ -40,3 +40,24 @@ def test_write_traffic(tmp_path):
     assert rec["plan"] == {"fused_slab": 3, "slab_chunk": 2048, "col_chunk": 1024, "coop_cols": 0,
                            "coop_lookahead": 1}
     assert rec["workload"] == "gsm128_fresnel_c64" and len(rec["kernels_sha"]) == 16
+
+
+def test_write_traffic_n256_workload(tmp_path):
+    """The N = 256 sample's record carries its own workload name and plan, so that the N = 256 roofline and
+    the headline each take only their own figure."""
+    gib2_kib = 2 * 1024 * 1024
+    fetch = [("wolf::k_build_source", 64.0), ("wolf::k_row_fft", 500.0), ("wolf::k_axis_fft", 700.0),
+             ("__amd_rocclr_copyBuffer", gib2_kib / 2)]
+    write = [("wolf::k_build_source", 10.0), ("wolf::k_row_fft", 900.0), ("wolf::k_axis_fft", 1100.0),
+             ("__amd_rocclr_copyBuffer", gib2_kib)]
+    fp, wp, out = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "t.json"
+    _counter_csv(fp, "FETCH_SIZE", fetch)
+    _counter_csv(wp, "WRITE_SIZE", write)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--write-traffic", str(fp), str(wp),
+                        "--plan", "0,512,64", "--traffic", str(out), "--traffic-workload", "gsm256_fresnel_c64"],
+                       capture_output=True, text=True, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    rec = json.load(open(out))
+    assert rec["workload"] == "gsm256_fresnel_c64"
+    assert rec["plan"] == {"fused_slab": 0, "slab_chunk": 512, "col_chunk": 64, "coop_cols": 0, "coop_lookahead": 1}
+    assert rec["propagate_bytes_per_launch"] == int(1200.0 * 1024 * 2.0) + int(2000.0 * 1024)
