@@ -272,6 +272,22 @@ template <class T, int NZ> constexpr int pad_groups() {
   return (sizeof(T) == 16 && S::L1 <= 16 && phases_fit_more) ? 1 : S::Q;
 }
 
+// Tiles of a pass in XCD order. The hardware deals consecutive workgroups to the 8 XCDs in turn, and with
+// the plain grid-stride order neighbouring tiles ran on different XCDs: where a line's rows are not
+// 128-byte aligned (N = 200: 1600 B), two neighbouring tiles share the cache lines at their boundary, and
+// each XCD fetched those lines again. Here XCD x takes a contiguous share of the tiles, in proportion to
+// its workgroups (b < G with b mod 8 = x), and its workgroups stride through that share, so neighbouring
+// tiles run at the same time on one XCD and meet in its L2. A partition of [0, tiles) for any grid size.
+struct TileRange {
+  long long first, end, step;
+};
+__device__ __forceinline__ TileRange xcd_tiles(long long tiles) {
+  const long long G = gridDim.x, x = blockIdx.x % 8, r = G % 8;
+  const long long below = (G / 8) * x + (r < x ? r : x);             // workgroups on XCDs 0 .. x-1
+  const long long upto = (G / 8) * (x + 1) + (r < x + 1 ? r : x + 1);  // ... on XCDs 0 .. x
+  return TileRange{tiles * below / G + blockIdx.x / 8, tiles * upto / G, upto - below};
+}
+
 template <class T, int NZ, int SIGN, bool CONTIG>
 __global__ __launch_bounds__((LineCfg<T, NZ>::kThreads)) void k_axis_pad(const T* src, T* dst, PadJob j) {
   using S = LineCfg<T, NZ>;
@@ -291,7 +307,8 @@ __global__ __launch_bounds__((LineCfg<T, NZ>::kThreads)) void k_axis_pad(const T
   // Per-element offsets m * stride (the compiler keeps them across tiles): one start and
   // wave-uniform steps took fewer registers but ran slower here (N = 200: 25.4 ms instead of 22.7 ms).
   const long long as = j.axis_stride;
-  for (long long tile = blockIdx.x; tile < j.tiles; tile += gridDim.x) {
+  const TileRange tr = xcd_tiles(j.tiles);
+  for (long long tile = tr.first; tile < tr.end; tile += tr.step) {
     const long long o = tile / j.tiles_per_outer;
     const long long col = (tile - o * j.tiles_per_outer) * C + c;
     const bool valid = col < j.ncols;
@@ -394,7 +411,8 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
   const long long as = j.axis_stride, in_step = (long long)N2 * as, out_step = (long long)N1 * as;
   constexpr int RA = 4 * KW, RZ = KW > 0 ? 4 * KW + 4 : H;  // rows below RA: all lanes; from RZ: none
   static_assert(KW >= 0 && RA <= H && (KW == 0 || KW < N2 / 2), "bands of N within N_z / 2");
-  for (long long tile = blockIdx.x; tile < j.tiles; tile += gridDim.x) {
+  const TileRange tr = xcd_tiles(j.tiles);
+  for (long long tile = tr.first; tile < tr.end; tile += tr.step) {
     const long long o = tile / j.tiles_per_outer;
     const long long col0 = (tile - o * j.tiles_per_outer) * C;
     const long long col = col0 + c;

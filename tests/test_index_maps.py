@@ -1,5 +1,5 @@
 """Host checks of index maps: the compile-time row ranges of the folded zero-padded FFT pass at N_z = 512
-and 128, and the workgroup order of the one-pass sums.
+and 128, the workgroup order of the one-pass sums, and the XCD order of the padded passes' tiles.
 
 A padded axis (Sec. 3.3) embeds N data points at offset s = (N_z - N)/2 of an N_z-point transform,
 N_z = 2 L2^2 (L2 = 16 or 8, L1 = 2 L2). Thread t of a line holds the first-stage inputs at data indices
@@ -87,3 +87,33 @@ def test_one_pass_block_order(gx, gy):
         assert y % 8 == l % 8
         seen.add((x, y))
     assert len(seen) == gx * gy
+
+
+def _xcd_tiles(G, b, tiles):
+    """The padded passes' tile range of workgroup b in a grid of G: (first, end, step)."""
+    x, r = b % 8, G % 8
+    below = (G // 8) * x + min(r, x)
+    upto = (G // 8) * (x + 1) + min(r, x + 1)
+    return tiles * below // G + b // 8, tiles * upto // G, upto - below
+
+
+@pytest.mark.parametrize("G", [1, 3, 7, 8, 9, 13, 64, 100, 777, 4096])
+def test_xcd_tile_order_is_a_partition(G):
+    """Every tile is taken by exactly one workgroup (grid G = min(tiles, 4096) as launched, and larger
+    tile counts), each XCD's share is contiguous, and the shares differ by at most one tile per workgroup."""
+    for tiles in sorted({G, G + 1, 2 * G + 5, 8 * G + 3, 10 * G, 12345}):
+        if tiles < G:
+            continue
+        seen = [0] * tiles
+        shares = {}
+        for b in range(G):
+            first, end, step = _xcd_tiles(G, b, tiles)
+            assert step >= 1
+            for t in range(first, end, step):
+                seen[t] += 1
+                shares.setdefault(b % 8, []).append(t)
+        assert all(c == 1 for c in seen), (G, tiles)
+        for x, ts in shares.items():
+            assert sorted(ts) == list(range(min(ts), max(ts) + 1)), (G, tiles, x)
+        per_wg = [len(range(*_xcd_tiles(G, b, tiles))) for b in range(G)]
+        assert max(per_wg) - min(per_wg) <= 2, (G, tiles)
