@@ -445,6 +445,22 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
       }
     }
     // Every load of the tile has been consumed here, so the stores below may overwrite src.
+    // Output k2 of phase p: data index 2 t + p - s + L1 k2, stored where it is in the data.
+    const long long at0 = base + (long long)(2 * t - sft) * as;  // output k2 = 0 of phase 0
+    auto store = [&](int p, int k2, const T& val) {
+      const int m = 2 * t + p - sft + N1 * k2, d = k2 - N2 / 2;
+      const long long at = at0 + p * as + k2 * out_step;
+      if (KW > 0 && d >= -KW && d < KW) {
+        if (valid) dst[at] = cmul(val, tpost[m]);
+      } else if (KW == 0 || (d >= -KW - 1 && d <= KW)) {
+        if (valid && m >= 0 && m < n) dst[at] = cmul(val, tpost[m]);
+      }
+    };
+    // Along a contiguous line the two phases fill alternate elements of the same memory lines: phase 0's
+    // outputs wait in registers and both phases store together, so that no line leaves the L2 half written.
+    // Where the registers allow it (complex64; at N_z = 512 the bands KW = 1 .. 3; elsewhere they spill).
+    constexpr bool kDefer = CONTIG && sizeof(T) == 8 && (NZ < 512 || (KW >= 1 && KW <= 3));
+    T u0[N2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       T v[H];
@@ -462,16 +478,20 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
       for (int n2 = 0; n2 < N2; ++n2) u[n2] = xch[L::at(t, n2, c)];
       __syncthreads();  // the buffer is rewritten by the next phase or tile
       dft_any<N2, SIGN>(u);
-      const int mk = 2 * t + p - sft;  // data index of output k2 = 0
-      long long at = base + (long long)mk * as;
+      if constexpr (kDefer) {
+        if (p == 0) {
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2, at += out_step) {
-        const int m = mk + N1 * k2, d = k2 - N2 / 2;
-        if (KW > 0 && d >= -KW && d < KW) {
-          if (valid) dst[at] = cmul(u[k2], tpost[m]);
-        } else if (KW == 0 || (d >= -KW - 1 && d <= KW)) {
-          if (valid && m >= 0 && m < n) dst[at] = cmul(u[k2], tpost[m]);
+          for (int k2 = 0; k2 < N2; ++k2) u0[k2] = u[k2];
+        } else {
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) {
+            store(0, k2, u0[k2]);
+            store(1, k2, u[k2]);
+          }
         }
+      } else {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) store(p, k2, u[k2]);
       }
     }
   }
