@@ -613,13 +613,13 @@ hipError_t launch_operator_padfft(int n, int nz, const T* in, T* out, const Oper
   const PadJob i2{NN, NN, N, 1, N, n, sft, op.pre2, op.post2, 0, 0};    // stride N, N^2 blocks of N lines
   const PadJob j1{N, NNN, NN, 1, NN, n, sft, op.pre1, op.post1, 0, 0};  // stride N^2, N blocks of N^2 lines
   const PadJob i1{1, 0, NNN, 1, NNN, n, sft, op.pre1, post1, 0, 0};     // stride N^3, N^3 lines
-  // Padded (N_z > N): the j2, i2 and j1 passes run over groups of whole i1 planes of at most 256 MB, one group
-  // after the other, so that each group's second and third passes find it in the memory-side cache; the i1
-  // pass then runs over the whole array. N = 200 padded to 512: 24.7 -> 23.1 ms in complex64 (groups of 4
-  // planes); N = 256 to 512: 66.4 -> 58.3 ms (1 plane); N = 200 to 512 in complex128: 47.5 -> 44.6 ms. The
-  // unpadded passes measured slower grouped, and stay whole.
+  // The j2, i2 and j1 passes run over groups of whole i1 planes of at most 256 MB, one group after the other,
+  // so that each group's second and third passes find it in the memory-side cache; the i1 pass then runs over
+  // the whole array. N = 200 padded to 512: 24.7 -> 23.1 ms in complex64 (groups of 4 planes); N = 256 to 512:
+  // 66.4 -> 58.3 ms (1 plane); N = 200 to 512 in complex128: 47.5 -> 44.6 ms; N = 200 unpadded (with the tiles
+  // in XCD order): 22.29 -> 22.03 ms.
   const long long P = (256ll << 20) / (NNN * (long long)sizeof(T));  // planes per group
-  if (nz > n && P < N) {
+  if (P < N) {
     const long long pg = P < 1 ? 1 : P;
     for (long long i0 = 0; i0 < N; i0 += pg) {
       const long long pp = i0 + pg <= N ? pg : N - i0, off = i0 * NNN;

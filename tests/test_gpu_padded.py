@@ -138,11 +138,12 @@ def test_padded_full_size_gsm(gpu_lib, n, nz, dtype):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n,nz,dtype", [(136, 512, torch.complex64), (200, 512, torch.complex128)])
+@pytest.mark.parametrize("n,nz,dtype", [(136, 512, torch.complex64), (200, 512, torch.complex128),
+                                        (200, 200, torch.complex64), (144, 144, torch.complex128)])
 def test_padded_plane_groups_out_of_place(gpu_lib, n, nz, dtype):
-    """The padded passes run over groups of i1 planes (12 and 2 planes here); out of place each group's first
-    pass reads its planes of the input. The result equals the in-place one bit for bit and the input is left
-    unchanged."""
+    """The passes run over groups of i1 planes (12, 2, 4 and 5 planes here; 136 and 144 leave a ragged last
+    group), padded and unpadded; out of place each group's first pass reads its planes of the input. The
+    result equals the in-place one bit for bit and the input is left unchanged."""
     sp = SimpleNamespace(model=WI.MODEL_GSM, amplitude=1.0, sigma_s_m=0.1e-3, sigma_g_m=0.05e-3, geometry=WI.GEO_NONE,
                          geo_r0_m=0.0, geo_r1_m=0.0, intensity_map=None, mask=None, lens_focal_m=0.0, wavelength_m=0.0)
     w = gpu_lib.build_source(sp, n, 20e-6, dtype)
