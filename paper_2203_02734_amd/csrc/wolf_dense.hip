@@ -458,8 +458,9 @@ void k_axis_pad_fold(const T* src, T* dst, PadJob j) {
     };
     // Along a contiguous line the two phases fill alternate elements of the same memory lines: phase 0's
     // outputs wait in registers and both phases store together, so that no line leaves the L2 half written.
-    // Where the registers allow it (complex64; at N_z = 512 the bands KW = 1 .. 3; elsewhere they spill).
-    constexpr bool kDefer = CONTIG && sizeof(T) == 8 && (NZ < 512 || (KW >= 1 && KW <= 3));
+    // Where the registers allow it (N_z <= 128; at N_z = 512 the complex64 bands KW = 1 .. 3; elsewhere they
+    // spill).
+    constexpr bool kDefer = CONTIG && (NZ < 512 || (sizeof(T) == 8 && KW >= 1 && KW <= 3));
     T u0[N2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
